@@ -1,0 +1,203 @@
+/*
+ * ssd.h -- C ABI of the MI355X sliding super point detector.
+ *
+ * The method is the one of "Regain Sliding super point from distributed edge
+ * routers by GPU" (Jie Xu, 2018): a reversible sliding estimator array (RSEA,
+ * Sec. 3.3) of r rows x 2^q sliding estimators (Sec. 3.2) of eta cells each,
+ * updated by every (cip, oip) pair (Alg. 2) and inverted at the end of every
+ * slot to regain the hosts whose opposite number over the last k slots is at
+ * least theta (Def. 4, Alg. 3/4, parallel form Sec. 4.2), with per-router
+ * arrays merged per slot in the distributed deployment (Alg. 5).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int status: SSD_OK (0) or a negative SSD_E_* code.
+ *     No C++ exception crosses the ABI.  ssd_last_error() gives a message for
+ *     the last failing call on the calling thread.
+ *   - Device memory and the HIP stream belong to the caller.  The library owns
+ *     only the opaque host object (and a small pinned host mailbox inside it).
+ *     Device pointers must stay valid until ssd_destroy().
+ *   - Work is enqueued on the caller's stream.  ssd_scan_slice() is
+ *     asynchronous; ssd_close_slice() returns after the results reached host
+ *     memory.  A detector is not thread-safe; separate detectors are
+ *     independent.
+ *   - IPv4 addresses are host-order uint32 (a.b.c.d = a<<24|b<<16|c<<8|d).
+ *   - SSD_E_DEVICE means a HIP call failed; the detector then refuses further
+ *     work (SSD_E_STATE) and must be destroyed.
+ */
+#ifndef SSD_H
+#define SSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSD_ABI_VERSION 1u
+
+#define SSD_OK 0
+#define SSD_E_PARAM (-1)    /* invalid parameter or argument                       */
+#define SSD_E_NOMEM (-2)    /* a caller buffer is too small or misaligned          */
+#define SSD_E_ORDER (-3)    /* slice_id is not the open slice                       */
+#define SSD_E_OVERFLOW (-4) /* a candidate level exceeded max_tuples, or accepted
+                               hosts exceeded max_results; no list is returned      */
+#define SSD_E_INCOMPAT (-5) /* merged detectors differ in geometry, tables or clock */
+#define SSD_E_TRUNC (-6)    /* the output array is too small; *n_out = needed size  */
+#define SSD_E_DEVICE (-7)   /* a HIP call failed                                    */
+#define SSD_E_STATE (-8)    /* the detector is unusable after an earlier failure    */
+
+/* ssd_params.flags */
+#define SSD_VERIFY_REHASH 0x1u /* drop a regained host x unless RHFG[0](x) equals the
+                                  tuple's row-0 column (off = the paper's method)   */
+/* ssd_close_slice() flags */
+#define SSD_ADVANCE_ONLY 0x1u  /* only advance the slot clock (router detectors)    */
+
+/*
+ * Detector geometry and limits.
+ *   q, r, delta: RSEA of r rows x 2^q columns; RHFG[i](cip) =
+ *       ((cip >> ((i-1)*delta)) XOR RHFG[0](cip)) mod 2^q for i >= 1 (Eq. 2,
+ *       read with a (i-1)*delta shift so that the hashes are invertible).
+ *       3 <= r <= 16, 4 <= q <= 20, 1 <= delta < q, delta <= 12,
+ *       key_bits <= (r-2)*delta + q <= 64.
+ *   eta: cells per sliding estimator, a power of two, 1024..65536 (Sec. 3.2).
+ *   k: window length in slots, 1..254 (cells are 8-bit slot stamps).
+ *   theta: super point threshold on the opposite number (Def. 2), >= 1.  An
+ *       estimator is hot when its in-window cell count reaches
+ *       T = ceil(eta * (1 - exp(-theta/eta))) (Sec. 3.3).
+ *   key_bits: host address width, 8..32 (32 for IPv4).  Regained values with
+ *       a bit at or above key_bits are dropped.
+ *   flags: SSD_VERIFY_REHASH or 0.
+ *   max_tuples: capacity of each candidate-tuple level (Sec. 4.2 buffers).
+ *   max_results: capacity for accepted hosts before de-duplication.
+ */
+typedef struct {
+    uint32_t abi_version; /* = SSD_ABI_VERSION */
+    uint32_t q, r, delta;
+    uint32_t eta;
+    uint32_t k;
+    uint32_t theta;
+    uint32_t key_bits;
+    uint32_t flags;
+    uint32_t reserved; /* = 0 */
+    uint64_t max_tuples;
+    uint64_t max_results;
+} ssd_params;
+
+/* One regained host: its address, the in-window cell count R of its union
+ * estimator (Alg. 1 over its r estimators) and the estimate of Eq. 1,
+ * -eta * ln(max(eta - R, 1) / eta), in double. */
+typedef struct {
+    uint32_t ip;
+    uint32_t rk;
+    double est;
+} ssd_super_point;
+
+typedef struct ssd_detector ssd_detector;
+
+/* Read-only facts about a detector. */
+typedef struct {
+    uint64_t open_slice;     /* slice that scans currently write               */
+    uint32_t hot_threshold;  /* T                                              */
+    uint32_t r;
+    uint64_t state_bytes;    /* r * 2^q * eta                                  */
+    uint64_t level_counts[16]; /* tuples per candidate level at the last close
+                                  (level 0 = rows 0..2, level L = row L+2)      */
+    uint32_t hot_counts[16]; /* |HSE(i)| at the last close                     */
+    uint64_t accepted;       /* accepted tuples at the last close              */
+    uint64_t reported;       /* hosts in the last result list                  */
+} ssd_info;
+
+/* Sizes the caller must allocate on the device for params p: the estimator
+ * state (16-byte aligned) and the library's scratch (256-byte aligned).
+ * Returns SSD_E_PARAM if p is invalid. */
+int ssd_query_sizes(const ssd_params *p, uint64_t *state_bytes, uint64_t *scratch_bytes);
+
+/* Create a detector (Sec. 3.2: every cell starts empty, once).
+ *   tables_host: uint32[2][4][256] host array, the tabulation tables of
+ *       RHFG[0] ([0]) and of the cell hash H1 ([1]) (simple tabulation
+ *       hashing, cited in Sec. 3.2 and 3.3); copied, not retained.
+ *   state_dev / scratch_dev: caller-owned device buffers of at least the
+ *       sizes from ssd_query_sizes(); their contents are overwritten.
+ *   stream: hipStream_t (NULL = default stream) on which all work runs; the
+ *       device current at this call is the detector's device.
+ *   out: receives the detector.  The open slice is 0. */
+int ssd_init_detector(const ssd_params *p, const uint32_t *tables_host,
+                      void *state_dev, uint64_t state_bytes,
+                      void *scratch_dev, uint64_t scratch_bytes,
+                      void *stream, ssd_detector **out);
+
+/* Scan n (cip, oip) pairs into the open slice (Alg. 2; parallel form
+ * Sec. 4.1).  pairs_dev: device array uint32[n][2], 8-byte aligned, with
+ * [i][0] the monitored host cip and [i][1] its peer oip; borrowed until the
+ * stream passes this call.  slice_id must equal the open slice
+ * (SSD_E_ORDER otherwise).  Any number of calls per slice; the result does
+ * not depend on how pairs are split over calls or ordered.  n = 0 is a no-op. */
+int ssd_scan_slice(ssd_detector *d, const uint32_t *pairs_dev, uint64_t n, uint64_t slice_id);
+
+/* Close the open slice t.  Without flags: estimate every sliding estimator
+ * over slots max(0, t-k+1)..t, regain the candidate hosts (Sec. 4.2) and
+ * report SSP(max(0, t-k+1), k) sorted by ip, one entry per ip with its largest
+ * R; write up to cap entries to out_host (host memory) and the count to
+ * *n_out.  With SSD_ADVANCE_ONLY (router detectors in the distributed case):
+ * only advance the clock; *n_out = 0.  The open slice becomes t+1 in every
+ * case except SSD_E_DEVICE.  SSD_E_TRUNC: cap was too small (the list is kept
+ * for ssd_get_results()).  SSD_E_OVERFLOW: a capacity was exceeded and no
+ * list is returned; the window contents are unchanged. */
+int ssd_close_slice(ssd_detector *d, uint32_t flags, ssd_super_point *out_host,
+                    uint64_t cap, uint64_t *n_out);
+
+/* The list of the last close again (host copy). */
+int ssd_get_results(ssd_detector *d, ssd_super_point *out_host, uint64_t cap, uint64_t *n_out);
+
+/* Distributed merge (Alg. 5): overwrite global's window contents, for every
+ * cell, with the most recent hit over the routers' cells (per-cell maximum
+ * slot stamp, i.e. minimum distance).  All detectors must share geometry,
+ * tables, device and open slice (SSD_E_INCOMPAT otherwise) and run on one
+ * device; the work runs on global's stream, after the routers' scans (the
+ * caller orders the streams if they differ).  n >= 1; routers must not
+ * include global. */
+int ssd_merge_router_state(ssd_detector *global, ssd_detector *const *routers, uint32_t n);
+
+/* Parity and inspection. */
+
+/* Canonical window state of the open slice t, after its scans and before its
+ * close: out_dev[i] (device, uint16, n_cells = r*2^q*eta entries in
+ * [row][column][cell] order) = t - (slot of the cell's latest hit) when that
+ * is below k, else 0xFFFF.  Synchronous. */
+int ssd_read_canonical_state(ssd_detector *d, uint16_t *out_dev, uint64_t n_cells);
+
+/* R_k of every estimator at the last close, uint32[r][2^q] (host). */
+int ssd_read_rk(ssd_detector *d, uint32_t *out_host, uint64_t n);
+
+/* Hot estimator lists HSE(0..r-1) of the last close: counts_host[r] and the
+ * ascending column lists packed row after row into lists_host (capacity
+ * cap entries). */
+int ssd_read_hot(ssd_detector *d, uint32_t *counts_host, uint32_t *lists_host, uint64_t cap);
+
+/* Candidate tuples that reached the final test at the last close, one column
+ * per row: out_host is uint32[cap][r]; *n_out = number of tuples (order is
+ * not specified).  SSD_E_TRUNC if cap is too small. */
+int ssd_read_tuples(ssd_detector *d, uint32_t *out_host, uint64_t cap, uint64_t *n_out);
+
+int ssd_get_info(ssd_detector *d, ssd_info *out);
+
+/* Tuning knobs; none changes results.
+ *   SSD_TUNE_SCAN_PASS_BYTES: state bytes one scan pass covers (0 = one pass
+ *       over the whole state).  Passes sized to the device's last-level cache
+ *       keep a pass's random byte stores cache-resident.
+ *   SSD_TUNE_SORT_BLOCK_LIMIT: result lists up to this many accepted hosts
+ *       are sorted inside one workgroup (at most 8192, the default); longer
+ *       lists use the multi-kernel sort. */
+#define SSD_TUNE_SCAN_PASS_BYTES 1u
+#define SSD_TUNE_SORT_BLOCK_LIMIT 2u
+int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
+
+void ssd_destroy(ssd_detector *d);
+const char *ssd_strerror(int status);
+const char *ssd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSD_H */

@@ -1,0 +1,270 @@
+"""MI355X sliding super point detector (arXiv 1803.11036), Python binding.
+
+A thin ctypes binding of the C ABI declared in ``include/ssd.h``: the names
+match the C calls without their ``ssd_`` prefix, and every function only
+marshals arguments -- the hot path (scan, hot detection, candidate expansion,
+verification, sort, merge) runs in the HIP kernels of ``libssd.so``.  PyTorch
+provides device memory and streams.
+
+The library must be built (``__graft_entry__.build()`` or
+``python -m paper_1803_11036_amd.build``); importing this package without it
+raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+__all__ = [
+    "SSD_VERIFY_REHASH", "SSD_ADVANCE_ONLY", "SSDError", "Params", "make_params",
+    "query_sizes", "Detector", "init_detector", "scan_slice", "close_slice",
+    "get_results", "merge_router_state", "read_canonical_state", "read_rk",
+    "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
+    "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT",
+    "library_path", "RESULT_DTYPE",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libssd.so")
+
+SSD_ABI_VERSION = 1
+SSD_VERIFY_REHASH = 0x1
+SSD_ADVANCE_ONLY = 0x1
+SSD_E_TRUNC = -6
+
+RESULT_DTYPE = np.dtype([("ip", "<u4"), ("rk", "<u4"), ("est", "<f8")])
+
+
+class Params(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("q", C.c_uint32), ("r", C.c_uint32),
+                ("delta", C.c_uint32), ("eta", C.c_uint32), ("k", C.c_uint32),
+                ("theta", C.c_uint32), ("key_bits", C.c_uint32), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32), ("max_tuples", C.c_uint64), ("max_results", C.c_uint64)]
+
+
+class _SuperPoint(C.Structure):
+    _fields_ = [("ip", C.c_uint32), ("rk", C.c_uint32), ("est", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("open_slice", C.c_uint64), ("hot_threshold", C.c_uint32), ("r", C.c_uint32),
+                ("state_bytes", C.c_uint64), ("level_counts", C.c_uint64 * 16),
+                ("hot_counts", C.c_uint32 * 16), ("accepted", C.c_uint64), ("reported", C.c_uint64)]
+
+
+assert C.sizeof(_SuperPoint) == RESULT_DTYPE.itemsize == 16
+
+
+class SSDError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(_LIB_PATH)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        u64p = C.POINTER(C.c_uint64)
+        L.ssd_query_sizes.argtypes = [C.POINTER(Params), u64p, u64p]
+        L.ssd_init_detector.argtypes = [C.POINTER(Params), C.POINTER(C.c_uint32), vp, u64, vp, u64, vp,
+                                        C.POINTER(vp)]
+        L.ssd_scan_slice.argtypes = [vp, vp, u64, u64]
+        L.ssd_close_slice.argtypes = [vp, u32, vp, u64, u64p]
+        L.ssd_get_results.argtypes = [vp, vp, u64, u64p]
+        L.ssd_merge_router_state.argtypes = [vp, C.POINTER(vp), u32]
+        L.ssd_read_canonical_state.argtypes = [vp, vp, u64]
+        L.ssd_read_rk.argtypes = [vp, vp, u64]
+        L.ssd_read_hot.argtypes = [vp, vp, vp, u64]
+        L.ssd_read_tuples.argtypes = [vp, vp, u64, u64p]
+        L.ssd_get_info.argtypes = [vp, C.POINTER(_Info)]
+        L.ssd_set_tuning.argtypes = [vp, u32, u64]
+        L.ssd_destroy.argtypes = [vp]
+        L.ssd_destroy.restype = None
+        L.ssd_strerror.argtypes = [C.c_int]
+        L.ssd_strerror.restype = C.c_char_p
+        L.ssd_last_error.argtypes = []
+        L.ssd_last_error.restype = C.c_char_p
+        for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice", "ssd_close_slice",
+                     "ssd_get_results", "ssd_merge_router_state", "ssd_read_canonical_state",
+                     "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
+                     "ssd_set_tuning"):
+            getattr(L, name).restype = C.c_int
+        _lib_handle = L
+    return _lib_handle
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        L = _lib()
+        raise SSDError(status, where, L.ssd_last_error().decode() or L.ssd_strerror(status).decode())
+
+
+def make_params(q: int, r: int, delta: int, eta: int, k: int, theta: int, key_bits: int = 32,
+                verify_rehash: bool = False, max_tuples: int = 1 << 22, max_results: int = 1 << 20) -> Params:
+    return Params(SSD_ABI_VERSION, q, r, delta, eta, k, theta, key_bits,
+                  SSD_VERIFY_REHASH if verify_rehash else 0, 0, max_tuples, max_results)
+
+
+def query_sizes(params: Params) -> Tuple[int, int]:
+    s, t = C.c_uint64(), C.c_uint64()
+    _check(_lib().ssd_query_sizes(C.byref(params), C.byref(s), C.byref(t)), "query_sizes")
+    return s.value, t.value
+
+
+class Detector:
+    """Owns the torch device buffers of one detector and its library handle."""
+
+    def __init__(self, params: Params, tables: np.ndarray, device=None, stream: Optional[torch.cuda.Stream] = None):
+        L = _lib()
+        self.params = params
+        self.device = torch.device(device if device is not None else "cuda")
+        state_bytes, scratch_bytes = query_sizes(params)
+        # allocations from torch; 256-byte aligned
+        self.state = torch.empty(state_bytes, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        tabs = np.ascontiguousarray(tables, dtype=np.uint32).reshape(-1)
+        if tabs.size != 2048:
+            raise ValueError("tables must hold 2 x 4 x 256 words")
+        self._tables = tabs
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.ssd_init_detector(C.byref(params), tabs.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       self.state.data_ptr(), state_bytes, self.scratch.data_ptr(),
+                                       scratch_bytes, self.stream.cuda_stream, C.byref(h)), "init_detector")
+        self.handle = h
+
+    def destroy(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib().ssd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def r(self) -> int:
+        return self.params.r
+
+    @property
+    def n_se(self) -> int:
+        return self.params.r << self.params.q
+
+
+def init_detector(params: Params, tables: np.ndarray, device=None, stream=None) -> Detector:
+    return Detector(params, tables, device, stream)
+
+
+def destroy(det: Detector) -> None:
+    det.destroy()
+
+
+def scan_slice(det: Detector, pairs: torch.Tensor, slice_id: int) -> None:
+    """pairs: contiguous (n, 2) 32-bit tensor on the detector's device, [:,0] = cip."""
+    if pairs.numel() and (pairs.device != det.state.device or pairs.element_size() != 4
+                          or not pairs.is_contiguous() or pairs.dim() != 2 or pairs.shape[1] != 2):
+        raise ValueError("pairs must be a contiguous (n, 2) 32-bit tensor on the detector's device")
+    n = pairs.shape[0] if pairs.dim() == 2 else 0
+    _check(_lib().ssd_scan_slice(det.handle, pairs.data_ptr() if n else None, n, slice_id), "scan_slice")
+
+
+def _results(det: Detector, fn, *args) -> np.ndarray:
+    L = _lib()
+    n = C.c_uint64()
+    cap = 4096
+    while True:
+        out = np.zeros(cap, dtype=RESULT_DTYPE)
+        st = fn(det.handle, *args, out.ctypes.data, cap, C.byref(n))
+        if st == SSD_E_TRUNC and n.value > cap:
+            cap = int(n.value)
+            fn = L.ssd_get_results
+            args = ()
+            continue
+        _check(st, fn.__name__)
+        return out[:n.value].copy()
+
+
+def close_slice(det: Detector, advance_only: bool = False) -> np.ndarray:
+    """Close the open slice; returns the SSP list (structured array ip, rk, est)."""
+    return _results(det, _lib().ssd_close_slice, SSD_ADVANCE_ONLY if advance_only else 0)
+
+
+def get_results(det: Detector) -> np.ndarray:
+    return _results(det, _lib().ssd_get_results)
+
+
+def merge_router_state(global_det: Detector, routers: Sequence[Detector]) -> None:
+    arr = (C.c_void_p * len(routers))(*[r.handle.value for r in routers])
+    _check(_lib().ssd_merge_router_state(global_det.handle, arr, len(routers)), "merge_router_state")
+
+
+def read_canonical_state(det: Detector) -> torch.Tensor:
+    """Canonical window state (int16 tensor on the device; view as uint16)."""
+    n = det.n_se * det.params.eta
+    out = torch.empty(n, dtype=torch.int16, device=det.state.device)
+    _check(_lib().ssd_read_canonical_state(det.handle, out.data_ptr(), n), "read_canonical_state")
+    return out
+
+
+def read_rk(det: Detector) -> np.ndarray:
+    out = np.zeros((det.params.r, 1 << det.params.q), dtype=np.uint32)
+    _check(_lib().ssd_read_rk(det.handle, out.ctypes.data, out.size), "read_rk")
+    return out
+
+
+def read_hot(det: Detector) -> List[np.ndarray]:
+    counts = np.zeros(det.params.r, dtype=np.uint32)
+    flat = np.zeros(det.n_se, dtype=np.uint32)
+    _check(_lib().ssd_read_hot(det.handle, counts.ctypes.data, flat.ctypes.data, flat.size), "read_hot")
+    out, o = [], 0
+    for c in counts.tolist():
+        out.append(flat[o:o + c].copy())
+        o += c
+    return out
+
+
+def read_tuples(det: Detector) -> np.ndarray:
+    L = _lib()
+    n = C.c_uint64()
+    st = L.ssd_read_tuples(det.handle, None, 0, C.byref(n))
+    if st not in (0, SSD_E_TRUNC):
+        _check(st, "read_tuples")
+    out = np.zeros((n.value, det.params.r), dtype=np.uint32)
+    if n.value:
+        _check(L.ssd_read_tuples(det.handle, out.ctypes.data, n.value, C.byref(n)), "read_tuples")
+    return out
+
+
+def get_info(det: Detector) -> Dict[str, object]:
+    info = _Info()
+    _check(_lib().ssd_get_info(det.handle, C.byref(info)), "get_info")
+    r = info.r
+    return {"open_slice": info.open_slice, "hot_threshold": info.hot_threshold,
+            "state_bytes": info.state_bytes, "level_counts": list(info.level_counts)[:max(r - 2, 0)],
+            "hot_counts": list(info.hot_counts)[:r], "accepted": info.accepted, "reported": info.reported}
+
+
+SSD_TUNE_SCAN_PASS_BYTES = 1
+SSD_TUNE_SORT_BLOCK_LIMIT = 2
+
+
+def set_tuning(det: Detector, knob: int, value: int) -> None:
+    _check(_lib().ssd_set_tuning(det.handle, knob, value), "set_tuning")

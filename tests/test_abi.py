@@ -1,0 +1,96 @@
+"""C ABI checks that need no GPU: the library loads, exports every call that
+include/ssd.h declares, and validates parameters on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1803_11036_amd as ssd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "ssd.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call():
+    names = _declared()
+    assert len(names) >= 15
+    lib = C.CDLL(ssd.library_path())
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_names_match_the_abi():
+    for n in _declared():
+        py = n[len("ssd_"):]
+        if py in ("strerror", "last_error"):
+            continue
+        assert hasattr(ssd, py), py
+
+
+def _p(**kw):
+    base = dict(q=12, r=6, delta=5, eta=1024, k=4, theta=1024)
+    base.update(kw)
+    return ssd.make_params(**base)
+
+
+def test_query_sizes():
+    state, scratch = ssd.query_sizes(_p())
+    assert state == 6 * 4096 * 1024
+    assert scratch > 6 * 4096 * 8 and scratch % 256 == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(r=2), dict(r=17), dict(q=3), dict(q=21), dict(delta=0), dict(delta=12, q=12),
+    dict(eta=1000), dict(eta=512), dict(eta=1 << 17), dict(k=0), dict(k=255), dict(theta=0),
+    dict(key_bits=7), dict(key_bits=33), dict(q=12, r=4, delta=5),            # covers 22 < 32 bits
+    dict(q=20, r=16, delta=12, key_bits=32),                                  # covers > 64 bits
+    dict(max_tuples=0), dict(max_results=0), dict(max_results=1 << 29),
+])
+def test_invalid_params_rejected(bad):
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.query_sizes(_p(**bad))
+    assert e.value.status == -1
+
+
+def test_abi_version_and_flags_checked():
+    p = _p()
+    p.abi_version = 2
+    with pytest.raises(ssd.SSDError):
+        ssd.query_sizes(p)
+    p = _p()
+    p.flags = 0x10
+    with pytest.raises(ssd.SSDError):
+        ssd.query_sizes(p)
+    p = _p()
+    p.reserved = 1
+    with pytest.raises(ssd.SSDError):
+        ssd.query_sizes(p)
+
+
+def test_paper_parameter_set_is_valid():
+    """Sec. 5 runs eta = 2^11, q = 14, r = 5, delta = 6 (with 16-bit recorders;
+    here with k <= 254)."""
+    state, _ = ssd.query_sizes(ssd.make_params(q=14, r=5, delta=6, eta=2048, k=254, theta=1024))
+    assert state == 5 * (1 << 14) * 2048
+
+
+def test_init_rejects_before_touching_the_device():
+    lib = C.CDLL(ssd.library_path())
+    lib.ssd_init_detector.argtypes = [C.c_void_p] * 8
+    lib.ssd_init_detector.restype = C.c_int
+    out = C.c_void_p()
+    p = _p(r=2)
+    assert lib.ssd_init_detector(C.addressof(p), None, None, 0, None, 0, None, C.addressof(out)) == -1
+    p = _p()
+    tabs = (C.c_uint32 * 2048)()
+    # NULL device buffers are rejected as too small before any HIP call
+    assert lib.ssd_init_detector(C.addressof(p), C.addressof(tabs), None, 0, None, 0, None,
+                                 C.addressof(out)) == -2
+    assert out.value is None

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP detector, called through the C ABI, against the CPU
+oracle on the same seeded inputs.  Integer products (window state, R_k, hot
+lists, candidate tuples, regained hosts and their R) must match bit for bit;
+the f64 estimate within 1e-6 relative."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1803_11036_amd as ssd
+import tracegen as tg
+from _parity import close_both, compare_state, log, make_pair, scan_both, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _slices_small(seed, n_slices, key_bits, theta, q, sizes=None, heavy=20, heavy_peers=None):
+    """Random slices over a key_bits-wide host space: light background plus
+    heavy hosts that enter and leave."""
+    rng = np.random.default_rng(seed)
+    hosts = rng.choice(2 ** key_bits, 4000, replace=False).astype(np.uint32)
+    hv = rng.choice(2 ** key_bits, heavy, replace=False).astype(np.uint32)
+    start = rng.integers(0, max(1, n_slices - 2), heavy)
+    span = rng.integers(1, 8, heavy)
+    hp = heavy_peers or 2 * theta
+    out = []
+    for s in range(n_slices):
+        n_bg = int(sizes[s]) if sizes is not None else int(0.05 * (1 << q) * theta)
+        bg = np.stack([rng.choice(hosts, n_bg),
+                       rng.integers(0, 2 ** 32, n_bg, dtype=np.uint64).astype(np.uint32)], 1)
+        parts = [bg]
+        for h, a, b in zip(hv, start, start + span):
+            if a <= s < b:
+                parts.append(np.stack([np.full(hp // 2, h, np.uint32),
+                                       rng.integers(0, 2 ** 32, hp // 2, dtype=np.uint64).astype(np.uint32)], 1))
+        p = np.concatenate(parts).astype(np.uint32)
+        out.append(p[rng.permutation(p.shape[0])])
+    return out
+
+
+def test_tiny_config():
+    """1 router, 8 slices of 1M pairs, k = 4, 2^12 x 6 estimators of 1024
+    cells: every product compared at every slice, full window state."""
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    for t in range(cfg.n_slices):
+        log(f"tiny slice {t}")
+        scan_both(g, o, tr.pairs(0, t), t)
+        compare_state(g, o)
+        res = close_both(g, o)
+    assert len(res) > 100
+    assert np.all(np.isin(tr.planted_ips(), res["ip"]))
+
+
+@pytest.mark.parametrize("splits", [1, 3, 7])
+def test_ragged_batches_and_empty_slices(splits):
+    """Pair counts that leave ragged tails (0, 1, 63, 64, 65, 257, odd sizes),
+    several scan calls per slice, and empty slices."""
+    q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
+    sizes = [0, 1, 63, 64, 65, 257, 10007, 0, 12345, 9999, 0, 10240]
+    sl = _slices_small(5 + splits, len(sizes), kb, theta, q, sizes=sizes)
+    sl = [s if sizes[i] else s[:0] for i, s in enumerate(sl)]
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(3), key_bits=kb)
+    for t, p in enumerate(sl):
+        log(f"ragged splits={splits} slice {t} n={p.shape[0]}")
+        scan_both(g, o, p, t, splits=splits if p.shape[0] >= splits else 1)
+        compare_state(g, o)
+        close_both(g, o)
+
+
+@pytest.mark.parametrize("k", [1, 3, 17, 254])
+def test_stamp_wrap_and_expiry(k):
+    """300 slices: the 8-bit slot stamps wrap (255 slots) and the rotating
+    expiry must keep every cell's distance exact, for the discrete window
+    (k = 1, Sec. 3.1), short and maximal windows."""
+    q, r, delta, eta, theta, kb = 8, 4, 4, 1024, 150, 16
+    n = 300
+    # about 0.15 * 2^q * theta distinct background pairs per window
+    per_slice = max(20, int(0.15 * (1 << q) * theta / k))
+    sl = _slices_small(40 + k, n, kb, theta, q, sizes=[per_slice] * n, heavy=60 if k < 100 else 8)
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(4), key_bits=kb)
+    for t, p in enumerate(sl):
+        scan_both(g, o, p, t)
+        if t % 10 == 0 or t > 250:
+            compare_state(g, o)
+        close_both(g, o, check_internals=(t % 25 == 0))
+    log(f"wrap k={k} done")
+
+
+def test_rehash_mode():
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs, rehash=True)
+    for t in range(5):
+        scan_both(g, o, tr.pairs(0, t), t)
+        res = close_both(g, o)
+    assert np.all(np.isin(tr.planted_ips(), res["ip"]))
+
+
+def test_key_width_beyond_32_bits():
+    """(r-2)*delta + q = 34 > 32: tuples that would set bits 32..33 are
+    dropped (R13), on both sides."""
+    q, r, delta, eta, k, theta = 10, 5, 8, 1024, 3, 150
+    sl = _slices_small(77, 6, 32, theta, q, heavy=40)
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(8))
+    for t, p in enumerate(sl):
+        scan_both(g, o, p, t)
+        compare_state(g, o)
+        close_both(g, o)
+
+
+def test_merge_routers():
+    """Alg. 5: four router detectors merged into a global one every slot;
+    the global close must match the oracle's merged RSEA, and routers only
+    advance their clocks."""
+    q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
+    tabs = tg.hash_tables(9)
+    nR = 4
+    gpu_r, orc_r = zip(*[make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb) for _ in range(nR)])
+    g, o = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
+    rng = np.random.default_rng(10)
+    for t in range(8):
+        sl = _slices_small(100 + t, 1, kb, theta // 2, q, heavy=15)[0]
+        parts = np.array_split(sl[rng.permutation(sl.shape[0])], nR)
+        for j in range(nR):
+            scan_both(gpu_r[j], orc_r[j], parts[j], t)
+        ssd.merge_router_state(g, list(gpu_r))
+        o.merge_from(list(orc_r))
+        compare_state(g, o)
+        close_both(g, o)
+        for j in range(nR):
+            assert len(ssd.close_slice(gpu_r[j], advance_only=True)) == 0
+            orc_r[j].close(advance_only=True)
+            compare_state(gpu_r[j], orc_r[j])
+
+
+def test_scan_pass_windows_do_not_change_state():
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_PASS_BYTES, 3 << 20)     # 8 passes, ragged last one
+    for t in range(3):
+        scan_both(g, o, tr.pairs(0, t), t)
+        compare_state(g, o)
+        close_both(g, o, check_internals=False)
+
+
+def test_multi_kernel_sort_path():
+    """Result lists above the single-workgroup limit go through the global
+    bitonic sort; forcing that path must not change the list."""
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SORT_BLOCK_LIMIT, 0)
+    for t in range(5):
+        scan_both(g, o, tr.pairs(0, t), t)
+        res = close_both(g, o, check_internals=False)
+    assert len(res) > 1000
+
+
+def test_errors_order_and_overflow():
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    p = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                        max_tuples=64)
+    g = ssd.init_detector(p, tabs, device="cuda:0")
+    pairs = to_dev(tr.pairs(0, 0))
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.scan_slice(g, pairs, 1)
+    assert e.value.status == -3
+    for t in range(4):
+        ssd.scan_slice(g, to_dev(tr.pairs(0, t)), t)
+        if t < 3:
+            ssd.close_slice(g, advance_only=True)
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.close_slice(g)            # full window: far more than 64 candidate tuples
+    assert e.value.status == -4
+    assert ssd.get_info(g)["open_slice"] == 4
+    # the detector stays usable after an overflow
+    ssd.scan_slice(g, pairs, 4)
+    with pytest.raises(ssd.SSDError):
+        ssd.close_slice(g)
+    g2 = ssd.init_detector(ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k,
+                                           theta=cfg.theta), tabs, device="cuda:0")
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.merge_router_state(g2, [g])
+    assert e.value.status == -5
