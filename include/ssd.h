@@ -190,7 +190,17 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       lists use the multi-kernel sort. */
 #define SSD_TUNE_SCAN_PASS_BYTES 1u
 #define SSD_TUNE_SORT_BLOCK_LIMIT 2u
+#define SSD_TUNE_TIMING 3u          /* 1: time every phase with HIP events */
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
+
+/* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per
+ * phase, measured with HIP events recorded on the detector's stream around
+ * each phase's kernels, and the number of kernel launches per phase.
+ * Phases: 0 scan, 1 hot detection, 2 hot lists, 3 candidate expansion,
+ * 4 final test, 5 sort/report, 6 merge.  Synchronises the stream; reset != 0
+ * clears the totals after reading. */
+#define SSD_PHASES 7u
+int ssd_read_timing(ssd_detector *d, double *ms_out, uint64_t *launches_out, int reset);
 
 void ssd_destroy(ssd_detector *d);
 const char *ssd_strerror(int status);

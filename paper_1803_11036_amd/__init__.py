@@ -24,7 +24,7 @@ __all__ = [
     "query_sizes", "Detector", "init_detector", "scan_slice", "close_slice",
     "get_results", "merge_router_state", "read_canonical_state", "read_rk",
     "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
-    "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT",
+    "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
     "library_path", "RESULT_DTYPE",
 ]
 
@@ -93,6 +93,7 @@ def _lib():
         L.ssd_read_tuples.argtypes = [vp, vp, u64, u64p]
         L.ssd_get_info.argtypes = [vp, C.POINTER(_Info)]
         L.ssd_set_tuning.argtypes = [vp, u32, u64]
+        L.ssd_read_timing.argtypes = [vp, vp, vp, C.c_int]
         L.ssd_destroy.argtypes = [vp]
         L.ssd_destroy.restype = None
         L.ssd_strerror.argtypes = [C.c_int]
@@ -102,7 +103,7 @@ def _lib():
         for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice", "ssd_close_slice",
                      "ssd_get_results", "ssd_merge_router_state", "ssd_read_canonical_state",
                      "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
-                     "ssd_set_tuning"):
+                     "ssd_set_tuning", "ssd_read_timing"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
     return _lib_handle
@@ -264,6 +265,17 @@ def get_info(det: Detector) -> Dict[str, object]:
 
 SSD_TUNE_SCAN_PASS_BYTES = 1
 SSD_TUNE_SORT_BLOCK_LIMIT = 2
+SSD_TUNE_TIMING = 3
+PHASES = ("scan", "hot_detect", "hot_lists", "expand", "verify", "report", "merge")
+
+
+def read_timing(det: Detector, reset: bool = False) -> Dict[str, Tuple[float, int]]:
+    """Device ms and kernel launches per phase, from HIP events on the
+    detector's stream (needs SSD_TUNE_TIMING on)."""
+    ms = np.zeros(len(PHASES), dtype=np.float64)
+    n = np.zeros(len(PHASES), dtype=np.uint64)
+    _check(_lib().ssd_read_timing(det.handle, ms.ctypes.data, n.ctypes.data, int(reset)), "read_timing")
+    return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(PHASES)}
 
 
 def set_tuning(det: Detector, knob: int, value: int) -> None:

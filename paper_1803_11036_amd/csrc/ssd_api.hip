@@ -134,6 +134,14 @@ struct ssd_detector {
     std::vector<SuperPointDev> staging;
     Ctl last;                           // control block of the last close
     bool have_last;
+    // phase timing with HIP events (opt-in)
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<uint32_t> ev_free;
+    struct Pending { uint32_t a, b, phase, launches; };
+    std::vector<Pending> pending;
+    double ph_ms[SSD_PHASES];
+    uint64_t ph_launches[SSD_PHASES];
 
     template <class T> T* at(uint64_t off) const { return reinterpret_cast<T*>(scratch + off); }
     uint64_t n_se() const { return (uint64_t)p.r << p.q; }
@@ -154,6 +162,64 @@ int dev_fail(ssd_detector* d, hipError_t e, const char* what)
         hipError_t e_ = (call);                                  \
         if (e_ != hipSuccess) return dev_fail((d), e_, #call);   \
     } while (0)
+
+// ---- phase timing: a start/stop event pair around each phase's launches
+uint32_t ev_get(ssd_detector* d)
+{
+    if (!d->ev_free.empty()) {
+        uint32_t i = d->ev_free.back();
+        d->ev_free.pop_back();
+        return i;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return UINT32_MAX;
+    d->ev_pool.push_back(e);
+    return (uint32_t)d->ev_pool.size() - 1;
+}
+
+struct PhaseMark {
+    uint32_t a = UINT32_MAX;
+};
+
+PhaseMark phase_begin(ssd_detector* d)
+{
+    PhaseMark m;
+    if (!d->timing) return m;
+    m.a = ev_get(d);
+    if (m.a != UINT32_MAX && hipEventRecord(d->ev_pool[m.a], d->stream) != hipSuccess) {
+        d->ev_free.push_back(m.a);
+        m.a = UINT32_MAX;
+    }
+    return m;
+}
+
+void phase_end(ssd_detector* d, PhaseMark m, uint32_t phase, uint32_t launches)
+{
+    if (!d->timing || m.a == UINT32_MAX) return;
+    uint32_t b = ev_get(d);
+    if (b == UINT32_MAX) { d->ev_free.push_back(m.a); return; }
+    if (hipEventRecord(d->ev_pool[b], d->stream) != hipSuccess) {
+        d->ev_free.push_back(m.a);
+        d->ev_free.push_back(b);
+        return;
+    }
+    d->pending.push_back({m.a, b, phase, launches});
+}
+
+// after the stream passed every pending stop event
+void phase_collect(ssd_detector* d)
+{
+    for (const auto& p : d->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, d->ev_pool[p.a], d->ev_pool[p.b]) == hipSuccess) {
+            d->ph_ms[p.phase] += ms;
+            d->ph_launches[p.phase] += p.launches;
+        }
+        d->ev_free.push_back(p.a);
+        d->ev_free.push_back(p.b);
+    }
+    d->pending.clear();
+}
 
 int usable(ssd_detector* d)
 {
@@ -250,6 +316,8 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
     d->pass_bytes = 0;
     d->sort_block_limit = SORT_SMALL;
     d->have_last = false;
+    d->timing = false;
+    for (uint32_t i = 0; i < SSD_PHASES; i++) { d->ph_ms[i] = 0; d->ph_launches[i] = 0; }
     memcpy(d->tables_host, tables_host, sizeof d->tables_host);
     hipError_t e = hipGetDevice(&d->device);
     if (e != hipSuccess) { rc = dev_fail(d, e, "hipGetDevice"); delete d; return rc; }
@@ -273,6 +341,7 @@ void ssd_destroy(ssd_detector* d)
     (void)hipSetDevice(d->device);
     if (!d->broken) (void)hipStreamSynchronize(d->stream);
     if (d->mailbox) (void)hipHostFree(d->mailbox);
+    for (hipEvent_t e : d->ev_pool) (void)hipEventDestroy(e);
     delete d;
 }
 
@@ -281,6 +350,7 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
     switch (knob) {
     case SSD_TUNE_SCAN_PASS_BYTES: d->pass_bytes = value; return SSD_OK;
+    case SSD_TUNE_TIMING: d->timing = value != 0; return SSD_OK;
     case SSD_TUNE_SORT_BLOCK_LIMIT:
         if (value > SORT_SMALL) return fail(SSD_E_PARAM, "sort block limit above %u", SORT_SMALL);
         d->sort_block_limit = value;
@@ -316,11 +386,15 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
         per_pass = d->pass_bytes / se_bytes;
         if (per_pass < 1) per_pass = 1;
     }
+    PhaseMark pm = phase_begin(d);
+    uint32_t launches = 0;
     for (uint64_t lo = 0; lo < n_se; lo += per_pass) {
         a.se_lo = lo;
         a.se_hi = lo + per_pass < n_se ? lo + per_pass : n_se;
         HIPCHK(d, launch_scan(a, d->stream));
+        launches++;
     }
+    phase_end(d, pm, 0, launches);
     return SSD_OK;
 }
 
@@ -343,7 +417,9 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     Ctl* ctl = d->at<Ctl>(d->L.ctl);
     // 1. R_k of every estimator, rotating expiry
     DetectArgs da = detect_args(d, true);
+    PhaseMark pm = phase_begin(d);
     HIPCHK(d, launch_hot_detect(da, s));
+    phase_end(d, pm, 1, 1);
     // 2. hot lists and transposed hot bits
     CompactArgs ca{};
     ca.rk = d->at<uint32_t>(d->L.rk);
@@ -351,7 +427,9 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     ca.hotT = d->at<uint64_t>(d->L.hotT);
     ca.ctl = ctl;
     ca.q = p.q; ca.delta = p.delta; ca.nw = d->L.nw; ca.T = d->T;
+    pm = phase_begin(d);
     HIPCHK(d, launch_hot_compact(ca, p.r, s));
+    phase_end(d, pm, 2, 1);
     // 3. candidate levels: rows 0..2, then one row per level
     ExpandArgs ea{};
     ea.hot_list = ca.hot_list;
@@ -362,6 +440,7 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     ea.row = 2;
     ea.out_x = d->at<uint64_t>(d->L.ctb_x[0]);
     ea.out_h0 = d->at<uint32_t>(d->L.ctb_h0[0]);
+    pm = phase_begin(d);
     HIPCHK(d, launch_expand0(ea, s));
     for (uint32_t row = 3; row < p.r; row++) {
         const uint32_t lvl = row - 2;
@@ -372,6 +451,7 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
         ea.out_h0 = d->at<uint32_t>(d->L.ctb_h0[lvl & 1]);
         HIPCHK(d, launch_extend(ea, s));
     }
+    phase_end(d, pm, 3, p.r - 2);
     // 4. final test of every full tuple
     const uint32_t lf = p.r - 3;
     VerifyArgs va{};
@@ -387,9 +467,12 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     va.chunks = p.eta / 16u; va.T = d->T; va.level = lf;
     va.rehash = (p.flags & SSD_VERIFY_REHASH) ? 1u : 0u;
     va.L = da.L;
+    pm = phase_begin(d);
     HIPCHK(d, launch_verify(va, s));
+    phase_end(d, pm, 4, 1);
     HIPCHK(d, hipMemcpyAsync(d->mailbox, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(d, hipStreamSynchronize(s));
+    phase_collect(d);
     Ctl c = *d->mailbox;
     d->clock++;
     d->last = c;
@@ -410,12 +493,15 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
         ra.out = d->at<SuperPointDev>(d->L.out);
         ra.ctl = ctl;
         ra.eta = p.eta;
+        pm = phase_begin(d);
         if (n_acc <= d->sort_block_limit) HIPCHK(d, launch_sort_small(ra, s));
         else HIPCHK(d, launch_sort_large(ra, d->at<unsigned long long>(d->L.sort_tmp), n_acc, s));
+        phase_end(d, pm, 5, 1);
         d->staging.resize(n_acc);
         HIPCHK(d, hipMemcpyAsync(d->mailbox, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIPCHK(d, hipMemcpyAsync(d->staging.data(), ra.out, n_acc * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
         HIPCHK(d, hipStreamSynchronize(s));
+        phase_collect(d);
         const uint64_t m = d->mailbox->n_out;
         d->last.n_out = m;
         d->results.resize(m);
@@ -466,14 +552,17 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
     a.cur = stamp_of(g->clock);
     a.k = g->p.k;
     // associative merge in batches; later batches fold the partial result in
-    uint32_t done = 0;
+    uint32_t done = 0, launches = 0;
+    PhaseMark pm = phase_begin(g);
     while (done < n) {
         uint32_t m = 0;
         if (done > 0) a.src[m++] = g->state;
         while (m < MAX_MERGE_SOURCES && done < n) a.src[m++] = routers[done++]->state;
         a.n_src = m;
         HIPCHK(g, launch_merge(a, g->stream));
+        launches++;
     }
+    phase_end(g, pm, 6, launches);
     return SSD_OK;
 }
 
@@ -542,6 +631,20 @@ int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t*
         uint32_t* o = out_host + t * d->p.r;
         o[0] = h0[t];
         for (uint32_t i = 1; i < d->p.r; i++) o[i] = ((uint32_t)(x[t] >> ((i - 1) * d->p.delta)) & qmask) ^ h0[t];
+    }
+    return SSD_OK;
+}
+
+int ssd_read_timing(ssd_detector* d, double* ms_out, uint64_t* launches_out, int reset)
+{
+    int rc = usable(d);
+    if (rc) return rc;
+    HIPCHK(d, hipStreamSynchronize(d->stream));
+    phase_collect(d);
+    for (uint32_t i = 0; i < SSD_PHASES; i++) {
+        if (ms_out) ms_out[i] = d->ph_ms[i];
+        if (launches_out) launches_out[i] = d->ph_launches[i];
+        if (reset) { d->ph_ms[i] = 0; d->ph_launches[i] = 0; }
     }
     return SSD_OK;
 }
