@@ -94,7 +94,7 @@ def main() -> int:
     ap.add_argument("--latency-steps", type=int, default=10)
     ap.add_argument("--cpu-slices", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pass-mib", type=int, default=None, help="scan pass window (MiB of state)")
+    ap.add_argument("--pass-mib", type=int, default=None, help="scan pass window (MiB of state; default: library)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (PMC calibration)")
     args = ap.parse_args()

@@ -183,8 +183,8 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 
 /* Tuning knobs; none changes results.
  *   SSD_TUNE_SCAN_PASS_BYTES: state bytes one scan pass covers (0 = one pass
- *       over the whole state).  Passes sized to the device's last-level cache
- *       keep a pass's random byte stores cache-resident.
+ *       over the whole state; default 128 MiB).  Passes sized to the device's
+ *       last-level cache keep a pass's random byte stores cache-resident.
  *   SSD_TUNE_SORT_BLOCK_LIMIT: result lists up to this many accepted hosts
  *       are sorted inside one workgroup (at most 8192, the default); longer
  *       lists use the multi-kernel sort. */

@@ -45,6 +45,9 @@ struct ScanArgs {
 struct DetectArgs {
     uint8_t* state;
     uint32_t* rk;
+    uint64_t* hotbits;        // [r][2^q / 64] row bitmasks of hot estimators
+    uint64_t* hotT;           // [r][2^(q-delta)][nw] key-transposed hot bits
+    uint32_t q, delta, nw, T;
     uint64_t n_waves;         // estimators visited
     uint64_t se_base, se_step;
     uint32_t log2eta, chunks; // chunks = eta / 16
@@ -54,11 +57,10 @@ struct DetectArgs {
 };
 
 struct CompactArgs {
-    const uint32_t* rk;
+    const uint64_t* hotbits;
     uint32_t* hot_list;
-    uint64_t* hotT;
     Ctl* ctl;
-    uint32_t q, delta, nw, T;
+    uint32_t q;
 };
 
 struct ExpandArgs {
@@ -90,6 +92,7 @@ struct ReportArgs {
     SuperPointDev* out;
     Ctl* ctl;
     uint32_t eta;
+    uint64_t limit;           // single-block sort only when n_acc <= limit
 };
 
 struct MergeArgs {

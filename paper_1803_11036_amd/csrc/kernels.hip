@@ -53,6 +53,32 @@ __device__ __forceinline__ unsigned long long wave_append(uint32_t cnt, unsigned
     return base + (incl - cnt);
 }
 
+// Same for a 256-thread block (every thread must call it): one atomic per block.
+__device__ __forceinline__ unsigned long long block_append_256(uint32_t cnt, unsigned long long* counter)
+{
+    __shared__ uint32_t wtot[4];
+    __shared__ unsigned long long bbase;
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o) incl += v;
+    }
+    if (lane == 63) wtot[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        bbase = tot ? atomicAdd(counter, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    uint32_t woff = 0;
+    for (uint32_t w = 0; w < wid; w++) woff += wtot[w];
+    const unsigned long long base = bbase;
+    __syncthreads();
+    return base + woff + (incl - cnt);
+}
+
 // Live cells of a 32-bit word of four cells: bits 8, 24 (bytes 0, 2) and
 // 9, 25 (bytes 1, 3) are set for live cells.
 __device__ __forceinline__ uint32_t live_bits(uint32_t w, const LiveCfg& L)
@@ -153,14 +179,27 @@ __global__ __launch_bounds__(256) void k_hot_detect(DetectArgs a)
     }
     if (a.count) {
         live = wave_sum(live);
-        if (lane == 0) a.rk[s] = live;
+        if (lane == 0) {
+            a.rk[s] = live;
+            if (live >= a.T) {
+                // hot (Sec. 3.3): row bitmask and key-transposed bitmask
+                const uint32_t row = (uint32_t)(s >> a.q), c = (uint32_t)s & ((1u << a.q) - 1u);
+                const uint32_t sh = a.q - a.delta;
+                const uint32_t key = c & ((1u << sh) - 1u), j = c >> sh;
+                const uint32_t rw = a.q >= 6 ? (1u << (a.q - 6)) : 1u;    // words per row bitmask
+                atomicOr(reinterpret_cast<unsigned long long*>(a.hotbits) + (uint64_t)row * rw + (c >> 6),
+                         1ull << (c & 63u));
+                atomicOr(reinterpret_cast<unsigned long long*>(a.hotT) +
+                             ((uint64_t)row * (1ull << sh) + key) * a.nw + (j >> 6),
+                         1ull << (j & 63u));
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------- hot lists
-// One 1024-thread block per row: ascending list of hot columns (R_k >= T,
-// Sec. 3.3) and the row's hot bits transposed by overlap key: bit j of
-// hotT[row][key] <=> column key | (j << (q - delta)) is hot.
+// One 1024-thread block per row: the ascending list of hot columns, read from
+// the row bitmask that hot detection set.
 
 __device__ __forceinline__ uint32_t block_exclusive_scan_1024(uint32_t v, uint32_t* lds /*[16]*/, uint32_t* total)
 {
@@ -188,31 +227,26 @@ __global__ __launch_bounds__(1024) void k_hot_compact(CompactArgs a)
 {
     __shared__ uint32_t lds[16];
     const uint32_t row = blockIdx.x;
-    const uint32_t n = 1u << a.q;
-    const uint32_t keys = 1u << (a.q - a.delta);
-    const uint32_t* rk = a.rk + ((uint64_t)row << a.q);
-    uint64_t* hotT = a.hotT + (uint64_t)row * keys * a.nw;
-    for (uint32_t i = threadIdx.x; i < keys * a.nw; i += 1024u) hotT[i] = 0;
+    const uint32_t words = a.q >= 6 ? (1u << (a.q - 6)) : 1u;
+    const uint64_t* bits = a.hotbits + (uint64_t)row * words;
     if (row == 0 && threadIdx.x == 0) {
         for (int l = 0; l < 16; l++) a.ctl->level_n[l] = 0;
         a.ctl->n_acc = 0;
         a.ctl->n_out = 0;
     }
-    __syncthreads();
-    const uint32_t per = (n + 1023u) / 1024u;
-    const uint32_t c0 = min(n, threadIdx.x * per), c1 = min(n, c0 + per);
+    const uint32_t per = (words + 1023u) / 1024u;
+    const uint32_t w0 = min(words, threadIdx.x * per), w1 = min(words, w0 + per);
     uint32_t cnt = 0;
-    for (uint32_t c = c0; c < c1; c++) cnt += rk[c] >= a.T;
+    for (uint32_t w = w0; w < w1; w++) cnt += __popcll(bits[w]);
     uint32_t total;
     uint32_t off = block_exclusive_scan_1024(cnt, lds, &total);
     uint32_t* list = a.hot_list + ((uint64_t)row << a.q);
-    const uint32_t sh = a.q - a.delta, kmask = keys - 1u;
-    for (uint32_t c = c0; c < c1; c++) {
-        if (rk[c] >= a.T) {
-            list[off++] = c;
-            const uint32_t key = c & kmask, j = c >> sh;
-            atomicOr(reinterpret_cast<unsigned long long*>(&hotT[(uint64_t)key * a.nw + (j >> 6)]),
-                     1ull << (j & 63u));
+    for (uint32_t w = w0; w < w1; w++) {
+        uint64_t b = bits[w];
+        while (b) {
+            const uint32_t i = (uint32_t)__ffsll((long long)b) - 1u;
+            b &= b - 1;
+            list[off++] = w * 64u + i;
         }
     }
     if (threadIdx.x == 0) a.ctl->hot_n[row] = total;
@@ -273,25 +307,27 @@ __global__ __launch_bounds__(256) void k_expand0(ExpandArgs a)
 {
     const uint64_t n0 = a.ctl->hot_n[0], n1 = a.ctl->hot_n[1];
     const uint64_t Q = n0 * n1;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t waves = (uint64_t)gridDim.x * 4u;
     const uint32_t qmask = (1u << a.q) - 1u;
     const uint32_t* l0 = a.hot_list;
     const uint32_t* l1 = a.hot_list + (1ull << a.q);
-    for (uint64_t base = ((uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6)) * 64u; base < Q; base += waves * 64u) {
-        const uint64_t idx = base + lane;
+    const bool small = Q <= 0xFFFFFFFFull;
+    for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < Q; base += (uint64_t)gridDim.x * 256u) {
+        const uint64_t idx = base + threadIdx.x;
         const uint32_t valid = idx < Q;
         uint32_t he0 = 0;
         uint64_t x = 0;
         if (valid) {
-            he0 = l0[idx / n1];
-            const uint32_t he1 = l1[idx % n1];
+            uint64_t ia, ib;
+            if (small) { ia = (uint32_t)idx / (uint32_t)n1; ib = (uint32_t)idx - (uint32_t)ia * (uint32_t)n1; }
+            else { ia = idx / n1; ib = idx % n1; }
+            he0 = l0[ia];
+            const uint32_t he1 = l1[ib];
             x = (uint64_t)((he0 ^ he1) & qmask);                // B(1): host bits 0..q-1
             if (a.key_bits < 64 && (x >> a.key_bits) != 0) x = ~0ull;
         }
         const uint32_t ok = valid && x != ~0ull;
         const uint32_t cnt = extend_one<false>(a, he0, x, 2, 0, ok);
-        const unsigned long long slot = wave_append(cnt, &a.ctl->level_n[0]);
+        const unsigned long long slot = block_append_256(cnt, &a.ctl->level_n[0]);
         extend_one<true>(a, he0, x, 2, slot, ok);
     }
 }
@@ -302,15 +338,13 @@ __global__ __launch_bounds__(256) void k_extend(ExpandArgs a)
     const uint32_t level = a.row - 2;
     const uint64_t nin_raw = a.ctl->level_n[level - 1];
     const uint64_t nin = nin_raw < a.cap ? nin_raw : a.cap;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t waves = (uint64_t)gridDim.x * 4u;
-    for (uint64_t base = ((uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6)) * 64u; base < nin; base += waves * 64u) {
-        const uint64_t idx = base + lane;
+    for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < nin; base += (uint64_t)gridDim.x * 256u) {
+        const uint64_t idx = base + threadIdx.x;
         const uint32_t valid = idx < nin;
         const uint32_t he0 = valid ? a.in_h0[idx] : 0u;
         const uint64_t x = valid ? a.in_x[idx] : 0ull;
         const uint32_t cnt = extend_one<false>(a, he0, x, a.row, 0, valid);
-        const unsigned long long slot = wave_append(cnt, &a.ctl->level_n[level]);
+        const unsigned long long slot = block_append_256(cnt, &a.ctl->level_n[level]);
         extend_one<true>(a, he0, x, a.row, slot, valid);
     }
 }
@@ -373,6 +407,7 @@ __global__ __launch_bounds__(1024) void k_sort_small(ReportArgs a)
     __shared__ unsigned long long s[SORT_SMALL];
     __shared__ uint32_t lds[16];
     const uint64_t nraw = a.ctl->n_acc;
+    if (nraw > a.limit) return;               // longer lists take the multi-kernel sort
     const uint32_t n = (uint32_t)(nraw < SORT_SMALL ? nraw : SORT_SMALL);
     uint32_t N = 1;
     while (N < n) N <<= 1;

@@ -46,9 +46,15 @@ uint32_t log2u(uint64_t x)
 }
 
 struct Layout {
-    uint64_t ctl, tables, rk, hot_list, hotT, ctb_x[2], ctb_h0[2], acc, sort_tmp, out, total;
+    uint64_t ctl, tables, rk, hot_list, hotbits, hotT, hot_end, ctb_x[2], ctb_h0[2], acc, sort_tmp, out, total;
     uint32_t nw;
 };
+
+constexpr uint32_t PREFIX_MAX = SORT_SMALL;   // result entries staged in pinned memory per close
+// Scan pass window: random byte stores confined to 128 MiB of state stay in
+// the 256 MB Infinity Cache (measured best of 64..768 MiB on the core-link
+// workload; one pass when the state is smaller).
+constexpr uint64_t DEFAULT_PASS_BYTES = 128ull << 20;
 
 int validate(const ssd_params* p)
 {
@@ -81,7 +87,10 @@ Layout layout(const ssd_params* p)
     L.tables = o; o = align_up(o + 2048 * 4);
     L.rk = o; o = align_up(o + n_se * 4);
     L.hot_list = o; o = align_up(o + n_se * 4);
-    L.hotT = o; o = align_up(o + (uint64_t)p->r * (1ull << (p->q - p->delta)) * L.nw * 8);
+    // hotbits and hotT are adjacent: one fill clears both before every close
+    L.hotbits = o; o = o + (uint64_t)p->r * (p->q >= 6 ? (1ull << (p->q - 6)) : 1ull) * 8;
+    L.hotT = o; o = o + (uint64_t)p->r * (1ull << (p->q - p->delta)) * L.nw * 8;
+    L.hot_end = o; o = align_up(o);
     for (int b = 0; b < 2; b++) { L.ctb_x[b] = o; o = align_up(o + p->max_tuples * 8); }
     for (int b = 0; b < 2; b++) { L.ctb_h0[b] = o; o = align_up(o + p->max_tuples * 4); }
     L.acc = o; o = align_up(o + p->max_results * 8);
@@ -134,6 +143,7 @@ struct ssd_detector {
     std::vector<SuperPointDev> staging;
     Ctl last;                           // control block of the last close
     bool have_last;
+    uint64_t last_reported;             // list length of the last close (sizes the staged prefix)
     // phase timing with HIP events (opt-in)
     bool timing;
     std::vector<hipEvent_t> ev_pool;
@@ -238,6 +248,12 @@ DetectArgs detect_args(const ssd_detector* d, bool count)
     DetectArgs a{};
     a.state = d->state;
     a.rk = d->at<uint32_t>(d->L.rk);
+    a.hotbits = d->at<uint64_t>(d->L.hotbits);
+    a.hotT = d->at<uint64_t>(d->L.hotT);
+    a.q = d->p.q;
+    a.delta = d->p.delta;
+    a.nw = d->L.nw;
+    a.T = d->T;
     a.log2eta = d->log2eta;
     a.chunks = d->p.eta / 16u;
     a.count = count ? 1u : 0u;
@@ -313,17 +329,18 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
     d->scratch = static_cast<uint8_t*>(scratch_dev);
     d->stream = static_cast<hipStream_t>(stream);
     d->broken = false;
-    d->pass_bytes = 0;
+    d->pass_bytes = DEFAULT_PASS_BYTES;
     d->sort_block_limit = SORT_SMALL;
     d->have_last = false;
+    d->last_reported = 0;
     d->timing = false;
     for (uint32_t i = 0; i < SSD_PHASES; i++) { d->ph_ms[i] = 0; d->ph_launches[i] = 0; }
     memcpy(d->tables_host, tables_host, sizeof d->tables_host);
     hipError_t e = hipGetDevice(&d->device);
     if (e != hipSuccess) { rc = dev_fail(d, e, "hipGetDevice"); delete d; return rc; }
-    e = hipHostMalloc((void**)&d->mailbox, sizeof(Ctl) + 2048 * 4, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&d->mailbox, sizeof(Ctl) + PREFIX_MAX * sizeof(SuperPointDev), hipHostMallocDefault);
     if (e != hipSuccess) { rc = dev_fail(d, e, "hipHostMalloc"); delete d; return rc; }
-    uint32_t* tab_stage = reinterpret_cast<uint32_t*>(d->mailbox + 1);
+    uint32_t* tab_stage = reinterpret_cast<uint32_t*>(d->mailbox + 1);   // 8 KiB fits the prefix area
     memcpy(tab_stage, tables_host, 2048 * 4);
     // every cell starts empty (Sec. 3.2: initialised once)
     e = launch_fill_u32(reinterpret_cast<uint32_t*>(d->state), need_state / 4, 0u, d->stream);
@@ -415,25 +432,25 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     }
     const hipStream_t s = d->stream;
     Ctl* ctl = d->at<Ctl>(d->L.ctl);
-    // 1. R_k of every estimator, rotating expiry
+    // 1. R_k of every estimator, hot bits, rotating expiry
+    HIPCHK(d, launch_fill_u32(d->at<uint32_t>(d->L.hotbits), (d->L.hot_end - d->L.hotbits) / 4, 0u, s));
     DetectArgs da = detect_args(d, true);
     PhaseMark pm = phase_begin(d);
     HIPCHK(d, launch_hot_detect(da, s));
     phase_end(d, pm, 1, 1);
-    // 2. hot lists and transposed hot bits
+    // 2. ascending hot lists
     CompactArgs ca{};
-    ca.rk = d->at<uint32_t>(d->L.rk);
+    ca.hotbits = d->at<uint64_t>(d->L.hotbits);
     ca.hot_list = d->at<uint32_t>(d->L.hot_list);
-    ca.hotT = d->at<uint64_t>(d->L.hotT);
     ca.ctl = ctl;
-    ca.q = p.q; ca.delta = p.delta; ca.nw = d->L.nw; ca.T = d->T;
+    ca.q = p.q;
     pm = phase_begin(d);
     HIPCHK(d, launch_hot_compact(ca, p.r, s));
     phase_end(d, pm, 2, 1);
     // 3. candidate levels: rows 0..2, then one row per level
     ExpandArgs ea{};
     ea.hot_list = ca.hot_list;
-    ea.hotT = ca.hotT;
+    ea.hotT = d->at<uint64_t>(d->L.hotT);
     ea.ctl = ctl;
     ea.cap = p.max_tuples;
     ea.q = p.q; ea.delta = p.delta; ea.nw = d->L.nw; ea.key_bits = p.key_bits;
@@ -470,7 +487,24 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     pm = phase_begin(d);
     HIPCHK(d, launch_verify(va, s));
     phase_end(d, pm, 4, 1);
+    // 5. sort by ip, keep the largest R per ip, estimate (Eq. 1) -- in one
+    // block when the list is short; the control block and a prefix of the
+    // list come back with a single synchronisation
+    ReportArgs ra{};
+    ra.keys = d->at<unsigned long long>(d->L.acc);
+    ra.out = d->at<SuperPointDev>(d->L.out);
+    ra.ctl = ctl;
+    ra.eta = p.eta;
+    ra.limit = d->sort_block_limit < p.max_results ? d->sort_block_limit : p.max_results;
+    pm = phase_begin(d);
+    HIPCHK(d, launch_sort_small(ra, s));
+    phase_end(d, pm, 5, 1);
+    uint64_t prefix = 2 * d->last_reported + 64;
+    if (prefix > PREFIX_MAX) prefix = PREFIX_MAX;
+    if (prefix > p.max_results) prefix = p.max_results;
+    SuperPointDev* stage = reinterpret_cast<SuperPointDev*>(d->mailbox + 1);
     HIPCHK(d, hipMemcpyAsync(d->mailbox, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(d, hipMemcpyAsync(stage, ra.out, prefix * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
     HIPCHK(d, hipStreamSynchronize(s));
     phase_collect(d);
     Ctl c = *d->mailbox;
@@ -479,39 +513,43 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     d->have_last = true;
     d->results.clear();
     for (uint32_t l = 0; l <= lf; l++)
-        if (c.level_n[l] > p.max_tuples)
+        if (c.level_n[l] > p.max_tuples) {
+            d->last_reported = 0;
             return fail(SSD_E_OVERFLOW, "candidate level %u holds %llu tuples > max_tuples %llu", l,
                         (unsigned long long)c.level_n[l], (unsigned long long)p.max_tuples);
-    if (c.n_acc > p.max_results)
+        }
+    if (c.n_acc > p.max_results) {
+        d->last_reported = 0;
         return fail(SSD_E_OVERFLOW, "%llu accepted hosts > max_results %llu", (unsigned long long)c.n_acc,
                     (unsigned long long)p.max_results);
-    // 5. sort by ip, keep the largest R per ip, estimate (Eq. 1)
-    const uint64_t n_acc = c.n_acc;
-    if (n_acc) {
-        ReportArgs ra{};
-        ra.keys = d->at<unsigned long long>(d->L.acc);
-        ra.out = d->at<SuperPointDev>(d->L.out);
-        ra.ctl = ctl;
-        ra.eta = p.eta;
+    }
+    const SuperPointDev* src = stage;
+    if (c.n_acc > ra.limit) {
+        // long list: multi-kernel sort, then the whole list
         pm = phase_begin(d);
-        if (n_acc <= d->sort_block_limit) HIPCHK(d, launch_sort_small(ra, s));
-        else HIPCHK(d, launch_sort_large(ra, d->at<unsigned long long>(d->L.sort_tmp), n_acc, s));
+        HIPCHK(d, launch_sort_large(ra, d->at<unsigned long long>(d->L.sort_tmp), c.n_acc, s));
         phase_end(d, pm, 5, 1);
-        d->staging.resize(n_acc);
+        d->staging.resize(c.n_acc);
         HIPCHK(d, hipMemcpyAsync(d->mailbox, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIPCHK(d, hipMemcpyAsync(d->staging.data(), ra.out, n_acc * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
+        HIPCHK(d, hipMemcpyAsync(d->staging.data(), ra.out, c.n_acc * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
         HIPCHK(d, hipStreamSynchronize(s));
         phase_collect(d);
-        const uint64_t m = d->mailbox->n_out;
-        d->last.n_out = m;
-        d->results.resize(m);
-        for (uint64_t i = 0; i < m; i++) {
-            d->results[i].ip = d->staging[i].ip;
-            d->results[i].rk = d->staging[i].rk;
-            d->results[i].est = d->staging[i].est;
-        }
-    } else {
-        d->last.n_out = 0;
+        c.n_out = d->mailbox->n_out;
+        src = d->staging.data();
+    } else if (c.n_out > prefix) {
+        d->staging.resize(c.n_out);
+        HIPCHK(d, hipMemcpyAsync(d->staging.data(), ra.out, c.n_out * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
+        HIPCHK(d, hipStreamSynchronize(s));
+        src = d->staging.data();
+    }
+    const uint64_t m = c.n_out;
+    d->last.n_out = m;
+    d->last_reported = m;
+    d->results.resize(m);
+    for (uint64_t i = 0; i < m; i++) {
+        d->results[i].ip = src[i].ip;
+        d->results[i].rk = src[i].rk;
+        d->results[i].est = src[i].est;
     }
     return ssd_get_results(d, out_host, cap, n_out);
 }

@@ -1,0 +1,102 @@
+"""GPU parity at full workload sizes.
+
+- The single core link (6M pairs per slice, 6 x 2^16 estimators of 4096 cells,
+  k = 10) in the launch configuration that bench.py times, against the oracle
+  for one full window plus a slide: regained hosts, R_k, hot lists and
+  candidate tuples every slice, the window state on sampled estimators.
+- The 16-router distributed workload at full size through a property that
+  holds at any size: merging the routers' states gives the state, R_k and host
+  list of one detector that scanned every router's pairs (Alg. 5, reading R3).
+- The same 16-router topology on a smaller array against the oracle's merge.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1803_11036_amd as ssd
+import tracegen as tg
+from _parity import close_both, compare_state, log, make_pair, scan_both, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_core_link_full_size():
+    cfg = tg.config("core_link")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    # same parameters as bench.py
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs,
+                     max_tuples=1 << 22, max_results=1 << 20)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(g.n_se, 2048, replace=False))
+    for t in range(cfg.k + 2):
+        scan_both(g, o, tr.pairs(0, t), t)
+        if t % 4 == 3 or t == cfg.k + 1:
+            compare_state(g, o, sample_se=sample)
+        res = close_both(g, o)
+        log(f"core_link slice {t}: {len(res)} hosts")
+    assert len(res) > 500
+
+
+def _run_distributed(cfg, tr, tabs, n_slices, with_union=True, with_oracle=False, distinct_only=False):
+    R = cfg.n_streams
+    params = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                             max_tuples=1 << 22, max_results=1 << 20)
+    routers = [ssd.init_detector(params, tabs, device="cuda:0") for _ in range(R)]
+    glob = ssd.init_detector(params, tabs, device="cuda:0")
+    union = ssd.init_detector(params, tabs, device="cuda:0") if with_union else None
+    orc_r = [oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs) for _ in range(R)] \
+        if with_oracle else None
+    orc_g = oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs) if with_oracle else None
+    last = None
+    for t in range(n_slices):
+        per = tr.distinct_all(t) if distinct_only else tr.pairs_all(t)
+        for j in range(R):
+            dp = to_dev(per[j])
+            ssd.scan_slice(routers[j], dp, t)
+            if union is not None:
+                ssd.scan_slice(union, dp, t)
+            if orc_r is not None:
+                orc_r[j].scan(per[j])
+        ssd.merge_router_state(glob, routers)
+        if union is not None:
+            a = ssd.read_canonical_state(glob)
+            b = ssd.read_canonical_state(union)
+            assert torch.equal(a, b), f"slice {t}: merged state differs from the union's"
+            del a, b
+        if orc_g is not None:
+            orc_g.merge_from(orc_r)
+            compare_state(glob, orc_g)
+            res = close_both(glob, orc_g)
+            for j in range(R):
+                orc_r[j].close(advance_only=True)
+        else:
+            res = ssd.close_slice(glob)
+        if union is not None:
+            ru = ssd.close_slice(union)
+            assert np.array_equal(res, ru), f"slice {t}: host lists differ"
+            assert np.array_equal(ssd.read_rk(glob), ssd.read_rk(union))
+        for j in range(R):
+            ssd.close_slice(routers[j], advance_only=True)
+        log(f"{cfg.name} slice {t}: {len(res)} hosts")
+        last = res
+    return last
+
+
+def test_distributed_full_size_merge_equals_union():
+    cfg = tg.config("distributed")
+    tr = tg.Trace(cfg)
+    res = _run_distributed(cfg, tr, tg.hash_tables(cfg.hash_seed), cfg.k + 1)
+    planted = tr.planted_ips()
+    # planted hosts spread over 2-8 routers, most below theta at every router
+    assert np.isin(planted[tr.degree[cfg.n_hosts:] >= 2 * cfg.theta], res["ip"]).mean() > 0.9
+
+
+def test_distributed_16_routers_against_oracle():
+    cfg = tg.config("distributed", n_hosts=100_000, n_planted=40, q=12, r=6, delta=5, eta=1024,
+                    theta=512)
+    tr = tg.Trace(cfg)
+    res = _run_distributed(cfg, tr, tg.hash_tables(cfg.hash_seed), cfg.k + 2, with_union=False,
+                           with_oracle=True, distinct_only=True)
+    assert len(res) > 20

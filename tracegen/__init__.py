@@ -264,8 +264,8 @@ class Trace:
         x = (host.astype(np.uint64) << _U64(32)) | p.astype(np.uint64)
         return (_rand64(self._peer_key, x) >> _U64(32)).astype(np.uint32)
 
-    def distinct(self, stream: int, s: int) -> np.ndarray:
-        """Distinct (cip, oip) pairs of slice ``s`` at stream ``stream``."""
+    def _chunk(self, s: int):
+        """Hosts, pool indices and routers of every distinct pair of slice s."""
         c = self.cfg
         k = c.k
         s0 = s % k
@@ -273,8 +273,6 @@ class Trace:
         hosts = np.nonzero(act)[0]
         cnt = (self.degree[hosts] - s0 + k - 1) // k        # pool indices p = s0 + k*j
         tot = int(cnt.sum())
-        if tot == 0:
-            return np.zeros((0, 2), dtype=np.uint32)
         h = np.repeat(hosts, cnt)
         first = np.cumsum(cnt) - cnt
         j = np.arange(tot, dtype=np.int64) - np.repeat(first, cnt)
@@ -283,17 +281,40 @@ class Trace:
             # deal the chunk's peers round-robin over the host's routers
             m = self.route_m[h]
             router = (self.route_base[h] + (j % m) * self.route_step[h]) % c.n_streams
-            keep = router == stream
-            h, p = h[keep], p[keep]
+        else:
+            router = np.zeros(tot, dtype=np.int64)
+        return h, p, router
+
+    def _rows(self, h: np.ndarray, p: np.ndarray) -> np.ndarray:
         out = np.empty((h.size, 2), dtype=np.uint32)
         out[:, 0] = self.ip[h]
         out[:, 1] = self._peer(h, p)
         return out
 
+    def distinct(self, stream: int, s: int) -> np.ndarray:
+        """Distinct (cip, oip) pairs of slice ``s`` at stream ``stream``."""
+        h, p, router = self._chunk(s)
+        keep = router == stream
+        return self._rows(h[keep], p[keep])
+
+    def distinct_all(self, s: int) -> List[np.ndarray]:
+        """Distinct pairs of slice ``s`` for every stream, in one pass."""
+        h, p, router = self._chunk(s)
+        order = np.argsort(router, kind="stable")
+        bounds = np.searchsorted(router[order], np.arange(self.cfg.n_streams + 1))
+        rows = self._rows(h[order], p[order])
+        return [rows[bounds[i]:bounds[i + 1]] for i in range(self.cfg.n_streams)]
+
     def pairs(self, stream: int, s: int, n: Optional[int] = None) -> np.ndarray:
         """The slice's ``N`` pairs: distinct pairs plus uniform repeats, shuffled."""
+        return self._fill(stream, s, self.distinct(stream, s), n)
+
+    def pairs_all(self, s: int) -> List[np.ndarray]:
+        """``pairs(stream, s)`` for every stream (same values, one pass)."""
+        return [self._fill(i, s, d, None) for i, d in enumerate(self.distinct_all(s))]
+
+    def _fill(self, stream: int, s: int, d: np.ndarray, n: Optional[int]) -> np.ndarray:
         c = self.cfg
-        d = self.distinct(stream, s)
         N = int(self.n_pairs[stream]) if n is None else int(n)
         D = d.shape[0]
         if D == 0 or N == 0:
