@@ -201,12 +201,16 @@ def main() -> int:
     dom = max(cand, key=lambda k: cand[k][0])
     _, bytes_per_launch, ms_per_launch = cand[dom]
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
+    launches_per_unit = timing["scan"][1] // args.steps if dom == "k_scan" else 1
     traffic = load_traffic(dom, cfg.name)
+    if traffic is not None:
+        traffic *= launches_per_unit          # counters are per launch; the scan unit is one call
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": traffic, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "ms_per_launch": round(ms_per_launch, 5),
-                "launches_per_step": timing["scan"][1] // args.steps if dom == "k_scan" else 1}
+                "launches_per_step": launches_per_unit,
+                "traffic_gbs": round(traffic / (ms_per_launch * 1e-3) / 1e9, 1) if traffic else None}
 
     cpu = None
     if not args.no_cpu_baseline:
