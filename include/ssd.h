@@ -191,20 +191,73 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_TUNE_SCAN_PASS_BYTES 1u
 #define SSD_TUNE_SORT_BLOCK_LIMIT 2u
 #define SSD_TUNE_TIMING 3u          /* 1: time every phase with HIP events */
+#define SSD_TUNE_SCAN_TILE_PAIRS 4u /* batches: pairs per scan work tile (default 262144) */
+#define SSD_TUNE_GRAPH 5u           /* batches: 1 (default) = replay the close as a HIP graph */
+#define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = time the candidate (pass window, tile)
+                                       pairs on the next scans and keep the fastest */
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 
 /* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per
  * phase, measured with HIP events recorded on the detector's stream around
  * each phase's kernels, and the number of kernel launches per phase.
  * Phases: 0 scan, 1 hot detection, 2 hot lists, 3 candidate expansion,
- * 4 final test, 5 sort/report, 6 merge.  Synchronises the stream; reset != 0
- * clears the totals after reading. */
-#define SSD_PHASES 7u
+ * 4 final test, 5 sort/report, 6 merge, 7 whole close replayed as a graph
+ * (batches; its kernels are then not timed one by one).  Synchronises the
+ * stream; reset != 0 clears the totals after reading. */
+#define SSD_PHASES 8u
 int ssd_read_timing(ssd_detector *d, double *ms_out, uint64_t *launches_out, int reset);
 
 void ssd_destroy(ssd_detector *d);
 const char *ssd_strerror(int status);
 const char *ssd_last_error(void);
+
+/* ---- Batches: many monitored links closed together ------------------------
+ *
+ * n independent detectors ("links"), each with its own ssd_params and hash
+ * tables, sharing one slot clock, one stream and one caller-owned state and
+ * scratch buffer.  A scan covers every link's pairs of the open slice in one
+ * persistent launch; a close reconstructs every link with one fixed launch
+ * sequence, captured once as a HIP graph and replayed every slot.  Each
+ * link's results are identical to those of a separate detector fed the same
+ * pairs (same method as above: Alg. 2 scans, Sec. 4.2 reconstruction). */
+typedef struct ssd_batch ssd_batch;
+
+/* Device sizes for the n links described by p[0..n-1] (1 <= n <= 1024). */
+int ssd_batch_query_sizes(const ssd_params *p, uint32_t n, uint64_t *state_bytes, uint64_t *scratch_bytes);
+
+/* tables_host: uint32[n][2][4][256], each link's RHFG[0] and H1 tables
+ * (copied).  state_dev (16-byte aligned) and scratch_dev (256-byte aligned)
+ * are caller-owned device buffers of at least the queried sizes; stream is
+ * a hipStream_t.  The open slice is 0. */
+int ssd_batch_init(const ssd_params *p, uint32_t n, const uint32_t *tables_host,
+                   void *state_dev, uint64_t state_bytes, void *scratch_dev, uint64_t scratch_bytes,
+                   void *stream, ssd_batch **out);
+
+/* Scan the open slice of every link: link l's pairs are
+ * pairs_dev[offsets_host[l] .. offsets_host[l+1]) (uint32[.][2] on the device,
+ * 8-byte aligned, cip first; offsets non-decreasing, host array of n+1).
+ * Asynchronous; the pairs are borrowed until the stream passes this call.
+ * slice_id must equal the open slice (SSD_E_ORDER). */
+int ssd_batch_scan(ssd_batch *b, const uint32_t *pairs_dev, const uint64_t *offsets_host, uint64_t slice_id);
+
+/* Close the open slice of every link (see ssd_close_slice).  Writes the
+ * links' lists one after another into out_host (up to cap entries in total),
+ * counts_host[l] = entries of link l and status_host[l] = SSD_OK or
+ * SSD_E_OVERFLOW (that link's capacities were exceeded; it reports nothing).
+ * Returns SSD_E_TRUNC when cap is too small (counts are set; fetch the lists
+ * with ssd_batch_get_results).  The open slice advances in every case except
+ * SSD_E_DEVICE. */
+int ssd_batch_close(ssd_batch *b, ssd_super_point *out_host, uint64_t cap, uint64_t *counts_host,
+                    int *status_host);
+int ssd_batch_get_results(ssd_batch *b, ssd_super_point *out_host, uint64_t cap, uint64_t *counts_host,
+                          int *status_host);
+
+/* Tuning knobs SSD_TUNE_* (none changes results) and phase timing (as for
+ * single detectors). */
+int ssd_batch_set_tuning(ssd_batch *b, uint32_t knob, uint64_t value);
+int ssd_batch_get_tuning(ssd_batch *b, uint32_t knob, uint64_t *value);
+int ssd_batch_read_timing(ssd_batch *b, double *ms_out, uint64_t *launches_out, int reset);
+void ssd_batch_destroy(ssd_batch *b);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,9 @@ __all__ = [
     "get_results", "merge_router_state", "read_canonical_state", "read_rk",
     "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
     "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
+    "SSD_TUNE_SCAN_TILE_PAIRS", "SSD_TUNE_GRAPH", "SSD_TUNE_AUTOTUNE", "PHASES",
+    "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
+    "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_destroy",
     "library_path", "RESULT_DTYPE",
 ]
 
@@ -94,6 +97,16 @@ def _lib():
         L.ssd_get_info.argtypes = [vp, C.POINTER(_Info)]
         L.ssd_set_tuning.argtypes = [vp, u32, u64]
         L.ssd_read_timing.argtypes = [vp, vp, vp, C.c_int]
+        L.ssd_batch_query_sizes.argtypes = [vp, u32, u64p, u64p]
+        L.ssd_batch_init.argtypes = [vp, u32, vp, vp, u64, vp, u64, vp, C.POINTER(vp)]
+        L.ssd_batch_scan.argtypes = [vp, vp, vp, u64]
+        L.ssd_batch_close.argtypes = [vp, vp, u64, vp, vp]
+        L.ssd_batch_get_results.argtypes = [vp, vp, u64, vp, vp]
+        L.ssd_batch_set_tuning.argtypes = [vp, u32, u64]
+        L.ssd_batch_get_tuning.argtypes = [vp, u32, u64p]
+        L.ssd_batch_read_timing.argtypes = [vp, vp, vp, C.c_int]
+        L.ssd_batch_destroy.argtypes = [vp]
+        L.ssd_batch_destroy.restype = None
         L.ssd_destroy.argtypes = [vp]
         L.ssd_destroy.restype = None
         L.ssd_strerror.argtypes = [C.c_int]
@@ -103,7 +116,9 @@ def _lib():
         for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice", "ssd_close_slice",
                      "ssd_get_results", "ssd_merge_router_state", "ssd_read_canonical_state",
                      "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
-                     "ssd_set_tuning", "ssd_read_timing"):
+                     "ssd_set_tuning", "ssd_read_timing", "ssd_batch_query_sizes", "ssd_batch_init",
+                     "ssd_batch_scan", "ssd_batch_close", "ssd_batch_get_results", "ssd_batch_set_tuning",
+                     "ssd_batch_get_tuning", "ssd_batch_read_timing"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
     return _lib_handle
@@ -266,7 +281,10 @@ def get_info(det: Detector) -> Dict[str, object]:
 SSD_TUNE_SCAN_PASS_BYTES = 1
 SSD_TUNE_SORT_BLOCK_LIMIT = 2
 SSD_TUNE_TIMING = 3
-PHASES = ("scan", "hot_detect", "hot_lists", "expand", "verify", "report", "merge")
+SSD_TUNE_SCAN_TILE_PAIRS = 4
+SSD_TUNE_GRAPH = 5
+SSD_TUNE_AUTOTUNE = 6
+PHASES = ("scan", "hot_detect", "hot_lists", "expand", "verify", "report", "merge", "close_graph")
 
 
 def read_timing(det: Detector, reset: bool = False) -> Dict[str, Tuple[float, int]]:
@@ -280,3 +298,121 @@ def read_timing(det: Detector, reset: bool = False) -> Dict[str, Tuple[float, in
 
 def set_tuning(det: Detector, knob: int, value: int) -> None:
     _check(_lib().ssd_set_tuning(det.handle, knob, value), "set_tuning")
+
+
+# ---------------------------------------------------------------- batches
+
+def batch_query_sizes(params: Sequence[Params]) -> Tuple[int, int]:
+    arr = (Params * len(params))(*params)
+    st, sc = C.c_uint64(), C.c_uint64()
+    _check(_lib().ssd_batch_query_sizes(C.addressof(arr), len(params), C.byref(st), C.byref(sc)),
+           "batch_query_sizes")
+    return st.value, sc.value
+
+
+class Batch:
+    """n detectors ("links") scanned by one persistent launch and closed by
+    one replayed graph; owns their torch device buffers."""
+
+    def __init__(self, params: Sequence[Params], tables: Sequence[np.ndarray], device=None, stream=None):
+        L = _lib()
+        self.params = list(params)
+        self.n = len(self.params)
+        self.device = torch.device(device if device is not None else "cuda")
+        self._parr = (Params * self.n)(*self.params)
+        state_bytes, scratch_bytes = batch_query_sizes(self.params)
+        self.state = torch.empty(state_bytes, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        tabs = np.ascontiguousarray(np.stack([np.asarray(t, dtype=np.uint32).reshape(-1) for t in tables]))
+        if tabs.shape != (self.n, 2048):
+            raise ValueError("need one 2 x 4 x 256 table set per link")
+        self._tables = tabs
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.ssd_batch_init(C.addressof(self._parr), self.n, tabs.ctypes.data, self.state.data_ptr(),
+                                    state_bytes, self.scratch.data_ptr(), scratch_bytes, self.stream.cuda_stream,
+                                    C.byref(h)), "batch_init")
+        self.handle = h
+
+    def destroy(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib().ssd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def batch_init(params: Sequence[Params], tables: Sequence[np.ndarray], device=None, stream=None) -> Batch:
+    return Batch(params, tables, device, stream)
+
+
+def batch_destroy(b: Batch) -> None:
+    b.destroy()
+
+
+def batch_scan(b: Batch, pairs: torch.Tensor, offsets: Sequence[int], slice_id: int) -> None:
+    """pairs: contiguous (N, 2) 32-bit tensor on the batch's device holding every
+    link's pairs; link l owns rows offsets[l]..offsets[l+1]."""
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if off.shape != (b.n + 1,):
+        raise ValueError("offsets needs n + 1 entries")
+    if pairs.numel() and (pairs.device != b.state.device or pairs.element_size() != 4
+                          or not pairs.is_contiguous() or pairs.dim() != 2 or pairs.shape[1] != 2):
+        raise ValueError("pairs must be a contiguous (N, 2) 32-bit tensor on the batch's device")
+    if int(off[-1]) > (pairs.shape[0] if pairs.dim() == 2 else 0):
+        raise ValueError("offsets run past the pairs tensor")
+    ptr = pairs.data_ptr() if pairs.numel() else None
+    _check(_lib().ssd_batch_scan(b.handle, ptr, off.ctypes.data, slice_id), "batch_scan")
+
+
+def _batch_lists(b: Batch, fn, *args):
+    L = _lib()
+    counts = np.zeros(b.n, dtype=np.uint64)
+    status = np.zeros(b.n, dtype=np.int32)
+    cap = 1 << 16
+    while True:
+        out = np.zeros(cap, dtype=RESULT_DTYPE)
+        st = fn(b.handle, *args, out.ctypes.data, cap, counts.ctypes.data, status.ctypes.data)
+        total = int(counts.sum())
+        if st == SSD_E_TRUNC and total > cap:
+            cap = total
+            fn, args = L.ssd_batch_get_results, ()
+            continue
+        _check(st, fn.__name__)
+        lists, o = [], 0
+        for c in counts.tolist():
+            lists.append(out[o:o + c].copy())
+            o += c
+        return lists, status
+
+
+def batch_close(b: Batch):
+    """Close the open slice of every link: (list of per-link result arrays,
+    per-link status codes: 0 or -4 = capacity exceeded)."""
+    return _batch_lists(b, _lib().ssd_batch_close)
+
+
+def batch_get_results(b: Batch):
+    return _batch_lists(b, _lib().ssd_batch_get_results)
+
+
+def batch_set_tuning(b: Batch, knob: int, value: int) -> None:
+    _check(_lib().ssd_batch_set_tuning(b.handle, knob, value), "batch_set_tuning")
+
+
+def batch_get_tuning(b: Batch, knob: int) -> int:
+    v = C.c_uint64()
+    _check(_lib().ssd_batch_get_tuning(b.handle, knob, C.byref(v)), "batch_get_tuning")
+    return v.value
+
+
+def batch_read_timing(b: Batch, reset: bool = False) -> Dict[str, Tuple[float, int]]:
+    ms = np.zeros(len(PHASES), dtype=np.float64)
+    n = np.zeros(len(PHASES), dtype=np.uint64)
+    _check(_lib().ssd_batch_read_timing(b.handle, ms.ctypes.data, n.ctypes.data, int(reset)), "batch_read_timing")
+    return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(PHASES)}

@@ -9,8 +9,10 @@ namespace ssd {
 constexpr uint32_t MAX_ROWS = 16;
 constexpr uint32_t MAX_MERGE_SOURCES = 64;
 constexpr uint32_t SORT_SMALL = 8192;   // result lists up to this size sort in one block's LDS
+constexpr uint32_t MAX_LINKS = 1024;    // detectors in one batch
+constexpr uint32_t LEVEL_VERIFY = 0xFFFFu;
 
-// Device control block: counters written by the kernels, read back per close.
+// Device control block of one detector: counters written by the kernels.
 struct Ctl {
     uint32_t hot_n[MAX_ROWS];
     unsigned long long level_n[MAX_ROWS];
@@ -32,87 +34,109 @@ struct LiveCfg {
     uint32_t c1, c2, wrap;
 };
 
+// One detector ("link") as every close kernel sees it.  Device resident; the
+// per-slice fields are written by k_prepare from the device clock at the start
+// of every close, so a captured close replays with fixed arguments.
+struct LinkDesc {
+    uint8_t* state;
+    const uint32_t* tables;       // [2][4][256]
+    uint32_t* rk;                 // [r][2^q]
+    uint64_t* hotbits;            // [r][max(1, 2^q / 64)] row bitmasks of hot estimators
+    uint64_t* hotT;               // [r][2^(q-delta)][nw] key-transposed hot bits
+    uint32_t* hot_list;           // [r][2^q]
+    uint64_t* ctb_x[2];           // candidate buffers: regained bits
+    uint32_t* ctb_h0[2];          //                    and he_0
+    unsigned long long* acc;      // accepted keys
+    SuperPointDev* out;           // result list
+    Ctl* ctl;
+    uint64_t n_se, max_tuples, max_results, sort_limit;
+    uint32_t q, r, delta, eta, log2eta, k, T, nw, key_bits, rehash;
+    // per slice
+    LiveCfg L;
+    uint32_t expire_period, expire_phase;
+};
+
+struct Clock {
+    unsigned long long t;         // open slice
+};
+
+// direct scan of one detector, one pass window
 struct ScanArgs {
     const uint2* pairs;
     uint64_t n;
     uint8_t* state;
-    const uint32_t* tables;   // [2][4][256]
+    const uint32_t* tables;
     uint32_t q, r, delta, log2eta;
-    uint64_t se_lo, se_hi;    // estimator window of this pass
+    uint64_t se_lo, se_hi;        // estimator window of this pass
+    uint32_t stamp;
+};
+
+// persistent batched scan: tiles of one link's pairs and one estimator window
+struct ScanTile {
+    uint32_t link, pad;
+    uint64_t start, n;            // pairs [start, start + n) of the batch buffer
+    uint64_t se_lo, se_hi;        // estimator window of the link
+};
+
+struct TileScanArgs {
+    const uint2* pairs;
+    const LinkDesc* links;
+    const ScanTile* tiles;
+    unsigned long long* counter;  // next tile; zero before the launch
+    uint64_t n_tiles;
     uint32_t stamp;
 };
 
 struct DetectArgs {
-    uint8_t* state;
-    uint32_t* rk;
-    uint64_t* hotbits;        // [r][2^q / 64] row bitmasks of hot estimators
-    uint64_t* hotT;           // [r][2^(q-delta)][nw] key-transposed hot bits
-    uint32_t q, delta, nw, T;
-    uint64_t n_waves;         // estimators visited
-    uint64_t se_base, se_step;
-    uint32_t log2eta, chunks; // chunks = eta / 16
-    uint32_t count;           // compute R_k (0: expiry only)
-    uint32_t expire_period, expire_phase;
-    LiveCfg L;
+    const LinkDesc* links;
+    const uint64_t* se_prefix;    // [n_links + 1] estimators before each link
+    uint32_t n_links;
+    uint64_t total;               // waves launched
+    uint32_t expire_only;         // link 0 only: visit the estimators of this slot's expiry phase
 };
 
-struct CompactArgs {
-    const uint64_t* hotbits;
-    uint32_t* hot_list;
-    Ctl* ctl;
-    uint32_t q;
-};
-
-struct ExpandArgs {
-    const uint32_t* hot_list;
-    const uint64_t* hotT;
-    Ctl* ctl;
-    const uint64_t* in_x;
-    const uint32_t* in_h0;
-    uint64_t* out_x;
-    uint32_t* out_h0;
-    uint64_t cap;
-    uint32_t q, delta, nw, key_bits, row;
-};
-
-struct VerifyArgs {
-    const uint8_t* state;
-    const uint32_t* tables;
-    Ctl* ctl;
-    const uint64_t* in_x;
-    const uint32_t* in_h0;
-    unsigned long long* acc;
-    uint64_t cap, max_results;
-    uint32_t q, r, delta, log2eta, chunks, T, level, rehash;
-    LiveCfg L;
-};
-
-struct ReportArgs {
-    const unsigned long long* keys;
-    SuperPointDev* out;
-    Ctl* ctl;
-    uint32_t eta;
-    uint64_t limit;           // single-block sort only when n_acc <= limit
+struct LevelArgs {
+    const LinkDesc* links;
+    uint32_t n_links;
+    uint64_t* prefix;             // [n_links + 1] work items before each link (padded to 256)
+    uint32_t level;               // 0 = rows 0..2, L = row L+2, LEVEL_VERIFY = final test
 };
 
 struct MergeArgs {
     const uint8_t* src[MAX_MERGE_SOURCES];
     uint32_t n_src;
     uint8_t* dst;
-    uint64_t n16;             // uint4 chunks per state
+    uint64_t n16;                 // uint4 chunks per state
     uint32_t cur, k;
 };
 
+struct PackArgs {
+    const LinkDesc* links;
+    uint32_t n_links;
+    SuperPointDev* packed;        // all links' lists, link after link
+    uint64_t cap;
+    unsigned long long* offsets;  // [n_links + 1]
+};
+
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, const Clock* clock, hipStream_t s);
+hipError_t launch_advance(Clock* clock, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
-hipError_t launch_hot_detect(const DetectArgs& a, hipStream_t s);
-hipError_t launch_hot_compact(const CompactArgs& a, uint32_t rows, hipStream_t s);
-hipError_t launch_expand0(const ExpandArgs& a, hipStream_t s);
-hipError_t launch_extend(const ExpandArgs& a, hipStream_t s);
-hipError_t launch_verify(const VerifyArgs& a, hipStream_t s);
-hipError_t launch_sort_small(const ReportArgs& a, hipStream_t s);
-hipError_t launch_sort_large(const ReportArgs& a, unsigned long long* tmp, uint64_t n, hipStream_t s);
+hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);
+hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
+hipError_t launch_level_prefix(const LevelArgs& a, hipStream_t s);
+hipError_t launch_expand0(const LevelArgs& a, hipStream_t s);
+hipError_t launch_extend(const LevelArgs& a, hipStream_t s);
+hipError_t launch_verify(const LevelArgs& a, hipStream_t s);
+hipError_t launch_sort_small(const LinkDesc* links, uint32_t n_links, hipStream_t s);
+hipError_t launch_sort_large(const LinkDesc* link, const LinkDesc& host_copy, unsigned long long* tmp, uint64_t n,
+                             hipStream_t s);
+hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_canonical(const uint8_t* state, uint16_t* out, uint64_t n, uint32_t cur, uint32_t k, hipStream_t s);
+
+// host-side copies of the per-slice rules (also used by the merge and the canonical reader)
+inline uint32_t stamp_of(uint64_t t) { return 1u + (uint32_t)(t % 255u); }
 
 }  // namespace ssd

@@ -35,25 +35,8 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-// Reserve `cnt` consecutive slots in a device-wide list for this lane; every
-// lane of the wave must call it.  One atomic per wave.
-__device__ __forceinline__ unsigned long long wave_append(uint32_t cnt, unsigned long long* counter)
-{
-    const int lane = threadIdx.x & 63;
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
-    uint32_t total = __shfl(incl, 63, 64);
-    unsigned long long base = 0;
-    if (lane == 63 && total) base = atomicAdd(counter, (unsigned long long)total);
-    base = __shfl(base, 63, 64);
-    return base + (incl - cnt);
-}
-
-// Same for a 256-thread block (every thread must call it): one atomic per block.
+// Reserve `cnt` consecutive slots of a device-wide list for this thread of a
+// 256-thread block (every thread must call it): one atomic per block.
 __device__ __forceinline__ unsigned long long block_append_256(uint32_t cnt, unsigned long long* counter)
 {
     __shared__ uint32_t wtot[4];
@@ -104,102 +87,36 @@ __device__ __forceinline__ uint32_t expire_word(uint32_t w, const LiveCfg& L)
     return w & ~(de | dd);
 }
 
-// ---------------------------------------------------------------- fill
-
-__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
+// Index of the link owning flattened item g: the largest l with prefix[l] <= g
+// (empty links have prefix[l] == prefix[l+1] and are skipped).
+__device__ __forceinline__ uint32_t find_link(const uint64_t* prefix, uint32_t n_links, uint64_t g)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+    uint32_t lo = 0, hi = n_links;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
-// ---------------------------------------------------------------- scan
-// Alg. 2 for every pair: one byte store per row.  The grid strides over the
-// pairs; `se_lo..se_hi` restricts the stores to one pass window of the state
-// so that a pass's random stores stay within the last-level cache.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__global__ __launch_bounds__(256) void k_scan(ScanArgs a)
+__device__ __forceinline__ void block_exclusive_scan_u64_1024(unsigned long long v, unsigned long long* lds /*[1024]*/,
+                                                              unsigned long long* excl, unsigned long long* total)
 {
-    __shared__ uint32_t tab[2048];
-    for (uint32_t i = threadIdx.x; i < 2048u; i += 256u) tab[i] = a.tables[i];
+    lds[threadIdx.x] = v;
     __syncthreads();
-    const uint32_t qmask = (1u << a.q) - 1u;
-    const uint32_t emask = (1u << a.log2eta) - 1u;
-    const uint8_t stamp = (uint8_t)a.stamp;
-    const uint32_t row_lo = (uint32_t)(a.se_lo >> a.q);
-    const uint32_t row_hi = (uint32_t)((a.se_hi - 1) >> a.q) + 1u;
-    const uint64_t stride = (uint64_t)gridDim.x * 256u;
-    for (uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x; p < a.n; p += stride) {
-        const uint2 pr = a.pairs[p];                      // x = cip, y = oip
-        const uint32_t d = tab_hash(tab + 1024, pr.y) & emask;   // H1(oip)
-        const uint32_t h0 = tab_hash(tab, pr.x) & qmask;          // RHFG[0](cip)
-        for (uint32_t i = row_lo; i < row_hi; i++) {
-            const uint32_t col = i == 0 ? h0 : ((shr32(pr.x, (i - 1) * a.delta) ^ h0) & qmask);
-            const uint64_t se = ((uint64_t)i << a.q) | col;
-            if (se >= a.se_lo && se < a.se_hi) a.state[(se << a.log2eta) | d] = stamp;
-        }
+    for (uint32_t o = 1; o < 1024u; o <<= 1) {
+        const unsigned long long t = threadIdx.x >= o ? lds[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        lds[threadIdx.x] += t;
+        __syncthreads();
     }
+    *excl = lds[threadIdx.x] - v;
+    *total = lds[1023];
+    __syncthreads();
 }
-
-// ---------------------------------------------------------------- hot detection
-// One wave per sliding estimator: R_k = live cells (Sec. 3.2), plus the
-// rotating expiry of estimators with index = phase (mod period).  CH uint4
-// chunks per lane per group keep several 1 KiB wave loads in flight.
-
-template <int CH>
-__global__ __launch_bounds__(256) void k_hot_detect(DetectArgs a)
-{
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (wave >= a.n_waves) return;
-    const uint64_t s = a.se_base + wave * a.se_step;
-    uint4* se = reinterpret_cast<uint4*>(a.state + (s << a.log2eta));
-    const uint32_t groups = a.chunks / (CH * 64u);
-    const bool expire = (s % a.expire_period) == a.expire_phase;
-    uint32_t live = 0;
-    for (uint32_t g = 0; g < groups; g++) {
-        uint4 v[CH];
-#pragma unroll
-        for (int c = 0; c < CH; c++) v[c] = se[(g * CH + c) * 64u + lane];
-        if (a.count) {
-#pragma unroll
-            for (int c = 0; c < CH; c++)
-                live += __popc(live_bits(v[c].x, a.L)) + __popc(live_bits(v[c].y, a.L)) +
-                        __popc(live_bits(v[c].z, a.L)) + __popc(live_bits(v[c].w, a.L));
-        }
-        if (expire) {
-#pragma unroll
-            for (int c = 0; c < CH; c++) {
-                uint4 n;
-                n.x = expire_word(v[c].x, a.L); n.y = expire_word(v[c].y, a.L);
-                n.z = expire_word(v[c].z, a.L); n.w = expire_word(v[c].w, a.L);
-                if (n.x != v[c].x || n.y != v[c].y || n.z != v[c].z || n.w != v[c].w)
-                    se[(g * CH + c) * 64u + lane] = n;
-            }
-        }
-    }
-    if (a.count) {
-        live = wave_sum(live);
-        if (lane == 0) {
-            a.rk[s] = live;
-            if (live >= a.T) {
-                // hot (Sec. 3.3): row bitmask and key-transposed bitmask
-                const uint32_t row = (uint32_t)(s >> a.q), c = (uint32_t)s & ((1u << a.q) - 1u);
-                const uint32_t sh = a.q - a.delta;
-                const uint32_t key = c & ((1u << sh) - 1u), j = c >> sh;
-                const uint32_t rw = a.q >= 6 ? (1u << (a.q - 6)) : 1u;    // words per row bitmask
-                atomicOr(reinterpret_cast<unsigned long long*>(a.hotbits) + (uint64_t)row * rw + (c >> 6),
-                         1ull << (c & 63u));
-                atomicOr(reinterpret_cast<unsigned long long*>(a.hotT) +
-                             ((uint64_t)row * (1ull << sh) + key) * a.nw + (j >> 6),
-                         1ull << (j & 63u));
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------- hot lists
-// One 1024-thread block per row: the ascending list of hot columns, read from
-// the row bitmask that hot detection set.
 
 __device__ __forceinline__ uint32_t block_exclusive_scan_1024(uint32_t v, uint32_t* lds /*[16]*/, uint32_t* total)
 {
@@ -223,16 +140,194 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_1024(uint32_t v, uint32
     return off + incl - v;
 }
 
-__global__ __launch_bounds__(1024) void k_hot_compact(CompactArgs a)
+// ---------------------------------------------------------------- fill / clock
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// Per-slice constants of every link from the device clock (the open slice t).
+__global__ void k_prepare(LinkDesc* links, uint32_t n_links, const Clock* clock)
+{
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_links) return;
+    const unsigned long long t = clock->t;
+    const uint32_t k = links[l].k;
+    const uint32_t cur = 1u + (uint32_t)(t % 255u);
+    uint32_t lo, kp, wrap;
+    if (cur >= k) { lo = cur - k + 1u; kp = k; wrap = 0u; }
+    else { lo = cur + 256u - k; kp = k + 1u; wrap = 1u; }
+    LiveCfg c;
+    c.c1 = (256u - lo) * 0x00010001u;
+    c.c2 = (256u - kp) * 0x00010001u;
+    c.wrap = wrap;
+    links[l].L = c;
+    links[l].expire_period = 255u - k;
+    links[l].expire_phase = (uint32_t)(t % (255u - k));
+}
+
+__global__ void k_advance(Clock* clock)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) clock->t += 1ull;
+}
+
+// ---------------------------------------------------------------- scan
+// Alg. 2 for every pair: one byte store per row.  `se_lo..se_hi` restricts
+// the stores to one estimator window so that a pass's random stores stay in
+// the last-level cache.
+
+__device__ __forceinline__ void scan_pair(const uint32_t* tab, uint2 pr, uint8_t* state, uint32_t q, uint32_t delta,
+                                          uint32_t log2eta, uint32_t row_lo, uint32_t row_hi, uint64_t se_lo,
+                                          uint64_t se_hi, uint8_t stamp)
+{
+    const uint32_t qmask = (1u << q) - 1u;
+    const uint32_t d = tab_hash(tab + 1024, pr.y) & ((1u << log2eta) - 1u);   // H1(oip)
+    const uint32_t h0 = tab_hash(tab, pr.x) & qmask;                          // RHFG[0](cip)
+    for (uint32_t i = row_lo; i < row_hi; i++) {
+        const uint32_t col = i == 0 ? h0 : ((shr32(pr.x, (i - 1) * delta) ^ h0) & qmask);
+        const uint64_t se = ((uint64_t)i << q) | col;
+        if (se >= se_lo && se < se_hi) state[(se << log2eta) | d] = stamp;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan(ScanArgs a)
+{
+    __shared__ uint32_t tab[2048];
+    for (uint32_t i = threadIdx.x; i < 2048u; i += 256u) tab[i] = a.tables[i];
+    __syncthreads();
+    const uint32_t row_lo = (uint32_t)(a.se_lo >> a.q);
+    const uint32_t row_hi = (uint32_t)((a.se_hi - 1) >> a.q) + 1u;
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x; p < a.n; p += stride)
+        scan_pair(tab, a.pairs[p], a.state, a.q, a.delta, a.log2eta, row_lo, row_hi, a.se_lo, a.se_hi,
+                  (uint8_t)a.stamp);
+}
+
+// Persistent scan over many links: workgroups pull tiles (one link's pair
+// range and one estimator window) from a device counter.  Tiles are ordered by
+// window, so concurrent tiles store into the same cache-sized state range; a
+// workgroup reloads the tabulation tables only when its link changes.  Every
+// workgroup leaves once the counter passes the last tile.
+__global__ __launch_bounds__(256) void k_scan_tiles(TileScanArgs a)
+{
+    __shared__ uint32_t tab[2048];
+    __shared__ unsigned long long next;
+    uint32_t loaded = 0xFFFFFFFFu;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(a.counter, 1ull);
+        __syncthreads();
+        const unsigned long long t = next;
+        __syncthreads();
+        if (t >= a.n_tiles) break;
+        const ScanTile T = a.tiles[t];
+        const LinkDesc* D = a.links + T.link;
+        if (T.link != loaded) {
+            for (uint32_t i = threadIdx.x; i < 2048u; i += 256u) tab[i] = D->tables[i];
+            __syncthreads();
+            loaded = T.link;
+        }
+        const uint32_t q = D->q, delta = D->delta, log2eta = D->log2eta;
+        uint8_t* state = D->state;
+        const uint32_t row_lo = (uint32_t)(T.se_lo >> q);
+        const uint32_t row_hi = (uint32_t)((T.se_hi - 1) >> q) + 1u;
+        for (uint64_t p = T.start + threadIdx.x; p < T.start + T.n; p += 256u)
+            scan_pair(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, T.se_lo, T.se_hi, (uint8_t)a.stamp);
+    }
+}
+
+// ---------------------------------------------------------------- hot detection
+// One wave per sliding estimator: R_k = live cells (Sec. 3.2); a hot estimator
+// (Sec. 3.3) sets its bit in the row bitmask and in the key-transposed bitmask;
+// estimators of this slot's expiry phase clear their dead cells.  Up to CH
+// 1 KiB wave loads in flight per group.
+
+template <int CH>
+__global__ __launch_bounds__(256) void k_hot_detect(DetectArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t g = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (g >= a.total) return;
+    uint32_t l;
+    uint64_t s;
+    if (a.expire_only) {
+        l = 0;
+        s = a.links[0].expire_phase + g * a.links[0].expire_period;
+        if (s >= a.links[0].n_se) return;
+    } else {
+        l = uniform(find_link(a.se_prefix, a.n_links, g));
+        s = g - a.se_prefix[l];
+    }
+    const LinkDesc* D = a.links + l;
+    const uint32_t log2eta = D->log2eta;
+    const LiveCfg L = D->L;
+    uint4* se = reinterpret_cast<uint4*>(D->state + (s << log2eta));
+    const uint32_t per_lane = (1u << log2eta) >> 10;    // uint4 chunks per lane (eta >= 1024)
+    const bool expire = (s % D->expire_period) == D->expire_phase;
+    const bool count = !a.expire_only;
+    uint32_t live = 0;
+    for (uint32_t g0 = 0; g0 < per_lane; g0 += CH) {
+        uint4 v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++)
+            v[c] = (g0 + c < per_lane) ? se[(g0 + c) * 64u + lane] : make_uint4(0u, 0u, 0u, 0u);
+        if (count) {
+#pragma unroll
+            for (int c = 0; c < CH; c++)
+                if (g0 + c < per_lane)
+                    live += __popc(live_bits(v[c].x, L)) + __popc(live_bits(v[c].y, L)) +
+                            __popc(live_bits(v[c].z, L)) + __popc(live_bits(v[c].w, L));
+        }
+        if (expire) {
+#pragma unroll
+            for (int c = 0; c < CH; c++) {
+                if (g0 + c >= per_lane) continue;
+                uint4 n;
+                n.x = expire_word(v[c].x, L); n.y = expire_word(v[c].y, L);
+                n.z = expire_word(v[c].z, L); n.w = expire_word(v[c].w, L);
+                if (n.x != v[c].x || n.y != v[c].y || n.z != v[c].z || n.w != v[c].w)
+                    se[(g0 + c) * 64u + lane] = n;
+            }
+        }
+    }
+    if (count) {
+        live = wave_sum(live);
+        if (lane == 0) {
+            D->rk[s] = live;
+            if (live >= D->T) {
+                const uint32_t q = D->q;
+                const uint32_t row = (uint32_t)(s >> q), c = (uint32_t)s & ((1u << q) - 1u);
+                const uint32_t sh = q - D->delta;
+                const uint32_t key = c & ((1u << sh) - 1u), j = c >> sh;
+                const uint32_t rw = q >= 6 ? (1u << (q - 6)) : 1u;    // words per row bitmask
+                atomicOr(reinterpret_cast<unsigned long long*>(D->hotbits) + (uint64_t)row * rw + (c >> 6),
+                         1ull << (c & 63u));
+                atomicOr(reinterpret_cast<unsigned long long*>(D->hotT) +
+                             ((uint64_t)row * (1ull << sh) + key) * D->nw + (j >> 6),
+                         1ull << (j & 63u));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- hot lists
+// One 1024-thread block per (link, row): the ascending list of hot columns,
+// from the row bitmask.  The row-0 block also clears the link's counters.
+
+__global__ __launch_bounds__(1024) void k_hot_compact(const LinkDesc* links, const uint32_t* row_table)
 {
     __shared__ uint32_t lds[16];
-    const uint32_t row = blockIdx.x;
-    const uint32_t words = a.q >= 6 ? (1u << (a.q - 6)) : 1u;
-    const uint64_t* bits = a.hotbits + (uint64_t)row * words;
+    const uint32_t rt = row_table[blockIdx.x];
+    const LinkDesc* D = links + (rt >> 8);
+    const uint32_t row = rt & 255u;
+    const uint32_t q = D->q;
+    const uint32_t words = q >= 6 ? (1u << (q - 6)) : 1u;
+    const uint64_t* bits = D->hotbits + (uint64_t)row * words;
     if (row == 0 && threadIdx.x == 0) {
-        for (int l = 0; l < 16; l++) a.ctl->level_n[l] = 0;
-        a.ctl->n_acc = 0;
-        a.ctl->n_out = 0;
+        for (int l = 0; l < (int)MAX_ROWS; l++) D->ctl->level_n[l] = 0;
+        D->ctl->n_acc = 0;
+        D->ctl->n_out = 0;
     }
     const uint32_t per = (words + 1023u) / 1024u;
     const uint32_t w0 = min(words, threadIdx.x * per), w1 = min(words, w0 + per);
@@ -240,7 +335,7 @@ __global__ __launch_bounds__(1024) void k_hot_compact(CompactArgs a)
     for (uint32_t w = w0; w < w1; w++) cnt += __popcll(bits[w]);
     uint32_t total;
     uint32_t off = block_exclusive_scan_1024(cnt, lds, &total);
-    uint32_t* list = a.hot_list + ((uint64_t)row << a.q);
+    uint32_t* list = D->hot_list + ((uint64_t)row << q);
     for (uint32_t w = w0; w < w1; w++) {
         uint64_t b = bits[w];
         while (b) {
@@ -249,7 +344,40 @@ __global__ __launch_bounds__(1024) void k_hot_compact(CompactArgs a)
             list[off++] = w * 64u + i;
         }
     }
-    if (threadIdx.x == 0) a.ctl->hot_n[row] = total;
+    if (threadIdx.x == 0) D->ctl->hot_n[row] = total;
+}
+
+// ---------------------------------------------------------------- level work
+// Work items of one level for every link, prefix-summed; expansion levels pad
+// each link to whole 256-item blocks so that a block never spans two links.
+
+__global__ __launch_bounds__(1024) void k_level_prefix(LevelArgs a)
+{
+    __shared__ unsigned long long lds[1024];
+    unsigned long long own = 0;
+    for (uint32_t base = 0; base < a.n_links; base += 1024u) {
+        const uint32_t l = base + threadIdx.x;
+        unsigned long long n = 0;
+        if (l < a.n_links) {
+            const LinkDesc* D = a.links + l;
+            const Ctl* c = D->ctl;
+            if (a.level == 0) {
+                n = (unsigned long long)c->hot_n[0] * c->hot_n[1];
+            } else if (a.level == LEVEL_VERIFY) {
+                const unsigned long long m = c->level_n[D->r - 3];
+                n = m < D->max_tuples ? m : D->max_tuples;
+            } else if (a.level + 2 < D->r) {
+                const unsigned long long m = c->level_n[a.level - 1];
+                n = m < D->max_tuples ? m : D->max_tuples;
+            }
+            if (a.level != LEVEL_VERIFY) n = (n + 255ull) & ~255ull;
+        }
+        unsigned long long excl, total;
+        block_exclusive_scan_u64_1024(n, lds, &excl, &total);
+        if (l < a.n_links) a.prefix[l] = own + excl;
+        own += total;
+    }
+    if (threadIdx.x == 0) a.prefix[a.n_links] = own;
 }
 
 // ---------------------------------------------------------------- expansion
@@ -258,42 +386,38 @@ __global__ __launch_bounds__(1024) void k_hot_compact(CompactArgs a)
 // he_i, so the candidates are exactly the hot columns of row i under that key
 // (one transposed bitmask word per 64 candidates).  A tuple is stored as
 // (he_0, x) with x the host bits regained so far; he_i = (x >> (i-1)delta) mod
-// 2^q XOR he_0.  Tuples are appended with one atomic per wave; their order is
+// 2^q XOR he_0.  Tuples are appended with one atomic per block; their order is
 // not deterministic, the set is.
 
-struct Cand {
-    const uint64_t* words;   // candidate bitmask words of the key
-    uint32_t nw;
-};
-
-// count (pass 0) or emit (pass 1) the extensions of (he0, x) into row `row`
 template <bool EMIT>
-__device__ __forceinline__ uint32_t extend_one(const ExpandArgs& a, uint32_t he0, uint64_t x, uint32_t row,
-                                               uint64_t slot, uint32_t valid)
+__device__ __forceinline__ uint32_t extend_one(const LinkDesc* D, uint32_t he0, uint64_t x, uint32_t row,
+                                               uint64_t* out_x, uint32_t* out_h0, uint64_t slot, uint32_t valid)
 {
     if (!valid) return 0;
-    const uint32_t qmask = (1u << a.q) - 1u;
-    const uint32_t sh = a.q - a.delta;
+    const uint32_t q = D->q, delta = D->delta, nw = D->nw, key_bits = D->key_bits;
+    const uint32_t qmask = (1u << q) - 1u;
+    const uint32_t sh = q - delta;
     const uint32_t kmask = (1u << sh) - 1u;
-    const uint32_t bprev = (uint32_t)(x >> ((row - 2) * a.delta)) & qmask;       // B(row-1)
-    const uint32_t key = ((bprev >> a.delta) ^ he0) & kmask;
-    const uint64_t* w = a.hotT + ((uint64_t)row * (1ull << sh) + key) * a.nw;
-    const uint32_t newpos = (row - 2) * a.delta + a.q;       // first host bit B(row) adds
-    const uint32_t dmask = (1u << a.delta) - 1u;
+    const uint32_t bprev = (uint32_t)(x >> ((row - 2) * delta)) & qmask;       // B(row-1)
+    const uint32_t key = ((bprev >> delta) ^ he0) & kmask;
+    const uint64_t* w = D->hotT + ((uint64_t)row * (1ull << sh) + key) * nw;
+    const uint32_t newpos = (row - 2) * delta + q;           // first host bit B(row) adds
+    const uint32_t dmask = (1u << delta) - 1u;
     const uint32_t top0 = he0 >> sh;
+    const uint64_t cap = D->max_tuples;
     uint32_t cnt = 0;
-    for (uint32_t wi = 0; wi < a.nw; wi++) {
+    for (uint32_t wi = 0; wi < nw; wi++) {
         uint64_t bits = w[wi];
         while (bits) {
             const uint32_t j = (uint32_t)__ffsll((long long)bits) - 1u + wi * 64u;
             bits &= bits - 1;
             const uint64_t v = (uint64_t)((top0 ^ j) & dmask);              // top delta bits of B(row)
             const uint64_t nx = x | (v << newpos);
-            if (a.key_bits < 64 && (nx >> a.key_bits) != 0) continue;      // bits beyond the key width
+            if ((nx >> key_bits) != 0) continue;                           // bits beyond the key width
             if (EMIT) {
-                if (slot + cnt < a.cap) {
-                    a.out_x[slot + cnt] = nx;
-                    a.out_h0[slot + cnt] = he0;
+                if (slot + cnt < cap) {
+                    out_x[slot + cnt] = nx;
+                    out_h0[slot + cnt] = he0;
                 }
             }
             cnt++;
@@ -303,49 +427,57 @@ __device__ __forceinline__ uint32_t extend_one(const ExpandArgs& a, uint32_t he0
 }
 
 // Level 0: every (he_0, he_1) from HSE(0) x HSE(1), extended over row 2.
-__global__ __launch_bounds__(256) void k_expand0(ExpandArgs a)
+__global__ __launch_bounds__(256) void k_expand0(LevelArgs a)
 {
-    const uint64_t n0 = a.ctl->hot_n[0], n1 = a.ctl->hot_n[1];
-    const uint64_t Q = n0 * n1;
-    const uint32_t qmask = (1u << a.q) - 1u;
-    const uint32_t* l0 = a.hot_list;
-    const uint32_t* l1 = a.hot_list + (1ull << a.q);
-    const bool small = Q <= 0xFFFFFFFFull;
-    for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < Q; base += (uint64_t)gridDim.x * 256u) {
-        const uint64_t idx = base + threadIdx.x;
-        const uint32_t valid = idx < Q;
+    const uint64_t total = a.prefix[a.n_links];
+    for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < total; base += (uint64_t)gridDim.x * 256u) {
+        const uint32_t l = uniform(find_link(a.prefix, a.n_links, base));
+        const LinkDesc* D = a.links + l;
+        const uint64_t n0 = D->ctl->hot_n[0], n1 = D->ctl->hot_n[1];
+        const uint64_t Q = n0 * n1;
+        const uint64_t idx = base - a.prefix[l] + threadIdx.x;
+        const uint32_t qmask = (1u << D->q) - 1u;
+        uint32_t ok = idx < Q;
         uint32_t he0 = 0;
         uint64_t x = 0;
-        if (valid) {
+        if (ok) {
             uint64_t ia, ib;
-            if (small) { ia = (uint32_t)idx / (uint32_t)n1; ib = (uint32_t)idx - (uint32_t)ia * (uint32_t)n1; }
+            if (Q <= 0xFFFFFFFFull) { ia = (uint32_t)idx / (uint32_t)n1; ib = (uint32_t)idx - (uint32_t)ia * (uint32_t)n1; }
             else { ia = idx / n1; ib = idx % n1; }
-            he0 = l0[ia];
-            const uint32_t he1 = l1[ib];
-            x = (uint64_t)((he0 ^ he1) & qmask);                // B(1): host bits 0..q-1
-            if (a.key_bits < 64 && (x >> a.key_bits) != 0) x = ~0ull;
+            he0 = D->hot_list[ia];
+            const uint32_t he1 = D->hot_list[(1ull << D->q) + ib];
+            x = (uint64_t)((he0 ^ he1) & qmask);                 // B(1): host bits 0..q-1
+            if ((x >> D->key_bits) != 0) ok = 0;
         }
-        const uint32_t ok = valid && x != ~0ull;
-        const uint32_t cnt = extend_one<false>(a, he0, x, 2, 0, ok);
-        const unsigned long long slot = block_append_256(cnt, &a.ctl->level_n[0]);
-        extend_one<true>(a, he0, x, 2, slot, ok);
+        uint64_t* ox = D->ctb_x[0];
+        uint32_t* oh = D->ctb_h0[0];
+        const uint32_t cnt = extend_one<false>(D, he0, x, 2, ox, oh, 0, ok);
+        const unsigned long long slot = block_append_256(cnt, &D->ctl->level_n[0]);
+        extend_one<true>(D, he0, x, 2, ox, oh, slot, ok);
     }
 }
 
 // Level L >= 1: extend the tuples of level L-1 over row L+2.
-__global__ __launch_bounds__(256) void k_extend(ExpandArgs a)
+__global__ __launch_bounds__(256) void k_extend(LevelArgs a)
 {
-    const uint32_t level = a.row - 2;
-    const uint64_t nin_raw = a.ctl->level_n[level - 1];
-    const uint64_t nin = nin_raw < a.cap ? nin_raw : a.cap;
-    for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < nin; base += (uint64_t)gridDim.x * 256u) {
-        const uint64_t idx = base + threadIdx.x;
+    const uint32_t level = a.level, row = level + 2;
+    const uint64_t total = a.prefix[a.n_links];
+    for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < total; base += (uint64_t)gridDim.x * 256u) {
+        const uint32_t l = uniform(find_link(a.prefix, a.n_links, base));
+        const LinkDesc* D = a.links + l;
+        const unsigned long long raw = D->ctl->level_n[level - 1];
+        const uint64_t nin = raw < D->max_tuples ? raw : D->max_tuples;
+        const uint64_t idx = base - a.prefix[l] + threadIdx.x;
         const uint32_t valid = idx < nin;
-        const uint32_t he0 = valid ? a.in_h0[idx] : 0u;
-        const uint64_t x = valid ? a.in_x[idx] : 0ull;
-        const uint32_t cnt = extend_one<false>(a, he0, x, a.row, 0, valid);
-        const unsigned long long slot = block_append_256(cnt, &a.ctl->level_n[level]);
-        extend_one<true>(a, he0, x, a.row, slot, valid);
+        const uint64_t* ix = D->ctb_x[(level - 1) & 1];
+        const uint32_t* ih = D->ctb_h0[(level - 1) & 1];
+        const uint32_t he0 = valid ? ih[idx] : 0u;
+        const uint64_t x = valid ? ix[idx] : 0ull;
+        uint64_t* ox = D->ctb_x[level & 1];
+        uint32_t* oh = D->ctb_h0[level & 1];
+        const uint32_t cnt = extend_one<false>(D, he0, x, row, ox, oh, 0, valid);
+        const unsigned long long slot = block_append_256(cnt, &D->ctl->level_n[level]);
+        extend_one<true>(D, he0, x, row, ox, oh, slot, valid);
     }
 }
 
@@ -354,36 +486,41 @@ __global__ __launch_bounds__(256) void k_extend(ExpandArgs a)
 // re-hash check, then the UnionSE of Alg. 1 -- a cell counts only when it is
 // live in all r estimators -- and R >= T.  One wave per tuple.
 
-__global__ __launch_bounds__(256) void k_verify(VerifyArgs a)
+__global__ __launch_bounds__(256) void k_verify(LevelArgs a)
 {
-    const uint64_t nraw = a.ctl->level_n[a.level];
-    const uint64_t n = nraw < a.cap ? nraw : a.cap;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves = (uint64_t)gridDim.x * 4u;
-    const uint32_t qmask = (1u << a.q) - 1u;
-    for (uint64_t t = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6); t < n; t += waves) {
-        const uint32_t he0 = a.in_h0[t];
-        const uint64_t x = a.in_x[t];
-        if (a.rehash && (tab_hash(a.tables, (uint32_t)x) & qmask) != he0) continue;
-        const uint4* se[16];
-        for (uint32_t i = 0; i < a.r; i++) {
-            const uint32_t col = i == 0 ? he0 : (((uint32_t)(x >> ((i - 1) * a.delta)) & qmask) ^ he0);
-            se[i] = reinterpret_cast<const uint4*>(a.state + ((((uint64_t)i << a.q) | col) << a.log2eta));
+    const uint64_t total = a.prefix[a.n_links];
+    for (uint64_t t = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6); t < total; t += waves) {
+        const uint32_t l = uniform(find_link(a.prefix, a.n_links, t));
+        const LinkDesc* D = a.links + l;
+        const uint64_t idx = t - a.prefix[l];
+        const uint32_t lf = D->r - 3;
+        const uint32_t he0 = D->ctb_h0[lf & 1][idx];
+        const uint64_t x = D->ctb_x[lf & 1][idx];
+        const uint32_t q = D->q, qmask = (1u << q) - 1u;
+        if (D->rehash && (tab_hash(D->tables, (uint32_t)x) & qmask) != he0) continue;
+        const LiveCfg L = D->L;
+        const uint4* se[MAX_ROWS];
+        for (uint32_t i = 0; i < D->r; i++) {
+            const uint32_t col = i == 0 ? he0 : (((uint32_t)(x >> ((i - 1) * D->delta)) & qmask) ^ he0);
+            se[i] = reinterpret_cast<const uint4*>(D->state + ((((uint64_t)i << q) | col) << D->log2eta));
         }
+        const uint32_t chunks = D->eta >> 4;
         uint32_t cnt = 0;
-        for (uint32_t c = lane; c < a.chunks; c += 64u) {
+        for (uint32_t c = lane; c < chunks; c += 64u) {
             uint32_t m0 = ~0u, m1 = ~0u, m2 = ~0u, m3 = ~0u;
-            for (uint32_t i = 0; i < a.r; i++) {
+            for (uint32_t i = 0; i < D->r; i++) {
                 const uint4 v = se[i][c];
-                m0 &= live_bits(v.x, a.L); m1 &= live_bits(v.y, a.L);
-                m2 &= live_bits(v.z, a.L); m3 &= live_bits(v.w, a.L);
+                m0 &= live_bits(v.x, L); m1 &= live_bits(v.y, L);
+                m2 &= live_bits(v.z, L); m3 &= live_bits(v.w, L);
             }
             cnt += __popc(m0) + __popc(m1) + __popc(m2) + __popc(m3);
         }
         const uint32_t R = wave_sum(cnt);
-        if (lane == 0 && R >= a.T) {
-            const unsigned long long idx = atomicAdd(&a.ctl->n_acc, 1ull);
-            if (idx < a.max_results) a.acc[idx] = (x << 32) | (uint64_t)(0xFFFFFFFFu - R);
+        if (lane == 0 && R >= D->T) {
+            const unsigned long long i = atomicAdd(&D->ctl->n_acc, 1ull);
+            if (i < D->max_results) D->acc[i] = (x << 32) | (uint64_t)(0xFFFFFFFFu - R);
         }
     }
 }
@@ -400,18 +537,21 @@ __device__ __forceinline__ double estimate(uint32_t eta, uint32_t R)
     return -(double)eta * log(z0 / (double)eta);
 }
 
-// Single block: up to SORT_SMALL keys sorted in LDS (bitonic), de-duplicated
-// by ip and written as the result list.
-__global__ __launch_bounds__(1024) void k_sort_small(ReportArgs a)
+// One block per link: up to SORT_SMALL keys sorted in LDS (bitonic),
+// de-duplicated by ip and written as the result list.  Lists above the link's
+// limit are left to the multi-kernel sort.
+__global__ __launch_bounds__(1024) void k_sort_small(const LinkDesc* links)
 {
     __shared__ unsigned long long s[SORT_SMALL];
     __shared__ uint32_t lds[16];
-    const uint64_t nraw = a.ctl->n_acc;
-    if (nraw > a.limit) return;               // longer lists take the multi-kernel sort
+    const LinkDesc* D = links + blockIdx.x;
+    const uint64_t nraw = D->ctl->n_acc;
+    if (nraw > D->sort_limit || nraw > D->max_results) return;
     const uint32_t n = (uint32_t)(nraw < SORT_SMALL ? nraw : SORT_SMALL);
+    const unsigned long long* keys = D->acc;
     uint32_t N = 1;
     while (N < n) N <<= 1;
-    for (uint32_t i = threadIdx.x; i < N; i += 1024u) s[i] = i < n ? a.keys[i] : ~0ull;
+    for (uint32_t i = threadIdx.x; i < N; i += 1024u) s[i] = i < n ? keys[i] : ~0ull;
     __syncthreads();
     for (uint32_t k = 2; k <= N; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -426,7 +566,6 @@ __global__ __launch_bounds__(1024) void k_sort_small(ReportArgs a)
             __syncthreads();
         }
     }
-    // keep the first key of every ip run
     const uint32_t per = (N + 1023u) / 1024u;
     const uint32_t i0 = min(n, threadIdx.x * per), i1 = min(n, i0 + per);
     uint32_t cnt = 0;
@@ -435,14 +574,13 @@ __global__ __launch_bounds__(1024) void k_sort_small(ReportArgs a)
     uint32_t off = block_exclusive_scan_1024(cnt, lds, &total);
     for (uint32_t i = i0; i < i1; i++) {
         if (i == 0 || (s[i] >> 32) != (s[i - 1] >> 32)) {
-            const uint32_t ip = (uint32_t)(s[i] >> 32);
             const uint32_t R = 0xFFFFFFFFu - (uint32_t)s[i];
             SuperPointDev sp;
-            sp.ip = ip; sp.rk = R; sp.est = estimate(a.eta, R);
-            a.out[off++] = sp;
+            sp.ip = (uint32_t)(s[i] >> 32); sp.rk = R; sp.est = estimate(D->eta, R);
+            D->out[off++] = sp;
         }
     }
-    if (threadIdx.x == 0) a.ctl->n_out = total;
+    if (threadIdx.x == 0) D->ctl->n_out = total;
 }
 
 // Global bitonic step over N (power of two) keys, for lists above SORT_SMALL.
@@ -467,8 +605,8 @@ __global__ void k_pad_keys(unsigned long long* dst, const unsigned long long* sr
         dst[i] = i < n ? src[i] : ~0ull;
 }
 
-// Single block: de-duplicate n sorted keys into the result list, in chunks.
-__global__ __launch_bounds__(1024) void k_dedup_sorted(ReportArgs a, const unsigned long long* sorted, uint64_t n)
+// Single block: de-duplicate n sorted keys into the link's result list.
+__global__ __launch_bounds__(1024) void k_dedup_sorted(const LinkDesc* D, const unsigned long long* sorted, uint64_t n)
 {
     __shared__ uint32_t lds[16];
     uint64_t out_base = 0;
@@ -486,13 +624,30 @@ __global__ __launch_bounds__(1024) void k_dedup_sorted(ReportArgs a, const unsig
             if (i == 0 || (sorted[i] >> 32) != (sorted[i - 1] >> 32)) {
                 const uint32_t R = 0xFFFFFFFFu - (uint32_t)sorted[i];
                 SuperPointDev sp;
-                sp.ip = (uint32_t)(sorted[i] >> 32); sp.rk = R; sp.est = estimate(a.eta, R);
-                a.out[o++] = sp;
+                sp.ip = (uint32_t)(sorted[i] >> 32); sp.rk = R; sp.est = estimate(D->eta, R);
+                D->out[o++] = sp;
             }
         }
         out_base += total;
     }
-    if (threadIdx.x == 0) a.ctl->n_out = out_base;
+    if (threadIdx.x == 0) D->ctl->n_out = out_base;
+}
+
+// One block per link: copy the link's list behind those of the links before it
+// into one packed array (up to cap entries in total) and record the offsets.
+__global__ __launch_bounds__(256) void k_pack(PackArgs a)
+{
+    const uint32_t l = blockIdx.x;
+    unsigned long long off = 0;
+    for (uint32_t j = 0; j < l; j++) off += a.links[j].ctl->n_out;
+    const LinkDesc* D = a.links + l;
+    const unsigned long long n = D->ctl->n_out;
+    if (threadIdx.x == 0) {
+        a.offsets[l] = off;
+        if (l == a.n_links - 1) a.offsets[a.n_links] = off + n;
+    }
+    for (unsigned long long i = threadIdx.x; i < n; i += 256u)
+        if (off + i < a.cap) a.packed[off + i] = D->out[i];
 }
 
 // ---------------------------------------------------------------- merge
@@ -562,62 +717,92 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, const Clock* clock, hipStream_t s)
+{
+    k_prepare<<<grid_for(n_links, 256, 64), 256, 0, s>>>(const_cast<LinkDesc*>(links), n_links, clock);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(Clock* clock, hipStream_t s)
+{
+    k_advance<<<1, 64, 0, s>>>(clock);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s)
 {
     k_scan<<<grid_for(a.n, 256, 256 * 16), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_hot_detect(const DetectArgs& a, hipStream_t s)
+hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s)
 {
-    const dim3 g((uint32_t)((a.n_waves + 3) / 4));
-    const uint32_t per_lane = a.chunks / 64u;   // uint4 chunks per lane per estimator
-    if (per_lane >= 8) k_hot_detect<8><<<g, 256, 0, s>>>(a);
-    else if (per_lane >= 4) k_hot_detect<4><<<g, 256, 0, s>>>(a);
-    else if (per_lane >= 2) k_hot_detect<2><<<g, 256, 0, s>>>(a);
+    k_scan_tiles<<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s)
+{
+    const dim3 g((uint32_t)((a.total + 3) / 4));
+    if (max_chunks_per_lane >= 8) k_hot_detect<8><<<g, 256, 0, s>>>(a);
+    else if (max_chunks_per_lane >= 4) k_hot_detect<4><<<g, 256, 0, s>>>(a);
+    else if (max_chunks_per_lane >= 2) k_hot_detect<2><<<g, 256, 0, s>>>(a);
     else k_hot_detect<1><<<g, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_hot_compact(const CompactArgs& a, uint32_t rows, hipStream_t s)
+hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s)
 {
-    k_hot_compact<<<rows, 1024, 0, s>>>(a);
+    k_hot_compact<<<rows, 1024, 0, s>>>(links, row_table);
     return hipGetLastError();
 }
 
-hipError_t launch_expand0(const ExpandArgs& a, hipStream_t s)
+hipError_t launch_level_prefix(const LevelArgs& a, hipStream_t s)
+{
+    k_level_prefix<<<1, 1024, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
 {
     k_expand0<<<2048, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_extend(const ExpandArgs& a, hipStream_t s)
+hipError_t launch_extend(const LevelArgs& a, hipStream_t s)
 {
     k_extend<<<2048, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_verify(const VerifyArgs& a, hipStream_t s)
+hipError_t launch_verify(const LevelArgs& a, hipStream_t s)
 {
     k_verify<<<2048, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_sort_small(const ReportArgs& a, hipStream_t s)
+hipError_t launch_sort_small(const LinkDesc* links, uint32_t n_links, hipStream_t s)
 {
-    k_sort_small<<<1, 1024, 0, s>>>(a);
+    k_sort_small<<<n_links, 1024, 0, s>>>(links);
     return hipGetLastError();
 }
 
-hipError_t launch_sort_large(const ReportArgs& a, unsigned long long* tmp, uint64_t n, hipStream_t s)
+hipError_t launch_sort_large(const LinkDesc* link, const LinkDesc& host_copy, unsigned long long* tmp, uint64_t n,
+                             hipStream_t s)
 {
     uint64_t N = 1;
     while (N < n) N <<= 1;
-    k_pad_keys<<<grid_for(N, 256, 8192), 256, 0, s>>>(tmp, a.keys, n, N);
+    k_pad_keys<<<grid_for(N, 256, 8192), 256, 0, s>>>(tmp, host_copy.acc, n, N);
     for (uint64_t k = 2; k <= N; k <<= 1)
         for (uint64_t j = k >> 1; j > 0; j >>= 1)
             k_bitonic_step<<<grid_for(N, 256, 8192), 256, 0, s>>>(tmp, N, j, k);
-    k_dedup_sorted<<<1, 1024, 0, s>>>(a, tmp, n);
+    k_dedup_sorted<<<1, 1024, 0, s>>>(link, tmp, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs& a, hipStream_t s)
+{
+    k_pack<<<a.n_links, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -1,7 +1,13 @@
-// C ABI of the sliding super point detector: parameter validation, scratch
+// C ABI of the sliding super point detector: parameter validation, device
 // layout, slot clock and launch sequencing.  Every step of the hot path runs
 // in the kernels of kernels.hip; this file only validates, sequences and
 // copies.
+//
+// An Engine is a set of detectors ("links") that share a slot clock, a stream
+// and one caller-owned state and scratch buffer, and are closed together by
+// one fixed launch sequence.  A single detector (ssd_detector) is an engine
+// of one link closed eagerly; a batch (ssd_batch) is an engine of n links
+// scanned by one persistent launch and closed by a replayed HIP graph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -9,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -36,7 +43,6 @@ int fail(int code, const char* fmt, ...)
 
 constexpr uint64_t ALIGN = 256;
 uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
-
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 uint32_t log2u(uint64_t x)
 {
@@ -45,16 +51,15 @@ uint32_t log2u(uint64_t x)
     return l;
 }
 
-struct Layout {
-    uint64_t ctl, tables, rk, hot_list, hotbits, hotT, hot_end, ctb_x[2], ctb_h0[2], acc, sort_tmp, out, total;
-    uint32_t nw;
-};
-
-constexpr uint32_t PREFIX_MAX = SORT_SMALL;   // result entries staged in pinned memory per close
+constexpr uint32_t PREFIX_MAX = SORT_SMALL;       // result entries staged in pinned memory per close
 // Scan pass window: random byte stores confined to 128 MiB of state stay in
 // the 256 MB Infinity Cache (measured best of 64..768 MiB on the core-link
 // workload; one pass when the state is smaller).
 constexpr uint64_t DEFAULT_PASS_BYTES = 128ull << 20;
+constexpr uint64_t DEFAULT_TILE_PAIRS = 262144;
+constexpr uint64_t MAX_TILES = 65536;             // batched scan work tiles per call
+constexpr uint64_t BATCH_STAGE = 16384;           // result entries staged by the batch graph
+constexpr uint32_t N_PHASES = SSD_PHASES;
 
 int validate(const ssd_params* p)
 {
@@ -77,200 +82,541 @@ int validate(const ssd_params* p)
     return SSD_OK;
 }
 
-Layout layout(const ssd_params* p)
-{
-    Layout L{};
-    const uint64_t n_se = (uint64_t)p->r << p->q;
-    L.nw = p->delta > 6 ? 1u << (p->delta - 6) : 1u;
-    uint64_t o = 0;
-    L.ctl = o; o = align_up(o + sizeof(Ctl));
-    L.tables = o; o = align_up(o + 2048 * 4);
-    L.rk = o; o = align_up(o + n_se * 4);
-    L.hot_list = o; o = align_up(o + n_se * 4);
-    // hotbits and hotT are adjacent: one fill clears both before every close
-    L.hotbits = o; o = o + (uint64_t)p->r * (p->q >= 6 ? (1ull << (p->q - 6)) : 1ull) * 8;
-    L.hotT = o; o = o + (uint64_t)p->r * (1ull << (p->q - p->delta)) * L.nw * 8;
-    L.hot_end = o; o = align_up(o);
-    for (int b = 0; b < 2; b++) { L.ctb_x[b] = o; o = align_up(o + p->max_tuples * 8); }
-    for (int b = 0; b < 2; b++) { L.ctb_h0[b] = o; o = align_up(o + p->max_tuples * 4); }
-    L.acc = o; o = align_up(o + p->max_results * 8);
-    uint64_t pw = 1;
-    while (pw < p->max_results) pw <<= 1;
-    L.sort_tmp = o; o = align_up(o + pw * 8);
-    L.out = o; o = align_up(o + p->max_results * sizeof(SuperPointDev));
-    L.total = o;
-    return L;
-}
-
 uint32_t hot_threshold(uint32_t eta, uint32_t theta)
 {
     // Sec. 3.3: R_k >= eta * (1 - e^(-theta/eta)), rounded up once
     return (uint32_t)ceil((double)eta * (1.0 - exp(-(double)theta / (double)eta)));
 }
 
-uint32_t stamp_of(uint64_t t) { return 1u + (uint32_t)(t % 255u); }
+uint32_t nw_of(const ssd_params& p) { return p.delta > 6 ? 1u << (p.delta - 6) : 1u; }
+uint64_t row_words(const ssd_params& p) { return p.q >= 6 ? (1ull << (p.q - 6)) : 1ull; }
 
-LiveCfg live_cfg(uint64_t t, uint32_t k)
+struct LinkLayout {
+    uint64_t state_off, state_bytes;
+    uint64_t tables, ctl, rk, hot_list, hotbits, hotT, ctb_x[2], ctb_h0[2], acc, out;
+};
+
+struct Layout {
+    uint64_t links = 0, se_prefix = 0, row_table = 0, level_prefix = 0, clock = 0, pack_offsets = 0, tiles = 0;
+    uint64_t ctl = 0, hot_begin = 0, hot_end = 0, sort_tmp = 0, packed = 0, total = 0;
+    uint64_t state_total = 0, pack_cap = 0, tile_cap = 0;
+    std::vector<LinkLayout> link;
+};
+
+// Scratch layout of an engine: header (descriptors, prefix tables, clock,
+// scan tiles), tables, control blocks, the hot-bit pool (cleared by one fill
+// per close), then every link's own buffers; states are packed link after link.
+Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_cap)
 {
-    const uint32_t cur = stamp_of(t);
-    uint32_t lo, kp, wrap;
-    if (cur >= k) { lo = cur - k + 1; kp = k; wrap = 0; }
-    else { lo = cur + 256 - k; kp = k + 1; wrap = 1; }
-    LiveCfg c;
-    c.c1 = (256u - lo) * 0x00010001u;
-    c.c2 = (256u - kp) * 0x00010001u;
-    c.wrap = wrap;
-    return c;
+    Layout L;
+    L.link.resize(n);
+    L.pack_cap = pack_cap;
+    L.tile_cap = tile_cap;
+    uint64_t rows = 0, maxres = 1;
+    for (uint32_t l = 0; l < n; l++) {
+        rows += p[l].r;
+        maxres = std::max<uint64_t>(maxres, p[l].max_results);
+    }
+    uint64_t o = 0;
+    L.links = o; o = align_up(o + n * sizeof(LinkDesc));
+    L.se_prefix = o; o = align_up(o + (n + 1) * 8);
+    L.row_table = o; o = align_up(o + rows * 4);
+    L.level_prefix = o; o = align_up(o + (n + 1) * 8);
+    L.clock = o; o = align_up(o + sizeof(Clock));
+    L.pack_offsets = o; o = align_up(o + (n + 1) * 8);
+    L.tiles = o; o = align_up(o + 8 + tile_cap * sizeof(ScanTile));
+    for (uint32_t l = 0; l < n; l++) { L.link[l].tables = o; o += 2048 * 4; }
+    o = align_up(o);
+    L.ctl = o;
+    for (uint32_t l = 0; l < n; l++) L.link[l].ctl = o + l * sizeof(Ctl);
+    o = align_up(o + n * sizeof(Ctl));
+    L.hot_begin = o;
+    for (uint32_t l = 0; l < n; l++) {
+        const ssd_params& q = p[l];
+        L.link[l].hotbits = o; o += q.r * row_words(q) * 8;
+        L.link[l].hotT = o; o += (uint64_t)q.r * (1ull << (q.q - q.delta)) * nw_of(q) * 8;
+    }
+    L.hot_end = o;
+    o = align_up(o);
+    for (uint32_t l = 0; l < n; l++) {
+        const ssd_params& q = p[l];
+        const uint64_t n_se = (uint64_t)q.r << q.q;
+        LinkLayout& K = L.link[l];
+        K.rk = o; o = align_up(o + n_se * 4);
+        K.hot_list = o; o = align_up(o + n_se * 4);
+        for (int b = 0; b < 2; b++) { K.ctb_x[b] = o; o = align_up(o + q.max_tuples * 8); }
+        for (int b = 0; b < 2; b++) { K.ctb_h0[b] = o; o = align_up(o + q.max_tuples * 4); }
+        K.acc = o; o = align_up(o + q.max_results * 8);
+        K.out = o; o = align_up(o + q.max_results * sizeof(SuperPointDev));
+    }
+    uint64_t pw = 1;
+    while (pw < maxres) pw <<= 1;
+    L.sort_tmp = o; o = align_up(o + pw * 8);
+    L.packed = o; o = align_up(o + pack_cap * sizeof(SuperPointDev));
+    L.total = o;
+    uint64_t so = 0;
+    for (uint32_t l = 0; l < n; l++) {
+        L.link[l].state_off = so;
+        L.link[l].state_bytes = ((uint64_t)p[l].r << p[l].q) * p[l].eta;
+        so += L.link[l].state_bytes;
+    }
+    L.state_total = so;
+    return L;
 }
 
 }  // namespace
 
-struct ssd_detector {
-    ssd_params p;
+// ---------------------------------------------------------------- engine
+
+struct Engine {
+    uint32_t n = 0;
+    std::vector<ssd_params> p;
+    std::vector<uint32_t> T;
     Layout L;
-    uint32_t T, log2eta;
-    uint64_t clock;
-    uint8_t* state;
-    uint8_t* scratch;
-    hipStream_t stream;
-    int device;
-    bool broken;
-    uint64_t pass_bytes;
-    uint64_t sort_block_limit;
-    uint32_t tables_host[2048];
-    Ctl* mailbox;                       // pinned host copy of the control block
-    std::vector<ssd_super_point> results;
-    std::vector<SuperPointDev> staging;
-    Ctl last;                           // control block of the last close
-    bool have_last;
-    uint64_t last_reported;             // list length of the last close (sizes the staged prefix)
-    // phase timing with HIP events (opt-in)
-    bool timing;
+    uint8_t* state = nullptr;
+    uint8_t* scratch = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint64_t clock = 0;
+    bool broken = false;
+    uint64_t se_total = 0;
+    uint32_t rows_total = 0, max_r = 0, max_chunks = 1;
+    std::vector<LinkDesc> hl;          // host copies of the device descriptors
+    std::vector<uint32_t> tables;      // n x 2048
+    // pinned host mailbox: control blocks, staged result entries, pack offsets
+    void* pinned = nullptr;
+    Ctl* mb_ctl = nullptr;
+    SuperPointDev* mb_stage = nullptr;
+    unsigned long long* mb_offsets = nullptr;
+    uint64_t stage_cap = 0;
+    // phase timing
+    bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<uint32_t> ev_free;
     struct Pending { uint32_t a, b, phase, launches; };
     std::vector<Pending> pending;
-    double ph_ms[SSD_PHASES];
-    uint64_t ph_launches[SSD_PHASES];
+    double ph_ms[N_PHASES] = {};
+    uint64_t ph_launches[N_PHASES] = {};
+    // graph replay of the close
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    // results of the last close
+    std::vector<std::vector<ssd_super_point>> results;
+    std::vector<int> status;
+    std::vector<Ctl> last;
+    bool have_last = false;
+    std::vector<SuperPointDev> staging;
 
-    template <class T> T* at(uint64_t off) const { return reinterpret_cast<T*>(scratch + off); }
-    uint64_t n_se() const { return (uint64_t)p.r << p.q; }
-    uint64_t state_bytes() const { return n_se() << log2eta; }
-    uint32_t expire_period() const { return 255u - p.k; }
+    template <class X> X* at(uint64_t off) const { return reinterpret_cast<X*>(scratch + off); }
+    LinkDesc* dev_links() const { return at<LinkDesc>(L.links); }
 };
 
 namespace {
 
-int dev_fail(ssd_detector* d, hipError_t e, const char* what)
+int dev_fail(Engine* e, hipError_t err, const char* what)
 {
-    if (d) d->broken = true;
-    return fail(SSD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    if (e) e->broken = true;
+    return fail(SSD_E_DEVICE, "%s: %s", what, hipGetErrorString(err));
 }
 
-#define HIPCHK(d, call)                                          \
-    do {                                                         \
-        hipError_t e_ = (call);                                  \
-        if (e_ != hipSuccess) return dev_fail((d), e_, #call);   \
+#define HIPCHK(e, call)                                            \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return dev_fail((e), e_, #call);     \
     } while (0)
 
-// ---- phase timing: a start/stop event pair around each phase's launches
-uint32_t ev_get(ssd_detector* d)
+int usable(Engine* e)
 {
-    if (!d->ev_free.empty()) {
-        uint32_t i = d->ev_free.back();
-        d->ev_free.pop_back();
+    if (e->broken) return fail(SSD_E_STATE, "detector unusable after an earlier device error");
+    hipError_t err = hipSetDevice(e->device);
+    if (err != hipSuccess) return dev_fail(e, err, "hipSetDevice");
+    return SSD_OK;
+}
+
+// ---- phase timing: a start/stop event pair around each phase's launches
+uint32_t ev_get(Engine* e)
+{
+    if (!e->ev_free.empty()) {
+        uint32_t i = e->ev_free.back();
+        e->ev_free.pop_back();
         return i;
     }
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return UINT32_MAX;
-    d->ev_pool.push_back(e);
-    return (uint32_t)d->ev_pool.size() - 1;
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return UINT32_MAX;
+    e->ev_pool.push_back(ev);
+    return (uint32_t)e->ev_pool.size() - 1;
 }
 
 struct PhaseMark {
     uint32_t a = UINT32_MAX;
 };
 
-PhaseMark phase_begin(ssd_detector* d)
+PhaseMark phase_begin(Engine* e)
 {
     PhaseMark m;
-    if (!d->timing) return m;
-    m.a = ev_get(d);
-    if (m.a != UINT32_MAX && hipEventRecord(d->ev_pool[m.a], d->stream) != hipSuccess) {
-        d->ev_free.push_back(m.a);
+    if (!e->timing) return m;
+    m.a = ev_get(e);
+    if (m.a != UINT32_MAX && hipEventRecord(e->ev_pool[m.a], e->stream) != hipSuccess) {
+        e->ev_free.push_back(m.a);
         m.a = UINT32_MAX;
     }
     return m;
 }
 
-void phase_end(ssd_detector* d, PhaseMark m, uint32_t phase, uint32_t launches)
+void phase_end(Engine* e, PhaseMark m, uint32_t phase, uint32_t launches)
 {
-    if (!d->timing || m.a == UINT32_MAX) return;
-    uint32_t b = ev_get(d);
-    if (b == UINT32_MAX) { d->ev_free.push_back(m.a); return; }
-    if (hipEventRecord(d->ev_pool[b], d->stream) != hipSuccess) {
-        d->ev_free.push_back(m.a);
-        d->ev_free.push_back(b);
+    if (!e->timing || m.a == UINT32_MAX) return;
+    uint32_t b = ev_get(e);
+    if (b == UINT32_MAX) { e->ev_free.push_back(m.a); return; }
+    if (hipEventRecord(e->ev_pool[b], e->stream) != hipSuccess) {
+        e->ev_free.push_back(m.a);
+        e->ev_free.push_back(b);
         return;
     }
-    d->pending.push_back({m.a, b, phase, launches});
+    e->pending.push_back({m.a, b, phase, launches});
 }
 
 // after the stream passed every pending stop event
-void phase_collect(ssd_detector* d)
+void phase_collect(Engine* e)
 {
-    for (const auto& p : d->pending) {
+    for (const auto& pd : e->pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, d->ev_pool[p.a], d->ev_pool[p.b]) == hipSuccess) {
-            d->ph_ms[p.phase] += ms;
-            d->ph_launches[p.phase] += p.launches;
+        if (hipEventElapsedTime(&ms, e->ev_pool[pd.a], e->ev_pool[pd.b]) == hipSuccess) {
+            e->ph_ms[pd.phase] += ms;
+            e->ph_launches[pd.phase] += pd.launches;
         }
-        d->ev_free.push_back(p.a);
-        d->ev_free.push_back(p.b);
+        e->ev_free.push_back(pd.a);
+        e->ev_free.push_back(pd.b);
     }
-    d->pending.clear();
+    e->pending.clear();
 }
 
-int usable(ssd_detector* d)
+void engine_release(Engine* e)
 {
-    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    if (d->broken) return fail(SSD_E_STATE, "detector unusable after an earlier device error");
-    hipError_t e = hipSetDevice(d->device);
-    if (e != hipSuccess) return dev_fail(d, e, "hipSetDevice");
+    (void)hipSetDevice(e->device);
+    if (!e->broken && e->scratch) (void)hipStreamSynchronize(e->stream);
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->pinned) (void)hipHostFree(e->pinned);
+    for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
+}
+
+int engine_query(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_cap, uint64_t* state_bytes,
+                 uint64_t* scratch_bytes)
+{
+    if (!p || n < 1 || n > MAX_LINKS) return fail(SSD_E_PARAM, "need 1..%u detectors", MAX_LINKS);
+    for (uint32_t l = 0; l < n; l++) {
+        int rc = validate(p + l);
+        if (rc) return rc;
+    }
+    Layout L = plan(p, n, pack_cap, tile_cap);
+    if (state_bytes) *state_bytes = L.state_total;
+    if (scratch_bytes) *scratch_bytes = L.total;
     return SSD_OK;
 }
 
-// Rotating expiry: estimators with index = t (mod 255-k) clear their dead
-// cells at this close, so a cell is cleared at most 254-k slots after it
-// left the window and stamps never wrap onto a live value.
-DetectArgs detect_args(const ssd_detector* d, bool count)
+int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tables, void* state_dev,
+                uint64_t state_bytes, void* scratch_dev, uint64_t scratch_bytes, void* stream, uint64_t pack_cap,
+                uint64_t tile_cap, uint64_t stage_cap)
 {
-    DetectArgs a{};
-    a.state = d->state;
-    a.rk = d->at<uint32_t>(d->L.rk);
-    a.hotbits = d->at<uint64_t>(d->L.hotbits);
-    a.hotT = d->at<uint64_t>(d->L.hotT);
-    a.q = d->p.q;
-    a.delta = d->p.delta;
-    a.nw = d->L.nw;
-    a.T = d->T;
-    a.log2eta = d->log2eta;
-    a.chunks = d->p.eta / 16u;
-    a.count = count ? 1u : 0u;
-    a.expire_period = d->expire_period();
-    a.expire_phase = (uint32_t)(d->clock % a.expire_period);
-    a.L = live_cfg(d->clock, d->p.k);
-    if (count) {
-        a.n_waves = d->n_se();
-        a.se_base = 0;
-        a.se_step = 1;
-    } else {
-        const uint64_t n = d->n_se();
-        a.se_base = a.expire_phase;
-        a.se_step = a.expire_period;
-        a.n_waves = a.se_base < n ? (n - a.se_base + a.se_step - 1) / a.se_step : 0;
+    int rc = engine_query(p, n, pack_cap, tile_cap, nullptr, nullptr);
+    if (rc) return rc;
+    if (!tables) return fail(SSD_E_PARAM, "tables_host is NULL");
+    e->n = n;
+    e->p.assign(p, p + n);
+    e->L = plan(p, n, pack_cap, tile_cap);
+    if (!state_dev || state_bytes < e->L.state_total || ((uintptr_t)state_dev & 15u))
+        return fail(SSD_E_NOMEM, "state buffer needs %llu bytes, 16-byte aligned", (unsigned long long)e->L.state_total);
+    if (!scratch_dev || scratch_bytes < e->L.total || ((uintptr_t)scratch_dev & (ALIGN - 1)))
+        return fail(SSD_E_NOMEM, "scratch buffer needs %llu bytes, 256-byte aligned", (unsigned long long)e->L.total);
+    e->state = static_cast<uint8_t*>(state_dev);
+    e->scratch = static_cast<uint8_t*>(scratch_dev);
+    e->stream = static_cast<hipStream_t>(stream);
+    e->tables.assign(tables, tables + (uint64_t)n * 2048);
+    e->T.resize(n);
+    e->hl.resize(n);
+    std::vector<uint64_t> se_prefix(n + 1, 0);
+    std::vector<uint32_t> row_table;
+    for (uint32_t l = 0; l < n; l++) {
+        const ssd_params& q = p[l];
+        const LinkLayout& K = e->L.link[l];
+        LinkDesc& D = e->hl[l];
+        memset(&D, 0, sizeof D);
+        D.state = e->state + K.state_off;
+        D.tables = e->at<uint32_t>(K.tables);
+        D.rk = e->at<uint32_t>(K.rk);
+        D.hotbits = e->at<uint64_t>(K.hotbits);
+        D.hotT = e->at<uint64_t>(K.hotT);
+        D.hot_list = e->at<uint32_t>(K.hot_list);
+        for (int b = 0; b < 2; b++) {
+            D.ctb_x[b] = e->at<uint64_t>(K.ctb_x[b]);
+            D.ctb_h0[b] = e->at<uint32_t>(K.ctb_h0[b]);
+        }
+        D.acc = e->at<unsigned long long>(K.acc);
+        D.out = e->at<SuperPointDev>(K.out);
+        D.ctl = e->at<Ctl>(K.ctl);
+        D.n_se = (uint64_t)q.r << q.q;
+        D.max_tuples = q.max_tuples;
+        D.max_results = q.max_results;
+        D.sort_limit = SORT_SMALL;
+        D.q = q.q; D.r = q.r; D.delta = q.delta; D.eta = q.eta; D.log2eta = log2u(q.eta); D.k = q.k;
+        D.T = e->T[l] = hot_threshold(q.eta, q.theta);
+        D.nw = nw_of(q);
+        D.key_bits = q.key_bits;
+        D.rehash = (q.flags & SSD_VERIFY_REHASH) ? 1u : 0u;
+        se_prefix[l + 1] = se_prefix[l] + D.n_se;
+        for (uint32_t i = 0; i < q.r; i++) row_table.push_back((l << 8) | i);
+        e->max_r = std::max(e->max_r, q.r);
+        e->max_chunks = std::max(e->max_chunks, q.eta >> 10);
     }
-    return a;
+    e->se_total = se_prefix[n];
+    e->rows_total = (uint32_t)row_table.size();
+    hipError_t err = hipGetDevice(&e->device);
+    if (err != hipSuccess) return dev_fail(e, err, "hipGetDevice");
+    e->stage_cap = stage_cap;
+    const uint64_t pinned_bytes = n * sizeof(Ctl) + stage_cap * sizeof(SuperPointDev) + (n + 1) * 8;
+    err = hipHostMalloc(&e->pinned, pinned_bytes, hipHostMallocDefault);
+    if (err != hipSuccess) return dev_fail(e, err, "hipHostMalloc");
+    e->mb_ctl = static_cast<Ctl*>(e->pinned);
+    e->mb_stage = reinterpret_cast<SuperPointDev*>(e->mb_ctl + n);
+    e->mb_offsets = reinterpret_cast<unsigned long long*>(e->mb_stage + stage_cap);
+    // every cell starts empty (Sec. 3.2: initialised once); scratch and clock zero
+    HIPCHK(e, launch_fill_u32(reinterpret_cast<uint32_t*>(e->state), e->L.state_total / 4, 0u, e->stream));
+    HIPCHK(e, launch_fill_u32(e->at<uint32_t>(0), e->L.total / 4, 0u, e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->at<uint32_t>(e->L.row_table), row_table.data(), row_table.size() * 4,
+                             hipMemcpyHostToDevice, e->stream));
+    for (uint32_t l = 0; l < n; l++)
+        HIPCHK(e, hipMemcpyAsync(e->at<uint32_t>(e->L.link[l].tables), tables + (uint64_t)l * 2048, 2048 * 4,
+                                 hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    e->results.assign(n, {});
+    e->status.assign(n, SSD_OK);
+    e->last.assign(n, Ctl{});
+    return SSD_OK;
+}
+
+// The close of every link as one fixed launch sequence (recordable in a graph):
+// per-slice constants, hot bits cleared, hot detection, hot lists, the
+// candidate levels, the final test, sorting, then the control blocks (and, for
+// batches, the packed lists) to pinned memory, and the clock advance.
+int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
+{
+    const hipStream_t s = e->stream;
+    LinkDesc* links = e->dev_links();
+    const bool t = e->timing && !e->use_graph;
+    auto begin = [&]() { return t ? phase_begin(e) : PhaseMark(); };
+    auto end = [&](PhaseMark m, uint32_t ph, uint32_t nl) { if (t) phase_end(e, m, ph, nl); };
+    HIPCHK(e, launch_prepare(links, e->n, e->at<Clock>(e->L.clock), s));
+    HIPCHK(e, launch_fill_u32(e->at<uint32_t>(e->L.hot_begin), (e->L.hot_end - e->L.hot_begin) / 4, 0u, s));
+    DetectArgs da{};
+    da.links = links;
+    da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
+    da.n_links = e->n;
+    da.total = e->se_total;
+    PhaseMark pm = begin();
+    HIPCHK(e, launch_hot_detect(da, e->max_chunks, s));
+    end(pm, 1, 1);
+    pm = begin();
+    HIPCHK(e, launch_hot_compact(links, e->at<uint32_t>(e->L.row_table), e->rows_total, s));
+    end(pm, 2, 1);
+    LevelArgs la{};
+    la.links = links;
+    la.n_links = e->n;
+    la.prefix = e->at<uint64_t>(e->L.level_prefix);
+    la.level = 0;
+    pm = begin();
+    HIPCHK(e, launch_level_prefix(la, s));
+    HIPCHK(e, launch_expand0(la, s));
+    for (uint32_t lvl = 1; lvl + 3 <= e->max_r; lvl++) {
+        la.level = lvl;
+        HIPCHK(e, launch_level_prefix(la, s));
+        HIPCHK(e, launch_extend(la, s));
+    }
+    end(pm, 3, e->max_r - 2);
+    la.level = LEVEL_VERIFY;
+    pm = begin();
+    HIPCHK(e, launch_level_prefix(la, s));
+    HIPCHK(e, launch_verify(la, s));
+    end(pm, 4, 1);
+    pm = begin();
+    HIPCHK(e, launch_sort_small(links, e->n, s));
+    end(pm, 5, 1);
+    HIPCHK(e, hipMemcpyAsync(e->mb_ctl, e->at<Ctl>(e->L.ctl), e->n * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (pack) {
+        PackArgs pa{};
+        pa.links = links;
+        pa.n_links = e->n;
+        pa.packed = e->at<SuperPointDev>(e->L.packed);
+        pa.cap = e->L.pack_cap;
+        pa.offsets = e->at<unsigned long long>(e->L.pack_offsets);
+        HIPCHK(e, launch_pack(pa, s));
+        HIPCHK(e, hipMemcpyAsync(e->mb_offsets, pa.offsets, (e->n + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(e, hipMemcpyAsync(e->mb_stage, pa.packed, e->stage_cap * sizeof(SuperPointDev),
+                                 hipMemcpyDeviceToHost, s));
+    } else if (single_prefix) {
+        HIPCHK(e, hipMemcpyAsync(e->mb_stage, e->hl[0].out, single_prefix * sizeof(SuperPointDev),
+                                 hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(e, launch_advance(e->at<Clock>(e->L.clock), s));
+    return SSD_OK;
+}
+
+// After the close's synchronisation: check every link's capacities, finish
+// links whose list needs the multi-kernel sort, and collect the lists.
+int collect_results(Engine* e, bool packed, uint64_t single_prefix)
+{
+    const hipStream_t s = e->stream;
+    e->have_last = true;
+    for (uint32_t l = 0; l < e->n; l++) {
+        const ssd_params& q = e->p[l];
+        Ctl c = e->mb_ctl[l];
+        e->last[l] = c;
+        e->results[l].clear();
+        e->status[l] = SSD_OK;
+        bool over = c.n_acc > q.max_results;
+        for (uint32_t lv = 0; lv + 3 <= q.r; lv++) over |= c.level_n[lv] > q.max_tuples;
+        if (over) {
+            e->status[l] = SSD_E_OVERFLOW;
+            continue;
+        }
+        const SuperPointDev* src = nullptr;
+        uint64_t m = c.n_out;
+        if (c.n_acc > e->hl[l].sort_limit) {
+            // long list: multi-kernel sort of this link, then its whole list
+            PhaseMark pm = phase_begin(e);
+            HIPCHK(e, launch_sort_large(e->dev_links() + l, e->hl[l], e->at<unsigned long long>(e->L.sort_tmp),
+                                        c.n_acc, s));
+            phase_end(e, pm, 5, 1);
+            e->staging.resize(c.n_acc);
+            HIPCHK(e, hipMemcpyAsync(&e->mb_ctl[l], e->hl[l].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+            HIPCHK(e, hipMemcpyAsync(e->staging.data(), e->hl[l].out, c.n_acc * sizeof(SuperPointDev),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(e, hipStreamSynchronize(s));
+            phase_collect(e);
+            m = e->mb_ctl[l].n_out;
+            e->last[l].n_out = m;
+            src = e->staging.data();
+        } else if (packed && e->mb_offsets[l] + m <= e->stage_cap) {
+            src = e->mb_stage + e->mb_offsets[l];
+        } else if (!packed && m <= single_prefix) {
+            src = e->mb_stage;
+        } else {
+            e->staging.resize(m);
+            if (m) {
+                HIPCHK(e, hipMemcpyAsync(e->staging.data(), e->hl[l].out, m * sizeof(SuperPointDev),
+                                         hipMemcpyDeviceToHost, s));
+                HIPCHK(e, hipStreamSynchronize(s));
+            }
+            src = e->staging.data();
+        }
+        e->results[l].resize(m);
+        for (uint64_t i = 0; i < m; i++) {
+            e->results[l][i].ip = src[i].ip;
+            e->results[l][i].rk = src[i].rk;
+            e->results[l][i].est = src[i].est;
+        }
+    }
+    return SSD_OK;
+}
+
+// Rotating expiry only (a router that only advances): per-slice constants,
+// the estimators of this slot's expiry phase, clock advance.
+int enqueue_advance_only(Engine* e)
+{
+    const hipStream_t s = e->stream;
+    LinkDesc* links = e->dev_links();
+    HIPCHK(e, launch_prepare(links, e->n, e->at<Clock>(e->L.clock), s));
+    DetectArgs da{};
+    da.links = links;
+    da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
+    da.n_links = 1;
+    da.expire_only = 1;
+    const uint64_t period = 255u - e->p[0].k;
+    da.total = (e->hl[0].n_se + period - 1) / period;
+    HIPCHK(e, launch_hot_detect(da, e->max_chunks, s));
+    HIPCHK(e, launch_advance(e->at<Clock>(e->L.clock), s));
+    return SSD_OK;
+}
+
+int read_timing(Engine* e, double* ms_out, uint64_t* launches_out, int reset)
+{
+    int rc = usable(e);
+    if (rc) return rc;
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    phase_collect(e);
+    for (uint32_t i = 0; i < N_PHASES; i++) {
+        if (ms_out) ms_out[i] = e->ph_ms[i];
+        if (launches_out) launches_out[i] = e->ph_launches[i];
+        if (reset) { e->ph_ms[i] = 0; e->ph_launches[i] = 0; }
+    }
+    return SSD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- single detector
+
+struct ssd_detector {
+    Engine e;
+    uint64_t pass_bytes = DEFAULT_PASS_BYTES;
+    uint64_t last_reported = 0;
+    const ssd_params& p() const { return e.p[0]; }
+    const LinkDesc& D() const { return e.hl[0]; }
+};
+
+// ---------------------------------------------------------------- batch
+
+struct ssd_batch {
+    Engine e;
+    uint64_t pass_bytes = DEFAULT_PASS_BYTES;
+    uint64_t tile_pairs = DEFAULT_TILE_PAIRS;
+    // pinned double-buffered tile lists for the persistent scan
+    void* tile_pinned[2] = {nullptr, nullptr};
+    hipEvent_t tile_done[2] = {nullptr, nullptr};
+    bool tile_used[2] = {false, false};
+    uint32_t tile_next = 0;
+    uint32_t scan_blocks = 2048;
+    hipStream_t capture_stream = nullptr;   // records the close graph (never runs work)
+    // autotuner: candidate (pass window, tile pairs), each scan timed with events
+    struct Cand { uint64_t pass, tile; double ns_per_pair; };
+    std::vector<Cand> cands;
+    int tune_idx = -1;                 // next candidate to time, -1 = not tuning
+    std::vector<std::pair<int, uint64_t>> tune_pending;   // (candidate, pairs) per timed scan
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tune_events;
+};
+
+namespace {
+
+// After a close's synchronisation: credit the timed scans to their candidates;
+// once every candidate has run, keep the fastest per pair.
+void autotune_collect(ssd_batch* b)
+{
+    for (size_t i = 0; i < b->tune_pending.size(); i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->tune_events[i].first, b->tune_events[i].second) == hipSuccess &&
+            b->tune_pending[i].second) {
+            ssd_batch::Cand& c = b->cands[b->tune_pending[i].first];
+            const double ns = ms * 1e6 / (double)b->tune_pending[i].second;
+            if (c.ns_per_pair < 0 || ns < c.ns_per_pair) c.ns_per_pair = ns;
+        }
+        (void)hipEventDestroy(b->tune_events[i].first);
+        (void)hipEventDestroy(b->tune_events[i].second);
+    }
+    b->tune_pending.clear();
+    b->tune_events.clear();
+    if (b->tune_idx >= (int)b->cands.size()) {
+        int best = 0;
+        for (int i = 1; i < (int)b->cands.size(); i++)
+            if (b->cands[i].ns_per_pair >= 0 &&
+                (b->cands[best].ns_per_pair < 0 || b->cands[i].ns_per_pair < b->cands[best].ns_per_pair))
+                best = i;
+        b->pass_bytes = b->cands[best].pass;
+        b->tile_pairs = b->cands[best].tile;
+        b->tune_idx = -1;
+    }
 }
 
 }  // namespace
@@ -295,13 +641,12 @@ const char* ssd_strerror(int s)
 
 const char* ssd_last_error(void) { return g_last_error.c_str(); }
 
+// ---- single detector
+
 int ssd_query_sizes(const ssd_params* p, uint64_t* state_bytes, uint64_t* scratch_bytes)
 {
-    int rc = validate(p);
-    if (rc) return rc;
-    if (state_bytes) *state_bytes = ((uint64_t)p->r << p->q) * p->eta;
-    if (scratch_bytes) *scratch_bytes = layout(p).total;
-    return SSD_OK;
+    if (!p) return fail(SSD_E_PARAM, "params is NULL");
+    return engine_query(p, 1, 0, 0, state_bytes, scratch_bytes);
 }
 
 int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* state_dev, uint64_t state_bytes,
@@ -309,45 +654,18 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
 {
     if (!out) return fail(SSD_E_PARAM, "out is NULL");
     *out = nullptr;
+    if (!p) return fail(SSD_E_PARAM, "params is NULL");
     int rc = validate(p);
     if (rc) return rc;
-    if (!tables_host) return fail(SSD_E_PARAM, "tables_host is NULL");
-    const Layout L = layout(p);
-    const uint64_t need_state = ((uint64_t)p->r << p->q) * p->eta;
-    if (!state_dev || state_bytes < need_state || ((uintptr_t)state_dev & 15u))
-        return fail(SSD_E_NOMEM, "state buffer needs %llu bytes, 16-byte aligned", (unsigned long long)need_state);
-    if (!scratch_dev || scratch_bytes < L.total || ((uintptr_t)scratch_dev & (ALIGN - 1)))
-        return fail(SSD_E_NOMEM, "scratch buffer needs %llu bytes, 256-byte aligned", (unsigned long long)L.total);
     ssd_detector* d = new (std::nothrow) ssd_detector();
     if (!d) return fail(SSD_E_NOMEM, "host allocation failed");
-    d->p = *p;
-    d->L = L;
-    d->T = hot_threshold(p->eta, p->theta);
-    d->log2eta = log2u(p->eta);
-    d->clock = 0;
-    d->state = static_cast<uint8_t*>(state_dev);
-    d->scratch = static_cast<uint8_t*>(scratch_dev);
-    d->stream = static_cast<hipStream_t>(stream);
-    d->broken = false;
-    d->pass_bytes = DEFAULT_PASS_BYTES;
-    d->sort_block_limit = SORT_SMALL;
-    d->have_last = false;
-    d->last_reported = 0;
-    d->timing = false;
-    for (uint32_t i = 0; i < SSD_PHASES; i++) { d->ph_ms[i] = 0; d->ph_launches[i] = 0; }
-    memcpy(d->tables_host, tables_host, sizeof d->tables_host);
-    hipError_t e = hipGetDevice(&d->device);
-    if (e != hipSuccess) { rc = dev_fail(d, e, "hipGetDevice"); delete d; return rc; }
-    e = hipHostMalloc((void**)&d->mailbox, sizeof(Ctl) + PREFIX_MAX * sizeof(SuperPointDev), hipHostMallocDefault);
-    if (e != hipSuccess) { rc = dev_fail(d, e, "hipHostMalloc"); delete d; return rc; }
-    uint32_t* tab_stage = reinterpret_cast<uint32_t*>(d->mailbox + 1);   // 8 KiB fits the prefix area
-    memcpy(tab_stage, tables_host, 2048 * 4);
-    // every cell starts empty (Sec. 3.2: initialised once)
-    e = launch_fill_u32(reinterpret_cast<uint32_t*>(d->state), need_state / 4, 0u, d->stream);
-    if (e == hipSuccess) e = launch_fill_u32(d->at<uint32_t>(0), L.total / 4, 0u, d->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d->at<uint32_t>(L.tables), tab_stage, 2048 * 4, hipMemcpyHostToDevice, d->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
-    if (e != hipSuccess) { rc = dev_fail(d, e, "init"); (void)hipHostFree(d->mailbox); delete d; return rc; }
+    rc = engine_init(&d->e, p, 1, tables_host, state_dev, state_bytes, scratch_dev, scratch_bytes, stream, 0, 0,
+                     PREFIX_MAX);
+    if (rc) {
+        engine_release(&d->e);
+        delete d;
+        return rc;
+    }
     *out = d;
     return SSD_OK;
 }
@@ -355,10 +673,7 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
 void ssd_destroy(ssd_detector* d)
 {
     if (!d) return;
-    (void)hipSetDevice(d->device);
-    if (!d->broken) (void)hipStreamSynchronize(d->stream);
-    if (d->mailbox) (void)hipHostFree(d->mailbox);
-    for (hipEvent_t e : d->ev_pool) (void)hipEventDestroy(e);
+    engine_release(&d->e);
     delete d;
 }
 
@@ -367,343 +682,500 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
     switch (knob) {
     case SSD_TUNE_SCAN_PASS_BYTES: d->pass_bytes = value; return SSD_OK;
-    case SSD_TUNE_TIMING: d->timing = value != 0; return SSD_OK;
-    case SSD_TUNE_SORT_BLOCK_LIMIT:
+    case SSD_TUNE_TIMING: d->e.timing = value != 0; return SSD_OK;
+    case SSD_TUNE_SORT_BLOCK_LIMIT: {
         if (value > SORT_SMALL) return fail(SSD_E_PARAM, "sort block limit above %u", SORT_SMALL);
-        d->sort_block_limit = value;
+        int rc = usable(&d->e);
+        if (rc) return rc;
+        d->e.hl[0].sort_limit = value;
+        HIPCHK(&d->e, hipMemcpyAsync(&d->e.dev_links()[0].sort_limit, &d->e.hl[0].sort_limit, 8,
+                                     hipMemcpyHostToDevice, d->e.stream));
+        HIPCHK(&d->e, hipStreamSynchronize(d->e.stream));
         return SSD_OK;
+    }
     default: return fail(SSD_E_PARAM, "unknown tuning knob %u", knob);
     }
 }
 
 int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint64_t slice_id)
 {
-    int rc = usable(d);
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
-    if (slice_id != d->clock)
+    if (slice_id != e->clock)
         return fail(SSD_E_ORDER, "scan of slice %llu while slice %llu is open", (unsigned long long)slice_id,
-                    (unsigned long long)d->clock);
+                    (unsigned long long)e->clock);
     if (n == 0) return SSD_OK;
     if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
+    const LinkDesc& D = d->D();
     ScanArgs a{};
     a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
     a.n = n;
-    a.state = d->state;
-    a.tables = d->at<uint32_t>(d->L.tables);
-    a.q = d->p.q;
-    a.r = d->p.r;
-    a.delta = d->p.delta;
-    a.log2eta = d->log2eta;
-    a.stamp = stamp_of(d->clock);
+    a.state = D.state;
+    a.tables = D.tables;
+    a.q = D.q; a.r = D.r; a.delta = D.delta; a.log2eta = D.log2eta;
+    a.stamp = stamp_of(e->clock);
     // passes over estimator windows of about pass_bytes each
-    const uint64_t n_se = d->n_se();
-    const uint64_t se_bytes = d->p.eta;
+    const uint64_t n_se = D.n_se;
     uint64_t per_pass = n_se;
-    if (d->pass_bytes) {
-        per_pass = d->pass_bytes / se_bytes;
-        if (per_pass < 1) per_pass = 1;
-    }
-    PhaseMark pm = phase_begin(d);
+    if (d->pass_bytes) per_pass = std::max<uint64_t>(1, d->pass_bytes / D.eta);
+    PhaseMark pm = phase_begin(e);
     uint32_t launches = 0;
     for (uint64_t lo = 0; lo < n_se; lo += per_pass) {
         a.se_lo = lo;
-        a.se_hi = lo + per_pass < n_se ? lo + per_pass : n_se;
-        HIPCHK(d, launch_scan(a, d->stream));
+        a.se_hi = std::min(lo + per_pass, n_se);
+        HIPCHK(e, launch_scan(a, e->stream));
         launches++;
     }
-    phase_end(d, pm, 0, launches);
+    phase_end(e, pm, 0, launches);
     return SSD_OK;
 }
 
 int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, uint64_t cap, uint64_t* n_out)
 {
-    int rc = usable(d);
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
     if (flags & ~SSD_ADVANCE_ONLY) return fail(SSD_E_PARAM, "unknown close flags 0x%x", flags);
     if (n_out) *n_out = 0;
-    const ssd_params& p = d->p;
     if (flags & SSD_ADVANCE_ONLY) {
-        DetectArgs da = detect_args(d, false);
-        if (da.n_waves) HIPCHK(d, launch_hot_detect(da, d->stream));
-        d->clock++;
-        d->results.clear();
-        d->have_last = false;
+        rc = enqueue_advance_only(e);
+        if (rc) return rc;
+        e->clock++;
+        e->results[0].clear();
+        e->have_last = false;
         return SSD_OK;
     }
-    const hipStream_t s = d->stream;
-    Ctl* ctl = d->at<Ctl>(d->L.ctl);
-    // 1. R_k of every estimator, hot bits, rotating expiry
-    HIPCHK(d, launch_fill_u32(d->at<uint32_t>(d->L.hotbits), (d->L.hot_end - d->L.hotbits) / 4, 0u, s));
-    DetectArgs da = detect_args(d, true);
-    PhaseMark pm = phase_begin(d);
-    HIPCHK(d, launch_hot_detect(da, s));
-    phase_end(d, pm, 1, 1);
-    // 2. ascending hot lists
-    CompactArgs ca{};
-    ca.hotbits = d->at<uint64_t>(d->L.hotbits);
-    ca.hot_list = d->at<uint32_t>(d->L.hot_list);
-    ca.ctl = ctl;
-    ca.q = p.q;
-    pm = phase_begin(d);
-    HIPCHK(d, launch_hot_compact(ca, p.r, s));
-    phase_end(d, pm, 2, 1);
-    // 3. candidate levels: rows 0..2, then one row per level
-    ExpandArgs ea{};
-    ea.hot_list = ca.hot_list;
-    ea.hotT = d->at<uint64_t>(d->L.hotT);
-    ea.ctl = ctl;
-    ea.cap = p.max_tuples;
-    ea.q = p.q; ea.delta = p.delta; ea.nw = d->L.nw; ea.key_bits = p.key_bits;
-    ea.row = 2;
-    ea.out_x = d->at<uint64_t>(d->L.ctb_x[0]);
-    ea.out_h0 = d->at<uint32_t>(d->L.ctb_h0[0]);
-    pm = phase_begin(d);
-    HIPCHK(d, launch_expand0(ea, s));
-    for (uint32_t row = 3; row < p.r; row++) {
-        const uint32_t lvl = row - 2;
-        ea.row = row;
-        ea.in_x = d->at<uint64_t>(d->L.ctb_x[(lvl - 1) & 1]);
-        ea.in_h0 = d->at<uint32_t>(d->L.ctb_h0[(lvl - 1) & 1]);
-        ea.out_x = d->at<uint64_t>(d->L.ctb_x[lvl & 1]);
-        ea.out_h0 = d->at<uint32_t>(d->L.ctb_h0[lvl & 1]);
-        HIPCHK(d, launch_extend(ea, s));
-    }
-    phase_end(d, pm, 3, p.r - 2);
-    // 4. final test of every full tuple
-    const uint32_t lf = p.r - 3;
-    VerifyArgs va{};
-    va.state = d->state;
-    va.tables = d->at<uint32_t>(d->L.tables);
-    va.ctl = ctl;
-    va.in_x = d->at<uint64_t>(d->L.ctb_x[lf & 1]);
-    va.in_h0 = d->at<uint32_t>(d->L.ctb_h0[lf & 1]);
-    va.acc = d->at<unsigned long long>(d->L.acc);
-    va.cap = p.max_tuples;
-    va.max_results = p.max_results;
-    va.q = p.q; va.r = p.r; va.delta = p.delta; va.log2eta = d->log2eta;
-    va.chunks = p.eta / 16u; va.T = d->T; va.level = lf;
-    va.rehash = (p.flags & SSD_VERIFY_REHASH) ? 1u : 0u;
-    va.L = da.L;
-    pm = phase_begin(d);
-    HIPCHK(d, launch_verify(va, s));
-    phase_end(d, pm, 4, 1);
-    // 5. sort by ip, keep the largest R per ip, estimate (Eq. 1) -- in one
-    // block when the list is short; the control block and a prefix of the
-    // list come back with a single synchronisation
-    ReportArgs ra{};
-    ra.keys = d->at<unsigned long long>(d->L.acc);
-    ra.out = d->at<SuperPointDev>(d->L.out);
-    ra.ctl = ctl;
-    ra.eta = p.eta;
-    ra.limit = d->sort_block_limit < p.max_results ? d->sort_block_limit : p.max_results;
-    pm = phase_begin(d);
-    HIPCHK(d, launch_sort_small(ra, s));
-    phase_end(d, pm, 5, 1);
-    uint64_t prefix = 2 * d->last_reported + 64;
-    if (prefix > PREFIX_MAX) prefix = PREFIX_MAX;
-    if (prefix > p.max_results) prefix = p.max_results;
-    SuperPointDev* stage = reinterpret_cast<SuperPointDev*>(d->mailbox + 1);
-    HIPCHK(d, hipMemcpyAsync(d->mailbox, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIPCHK(d, hipMemcpyAsync(stage, ra.out, prefix * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
-    HIPCHK(d, hipStreamSynchronize(s));
-    phase_collect(d);
-    Ctl c = *d->mailbox;
-    d->clock++;
-    d->last = c;
-    d->have_last = true;
-    d->results.clear();
-    for (uint32_t l = 0; l <= lf; l++)
-        if (c.level_n[l] > p.max_tuples) {
-            d->last_reported = 0;
-            return fail(SSD_E_OVERFLOW, "candidate level %u holds %llu tuples > max_tuples %llu", l,
-                        (unsigned long long)c.level_n[l], (unsigned long long)p.max_tuples);
-        }
-    if (c.n_acc > p.max_results) {
+    const ssd_params& p = d->p();
+    const uint64_t prefix =
+        std::min<uint64_t>(std::min<uint64_t>(2 * d->last_reported + 64, PREFIX_MAX), p.max_results);
+    rc = enqueue_close(e, false, prefix);
+    if (rc) return rc;
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    phase_collect(e);
+    e->clock++;
+    rc = collect_results(e, false, prefix);
+    if (rc) return rc;
+    if (e->status[0] != SSD_OK) {
         d->last_reported = 0;
-        return fail(SSD_E_OVERFLOW, "%llu accepted hosts > max_results %llu", (unsigned long long)c.n_acc,
-                    (unsigned long long)p.max_results);
+        const Ctl& c = e->last[0];
+        if (c.n_acc > p.max_results)
+            return fail(SSD_E_OVERFLOW, "%llu accepted hosts > max_results %llu", (unsigned long long)c.n_acc,
+                        (unsigned long long)p.max_results);
+        return fail(SSD_E_OVERFLOW, "a candidate level exceeded max_tuples %llu", (unsigned long long)p.max_tuples);
     }
-    const SuperPointDev* src = stage;
-    if (c.n_acc > ra.limit) {
-        // long list: multi-kernel sort, then the whole list
-        pm = phase_begin(d);
-        HIPCHK(d, launch_sort_large(ra, d->at<unsigned long long>(d->L.sort_tmp), c.n_acc, s));
-        phase_end(d, pm, 5, 1);
-        d->staging.resize(c.n_acc);
-        HIPCHK(d, hipMemcpyAsync(d->mailbox, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIPCHK(d, hipMemcpyAsync(d->staging.data(), ra.out, c.n_acc * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
-        HIPCHK(d, hipStreamSynchronize(s));
-        phase_collect(d);
-        c.n_out = d->mailbox->n_out;
-        src = d->staging.data();
-    } else if (c.n_out > prefix) {
-        d->staging.resize(c.n_out);
-        HIPCHK(d, hipMemcpyAsync(d->staging.data(), ra.out, c.n_out * sizeof(SuperPointDev), hipMemcpyDeviceToHost, s));
-        HIPCHK(d, hipStreamSynchronize(s));
-        src = d->staging.data();
-    }
-    const uint64_t m = c.n_out;
-    d->last.n_out = m;
-    d->last_reported = m;
-    d->results.resize(m);
-    for (uint64_t i = 0; i < m; i++) {
-        d->results[i].ip = src[i].ip;
-        d->results[i].rk = src[i].rk;
-        d->results[i].est = src[i].est;
-    }
+    d->last_reported = e->results[0].size();
     return ssd_get_results(d, out_host, cap, n_out);
 }
 
 int ssd_get_results(ssd_detector* d, ssd_super_point* out_host, uint64_t cap, uint64_t* n_out)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    const uint64_t m = d->results.size();
+    const auto& r = d->e.results[0];
+    const uint64_t m = r.size();
     if (n_out) *n_out = m;
     if (m > cap) return fail(SSD_E_TRUNC, "result list holds %llu entries, cap is %llu", (unsigned long long)m,
                              (unsigned long long)cap);
     if (m && !out_host) return fail(SSD_E_PARAM, "out_host is NULL");
-    if (m) memcpy(out_host, d->results.data(), m * sizeof(ssd_super_point));
+    if (m) memcpy(out_host, r.data(), m * sizeof(ssd_super_point));
     return SSD_OK;
 }
 
 int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32_t n)
 {
-    int rc = usable(g);
+    if (!g) return fail(SSD_E_PARAM, "detector is NULL");
+    int rc = usable(&g->e);
     if (rc) return rc;
     if (!routers || n < 1) return fail(SSD_E_PARAM, "need at least one router");
+    const ssd_params& gp = g->p();
     for (uint32_t j = 0; j < n; j++) {
         const ssd_detector* r = routers[j];
         if (!r) return fail(SSD_E_PARAM, "router %u is NULL", j);
         if (r == g) return fail(SSD_E_PARAM, "router %u is the global detector", j);
-        if (r->broken) return fail(SSD_E_STATE, "router %u is unusable", j);
-        if (r->p.q != g->p.q || r->p.r != g->p.r || r->p.delta != g->p.delta || r->p.eta != g->p.eta ||
-            r->p.k != g->p.k || r->p.key_bits != g->p.key_bits ||
-            memcmp(r->tables_host, g->tables_host, sizeof g->tables_host) != 0)
+        if (r->e.broken) return fail(SSD_E_STATE, "router %u is unusable", j);
+        const ssd_params& rp = r->p();
+        if (rp.q != gp.q || rp.r != gp.r || rp.delta != gp.delta || rp.eta != gp.eta || rp.k != gp.k ||
+            rp.key_bits != gp.key_bits || r->e.tables != g->e.tables)
             return fail(SSD_E_INCOMPAT, "router %u differs in geometry or hash tables", j);
-        if (r->clock != g->clock) return fail(SSD_E_INCOMPAT, "router %u is at slice %llu, global at %llu", j,
-                                              (unsigned long long)r->clock, (unsigned long long)g->clock);
-        if (r->device != g->device) return fail(SSD_E_INCOMPAT, "router %u is on another device", j);
+        if (r->e.clock != g->e.clock) return fail(SSD_E_INCOMPAT, "router %u is at slice %llu, global at %llu", j,
+                                                  (unsigned long long)r->e.clock, (unsigned long long)g->e.clock);
+        if (r->e.device != g->e.device) return fail(SSD_E_INCOMPAT, "router %u is on another device", j);
     }
     MergeArgs a{};
-    a.dst = g->state;
-    a.n16 = g->state_bytes() / 16u;
-    a.cur = stamp_of(g->clock);
-    a.k = g->p.k;
+    a.dst = g->D().state;
+    a.n16 = g->e.L.state_total / 16u;
+    a.cur = stamp_of(g->e.clock);
+    a.k = gp.k;
     // associative merge in batches; later batches fold the partial result in
     uint32_t done = 0, launches = 0;
-    PhaseMark pm = phase_begin(g);
+    PhaseMark pm = phase_begin(&g->e);
     while (done < n) {
         uint32_t m = 0;
-        if (done > 0) a.src[m++] = g->state;
-        while (m < MAX_MERGE_SOURCES && done < n) a.src[m++] = routers[done++]->state;
+        if (done > 0) a.src[m++] = g->D().state;
+        while (m < MAX_MERGE_SOURCES && done < n) a.src[m++] = routers[done++]->D().state;
         a.n_src = m;
-        HIPCHK(g, launch_merge(a, g->stream));
+        HIPCHK(&g->e, launch_merge(a, g->e.stream));
         launches++;
     }
-    phase_end(g, pm, 6, launches);
+    phase_end(&g->e, pm, 6, launches);
     return SSD_OK;
 }
 
 int ssd_read_canonical_state(ssd_detector* d, uint16_t* out_dev, uint64_t n_cells)
 {
-    int rc = usable(d);
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
-    const uint64_t n = d->state_bytes();
+    const uint64_t n = e->L.state_total;
     if (!out_dev || n_cells < n) return fail(SSD_E_NOMEM, "canonical state needs %llu cells", (unsigned long long)n);
-    HIPCHK(d, launch_canonical(d->state, out_dev, n, stamp_of(d->clock), d->p.k, d->stream));
-    HIPCHK(d, hipStreamSynchronize(d->stream));
+    HIPCHK(e, launch_canonical(d->D().state, out_dev, n, stamp_of(e->clock), d->p().k, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
     return SSD_OK;
 }
 
 int ssd_read_rk(ssd_detector* d, uint32_t* out_host, uint64_t n)
 {
-    int rc = usable(d);
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
-    if (!d->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
-    if (!out_host || n < d->n_se()) return fail(SSD_E_NOMEM, "R_k needs %llu entries", (unsigned long long)d->n_se());
-    HIPCHK(d, hipMemcpyAsync(out_host, d->at<uint32_t>(d->L.rk), d->n_se() * 4, hipMemcpyDeviceToHost, d->stream));
-    HIPCHK(d, hipStreamSynchronize(d->stream));
+    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
+    const uint64_t n_se = d->D().n_se;
+    if (!out_host || n < n_se) return fail(SSD_E_NOMEM, "R_k needs %llu entries", (unsigned long long)n_se);
+    HIPCHK(e, hipMemcpyAsync(out_host, d->D().rk, n_se * 4, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
     return SSD_OK;
 }
 
 int ssd_read_hot(ssd_detector* d, uint32_t* counts_host, uint32_t* lists_host, uint64_t cap)
 {
-    int rc = usable(d);
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
-    if (!d->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
+    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
     if (!counts_host) return fail(SSD_E_PARAM, "counts_host is NULL");
+    const Ctl& c = e->last[0];
     uint64_t total = 0;
-    for (uint32_t i = 0; i < d->p.r; i++) { counts_host[i] = d->last.hot_n[i]; total += d->last.hot_n[i]; }
+    for (uint32_t i = 0; i < d->p().r; i++) { counts_host[i] = c.hot_n[i]; total += c.hot_n[i]; }
     if (total > cap || (total && !lists_host)) return fail(SSD_E_TRUNC, "hot lists need %llu entries", (unsigned long long)total);
     uint64_t o = 0;
-    for (uint32_t i = 0; i < d->p.r; i++) {
-        if (d->last.hot_n[i])
-            HIPCHK(d, hipMemcpyAsync(lists_host + o, d->at<uint32_t>(d->L.hot_list) + ((uint64_t)i << d->p.q),
-                                     (uint64_t)d->last.hot_n[i] * 4, hipMemcpyDeviceToHost, d->stream));
-        o += d->last.hot_n[i];
+    for (uint32_t i = 0; i < d->p().r; i++) {
+        if (c.hot_n[i])
+            HIPCHK(e, hipMemcpyAsync(lists_host + o, d->D().hot_list + ((uint64_t)i << d->p().q),
+                                     (uint64_t)c.hot_n[i] * 4, hipMemcpyDeviceToHost, e->stream));
+        o += c.hot_n[i];
     }
-    HIPCHK(d, hipStreamSynchronize(d->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
     return SSD_OK;
 }
 
 int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t* n_out)
 {
-    int rc = usable(d);
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
-    if (!d->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
-    const uint32_t lf = d->p.r - 3;
-    uint64_t n = d->last.level_n[lf];
-    if (n > d->p.max_tuples) return fail(SSD_E_OVERFLOW, "the last close overflowed");
+    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
+    const ssd_params& p = d->p();
+    const uint32_t lf = p.r - 3;
+    const uint64_t n = e->last[0].level_n[lf];
+    if (e->status[0] != SSD_OK) return fail(SSD_E_OVERFLOW, "the last close overflowed");
     if (n_out) *n_out = n;
     if (n > cap) return fail(SSD_E_TRUNC, "%llu tuples, cap %llu", (unsigned long long)n, (unsigned long long)cap);
     if (!n) return SSD_OK;
     if (!out_host) return fail(SSD_E_PARAM, "out_host is NULL");
     std::vector<uint64_t> x(n);
     std::vector<uint32_t> h0(n);
-    HIPCHK(d, hipMemcpyAsync(x.data(), d->at<uint64_t>(d->L.ctb_x[lf & 1]), n * 8, hipMemcpyDeviceToHost, d->stream));
-    HIPCHK(d, hipMemcpyAsync(h0.data(), d->at<uint32_t>(d->L.ctb_h0[lf & 1]), n * 4, hipMemcpyDeviceToHost, d->stream));
-    HIPCHK(d, hipStreamSynchronize(d->stream));
+    HIPCHK(e, hipMemcpyAsync(x.data(), d->D().ctb_x[lf & 1], n * 8, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipMemcpyAsync(h0.data(), d->D().ctb_h0[lf & 1], n * 4, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
     // inspection only: expand the stored (he_0, regained bits) form to one column per row
-    const uint32_t qmask = (1u << d->p.q) - 1u;
+    const uint32_t qmask = (1u << p.q) - 1u;
     for (uint64_t t = 0; t < n; t++) {
-        uint32_t* o = out_host + t * d->p.r;
+        uint32_t* o = out_host + t * p.r;
         o[0] = h0[t];
-        for (uint32_t i = 1; i < d->p.r; i++) o[i] = ((uint32_t)(x[t] >> ((i - 1) * d->p.delta)) & qmask) ^ h0[t];
+        for (uint32_t i = 1; i < p.r; i++) o[i] = ((uint32_t)(x[t] >> ((i - 1) * p.delta)) & qmask) ^ h0[t];
     }
     return SSD_OK;
 }
 
 int ssd_read_timing(ssd_detector* d, double* ms_out, uint64_t* launches_out, int reset)
 {
-    int rc = usable(d);
-    if (rc) return rc;
-    HIPCHK(d, hipStreamSynchronize(d->stream));
-    phase_collect(d);
-    for (uint32_t i = 0; i < SSD_PHASES; i++) {
-        if (ms_out) ms_out[i] = d->ph_ms[i];
-        if (launches_out) launches_out[i] = d->ph_launches[i];
-        if (reset) { d->ph_ms[i] = 0; d->ph_launches[i] = 0; }
-    }
-    return SSD_OK;
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    return read_timing(&d->e, ms_out, launches_out, reset);
 }
 
 int ssd_get_info(ssd_detector* d, ssd_info* out)
 {
     if (!d || !out) return fail(SSD_E_PARAM, "NULL argument");
     memset(out, 0, sizeof *out);
-    out->open_slice = d->clock;
-    out->hot_threshold = d->T;
-    out->r = d->p.r;
-    out->state_bytes = d->state_bytes();
-    if (d->have_last) {
+    const Engine& e = d->e;
+    out->open_slice = e.clock;
+    out->hot_threshold = e.T[0];
+    out->r = d->p().r;
+    out->state_bytes = e.L.state_total;
+    if (e.have_last) {
         for (uint32_t i = 0; i < MAX_ROWS; i++) {
-            out->level_counts[i] = d->last.level_n[i];
-            out->hot_counts[i] = d->last.hot_n[i];
+            out->level_counts[i] = e.last[0].level_n[i];
+            out->hot_counts[i] = e.last[0].hot_n[i];
         }
-        out->accepted = d->last.n_acc;
-        out->reported = d->last.n_out;
+        out->accepted = e.last[0].n_acc;
+        out->reported = e.results[0].size();
     }
     return SSD_OK;
+}
+
+// ---- batch
+
+int ssd_batch_query_sizes(const ssd_params* p, uint32_t n, uint64_t* state_bytes, uint64_t* scratch_bytes)
+{
+    return engine_query(p, n, BATCH_STAGE, MAX_TILES, state_bytes, scratch_bytes);
+}
+
+int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host, void* state_dev,
+                   uint64_t state_bytes, void* scratch_dev, uint64_t scratch_bytes, void* stream, ssd_batch** out)
+{
+    if (!out) return fail(SSD_E_PARAM, "out is NULL");
+    *out = nullptr;
+    int rc = engine_query(p, n, BATCH_STAGE, MAX_TILES, nullptr, nullptr);
+    if (rc) return rc;
+    ssd_batch* b = new (std::nothrow) ssd_batch();
+    if (!b) return fail(SSD_E_NOMEM, "host allocation failed");
+    rc = engine_init(&b->e, p, n, tables_host, state_dev, state_bytes, scratch_dev, scratch_bytes, stream,
+                     BATCH_STAGE, MAX_TILES, BATCH_STAGE);
+    if (rc == SSD_OK) {
+        b->e.use_graph = true;
+        for (int i = 0; i < 2 && rc == SSD_OK; i++) {
+            hipError_t err = hipHostMalloc(&b->tile_pinned[i], 8 + MAX_TILES * sizeof(ScanTile), hipHostMallocDefault);
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&b->tile_done[i], hipEventDisableTiming);
+            if (err != hipSuccess) rc = dev_fail(&b->e, err, "batch staging");
+        }
+        hipDeviceProp_t prop;
+        if (rc == SSD_OK && hipGetDeviceProperties(&prop, b->e.device) == hipSuccess)
+            b->scan_blocks = (uint32_t)prop.multiProcessorCount * 8u;
+    }
+    if (rc) {
+        for (int i = 0; i < 2; i++) {
+            if (b->tile_pinned[i]) (void)hipHostFree(b->tile_pinned[i]);
+            if (b->tile_done[i]) (void)hipEventDestroy(b->tile_done[i]);
+        }
+        engine_release(&b->e);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SSD_OK;
+}
+
+void ssd_batch_destroy(ssd_batch* b)
+{
+    if (!b) return;
+    engine_release(&b->e);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    for (auto& ev : b->tune_events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    for (int i = 0; i < 2; i++) {
+        if (b->tile_pinned[i]) (void)hipHostFree(b->tile_pinned[i]);
+        if (b->tile_done[i]) (void)hipEventDestroy(b->tile_done[i]);
+    }
+    delete b;
+}
+
+int ssd_batch_set_tuning(ssd_batch* b, uint32_t knob, uint64_t value)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    switch (knob) {
+    case SSD_TUNE_SCAN_PASS_BYTES: b->pass_bytes = value; return SSD_OK;
+    case SSD_TUNE_SCAN_TILE_PAIRS:
+        if (value < 256) return fail(SSD_E_PARAM, "tile pairs below 256");
+        b->tile_pairs = value;
+        return SSD_OK;
+    case SSD_TUNE_TIMING: b->e.timing = value != 0; return SSD_OK;
+    case SSD_TUNE_GRAPH: b->e.use_graph = value != 0; return SSD_OK;
+    case SSD_TUNE_AUTOTUNE:
+        if (!value) { b->tune_idx = -1; return SSD_OK; }
+        b->cands.clear();
+        for (uint64_t pass : {64ull << 20, 128ull << 20, 256ull << 20, 0ull})
+            for (uint64_t tile : {65536ull, 262144ull, 1048576ull}) b->cands.push_back({pass, tile, -1.0});
+        b->tune_idx = 0;
+        return SSD_OK;
+    default: return fail(SSD_E_PARAM, "unknown tuning knob %u", knob);
+    }
+}
+
+int ssd_batch_get_tuning(ssd_batch* b, uint32_t knob, uint64_t* value)
+{
+    if (!b || !value) return fail(SSD_E_PARAM, "NULL argument");
+    switch (knob) {
+    case SSD_TUNE_SCAN_PASS_BYTES: *value = b->pass_bytes; return SSD_OK;
+    case SSD_TUNE_SCAN_TILE_PAIRS: *value = b->tile_pairs; return SSD_OK;
+    case SSD_TUNE_TIMING: *value = b->e.timing; return SSD_OK;
+    case SSD_TUNE_GRAPH: *value = b->e.use_graph; return SSD_OK;
+    case SSD_TUNE_AUTOTUNE: *value = b->tune_idx >= 0; return SSD_OK;
+    default: return fail(SSD_E_PARAM, "unknown tuning knob %u", knob);
+    }
+}
+
+int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offsets_host, uint64_t slice_id)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    Engine* e = &b->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (slice_id != e->clock)
+        return fail(SSD_E_ORDER, "scan of slice %llu while slice %llu is open", (unsigned long long)slice_id,
+                    (unsigned long long)e->clock);
+    if (!offsets_host) return fail(SSD_E_PARAM, "offsets_host is NULL");
+    for (uint32_t l = 0; l < e->n; l++)
+        if (offsets_host[l + 1] < offsets_host[l]) return fail(SSD_E_PARAM, "offsets decrease at link %u", l);
+    const uint64_t total_pairs = offsets_host[e->n] - offsets_host[0];
+    if (total_pairs == 0) return SSD_OK;
+    if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
+    uint64_t pass = b->pass_bytes, tile = b->tile_pairs;
+    int cand = -1;
+    if (b->tune_idx >= 0 && b->tune_idx < (int)b->cands.size()) {
+        cand = b->tune_idx++;
+        pass = b->cands[cand].pass;
+        tile = b->cands[cand].tile;
+    }
+    // windows of every link's state, ordered by address, then pair tiles per window
+    struct Win { uint64_t at; uint32_t link; uint64_t lo, hi; };
+    std::vector<Win> wins;
+    for (uint32_t l = 0; l < e->n; l++) {
+        if (offsets_host[l + 1] == offsets_host[l]) continue;
+        const LinkDesc& D = e->hl[l];
+        const uint64_t per = pass ? std::max<uint64_t>(1, pass / D.eta) : D.n_se;
+        for (uint64_t lo = 0; lo < D.n_se; lo += per)
+            wins.push_back({e->L.link[l].state_off + lo * D.eta, l, lo, std::min(lo + per, D.n_se)});
+    }
+    auto count_tiles = [&](uint64_t tp) {
+        uint64_t nt = 0;
+        for (const Win& w : wins) nt += (offsets_host[w.link + 1] - offsets_host[w.link] + tp - 1) / tp;
+        return nt;
+    };
+    while (count_tiles(tile) > MAX_TILES) tile *= 2;      // coarser tiles until the list fits
+    std::sort(wins.begin(), wins.end(), [](const Win& a, const Win& c) { return a.at < c.at; });
+    const uint32_t buf = b->tile_next;
+    b->tile_next ^= 1u;
+    if (b->tile_used[buf]) HIPCHK(e, hipEventSynchronize(b->tile_done[buf]));   // its last copy has run
+    unsigned long long* counter = static_cast<unsigned long long*>(b->tile_pinned[buf]);
+    ScanTile* tiles = reinterpret_cast<ScanTile*>(counter + 1);
+    *counter = 0;
+    uint64_t t = 0;
+    for (const Win& w : wins) {
+        const uint64_t base = offsets_host[w.link], np = offsets_host[w.link + 1] - base;
+        for (uint64_t st = 0; st < np; st += tile) {
+            ScanTile& T = tiles[t++];
+            T.link = w.link;
+            T.pad = 0;
+            T.start = base + st;
+            T.n = std::min(tile, np - st);
+            T.se_lo = w.lo;
+            T.se_hi = w.hi;
+        }
+    }
+    unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
+    HIPCHK(e, hipMemcpyAsync(dcounter, counter, 8 + t * sizeof(ScanTile), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipEventRecord(b->tile_done[buf], e->stream));
+    b->tile_used[buf] = true;
+    TileScanArgs a{};
+    a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
+    a.links = e->dev_links();
+    a.tiles = reinterpret_cast<const ScanTile*>(dcounter + 1);
+    a.counter = dcounter;
+    a.n_tiles = t;
+    a.stamp = stamp_of(e->clock);
+    hipEvent_t ta = nullptr, tb = nullptr;
+    if (cand >= 0) {
+        HIPCHK(e, hipEventCreate(&ta));
+        HIPCHK(e, hipEventCreate(&tb));
+        HIPCHK(e, hipEventRecord(ta, e->stream));
+    }
+    PhaseMark pm = phase_begin(e);
+    HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(b->scan_blocks, t), e->stream));
+    phase_end(e, pm, 0, 1);
+    if (cand >= 0) {
+        HIPCHK(e, hipEventRecord(tb, e->stream));
+        b->tune_pending.push_back({cand, total_pairs});
+        b->tune_events.push_back({ta, tb});
+    }
+    return SSD_OK;
+}
+
+int ssd_batch_close(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host, int* status_host)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    Engine* e = &b->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (e->use_graph) {
+        if (!e->gexec) {
+            // record on a stream of our own (the caller's may be the legacy
+            // default stream, which cannot be captured); replay on the caller's
+            if (!b->capture_stream)
+                HIPCHK(e, hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+            const hipStream_t caller = e->stream;
+            e->stream = b->capture_stream;
+            hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal);
+            if (err != hipSuccess) { e->stream = caller; return dev_fail(e, err, "hipStreamBeginCapture"); }
+            rc = enqueue_close(e, true, 0);
+            hipGraph_t g = nullptr;
+            err = hipStreamEndCapture(e->stream, &g);
+            e->stream = caller;
+            if (rc) return rc;
+            if (err != hipSuccess) return dev_fail(e, err, "hipStreamEndCapture");
+            e->graph = g;
+            HIPCHK(e, hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0));
+        }
+        PhaseMark pm = phase_begin(e);
+        HIPCHK(e, hipGraphLaunch(e->gexec, e->stream));
+        phase_end(e, pm, 7, 1);
+    } else {
+        rc = enqueue_close(e, true, 0);
+        if (rc) return rc;
+    }
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    phase_collect(e);
+    autotune_collect(b);
+    e->clock++;
+    rc = collect_results(e, true, 0);
+    if (rc) return rc;
+    return ssd_batch_get_results(b, out_host, cap, counts_host, status_host);
+}
+
+int ssd_batch_get_results(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host,
+                          int* status_host)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    const Engine& e = b->e;
+    uint64_t total = 0;
+    for (uint32_t l = 0; l < e.n; l++) {
+        if (counts_host) counts_host[l] = e.results[l].size();
+        if (status_host) status_host[l] = e.status[l];
+        total += e.results[l].size();
+    }
+    if (total > cap) return fail(SSD_E_TRUNC, "result lists hold %llu entries, cap is %llu",
+                                 (unsigned long long)total, (unsigned long long)cap);
+    if (total && !out_host) return fail(SSD_E_PARAM, "out_host is NULL");
+    uint64_t o = 0;
+    for (uint32_t l = 0; l < e.n; l++) {
+        if (!e.results[l].empty())
+            memcpy(out_host + o, e.results[l].data(), e.results[l].size() * sizeof(ssd_super_point));
+        o += e.results[l].size();
+    }
+    return SSD_OK;
+}
+
+int ssd_batch_read_timing(ssd_batch* b, double* ms_out, uint64_t* launches_out, int reset)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    return read_timing(&b->e, ms_out, launches_out, reset);
 }
 
 }  // extern "C"

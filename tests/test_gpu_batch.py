@@ -1,0 +1,95 @@
+"""Batched detectors: many links scanned by one persistent launch and closed by
+one replayed HIP graph must give, link by link and slice by slice, exactly the
+lists of separate detectors fed the same pairs -- and, for small links, the
+oracle's lists."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1803_11036_amd as ssd
+import tracegen as tg
+from _parity import log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(c, **kw):
+    return ssd.make_params(q=c.q, r=c.r, delta=c.delta, eta=c.eta, k=c.k, theta=c.theta, **kw)
+
+
+def _slice_pairs(traces, t):
+    per = [tr.pairs(0, t % tr.cfg.n_slices) for tr in traces]
+    offs = np.zeros(len(per) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([p.shape[0] for p in per])
+    return per, offs, to_dev(np.concatenate(per))
+
+
+@pytest.mark.parametrize("graph,autotune", [(1, 0), (0, 0), (1, 1)])
+def test_batch_equals_separate_detectors(graph, autotune):
+    cfgs = tg.batch_configs(n_links=64, pairs_scale=0.02)
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    b = ssd.batch_init([_params(c) for c in cfgs], tabs, device="cuda:0")
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_GRAPH, graph)
+    if autotune:
+        ssd.batch_set_tuning(b, ssd.SSD_TUNE_AUTOTUNE, 1)
+    # small windows so that 4 scans cover several tiles per link
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_SCAN_PASS_BYTES, 64 << 20)
+    plain = [ssd.init_detector(_params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    small = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta <= 64 << 20][:3]
+    orcs = {i: oracle.RSEA(cfgs[i].q, cfgs[i].r, cfgs[i].delta, cfgs[i].eta, cfgs[i].k, cfgs[i].theta, tabs[i])
+            for i in small}
+    n_slices = 14 if autotune else 6
+    total = 0
+    for t in range(n_slices):
+        per, offs, dev = _slice_pairs(traces, t)
+        ssd.batch_scan(b, dev, offs, t)
+        lists, status = ssd.batch_close(b)
+        assert np.all(status == 0)
+        for i in range(len(cfgs)):
+            ssd.scan_slice(plain[i], dev[int(offs[i]):int(offs[i + 1])], t)
+            res = ssd.close_slice(plain[i])
+            assert np.array_equal(lists[i], res), f"slice {t} link {i}: batch and separate detector differ"
+            total += len(res)
+        for i, o in orcs.items():
+            o.scan(per[i])
+            ip, rk, est = o.close()
+            assert np.array_equal(lists[i]["ip"], ip) and np.array_equal(lists[i]["rk"], rk)
+            assert np.all(np.abs(lists[i]["est"] - est) <= 1e-6 * np.abs(est))
+        log(f"batch graph={graph} autotune={autotune} slice {t}: {sum(len(x) for x in lists)} hosts")
+    assert total > 100
+    if autotune:
+        assert ssd.batch_get_tuning(b, ssd.SSD_TUNE_AUTOTUNE) == 0        # finished, a candidate kept
+    b.destroy()
+    for d in plain:
+        d.destroy()
+
+
+def test_batch_overflow_is_per_link():
+    """Links whose candidate capacity is exceeded report SSD_E_OVERFLOW and
+    nothing else; every other link still matches its separate detector."""
+    cfgs = tg.batch_configs(n_links=8, pairs_scale=0.02)
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    params = [_params(c) if i == 0 else _params(c, max_tuples=1) for i, c in enumerate(cfgs)]
+    b = ssd.batch_init(params, tabs, device="cuda:0")
+    ref = [ssd.init_detector(_params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    overflowed = 0
+    for t in range(6):
+        per, offs, dev = _slice_pairs(traces, t)
+        ssd.batch_scan(b, dev, offs, t)
+        lists, status = ssd.batch_close(b)
+        assert status[0] == 0
+        for i in range(len(cfgs)):
+            ssd.scan_slice(ref[i], dev[int(offs[i]):int(offs[i + 1])], t)
+            res = ssd.close_slice(ref[i])
+            if status[i] == 0:
+                assert np.array_equal(lists[i], res), f"slice {t} link {i}"
+            else:
+                assert status[i] == -4 and len(lists[i]) == 0
+                overflowed += 1
+    assert overflowed > 0
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.batch_scan(b, dev, offs, 99)
+    assert e.value.status == -3

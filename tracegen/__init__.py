@@ -21,8 +21,9 @@ available here, so these traces stand in for it; Sec. 5):
 
 * a host set with a heavy-tailed window degree ``d_h`` (rank-Zipf or Pareto);
 * each host owns a fixed pool of ``d_h`` random peers split into ``k`` chunks
-  by index mod ``k``; slice ``s`` emits chunk ``s mod k``, so a host active for
-  a whole window has exactly ``d_h`` distinct peers in it;
+  by (index + a per-host offset) mod ``k``; slice ``s`` emits chunk ``s mod
+  k``, so a host active for a whole window has exactly ``d_h`` distinct peers
+  in it, and the hosts' first peers spread evenly over the slices;
 * planted super points with their own pools, some active only in a slice
   range so that they enter and leave mid-window;
 * each slice is filled to exactly ``N`` pairs with repeats drawn uniformly
@@ -43,7 +44,7 @@ import numpy as np
 
 __all__ = [
     "GAMMA", "splitmix64", "splitmix64_mix", "hash_tables", "TraceConfig",
-    "CONFIGS", "Trace", "config",
+    "CONFIGS", "Trace", "config", "batch_configs",
 ]
 
 GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -182,6 +183,43 @@ def config(name: str, **overrides) -> TraceConfig:
     return dataclasses.replace(CONFIGS[name], **overrides)
 
 
+_BATCH_GEOMETRIES = [(12, 6, 5), (13, 6, 5), (14, 5, 6), (15, 5, 6), (16, 6, 4)]
+_BATCH_THETAS = [512, 1024, 2048, 4096, 8192]
+
+
+def batch_configs(n_links: int = 64, seed: int = 0x55D00003, pairs_scale: float = 1.0,
+                  load: float = 0.25) -> List[TraceConfig]:
+    """Independent monitored links of uneven rates, windows and thresholds:
+    pairs per slice log-uniform in [0.2M, 8M] (times pairs_scale), k uniform in
+    4..64, theta in {512, ..., 8192}, geometry (q, r, delta) one of five sets
+    covering 2^12..2^16 columns, eta = the power of two >= max(1024, theta),
+    a Pareto(1.2) host population sized so that a window carries about
+    load * 2^q * theta distinct pairs (and at most half the window's pairs),
+    plus a few planted super points."""
+    out = []
+    for l in range(n_links):
+        u = _uniform01(_key(seed, 0xBA7C4, l), np.arange(8))
+        N = int(round(math.exp(math.log(200_000) + u[0] * math.log(40.0)) * pairs_scale))
+        N = max(N, 2000)
+        k = 4 + int(u[1] * 61)
+        theta = _BATCH_THETAS[min(4, int(u[2] * 5))]
+        q, r, delta = _BATCH_GEOMETRIES[min(4, int(u[3] * 5))]
+        eta = 1024
+        while eta < theta:
+            eta *= 2
+        window_distinct = min(load * (1 << q) * theta, 0.5 * N * k)
+        hosts = max(100, int(window_distinct / 5.1))
+        n_planted = 5 + int(u[4] * 46)
+        n_planted = max(1, min(n_planted, int(0.2 * N * k / (2.5 * theta))))
+        out.append(TraceConfig(
+            name=f"batched_link{l}", n_streams=1, n_slices=k + 8, pairs_lo=N, pairs_hi=N,
+            k=k, theta=theta, q=q, r=r, delta=delta, eta=eta, n_hosts=hosts, degree_law="pareto",
+            pareto_alpha=1.2, degree_cap=max(1000, int(0.05 * window_distinct)),
+            n_planted=n_planted, planted_lo=int(1.5 * theta), planted_hi=4 * theta,
+            seed=seed ^ ((l + 1) << 20), hash_seed=1 + l))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # trace generation
 
@@ -258,6 +296,9 @@ class Trace:
         self.n_pairs = (c.pairs_lo + np.floor(u * (c.pairs_hi - c.pairs_lo + 1))).astype(np.int64)
         self.n_pairs = np.minimum(self.n_pairs, c.pairs_hi)
         self._peer_key = _key(c.seed, _P_PEER, 0)
+        # per-host chunk offset: spreads every host's first peers over the k slices
+        self.chunk_offset = (_rand64(_key(c.seed, _P_ACT, 1), np.arange(self.n_all))
+                             % _U64(c.k)).astype(np.int64)
 
     # peers of host h: pool index p in [0, degree[h])
     def _peer(self, host: np.ndarray, p: np.ndarray) -> np.ndarray:
@@ -268,15 +309,16 @@ class Trace:
         """Hosts, pool indices and routers of every distinct pair of slice s."""
         c = self.cfg
         k = c.k
-        s0 = s % k
+        # host h emits pool index p in slice s iff (p + offset_h) = s (mod k)
+        s0 = (s - self.chunk_offset) % k
         act = (self.start <= s) & (s < self.end) & (self.degree > s0)
         hosts = np.nonzero(act)[0]
-        cnt = (self.degree[hosts] - s0 + k - 1) // k        # pool indices p = s0 + k*j
+        cnt = (self.degree[hosts] - s0[hosts] + k - 1) // k      # p = s0_h + k*j
         tot = int(cnt.sum())
         h = np.repeat(hosts, cnt)
         first = np.cumsum(cnt) - cnt
         j = np.arange(tot, dtype=np.int64) - np.repeat(first, cnt)
-        p = s0 + k * j
+        p = s0[h] + k * j
         if c.n_streams > 1:
             # deal the chunk's peers round-robin over the host's routers
             m = self.route_m[h]
@@ -331,3 +373,25 @@ class Trace:
 
     def planted_ips(self) -> np.ndarray:
         return self.ip[self.cfg.n_hosts:]
+
+    def pairs_device(self, stream: int, s: int, device, n: Optional[int] = None):
+        """The slice's N pairs built on a torch device: the same distinct pairs
+        as ``pairs``, with the repeats and the shuffle drawn by a torch Philox
+        generator keyed like ``pairs`` (fast; a different but equally seeded
+        arrangement).  Returns an int32 (N, 2) tensor on ``device``."""
+        import torch
+        c = self.cfg
+        d = self.distinct(stream, s)
+        N = int(self.n_pairs[stream]) if n is None else int(n)
+        D = d.shape[0]
+        if D == 0 or N == 0:
+            return torch.zeros((0, 2), dtype=torch.int32, device=device)
+        if D > N:
+            raise ValueError(f"slice {s} of stream {stream} has {D} distinct pairs > {N}")
+        g = torch.Generator(device=device)
+        g.manual_seed(int(_key(c.seed, _P_PERM, stream, s)) & 0x7FFFFFFFFFFFFFFF)
+        dd = torch.from_numpy(d.view(np.int32)).to(device)
+        rep = torch.randint(0, D, (N - D,), generator=g, device=device)
+        idx = torch.cat([torch.arange(D, device=device), rep])
+        perm = torch.randperm(N, generator=g, device=device)
+        return dd[idx[perm]].contiguous()
