@@ -191,7 +191,7 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_TUNE_SCAN_PASS_BYTES 1u
 #define SSD_TUNE_SORT_BLOCK_LIMIT 2u
 #define SSD_TUNE_TIMING 3u          /* 1: time every phase with HIP events */
-#define SSD_TUNE_SCAN_TILE_PAIRS 4u /* batches: pairs per scan work tile (default 262144) */
+#define SSD_TUNE_SCAN_TILE_PAIRS 4u /* batches: pairs per scan work tile (default 4096) */
 #define SSD_TUNE_GRAPH 5u           /* batches: 1 (default) = replay the close as a HIP graph */
 #define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = time the candidate (pass window, tile)
                                        pairs on the next scans and keep the fastest */

@@ -71,19 +71,22 @@ struct ScanArgs {
     uint32_t stamp;
 };
 
-// persistent batched scan: tiles of one link's pairs and one estimator window
-struct ScanTile {
+// persistent batched scan: one estimator window of one link and that link's
+// pairs, cut into tiles of `tile` pairs; windows are ordered by state address
+struct ScanWindow {
     uint32_t link, pad;
-    uint64_t start, n;            // pairs [start, start + n) of the batch buffer
+    uint64_t start, n;            // the link's pairs [start, start + n) of the batch buffer
     uint64_t se_lo, se_hi;        // estimator window of the link
+    uint64_t tile_base;           // tiles before this window
 };
 
 struct TileScanArgs {
     const uint2* pairs;
     const LinkDesc* links;
-    const ScanTile* tiles;
+    const ScanWindow* wins;
     unsigned long long* counter;  // next tile; zero before the launch
-    uint64_t n_tiles;
+    uint32_t n_wins;
+    uint64_t n_tiles, tile;
     uint32_t stamp;
 };
 

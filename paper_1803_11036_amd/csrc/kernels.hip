@@ -205,11 +205,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
                   (uint8_t)a.stamp);
 }
 
-// Persistent scan over many links: workgroups pull tiles (one link's pair
-// range and one estimator window) from a device counter.  Tiles are ordered by
-// window, so concurrent tiles store into the same cache-sized state range; a
-// workgroup reloads the tabulation tables only when its link changes.  Every
-// workgroup leaves once the counter passes the last tile.
+// Persistent scan over many links: workgroups pull tile numbers from a device
+// counter; a tile is `tile` pairs of one link restricted to one estimator
+// window, found by binary search over the windows' tile prefix.  Windows are
+// ordered by state address and tiles are small, so the tiles in flight store
+// into a cache-sized range of state; a workgroup reloads the tabulation
+// tables only when its link changes.  Every workgroup leaves once the counter
+// passes the last tile.
 __global__ __launch_bounds__(256) void k_scan_tiles(TileScanArgs a)
 {
     __shared__ uint32_t tab[2048];
@@ -221,19 +223,27 @@ __global__ __launch_bounds__(256) void k_scan_tiles(TileScanArgs a)
         const unsigned long long t = next;
         __syncthreads();
         if (t >= a.n_tiles) break;
-        const ScanTile T = a.tiles[t];
-        const LinkDesc* D = a.links + T.link;
-        if (T.link != loaded) {
+        uint32_t lo = 0, hi = a.n_wins;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.wins[mid].tile_base <= t) lo = mid;
+            else hi = mid;
+        }
+        const ScanWindow W = a.wins[lo];
+        const uint64_t first = W.start + (t - W.tile_base) * a.tile;
+        const uint64_t last = min(first + a.tile, W.start + W.n);
+        const LinkDesc* D = a.links + W.link;
+        if (W.link != loaded) {
             for (uint32_t i = threadIdx.x; i < 2048u; i += 256u) tab[i] = D->tables[i];
             __syncthreads();
-            loaded = T.link;
+            loaded = W.link;
         }
         const uint32_t q = D->q, delta = D->delta, log2eta = D->log2eta;
         uint8_t* state = D->state;
-        const uint32_t row_lo = (uint32_t)(T.se_lo >> q);
-        const uint32_t row_hi = (uint32_t)((T.se_hi - 1) >> q) + 1u;
-        for (uint64_t p = T.start + threadIdx.x; p < T.start + T.n; p += 256u)
-            scan_pair(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, T.se_lo, T.se_hi, (uint8_t)a.stamp);
+        const uint32_t row_lo = (uint32_t)(W.se_lo >> q);
+        const uint32_t row_hi = (uint32_t)((W.se_hi - 1) >> q) + 1u;
+        for (uint64_t p = first + threadIdx.x; p < last; p += 256u)
+            scan_pair(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, W.se_lo, W.se_hi, (uint8_t)a.stamp);
     }
 }
 

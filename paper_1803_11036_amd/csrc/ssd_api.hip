@@ -56,8 +56,8 @@ constexpr uint32_t PREFIX_MAX = SORT_SMALL;       // result entries staged in pi
 // the 256 MB Infinity Cache (measured best of 64..768 MiB on the core-link
 // workload; one pass when the state is smaller).
 constexpr uint64_t DEFAULT_PASS_BYTES = 128ull << 20;
-constexpr uint64_t DEFAULT_TILE_PAIRS = 262144;
-constexpr uint64_t MAX_TILES = 65536;             // batched scan work tiles per call
+constexpr uint64_t DEFAULT_TILE_PAIRS = 4096;
+constexpr uint64_t MAX_WINDOWS = 65536;           // batched scan windows per call
 constexpr uint64_t BATCH_STAGE = 16384;           // result entries staged by the batch graph
 constexpr uint32_t N_PHASES = SSD_PHASES;
 
@@ -124,7 +124,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     L.level_prefix = o; o = align_up(o + (n + 1) * 8);
     L.clock = o; o = align_up(o + sizeof(Clock));
     L.pack_offsets = o; o = align_up(o + (n + 1) * 8);
-    L.tiles = o; o = align_up(o + 8 + tile_cap * sizeof(ScanTile));
+    L.tiles = o; o = align_up(o + 8 + tile_cap * sizeof(ScanWindow));
     for (uint32_t l = 0; l < n; l++) { L.link[l].tables = o; o += 2048 * 4; }
     o = align_up(o);
     L.ctl = o;
@@ -573,7 +573,7 @@ struct ssd_batch {
     Engine e;
     uint64_t pass_bytes = DEFAULT_PASS_BYTES;
     uint64_t tile_pairs = DEFAULT_TILE_PAIRS;
-    // pinned double-buffered tile lists for the persistent scan
+    // pinned double-buffered window lists for the persistent scan
     void* tile_pinned[2] = {nullptr, nullptr};
     hipEvent_t tile_done[2] = {nullptr, nullptr};
     bool tile_used[2] = {false, false};
@@ -933,7 +933,7 @@ int ssd_get_info(ssd_detector* d, ssd_info* out)
 
 int ssd_batch_query_sizes(const ssd_params* p, uint32_t n, uint64_t* state_bytes, uint64_t* scratch_bytes)
 {
-    return engine_query(p, n, BATCH_STAGE, MAX_TILES, state_bytes, scratch_bytes);
+    return engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, state_bytes, scratch_bytes);
 }
 
 int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host, void* state_dev,
@@ -941,16 +941,16 @@ int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host,
 {
     if (!out) return fail(SSD_E_PARAM, "out is NULL");
     *out = nullptr;
-    int rc = engine_query(p, n, BATCH_STAGE, MAX_TILES, nullptr, nullptr);
+    int rc = engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, nullptr, nullptr);
     if (rc) return rc;
     ssd_batch* b = new (std::nothrow) ssd_batch();
     if (!b) return fail(SSD_E_NOMEM, "host allocation failed");
     rc = engine_init(&b->e, p, n, tables_host, state_dev, state_bytes, scratch_dev, scratch_bytes, stream,
-                     BATCH_STAGE, MAX_TILES, BATCH_STAGE);
+                     BATCH_STAGE, MAX_WINDOWS, BATCH_STAGE);
     if (rc == SSD_OK) {
         b->e.use_graph = true;
         for (int i = 0; i < 2 && rc == SSD_OK; i++) {
-            hipError_t err = hipHostMalloc(&b->tile_pinned[i], 8 + MAX_TILES * sizeof(ScanTile), hipHostMallocDefault);
+            hipError_t err = hipHostMalloc(&b->tile_pinned[i], 8 + MAX_WINDOWS * sizeof(ScanWindow), hipHostMallocDefault);
             if (err == hipSuccess) err = hipEventCreateWithFlags(&b->tile_done[i], hipEventDisableTiming);
             if (err != hipSuccess) rc = dev_fail(&b->e, err, "batch staging");
         }
@@ -1001,8 +1001,8 @@ int ssd_batch_set_tuning(ssd_batch* b, uint32_t knob, uint64_t value)
     case SSD_TUNE_AUTOTUNE:
         if (!value) { b->tune_idx = -1; return SSD_OK; }
         b->cands.clear();
-        for (uint64_t pass : {64ull << 20, 128ull << 20, 256ull << 20, 0ull})
-            for (uint64_t tile : {65536ull, 262144ull, 1048576ull}) b->cands.push_back({pass, tile, -1.0});
+        for (uint64_t pass : {64ull << 20, 128ull << 20, 256ull << 20})
+            for (uint64_t tile : {1024ull, 4096ull, 16384ull}) b->cands.push_back({pass, tile, -1.0});
         b->tune_idx = 0;
         return SSD_OK;
     default: return fail(SSD_E_PARAM, "unknown tuning knob %u", knob);
@@ -1044,7 +1044,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
         pass = b->cands[cand].pass;
         tile = b->cands[cand].tile;
     }
-    // windows of every link's state, ordered by address, then pair tiles per window
+    // windows of every link's state, ordered by address; tiles are implicit
     struct Win { uint64_t at; uint32_t link; uint64_t lo, hi; };
     std::vector<Win> wins;
     for (uint32_t l = 0; l < e->n; l++) {
@@ -1054,42 +1054,40 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
         for (uint64_t lo = 0; lo < D.n_se; lo += per)
             wins.push_back({e->L.link[l].state_off + lo * D.eta, l, lo, std::min(lo + per, D.n_se)});
     }
-    auto count_tiles = [&](uint64_t tp) {
-        uint64_t nt = 0;
-        for (const Win& w : wins) nt += (offsets_host[w.link + 1] - offsets_host[w.link] + tp - 1) / tp;
-        return nt;
-    };
-    while (count_tiles(tile) > MAX_TILES) tile *= 2;      // coarser tiles until the list fits
+    if (wins.size() > MAX_WINDOWS) return fail(SSD_E_PARAM, "scan pass window too small: %zu windows", wins.size());
     std::sort(wins.begin(), wins.end(), [](const Win& a, const Win& c) { return a.at < c.at; });
     const uint32_t buf = b->tile_next;
     b->tile_next ^= 1u;
     if (b->tile_used[buf]) HIPCHK(e, hipEventSynchronize(b->tile_done[buf]));   // its last copy has run
     unsigned long long* counter = static_cast<unsigned long long*>(b->tile_pinned[buf]);
-    ScanTile* tiles = reinterpret_cast<ScanTile*>(counter + 1);
+    ScanWindow* ws = reinterpret_cast<ScanWindow*>(counter + 1);
     *counter = 0;
-    uint64_t t = 0;
-    for (const Win& w : wins) {
-        const uint64_t base = offsets_host[w.link], np = offsets_host[w.link + 1] - base;
-        for (uint64_t st = 0; st < np; st += tile) {
-            ScanTile& T = tiles[t++];
-            T.link = w.link;
-            T.pad = 0;
-            T.start = base + st;
-            T.n = std::min(tile, np - st);
-            T.se_lo = w.lo;
-            T.se_hi = w.hi;
-        }
+    uint64_t tiles = 0;
+    for (size_t i = 0; i < wins.size(); i++) {
+        const Win& w = wins[i];
+        ScanWindow& W = ws[i];
+        W.link = w.link;
+        W.pad = 0;
+        W.start = offsets_host[w.link];
+        W.n = offsets_host[w.link + 1] - W.start;
+        W.se_lo = w.lo;
+        W.se_hi = w.hi;
+        W.tile_base = tiles;
+        tiles += (W.n + tile - 1) / tile;
     }
     unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
-    HIPCHK(e, hipMemcpyAsync(dcounter, counter, 8 + t * sizeof(ScanTile), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipMemcpyAsync(dcounter, counter, 8 + wins.size() * sizeof(ScanWindow), hipMemcpyHostToDevice,
+                             e->stream));
     HIPCHK(e, hipEventRecord(b->tile_done[buf], e->stream));
     b->tile_used[buf] = true;
     TileScanArgs a{};
     a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
     a.links = e->dev_links();
-    a.tiles = reinterpret_cast<const ScanTile*>(dcounter + 1);
+    a.wins = reinterpret_cast<const ScanWindow*>(dcounter + 1);
     a.counter = dcounter;
-    a.n_tiles = t;
+    a.n_wins = (uint32_t)wins.size();
+    a.n_tiles = tiles;
+    a.tile = tile;
     a.stamp = stamp_of(e->clock);
     hipEvent_t ta = nullptr, tb = nullptr;
     if (cand >= 0) {
@@ -1098,7 +1096,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
         HIPCHK(e, hipEventRecord(ta, e->stream));
     }
     PhaseMark pm = phase_begin(e);
-    HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(b->scan_blocks, t), e->stream));
+    HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(b->scan_blocks, tiles), e->stream));
     phase_end(e, pm, 0, 1);
     if (cand >= 0) {
         HIPCHK(e, hipEventRecord(tb, e->stream));
