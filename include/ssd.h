@@ -259,6 +259,36 @@ int ssd_batch_get_tuning(ssd_batch *b, uint32_t knob, uint64_t *value);
 int ssd_batch_read_timing(ssd_batch *b, double *ms_out, uint64_t *launches_out, int reset);
 void ssd_batch_destroy(ssd_batch *b);
 
+/* ---- Groups: continuous batching over independent detectors ---------------
+ *
+ * A group runs one batched scan launch, or one batched close sequence, over
+ * any set of single detectors (each with its own parameters, tables, memory
+ * and slot clock), chosen afresh at every call.  A serving loop uses it to
+ * scan every stream whose packets have arrived, and to close every stream
+ * whose slot has ended, in one launch each while streams come and go.  Every
+ * member's results equal those of its own ssd_scan_slice / ssd_close_slice.
+ * Members must live on the group's device and use the group's stream; the
+ * group's scratch (caller-owned device memory) holds the members'
+ * descriptors and staging. */
+typedef struct ssd_group ssd_group;
+
+int ssd_group_query_sizes(uint32_t max_members, uint64_t *scratch_bytes);
+int ssd_group_init(uint32_t max_members, void *scratch_dev, uint64_t scratch_bytes, void *stream, ssd_group **out);
+
+/* Scan into the open slice of every member: member i's pairs are
+ * pairs_dev[offsets_host[i] .. offsets_host[i+1]); slice_ids_host[i] must
+ * equal member i's open slice (SSD_E_ORDER).  Asynchronous. */
+int ssd_group_scan(ssd_group *g, ssd_detector *const *members, uint32_t n, const uint32_t *pairs_dev,
+                   const uint64_t *offsets_host, const uint64_t *slice_ids_host);
+
+/* Close the open slice of every member (each advances by one slot); lists
+ * one after another in out_host, counts_host[i] / status_host[i] as for
+ * ssd_batch_close.  A member's list is also kept as its own last result
+ * (ssd_get_results). */
+int ssd_group_close(ssd_group *g, ssd_detector *const *members, uint32_t n, ssd_super_point *out_host,
+                    uint64_t cap, uint64_t *counts_host, int *status_host);
+void ssd_group_destroy(ssd_group *g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ __all__ = [
     "SSD_TUNE_SCAN_TILE_PAIRS", "SSD_TUNE_GRAPH", "SSD_TUNE_AUTOTUNE", "PHASES",
     "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
     "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_destroy",
+    "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_destroy",
     "library_path", "RESULT_DTYPE",
 ]
 
@@ -107,6 +108,12 @@ def _lib():
         L.ssd_batch_read_timing.argtypes = [vp, vp, vp, C.c_int]
         L.ssd_batch_destroy.argtypes = [vp]
         L.ssd_batch_destroy.restype = None
+        L.ssd_group_query_sizes.argtypes = [u32, u64p]
+        L.ssd_group_init.argtypes = [u32, vp, u64, vp, C.POINTER(vp)]
+        L.ssd_group_scan.argtypes = [vp, C.POINTER(vp), u32, vp, vp, vp]
+        L.ssd_group_close.argtypes = [vp, C.POINTER(vp), u32, vp, u64, vp, vp]
+        L.ssd_group_destroy.argtypes = [vp]
+        L.ssd_group_destroy.restype = None
         L.ssd_destroy.argtypes = [vp]
         L.ssd_destroy.restype = None
         L.ssd_strerror.argtypes = [C.c_int]
@@ -118,7 +125,8 @@ def _lib():
                      "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
                      "ssd_set_tuning", "ssd_read_timing", "ssd_batch_query_sizes", "ssd_batch_init",
                      "ssd_batch_scan", "ssd_batch_close", "ssd_batch_get_results", "ssd_batch_set_tuning",
-                     "ssd_batch_get_tuning", "ssd_batch_read_timing"):
+                     "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_group_query_sizes",
+                     "ssd_group_init", "ssd_group_scan", "ssd_group_close"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
     return _lib_handle
@@ -416,3 +424,90 @@ def batch_read_timing(b: Batch, reset: bool = False) -> Dict[str, Tuple[float, i
     n = np.zeros(len(PHASES), dtype=np.uint64)
     _check(_lib().ssd_batch_read_timing(b.handle, ms.ctypes.data, n.ctypes.data, int(reset)), "batch_read_timing")
     return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(PHASES)}
+
+
+# ---------------------------------------------------------------- groups
+
+def group_query_sizes(max_members: int) -> int:
+    v = C.c_uint64()
+    _check(_lib().ssd_group_query_sizes(max_members, C.byref(v)), "group_query_sizes")
+    return v.value
+
+
+class Group:
+    """Batched scan / close over any set of single detectors, chosen per call
+    (continuous batching).  Members must share its device and stream."""
+
+    def __init__(self, max_members: int, device=None, stream=None):
+        L = _lib()
+        self.max_members = max_members
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = group_query_sizes(max_members)
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.ssd_group_init(max_members, self.scratch.data_ptr(), nbytes, self.stream.cuda_stream,
+                                    C.byref(h)), "group_init")
+        self.handle = h
+
+    def destroy(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib().ssd_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def group_init(max_members: int, device=None, stream=None) -> Group:
+    return Group(max_members, device, stream)
+
+
+def group_destroy(g: Group) -> None:
+    g.destroy()
+
+
+def _members(dets: Sequence[Detector]):
+    return (C.c_void_p * len(dets))(*[d.handle.value for d in dets])
+
+
+def group_scan(g: Group, dets: Sequence[Detector], pairs: torch.Tensor, offsets: Sequence[int],
+               slice_ids: Sequence[int]) -> None:
+    """Member i's pairs are rows offsets[i]..offsets[i+1] of `pairs`, scanned
+    into its open slice slice_ids[i]."""
+    n = len(dets)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    ids = np.ascontiguousarray(slice_ids, dtype=np.uint64)
+    if off.shape != (n + 1,) or ids.shape != (n,):
+        raise ValueError("offsets needs n + 1 entries and slice_ids n")
+    if pairs.numel() and (pairs.device != g.scratch.device or pairs.element_size() != 4
+                          or not pairs.is_contiguous() or pairs.dim() != 2 or pairs.shape[1] != 2):
+        raise ValueError("pairs must be a contiguous (N, 2) 32-bit tensor on the group's device")
+    if int(off[-1]) > (pairs.shape[0] if pairs.dim() == 2 else 0):
+        raise ValueError("offsets run past the pairs tensor")
+    ptr = pairs.data_ptr() if pairs.numel() else None
+    _check(_lib().ssd_group_scan(g.handle, _members(dets), n, ptr, off.ctypes.data, ids.ctypes.data), "group_scan")
+
+
+def group_close(g: Group, dets: Sequence[Detector]):
+    """Close the open slice of every member: (per-member result arrays, status codes)."""
+    n = len(dets)
+    counts = np.zeros(n, dtype=np.uint64)
+    status = np.zeros(n, dtype=np.int32)
+    cap = 1 << 16
+    arr = _members(dets)
+    out = np.zeros(cap, dtype=RESULT_DTYPE)
+    st = _lib().ssd_group_close(g.handle, arr, n, out.ctypes.data, cap, counts.ctypes.data, status.ctypes.data)
+    if st == SSD_E_TRUNC:
+        # every member keeps its own list; fetch them one by one
+        return [get_results(d) for d in dets], status
+    _check(st, "group_close")
+    lists, o = [], 0
+    for c in counts.tolist():
+        lists.append(out[o:o + c].copy())
+        o += c
+    return lists, status

@@ -37,8 +37,13 @@ struct LiveCfg {
 // One detector ("link") as every close kernel sees it.  Device resident; the
 // per-slice fields are written by k_prepare from the device clock at the start
 // of every close, so a captured close replays with fixed arguments.
+struct Clock {
+    unsigned long long t;         // open slice
+};
+
 struct LinkDesc {
     uint8_t* state;
+    Clock* clock;                 // this link's slot clock (device)
     const uint32_t* tables;       // [2][4][256]
     uint32_t* rk;                 // [r][2^q]
     uint64_t* hotbits;            // [r][max(1, 2^q / 64)] row bitmasks of hot estimators
@@ -48,16 +53,14 @@ struct LinkDesc {
     uint32_t* ctb_h0[2];          //                    and he_0
     unsigned long long* acc;      // accepted keys
     SuperPointDev* out;           // result list
+    unsigned long long* sort_tmp; // scratch of the multi-kernel sort (may be shared)
     Ctl* ctl;
     uint64_t n_se, max_tuples, max_results, sort_limit;
+    uint64_t hot_words;           // u32 words of hotbits + hotT (cleared before every close)
     uint32_t q, r, delta, eta, log2eta, k, T, nw, key_bits, rehash;
     // per slice
     LiveCfg L;
     uint32_t expire_period, expire_phase;
-};
-
-struct Clock {
-    unsigned long long t;         // open slice
 };
 
 // direct scan of one detector, one pass window
@@ -78,6 +81,7 @@ struct ScanWindow {
     uint64_t start, n;            // the link's pairs [start, start + n) of the batch buffer
     uint64_t se_lo, se_hi;        // estimator window of the link
     uint64_t tile_base;           // tiles before this window
+    uint32_t stamp, pad2;         // the link's stamp for its open slice
 };
 
 struct TileScanArgs {
@@ -87,7 +91,6 @@ struct TileScanArgs {
     unsigned long long* counter;  // next tile; zero before the launch
     uint32_t n_wins;
     uint64_t n_tiles, tile;
-    uint32_t stamp;
 };
 
 struct DetectArgs {
@@ -122,8 +125,10 @@ struct PackArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
-hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, const Clock* clock, hipStream_t s);
-hipError_t launch_advance(Clock* clock, hipStream_t s);
+hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, hipStream_t s);
+hipError_t launch_advance(const LinkDesc* links, uint32_t n_links, hipStream_t s);
+hipError_t launch_clear_hot(const LinkDesc* links, uint32_t n_links, hipStream_t s);
+hipError_t launch_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);

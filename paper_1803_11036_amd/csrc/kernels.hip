@@ -148,12 +148,12 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-// Per-slice constants of every link from the device clock (the open slice t).
-__global__ void k_prepare(LinkDesc* links, uint32_t n_links, const Clock* clock)
+// Per-slice constants of every link from its device clock (the open slice t).
+__global__ void k_prepare(LinkDesc* links, uint32_t n_links)
 {
     const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n_links) return;
-    const unsigned long long t = clock->t;
+    const unsigned long long t = links[l].clock->t;
     const uint32_t k = links[l].k;
     const uint32_t cur = 1u + (uint32_t)(t % 255u);
     uint32_t lo, kp, wrap;
@@ -168,9 +168,27 @@ __global__ void k_prepare(LinkDesc* links, uint32_t n_links, const Clock* clock)
     links[l].expire_phase = (uint32_t)(t % (255u - k));
 }
 
-__global__ void k_advance(Clock* clock)
+__global__ void k_advance(const LinkDesc* links, uint32_t n_links)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) clock->t += 1ull;
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n_links) links[l].clock->t += 1ull;
+}
+
+// Copy every link's control block into one contiguous array (links whose
+// blocks live in separate allocations).
+__global__ void k_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst)
+{
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n_links) dst[l] = *links[l].ctl;
+}
+
+// Clear every link's hot bitmasks (grid: links x 16 blocks).
+__global__ __launch_bounds__(256) void k_clear_hot(const LinkDesc* links)
+{
+    const LinkDesc* D = links + blockIdx.x;
+    uint32_t* p = reinterpret_cast<uint32_t*>(D->hotbits);     // hotT follows hotbits
+    const uint64_t n = D->hot_words;
+    for (uint64_t i = blockIdx.y * 256u + threadIdx.x; i < n; i += 256u * gridDim.y) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- scan
@@ -243,7 +261,7 @@ __global__ __launch_bounds__(256) void k_scan_tiles(TileScanArgs a)
         const uint32_t row_lo = (uint32_t)(W.se_lo >> q);
         const uint32_t row_hi = (uint32_t)((W.se_hi - 1) >> q) + 1u;
         for (uint64_t p = first + threadIdx.x; p < last; p += 256u)
-            scan_pair(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, W.se_lo, W.se_hi, (uint8_t)a.stamp);
+            scan_pair(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, W.se_lo, W.se_hi, (uint8_t)W.stamp);
     }
 }
 
@@ -727,15 +745,27 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, const Clock* clock, hipStream_t s)
+hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, hipStream_t s)
 {
-    k_prepare<<<grid_for(n_links, 256, 64), 256, 0, s>>>(const_cast<LinkDesc*>(links), n_links, clock);
+    k_prepare<<<grid_for(n_links, 256, 64), 256, 0, s>>>(const_cast<LinkDesc*>(links), n_links);
     return hipGetLastError();
 }
 
-hipError_t launch_advance(Clock* clock, hipStream_t s)
+hipError_t launch_advance(const LinkDesc* links, uint32_t n_links, hipStream_t s)
 {
-    k_advance<<<1, 64, 0, s>>>(clock);
+    k_advance<<<grid_for(n_links, 256, 64), 256, 0, s>>>(links, n_links);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst, hipStream_t s)
+{
+    k_gather_ctl<<<grid_for(n_links, 256, 64), 256, 0, s>>>(links, n_links, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_hot(const LinkDesc* links, uint32_t n_links, hipStream_t s)
+{
+    k_clear_hot<<<dim3(n_links, 16), 256, 0, s>>>(links);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <string>
 #include <vector>
@@ -122,7 +123,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     L.se_prefix = o; o = align_up(o + (n + 1) * 8);
     L.row_table = o; o = align_up(o + rows * 4);
     L.level_prefix = o; o = align_up(o + (n + 1) * 8);
-    L.clock = o; o = align_up(o + sizeof(Clock));
+    L.clock = o; o = align_up(o + n * sizeof(Clock));       // one clock per link
     L.pack_offsets = o; o = align_up(o + (n + 1) * 8);
     L.tiles = o; o = align_up(o + 8 + tile_cap * sizeof(ScanWindow));
     for (uint32_t l = 0; l < n; l++) { L.link[l].tables = o; o += 2048 * 4; }
@@ -197,6 +198,7 @@ struct Engine {
     std::vector<Pending> pending;
     double ph_ms[N_PHASES] = {};
     uint64_t ph_launches[N_PHASES] = {};
+    bool gather_ctl = false;           // control blocks live with their links (groups)
     // graph replay of the close
     bool use_graph = false;
     hipGraph_t graph = nullptr;
@@ -355,7 +357,10 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
         }
         D.acc = e->at<unsigned long long>(K.acc);
         D.out = e->at<SuperPointDev>(K.out);
+        D.sort_tmp = e->at<unsigned long long>(e->L.sort_tmp);
         D.ctl = e->at<Ctl>(K.ctl);
+        D.clock = e->at<Clock>(e->L.clock) + l;
+        D.hot_words = (K.hotT - K.hotbits + (uint64_t)q.r * (1ull << (q.q - q.delta)) * nw_of(q) * 8) / 4;
         D.n_se = (uint64_t)q.r << q.q;
         D.max_tuples = q.max_tuples;
         D.max_results = q.max_results;
@@ -409,8 +414,8 @@ int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
     const bool t = e->timing && !e->use_graph;
     auto begin = [&]() { return t ? phase_begin(e) : PhaseMark(); };
     auto end = [&](PhaseMark m, uint32_t ph, uint32_t nl) { if (t) phase_end(e, m, ph, nl); };
-    HIPCHK(e, launch_prepare(links, e->n, e->at<Clock>(e->L.clock), s));
-    HIPCHK(e, launch_fill_u32(e->at<uint32_t>(e->L.hot_begin), (e->L.hot_end - e->L.hot_begin) / 4, 0u, s));
+    HIPCHK(e, launch_prepare(links, e->n, s));
+    HIPCHK(e, launch_clear_hot(links, e->n, s));
     DetectArgs da{};
     da.links = links;
     da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
@@ -444,6 +449,7 @@ int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
     pm = begin();
     HIPCHK(e, launch_sort_small(links, e->n, s));
     end(pm, 5, 1);
+    if (e->gather_ctl) HIPCHK(e, launch_gather_ctl(links, e->n, e->at<Ctl>(e->L.ctl), s));
     HIPCHK(e, hipMemcpyAsync(e->mb_ctl, e->at<Ctl>(e->L.ctl), e->n * sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (pack) {
         PackArgs pa{};
@@ -460,7 +466,7 @@ int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
         HIPCHK(e, hipMemcpyAsync(e->mb_stage, e->hl[0].out, single_prefix * sizeof(SuperPointDev),
                                  hipMemcpyDeviceToHost, s));
     }
-    HIPCHK(e, launch_advance(e->at<Clock>(e->L.clock), s));
+    HIPCHK(e, launch_advance(links, e->n, s));
     return SSD_OK;
 }
 
@@ -487,8 +493,7 @@ int collect_results(Engine* e, bool packed, uint64_t single_prefix)
         if (c.n_acc > e->hl[l].sort_limit) {
             // long list: multi-kernel sort of this link, then its whole list
             PhaseMark pm = phase_begin(e);
-            HIPCHK(e, launch_sort_large(e->dev_links() + l, e->hl[l], e->at<unsigned long long>(e->L.sort_tmp),
-                                        c.n_acc, s));
+            HIPCHK(e, launch_sort_large(e->dev_links() + l, e->hl[l], e->hl[l].sort_tmp, c.n_acc, s));
             phase_end(e, pm, 5, 1);
             e->staging.resize(c.n_acc);
             HIPCHK(e, hipMemcpyAsync(&e->mb_ctl[l], e->hl[l].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -528,7 +533,7 @@ int enqueue_advance_only(Engine* e)
 {
     const hipStream_t s = e->stream;
     LinkDesc* links = e->dev_links();
-    HIPCHK(e, launch_prepare(links, e->n, e->at<Clock>(e->L.clock), s));
+    HIPCHK(e, launch_prepare(links, e->n, s));
     DetectArgs da{};
     da.links = links;
     da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
@@ -537,7 +542,7 @@ int enqueue_advance_only(Engine* e)
     const uint64_t period = 255u - e->p[0].k;
     da.total = (e->hl[0].n_se + period - 1) / period;
     HIPCHK(e, launch_hot_detect(da, e->max_chunks, s));
-    HIPCHK(e, launch_advance(e->at<Clock>(e->L.clock), s));
+    HIPCHK(e, launch_advance(links, e->n, s));
     return SSD_OK;
 }
 
@@ -559,8 +564,11 @@ int read_timing(Engine* e, double* ms_out, uint64_t* launches_out, int reset)
 
 // ---------------------------------------------------------------- single detector
 
+std::atomic<uint64_t> g_next_detector_id{1};
+
 struct ssd_detector {
     Engine e;
+    uint64_t id = g_next_detector_id.fetch_add(1);   // unique for the process: host addresses get reused
     uint64_t pass_bytes = DEFAULT_PASS_BYTES;
     uint64_t last_reported = 0;
     const ssd_params& p() const { return e.p[0]; }
@@ -617,6 +625,84 @@ void autotune_collect(ssd_batch* b)
         b->tile_pairs = b->cands[best].tile;
         b->tune_idx = -1;
     }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- group
+
+struct ssd_group {
+    Engine e;                          // header-only engine over the bound members
+    uint32_t max_members = 0;
+    std::vector<uint64_t> bound;       // ids of the members whose descriptors are on the device
+};
+
+namespace {
+
+Layout plan_group(uint32_t max_members)
+{
+    Layout L;
+    uint64_t o = 0;
+    L.links = o; o = align_up(o + max_members * sizeof(LinkDesc));
+    L.se_prefix = o; o = align_up(o + (max_members + 1) * 8);
+    L.row_table = o; o = align_up(o + (uint64_t)max_members * MAX_ROWS * 4);
+    L.level_prefix = o; o = align_up(o + (max_members + 1) * 8);
+    L.pack_offsets = o; o = align_up(o + (max_members + 1) * 8);
+    L.tiles = o; o = align_up(o + 8 + MAX_WINDOWS * sizeof(ScanWindow));
+    L.ctl = o; o = align_up(o + max_members * sizeof(Ctl));    // unused: members' own blocks are read
+    L.packed = o; o = align_up(o + BATCH_STAGE * sizeof(SuperPointDev));
+    L.total = o;
+    L.pack_cap = BATCH_STAGE;
+    L.tile_cap = MAX_WINDOWS;
+    return L;
+}
+
+// Point the group's descriptors at these members (uploads only on change).
+int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
+{
+    Engine* e = &g->e;
+    if (!m || n < 1 || n > g->max_members) return fail(SSD_E_PARAM, "need 1..%u members", g->max_members);
+    bool same = g->bound.size() == n;
+    for (uint32_t i = 0; i < n; i++) {
+        if (!m[i]) return fail(SSD_E_PARAM, "member %u is NULL", i);
+        if (m[i]->e.broken) return fail(SSD_E_STATE, "member %u is unusable", i);
+        if (m[i]->e.device != e->device) return fail(SSD_E_INCOMPAT, "member %u is on another device", i);
+        if (m[i]->e.stream != e->stream) return fail(SSD_E_INCOMPAT, "member %u uses another stream", i);
+        for (uint32_t j = 0; j < i; j++)
+            if (m[j] == m[i]) return fail(SSD_E_PARAM, "member %u appears twice", i);
+        same = same && g->bound[i] == m[i]->id;
+    }
+    if (same) return SSD_OK;
+    e->n = n;
+    e->p.resize(n);
+    e->T.resize(n);
+    e->hl.resize(n);
+    e->max_r = 0;
+    e->max_chunks = 1;
+    std::vector<uint64_t> se_prefix(n + 1, 0);
+    std::vector<uint32_t> row_table;
+    for (uint32_t i = 0; i < n; i++) {
+        e->p[i] = m[i]->e.p[0];
+        e->T[i] = m[i]->e.T[0];
+        e->hl[i] = m[i]->e.hl[0];
+        se_prefix[i + 1] = se_prefix[i] + e->hl[i].n_se;
+        for (uint32_t r = 0; r < e->p[i].r; r++) row_table.push_back((i << 8) | r);
+        e->max_r = std::max(e->max_r, e->p[i].r);
+        e->max_chunks = std::max(e->max_chunks, e->p[i].eta >> 10);
+    }
+    e->se_total = se_prefix[n];
+    e->rows_total = (uint32_t)row_table.size();
+    HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice,
+                             e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->at<uint32_t>(e->L.row_table), row_table.data(), row_table.size() * 4,
+                             hipMemcpyHostToDevice, e->stream));
+    g->bound.resize(n);
+    for (uint32_t i = 0; i < n; i++) g->bound[i] = m[i]->id;
+    e->results.assign(n, {});
+    e->status.assign(n, SSD_OK);
+    e->last.assign(n, Ctl{});
+    return SSD_OK;
 }
 
 }  // namespace
@@ -1073,6 +1159,8 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
         W.se_lo = w.lo;
         W.se_hi = w.hi;
         W.tile_base = tiles;
+        W.stamp = stamp_of(e->clock);
+        W.pad2 = 0;
         tiles += (W.n + tile - 1) / tile;
     }
     unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
@@ -1088,7 +1176,6 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
     a.n_wins = (uint32_t)wins.size();
     a.n_tiles = tiles;
     a.tile = tile;
-    a.stamp = stamp_of(e->clock);
     hipEvent_t ta = nullptr, tb = nullptr;
     if (cand >= 0) {
         HIPCHK(e, hipEventCreate(&ta));
@@ -1174,6 +1261,162 @@ int ssd_batch_read_timing(ssd_batch* b, double* ms_out, uint64_t* launches_out, 
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
     return read_timing(&b->e, ms_out, launches_out, reset);
+}
+
+// ---- group
+
+int ssd_group_query_sizes(uint32_t max_members, uint64_t* scratch_bytes)
+{
+    if (max_members < 1 || max_members > MAX_LINKS) return fail(SSD_E_PARAM, "max_members outside 1..%u", MAX_LINKS);
+    if (scratch_bytes) *scratch_bytes = plan_group(max_members).total;
+    return SSD_OK;
+}
+
+int ssd_group_init(uint32_t max_members, void* scratch_dev, uint64_t scratch_bytes, void* stream, ssd_group** out)
+{
+    if (!out) return fail(SSD_E_PARAM, "out is NULL");
+    *out = nullptr;
+    if (max_members < 1 || max_members > MAX_LINKS) return fail(SSD_E_PARAM, "max_members outside 1..%u", MAX_LINKS);
+    const Layout L = plan_group(max_members);
+    if (!scratch_dev || scratch_bytes < L.total || ((uintptr_t)scratch_dev & (ALIGN - 1)))
+        return fail(SSD_E_NOMEM, "scratch buffer needs %llu bytes, 256-byte aligned", (unsigned long long)L.total);
+    ssd_group* g = new (std::nothrow) ssd_group();
+    if (!g) return fail(SSD_E_NOMEM, "host allocation failed");
+    Engine* e = &g->e;
+    g->max_members = max_members;
+    e->gather_ctl = true;
+    e->L = L;
+    e->scratch = static_cast<uint8_t*>(scratch_dev);
+    e->stream = static_cast<hipStream_t>(stream);
+    e->stage_cap = BATCH_STAGE;
+    hipError_t err = hipGetDevice(&e->device);
+    if (err == hipSuccess)
+        err = hipHostMalloc(&e->pinned, max_members * sizeof(Ctl) + BATCH_STAGE * sizeof(SuperPointDev) +
+                                            (max_members + 1) * 8, hipHostMallocDefault);
+    if (err != hipSuccess) {
+        int rc = dev_fail(e, err, "group init");
+        delete g;
+        return rc;
+    }
+    e->mb_ctl = static_cast<Ctl*>(e->pinned);
+    e->mb_stage = reinterpret_cast<SuperPointDev*>(e->mb_ctl + max_members);
+    e->mb_offsets = reinterpret_cast<unsigned long long*>(e->mb_stage + BATCH_STAGE);
+    *out = g;
+    return SSD_OK;
+}
+
+void ssd_group_destroy(ssd_group* g)
+{
+    if (!g) return;
+    engine_release(&g->e);
+    delete g;
+}
+
+int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const uint32_t* pairs_dev,
+                   const uint64_t* offsets_host, const uint64_t* slice_ids_host)
+{
+    if (!g) return fail(SSD_E_PARAM, "group is NULL");
+    Engine* e = &g->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (!offsets_host || !slice_ids_host) return fail(SSD_E_PARAM, "offsets or slice ids NULL");
+    rc = group_bind(g, members, n);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < n; i++) {
+        if (offsets_host[i + 1] < offsets_host[i]) return fail(SSD_E_PARAM, "offsets decrease at member %u", i);
+        if (slice_ids_host[i] != members[i]->e.clock)
+            return fail(SSD_E_ORDER, "member %u: scan of slice %llu while slice %llu is open", i,
+                        (unsigned long long)slice_ids_host[i], (unsigned long long)members[i]->e.clock);
+    }
+    if (offsets_host[n] == offsets_host[0]) return SSD_OK;
+    if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
+    // windows of every member's state (its own pass window), in member order
+    std::vector<ScanWindow> ws;
+    uint64_t tiles = 0;
+    const uint64_t tile = DEFAULT_TILE_PAIRS;
+    ws.push_back({});   // slot for the counter (8 bytes) ahead of the windows
+    for (uint32_t i = 0; i < n; i++) {
+        const uint64_t np = offsets_host[i + 1] - offsets_host[i];
+        if (!np) continue;
+        const LinkDesc& D = e->hl[i];
+        const uint64_t pass = members[i]->pass_bytes;
+        const uint64_t per = pass ? std::max<uint64_t>(1, pass / D.eta) : D.n_se;
+        for (uint64_t lo = 0; lo < D.n_se; lo += per) {
+            ScanWindow W{};
+            W.link = i;
+            W.start = offsets_host[i];
+            W.n = np;
+            W.se_lo = lo;
+            W.se_hi = std::min(lo + per, D.n_se);
+            W.tile_base = tiles;
+            W.stamp = stamp_of(members[i]->e.clock);
+            tiles += (np + tile - 1) / tile;
+            ws.push_back(W);
+        }
+    }
+    const uint64_t n_wins = ws.size() - 1;
+    if (n_wins > MAX_WINDOWS) return fail(SSD_E_PARAM, "too many scan windows (%llu)", (unsigned long long)n_wins);
+    // the device block is [counter (8 bytes)][windows]; the first vector entry only supplies the zero counter
+    unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
+    const unsigned long long zero = 0;
+    HIPCHK(e, hipMemcpyAsync(dcounter, &zero, 8, hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipMemcpyAsync(dcounter + 1, ws.data() + 1, n_wins * sizeof(ScanWindow), hipMemcpyHostToDevice,
+                             e->stream));
+    TileScanArgs a{};
+    a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
+    a.links = e->dev_links();
+    a.wins = reinterpret_cast<const ScanWindow*>(dcounter + 1);
+    a.counter = dcounter;
+    a.n_wins = (uint32_t)n_wins;
+    a.n_tiles = tiles;
+    a.tile = tile;
+    hipDeviceProp_t prop;
+    uint32_t blocks = 2048;
+    if (hipGetDeviceProperties(&prop, e->device) == hipSuccess) blocks = (uint32_t)prop.multiProcessorCount * 8u;
+    PhaseMark pm = phase_begin(e);
+    HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(blocks, tiles), e->stream));
+    phase_end(e, pm, 0, 1);
+    return SSD_OK;
+}
+
+int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_super_point* out_host,
+                    uint64_t cap, uint64_t* counts_host, int* status_host)
+{
+    if (!g) return fail(SSD_E_PARAM, "group is NULL");
+    Engine* e = &g->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    rc = group_bind(g, members, n);
+    if (rc) return rc;
+    rc = enqueue_close(e, true, 0);
+    if (rc) return rc;
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    phase_collect(e);
+    rc = collect_results(e, true, 0);
+    if (rc) return rc;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        Engine& me = members[i]->e;
+        me.clock++;
+        me.results[0] = e->results[i];
+        me.status[0] = e->status[i];
+        me.last[0] = e->last[i];
+        me.have_last = true;
+        members[i]->last_reported = e->results[i].size();
+        if (counts_host) counts_host[i] = e->results[i].size();
+        if (status_host) status_host[i] = e->status[i];
+        total += e->results[i].size();
+    }
+    if (total > cap) return fail(SSD_E_TRUNC, "result lists hold %llu entries, cap is %llu",
+                                 (unsigned long long)total, (unsigned long long)cap);
+    if (total && !out_host) return fail(SSD_E_PARAM, "out_host is NULL");
+    uint64_t o = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        if (!e->results[i].empty())
+            memcpy(out_host + o, e->results[i].data(), e->results[i].size() * sizeof(ssd_super_point));
+        o += e->results[i].size();
+    }
+    return SSD_OK;
 }
 
 }  // extern "C"

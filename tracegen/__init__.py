@@ -44,7 +44,7 @@ import numpy as np
 
 __all__ = [
     "GAMMA", "splitmix64", "splitmix64_mix", "hash_tables", "TraceConfig",
-    "CONFIGS", "Trace", "config", "batch_configs",
+    "CONFIGS", "Trace", "config", "batch_configs", "ServedStream", "served_workload",
 ]
 
 GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -188,7 +188,7 @@ _BATCH_THETAS = [512, 1024, 2048, 4096, 8192]
 
 
 def batch_configs(n_links: int = 64, seed: int = 0x55D00003, pairs_scale: float = 1.0,
-                  load: float = 0.25) -> List[TraceConfig]:
+                  load: float = 0.25, max_window_distinct: float = float("inf")) -> List[TraceConfig]:
     """Independent monitored links of uneven rates, windows and thresholds:
     pairs per slice log-uniform in [0.2M, 8M] (times pairs_scale), k uniform in
     4..64, theta in {512, ..., 8192}, geometry (q, r, delta) one of five sets
@@ -207,7 +207,7 @@ def batch_configs(n_links: int = 64, seed: int = 0x55D00003, pairs_scale: float 
         eta = 1024
         while eta < theta:
             eta *= 2
-        window_distinct = min(load * (1 << q) * theta, 0.5 * N * k)
+        window_distinct = min(load * (1 << q) * theta, 0.5 * N * k, max_window_distinct)
         hosts = max(100, int(window_distinct / 5.1))
         n_planted = 5 + int(u[4] * 46)
         n_planted = max(1, min(n_planted, int(0.2 * N * k / (2.5 * theta))))
@@ -374,6 +374,16 @@ class Trace:
     def planted_ips(self) -> np.ndarray:
         return self.ip[self.cfg.n_hosts:]
 
+    def window_pool(self) -> np.ndarray:
+        """Every host's whole peer pool: the distinct pairs of a full window
+        (activity ranges ignored)."""
+        d = self.degree
+        tot = int(d.sum())
+        h = np.repeat(np.arange(self.n_all), d)
+        first = np.cumsum(d) - d
+        p = np.arange(tot, dtype=np.int64) - np.repeat(first, d)
+        return self._rows(h, p)
+
     def pairs_device(self, stream: int, s: int, device, n: Optional[int] = None):
         """The slice's N pairs built on a torch device: the same distinct pairs
         as ``pairs``, with the repeats and the shuffle drawn by a torch Philox
@@ -395,3 +405,52 @@ class Trace:
         idx = torch.cat([torch.arange(D, device=device), rep])
         perm = torch.randperm(N, generator=g, device=device)
         return dd[idx[perm]].contiguous()
+
+
+# ----------------------------------------------------------------------------
+# served streams
+
+@dataclasses.dataclass
+class ServedStream:
+    """One stream of a serving run: detector configuration, slot length,
+    Poisson batch arrivals (stream seconds) and batch sizes.  Batch j is
+    rows [starts[j], starts[j] + sizes[j]) (cyclic) of the stream's reservoir,
+    the shuffled distinct pairs of one full window (Trace.window_pool)."""
+    cfg: TraceConfig
+    slot: float
+    n_slots: int
+    arrivals: np.ndarray
+    sizes: np.ndarray
+    starts: np.ndarray
+    reservoir_pairs: int
+
+    def slot_of(self) -> np.ndarray:
+        return np.floor(self.arrivals / self.slot).astype(np.int64)
+
+
+def served_workload(n_streams: int = 32, seed: int = 0x55D00004, pairs_scale: float = 1.0, n_slots: int = 6,
+                    mean_gap: float = 0.005, max_window_distinct: float = 4e6) -> List[ServedStream]:
+    """Streams with uneven rates: slot length uniform in [50, 500] ms of stream
+    time, rate weight w log-uniform in [0.2, 5], batches arriving as a Poisson
+    process of mean gap mean_gap / w, batch sizes log-uniform in [64K, 4M]
+    pairs (times pairs_scale); detector parameters as for batched links."""
+    cfgs = batch_configs(n_streams, seed, pairs_scale=pairs_scale, max_window_distinct=max_window_distinct)
+    out = []
+    for i, c in enumerate(cfgs):
+        key = _key(seed, 0x5E4FE, i)
+        u = _uniform01(key, np.arange(2))
+        slot = 0.05 + 0.45 * float(u[0])
+        w = math.exp(math.log(0.2) + float(u[1]) * math.log(25.0))
+        horizon = slot * n_slots
+        n_max = int(horizon / (mean_gap / w) * 2 + 64)
+        gaps = -np.log(_uniform01(_key(seed, 0x5E4FF, i), np.arange(n_max))) * (mean_gap / w)
+        arr = np.cumsum(gaps)
+        arr = arr[arr < horizon]
+        lo, hi = math.log(65536 * pairs_scale), math.log(4194304 * pairs_scale)
+        us = _uniform01(_key(seed, 0x5E500, i), np.arange(arr.size))
+        sizes = np.maximum(64, np.exp(lo + us * (hi - lo)).astype(np.int64))
+        tr_pool = int(Trace(c).degree.sum())
+        starts = (np.cumsum(sizes) - sizes) % max(tr_pool, 1)
+        out.append(ServedStream(cfg=c, slot=slot, n_slots=n_slots, arrivals=arr, sizes=sizes, starts=starts,
+                                reservoir_pairs=tr_pool))
+    return out
