@@ -43,11 +43,13 @@ class StreamInput:
     reservoir: torch.Tensor
 
     def batch(self, j: int) -> torch.Tensor:
+        """Exactly sizes[j] rows, wrapping around the reservoir as often as needed."""
         R = self.reservoir.shape[0]
-        a, n = int(self.starts[j]), int(self.sizes[j])
+        a, n = int(self.starts[j]) % R, int(self.sizes[j])
         if a + n <= R:
             return self.reservoir[a:a + n]
-        return torch.cat([self.reservoir[a:], self.reservoir[:a + n - R]])
+        idx = (torch.arange(n, device=self.reservoir.device) + a) % R
+        return self.reservoir[idx]
 
 
 @dataclasses.dataclass

@@ -1,0 +1,64 @@
+"""Accuracy of the regained lists against exact opposite numbers (Sec. 5):
+FPR = hosts reported but below theta / true super points, FNR = true super
+points not reported / true super points, TFR = FPR + FNR, over full windows.
+The rates are reported (the paper's 1.43% / 0.97% are on a trace that is not
+available, so they are context only); the assertions are loose sanity bounds
+on what the method must achieve on these synthetic traces."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1803_11036_amd as ssd
+import tracegen as tg
+from _parity import log, to_dev
+from oracle import truth
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(cfg, rehash=False, n_slices=None, use_device_fill=False):
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    p = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                        verify_rehash=rehash, max_tuples=1 << 22, max_results=1 << 20)
+    det = ssd.init_detector(p, tabs, device="cuda:0")
+    n_slices = n_slices or cfg.n_slices
+    sl, rows = [], []
+    for t in range(n_slices):
+        pairs = tr.pairs(0, t)
+        sl.append(pairs)
+        ssd.scan_slice(det, to_dev(pairs), t)
+        res = ssd.close_slice(det)
+        if t >= cfg.k - 1:                       # full windows only
+            true = truth.window_super_points(sl, t, cfg.k, cfg.theta)
+            got = res["ip"]
+            tp = np.intersect1d(got, true).size
+            fp, fn = got.size - tp, true.size - tp
+            rows.append((t, true.size, got.size, fp, fn))
+        if t >= cfg.k:
+            sl[t - cfg.k] = None                 # keep memory bounded
+    det.destroy()
+    n_true = sum(r[1] for r in rows)
+    fpr = sum(r[3] for r in rows) / max(1, n_true)
+    fnr = sum(r[4] for r in rows) / max(1, n_true)
+    return fpr, fnr, rows
+
+
+@pytest.mark.parametrize("name,rehash,k", [("tiny", False, 4), ("tiny", True, 4), ("tiny", True, 1)])
+def test_accuracy_tiny(name, rehash, k):
+    cfg = tg.config(name, k=k, pairs_lo=max(1_000_000, 2_000_000 // k), pairs_hi=max(1_000_000, 2_000_000 // k))
+    fpr, fnr, rows = _run(cfg, rehash=rehash)
+    log(f"accuracy {name} k={k} rehash={rehash}: FPR {100 * fpr:.2f}% FNR {100 * fnr:.2f}% "
+        f"TFR {100 * (fpr + fnr):.2f}% over {len(rows)} windows, true/reported per window "
+        f"{[(r[1], r[2]) for r in rows]}")
+    assert fnr < 0.05
+    if rehash:
+        assert fpr < 0.10
+
+
+def test_accuracy_core_link():
+    cfg = tg.config("core_link")
+    fpr, fnr, rows = _run(cfg, rehash=False, n_slices=cfg.k + 3)
+    log(f"accuracy core_link: FPR {100 * fpr:.2f}% FNR {100 * fnr:.2f}% TFR {100 * (fpr + fnr):.2f}% "
+        f"over {len(rows)} windows, true/reported per window {[(r[1], r[2]) for r in rows]}")
+    assert fnr < 0.05
