@@ -254,6 +254,10 @@ def main() -> int:
     ap.add_argument("--cpu-slices", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-mib", type=int, default=None, help="scan pass window (MiB of state; default: library)")
+    ap.add_argument("--scan-mode", choices=["passes", "binned"], default=None,
+                    help="single-detector scan: pass windows or bin-sorted stores (default: library)")
+    ap.add_argument("--bin-kib", type=int, default=None, help="binned scan: bin size in KiB (power of two)")
+    ap.add_argument("--apply-segments", type=int, default=None, help="binned scan: segments per store workgroup")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (PMC calibration)")
     ap.add_argument("--links", type=int, default=64, help="batched workload: number of links")
@@ -306,6 +310,13 @@ def main() -> int:
     det = ssd.init_detector(params, tables, device=dev)
     if args.pass_mib is not None:
         ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_PASS_BYTES, args.pass_mib << 20)
+    if args.scan_mode is not None:
+        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_MODE,
+                       ssd.SSD_SCAN_BINNED if args.scan_mode == "binned" else ssd.SSD_SCAN_PASSES)
+    if args.bin_kib is not None:
+        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_BIN_BYTES, args.bin_kib << 10)
+    if args.apply_segments is not None:
+        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_APPLY_SEGMENTS, args.apply_segments)
     ssd.set_tuning(det, ssd.SSD_TUNE_TIMING, 1)
     state_bytes = det.state.numel()
 
@@ -362,19 +373,27 @@ def main() -> int:
             kernels[name] = {"ms_total": round(ms, 4), "launches": launches,
                              "ms_per_launch": round(ms / launches, 5)}
     avg_pairs = n_timed / args.steps
-    # one scan call per step (all its pass launches), one hot detection launch per close
-    scan_ms = timing["scan"][0] / args.steps
+    binned = timing["scan_bin"][1] > 0
+    # one scan call per step (all its launches), one hot detection launch per close
+    scan_ms = (timing["scan"][0] + timing["scan_bin"][0]) / args.steps
     det_ms = timing["hot_detect"][0] / max(1, timing["hot_detect"][1])
-    # algorithmic bytes: the scan reads 8 B and writes r cell bytes per pair;
-    # hot detection reads the whole state once
+    # algorithmic bytes per scan call (the unit of the scan kernels):
+    #   pass scan k_scan: 8 B pair read + r cell bytes written per pair;
+    #   binned scan k_bin: 8 B pair read + r 4-byte offsets written per pair,
+    #               k_apply: r 4-byte offsets read + r cell bytes written per pair;
+    # hot detection reads the whole state once per close
+    stores = "k_apply" if binned else "k_scan"
     cand = {
-        "k_scan": (timing["scan"][0], avg_pairs * (8 + cfg.r), scan_ms),
+        stores: (timing["scan"][0], avg_pairs * (5 * cfg.r if binned else 8 + cfg.r), timing["scan"][0] / args.steps),
         "k_hot_detect": (timing["hot_detect"][0], float(state_bytes), det_ms),
     }
+    if binned:
+        cand["k_bin"] = (timing["scan_bin"][0], avg_pairs * (8 + 4 * cfg.r), timing["scan_bin"][0] / args.steps)
     dom = max(cand, key=lambda k: cand[k][0])
     _, bytes_per_launch, ms_per_launch = cand[dom]
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
-    launches_per_unit = timing["scan"][1] // args.steps if dom == "k_scan" else 1
+    launches_per_unit = {"k_hot_detect": 1, "k_bin": timing["scan_bin"][1] // args.steps}.get(
+        dom, timing["scan"][1] // args.steps)
     traffic = load_traffic(dom, cfg.name)
     if traffic is not None:
         traffic *= launches_per_unit          # counters are per launch; the scan unit is one call

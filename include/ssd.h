@@ -195,16 +195,28 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_TUNE_GRAPH 5u           /* batches: 1 (default) = replay the close as a HIP graph */
 #define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = time the candidate (pass window, tile)
                                        pairs on the next scans and keep the fastest */
+/*   SSD_TUNE_SCAN_MODE (single detectors): SSD_SCAN_PASSES = pass windows as
+ *       above; SSD_SCAN_BINNED = each call's pairs are first sorted by state
+ *       bin (SSD_TUNE_SCAN_BIN_BYTES, a power of two, default 2 MiB), then each
+ *       bin's stores are made by workgroups of one XCD, inside its L2;
+ *       SSD_SCAN_AUTO (default) = binned for states above 256 MiB, else passes. */
+#define SSD_TUNE_SCAN_MODE 7u
+#define SSD_TUNE_SCAN_BIN_BYTES 8u
+#define SSD_TUNE_SCAN_APPLY_SEGMENTS 9u   /* binned: binning segments per store workgroup (default 4) */
+#define SSD_SCAN_PASSES 0u
+#define SSD_SCAN_BINNED 1u
+#define SSD_SCAN_AUTO 2u
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 
 /* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per
  * phase, measured with HIP events recorded on the detector's stream around
  * each phase's kernels, and the number of kernel launches per phase.
- * Phases: 0 scan, 1 hot detection, 2 hot lists, 3 candidate expansion,
+ * Phases: 0 scan stores, 1 hot detection, 2 hot lists, 3 candidate expansion,
  * 4 final test, 5 sort/report, 6 merge, 7 whole close replayed as a graph
- * (batches; its kernels are then not timed one by one).  Synchronises the
- * stream; reset != 0 clears the totals after reading. */
-#define SSD_PHASES 8u
+ * (batches; its kernels are then not timed one by one), 8 scan binning (the
+ * sort step of the binned scan).  Synchronises the stream; reset != 0 clears
+ * the totals after reading. */
+#define SSD_PHASES 9u
 int ssd_read_timing(ssd_detector *d, double *ms_out, uint64_t *launches_out, int reset);
 
 void ssd_destroy(ssd_detector *d);

@@ -26,6 +26,8 @@ __all__ = [
     "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
     "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
     "SSD_TUNE_SCAN_TILE_PAIRS", "SSD_TUNE_GRAPH", "SSD_TUNE_AUTOTUNE", "PHASES",
+    "SSD_TUNE_SCAN_MODE", "SSD_TUNE_SCAN_BIN_BYTES", "SSD_TUNE_SCAN_APPLY_SEGMENTS", "SSD_SCAN_PASSES",
+    "SSD_SCAN_BINNED", "SSD_SCAN_AUTO",
     "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
     "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_destroy",
     "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_destroy",
@@ -292,7 +294,13 @@ SSD_TUNE_TIMING = 3
 SSD_TUNE_SCAN_TILE_PAIRS = 4
 SSD_TUNE_GRAPH = 5
 SSD_TUNE_AUTOTUNE = 6
-PHASES = ("scan", "hot_detect", "hot_lists", "expand", "verify", "report", "merge", "close_graph")
+SSD_TUNE_SCAN_MODE = 7
+SSD_TUNE_SCAN_BIN_BYTES = 8
+SSD_TUNE_SCAN_APPLY_SEGMENTS = 9
+SSD_SCAN_PASSES = 0
+SSD_SCAN_BINNED = 1
+SSD_SCAN_AUTO = 2
+PHASES = ("scan", "hot_detect", "hot_lists", "expand", "verify", "report", "merge", "close_graph", "scan_bin")
 
 
 def read_timing(det: Detector, reset: bool = False) -> Dict[str, Tuple[float, int]]:

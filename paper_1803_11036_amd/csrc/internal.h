@@ -93,6 +93,28 @@ struct TileScanArgs {
     uint64_t n_tiles, tile;
 };
 
+// binned scan, step 1: `pb` pairs per workgroup, their cell offsets sorted
+// by state bin into the workgroup's own segment of `pb * r` items
+struct BinArgs {
+    const uint2* pairs;
+    uint64_t n;                   // pairs of this chunk
+    const uint32_t* tables;
+    uint32_t* items;              // [blocks][pb * r] bin-local byte offsets
+    uint32_t* table;              // [n_bins + 1][blocks] start of bin b in segment j; row n_bins = item count
+    uint32_t q, r, delta, log2eta;
+    uint32_t bin_shift, n_bins, pb, blocks;
+};
+
+// binned scan, step 2: the stores of every bin
+struct ApplyArgs {
+    const uint32_t* items;
+    const uint32_t* table;
+    uint8_t* state;
+    uint32_t n_bins, blocks, seg, bin_shift;
+    uint32_t parts, per_part;     // workgroups per bin, segments per workgroup
+    uint32_t stamp, pad;
+};
+
 struct DetectArgs {
     const LinkDesc* links;
     const uint64_t* se_prefix;    // [n_links + 1] estimators before each link
@@ -131,6 +153,12 @@ hipError_t launch_clear_hot(const LinkDesc* links, uint32_t n_links, hipStream_t
 hipError_t launch_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s);
+// LDS words k_bin needs, and the launches of the two binned scan steps
+inline uint32_t bin_lds_words(uint32_t n_bins, uint32_t pb, uint32_t r) { return 2048u + n_bins + 1u + pb * r; }
+constexpr uint32_t BIN_PAIRS_PER_THREAD = 2;   // k_bin: at most 2048 pairs per 1024-thread workgroup
+constexpr uint32_t BIN_LDS_WORDS = 16384 - 32;   // dynamic LDS of k_bin: 64 KiB per workgroup less its static words
+hipError_t launch_bin(const BinArgs& a, hipStream_t s);
+hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);
 hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
 hipError_t launch_level_prefix(const LevelArgs& a, hipStream_t s);

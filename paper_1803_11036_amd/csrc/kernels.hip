@@ -265,17 +265,172 @@ __global__ __launch_bounds__(256) void k_scan_tiles(TileScanArgs a)
     }
 }
 
+// ---------------------------------------------------------------- binned scan
+// Alg. 2 in two steps, for states much larger than the caches.
+// k_bin: each workgroup takes `pb` pairs, computes their r cell addresses and
+// counting-sorts the bin-local offsets by state bin (bins of 2^bin_shift
+// bytes) in LDS, then writes them as one coalesced segment; the start of every
+// bin in the segment goes to a bin-major table.
+// k_apply: the byte stores, bin by bin.  Workgroup g runs on XCD g mod 8 (the
+// dispatcher deals workgroups to the XCDs in turn) and the bins of an XCD are
+// visited in ascending order by all its workgroups together, so the stores of
+// each XCD land in a range its own L2 holds.  Results do not depend on the
+// placement: every store is independent.
+
+__device__ __forceinline__ void pair_hashes(const uint32_t* tab, uint2 pr, uint32_t q, uint32_t log2eta,
+                                            uint32_t* h0, uint32_t* d)
+{
+    *d = tab_hash(tab + 1024, pr.y) & ((1u << log2eta) - 1u);   // H1(oip)
+    *h0 = tab_hash(tab, pr.x) & ((1u << q) - 1u);               // RHFG[0](cip)
+}
+
+__device__ __forceinline__ uint64_t cell_addr(uint2 pr, uint32_t i, uint32_t h0, uint32_t d, uint32_t q,
+                                              uint32_t delta, uint32_t log2eta)
+{
+    const uint32_t col = i == 0 ? h0 : ((shr32(pr.x, (i - 1) * delta) ^ h0) & ((1u << q) - 1u));
+    return ((((uint64_t)i << q) | col) << log2eta) | d;
+}
+
+
+__global__ __launch_bounds__(1024) void k_bin(BinArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wsum[16];
+    uint32_t* tab = lds;
+    uint32_t* hist = lds + 2048;
+    uint32_t* stage = hist + a.n_bins + 1;
+    for (uint32_t i = threadIdx.x; i < 2048u; i += 1024u) tab[i] = a.tables[i];
+    for (uint32_t i = threadIdx.x; i <= a.n_bins; i += 1024u) hist[i] = 0u;
+    __syncthreads();
+    const uint64_t p0 = (uint64_t)blockIdx.x * a.pb;
+    const uint32_t np = (uint32_t)min((uint64_t)a.pb, a.n - p0);
+    const uint32_t q = a.q, r = a.r, delta = a.delta, log2eta = a.log2eta, bs = a.bin_shift;
+    const uint32_t bmask = (1u << bs) - 1u;
+    // hash once: every item's bin-local offset, and its bin and rank within
+    // the bin (from the LDS counter), stay in registers until the bins' starts
+    // are known
+    uint32_t off[BIN_PAIRS_PER_THREAD][MAX_ROWS], key[BIN_PAIRS_PER_THREAD][MAX_ROWS];
+#pragma unroll
+    for (uint32_t u = 0; u < BIN_PAIRS_PER_THREAD; u++) {
+        const uint32_t p = threadIdx.x + u * 1024u;
+        if (p >= np) continue;
+        const uint2 pr = a.pairs[p0 + p];
+        uint32_t h0, d;
+        pair_hashes(tab, pr, q, log2eta, &h0, &d);
+#pragma unroll
+        for (uint32_t i = 0; i < MAX_ROWS; i++) {
+            if (i >= r) continue;
+            const uint64_t addr = cell_addr(pr, i, h0, d, q, delta, log2eta);
+            const uint32_t bin = (uint32_t)(addr >> bs);
+            off[u][i] = (uint32_t)addr & bmask;
+            key[u][i] = (bin << 16) | atomicAdd(&hist[bin], 1u);
+        }
+    }
+    __syncthreads();
+    // bin starts within the segment (exclusive scan, consecutive bins per thread)
+    const uint32_t per = (a.n_bins + 1023u) / 1024u;
+    const uint32_t b0 = min(a.n_bins, threadIdx.x * per), b1 = min(a.n_bins, b0 + per);
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; b++) sum += hist[b];
+    uint32_t total;
+    uint32_t start = block_exclusive_scan_1024(sum, wsum, &total);
+    for (uint32_t b = b0; b < b1; b++) {
+        const uint32_t c = hist[b];
+        hist[b] = start;
+        a.table[(uint64_t)b * a.blocks + blockIdx.x] = start;
+        start += c;
+    }
+    if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + blockIdx.x] = np * r;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t u = 0; u < BIN_PAIRS_PER_THREAD; u++) {
+        if (threadIdx.x + u * 1024u >= np) continue;
+#pragma unroll
+        for (uint32_t i = 0; i < MAX_ROWS; i++) {
+            if (i >= r) continue;
+            stage[hist[key[u][i] >> 16] + (key[u][i] & 0xFFFFu)] = off[u][i];
+        }
+    }
+    __syncthreads();
+    uint32_t* seg = a.items + (uint64_t)blockIdx.x * a.pb * r;
+    for (uint32_t i = threadIdx.x; i < np * r; i += 1024u) seg[i] = stage[i];
+}
+
+#ifndef SSD_APPLY_WAVES
+#define SSD_APPLY_WAVES 1
+#endif
+constexpr uint32_t APPLY_WAVES = SSD_APPLY_WAVES;   // waves (parts of one bin) per workgroup
+
+// Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w / blocks_per_bin)-th bin
+// from the top with w = g / 8; each wave takes one part of the bin, i.e.
+// segments [part * per_part, ...),
+// 64 segments per round: lane j holds segment j's run of the bin, and the
+// wave walks the concatenated runs 64 items at a time.
+__global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(ApplyArgs a)
+{
+    const uint32_t g = blockIdx.x, w = g >> 3;
+    const uint32_t blocks_per_bin = (a.parts + APPLY_WAVES - 1) / APPLY_WAVES;
+    const uint32_t walk = (g & 7u) + 8u * (w / blocks_per_bin);
+    if (walk >= a.n_bins) return;
+    const uint32_t bin = a.n_bins - 1u - walk;     // highest bins first: the lowest stay cached for hot detection
+    const uint32_t part = (w % blocks_per_bin) * APPLY_WAVES + (threadIdx.x >> 6);
+    if (part >= a.parts) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t j0 = part * a.per_part;
+    const uint32_t j1 = min(a.blocks, j0 + a.per_part);
+    uint8_t* base = a.state + ((uint64_t)bin << a.bin_shift);
+    const uint8_t stamp = (uint8_t)a.stamp;
+    const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
+    for (uint32_t jb = j0; jb < j1; jb += 64u) {
+        const uint32_t j = jb + lane;
+        uint32_t st = 0, c = 0;
+        if (j < j1) {
+            st = row[j];
+            c = row[a.blocks + j] - st;
+        }
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (lane >= (uint32_t)o) incl += v;
+        }
+        const uint32_t excl = incl - c;
+        const uint32_t total = __shfl(incl, 63, 64);
+        for (uint32_t t0 = 0; t0 < total; t0 += 64u) {
+            const uint32_t t = t0 + lane;
+            // the run holding item t: the largest lane whose run starts at or before t
+            uint32_t lo = 0;
+#pragma unroll
+            for (uint32_t sft = 32; sft > 0; sft >>= 1) {
+                const uint32_t e = __shfl(excl, (int)(lo + sft), 64);
+                if (e <= t) lo += sft;
+            }
+            const uint32_t rs = __shfl(st, (int)lo, 64);
+            const uint32_t re = __shfl(excl, (int)lo, 64);
+            if (t < total) {
+                const uint32_t off = a.items[(uint64_t)(jb + lo) * a.seg + rs + (t - re)];
+                base[off] = stamp;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- hot detection
 // One wave per sliding estimator: R_k = live cells (Sec. 3.2); a hot estimator
 // (Sec. 3.3) sets its bit in the row bitmask and in the key-transposed bitmask;
 // estimators of this slot's expiry phase clear their dead cells.  Up to CH
 // 1 KiB wave loads in flight per group.
 
+#ifndef SSD_DETECT_WAVES
+#define SSD_DETECT_WAVES 4
+#endif
+constexpr uint32_t DETECT_WAVES = SSD_DETECT_WAVES;   // waves (estimators) per workgroup
+
 template <int CH>
-__global__ __launch_bounds__(256) void k_hot_detect(DetectArgs a)
+__global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t g = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint64_t g = (uint64_t)blockIdx.x * DETECT_WAVES + (threadIdx.x >> 6);
     if (g >= a.total) return;
     uint32_t l;
     uint64_t s;
@@ -781,13 +936,31 @@ hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t
     return hipGetLastError();
 }
 
+hipError_t launch_bin(const BinArgs& a, hipStream_t s)
+{
+    const uint32_t words = bin_lds_words(a.n_bins, a.pb, a.r);
+    if (words > BIN_LDS_WORDS || a.blocks == 0) return hipErrorInvalidValue;
+    k_bin<<<a.blocks, 1024, words * 4u, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
+{
+    if (a.parts == 0 || a.per_part == 0) return hipErrorInvalidValue;
+    const uint64_t groups = (a.n_bins + 7u) / 8u;
+    const uint64_t blocks_per_bin = (a.parts + APPLY_WAVES - 1) / APPLY_WAVES;
+    k_apply<<<(uint32_t)(8ull * blocks_per_bin * groups), 64 * APPLY_WAVES, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s)
 {
-    const dim3 g((uint32_t)((a.total + 3) / 4));
-    if (max_chunks_per_lane >= 8) k_hot_detect<8><<<g, 256, 0, s>>>(a);
-    else if (max_chunks_per_lane >= 4) k_hot_detect<4><<<g, 256, 0, s>>>(a);
-    else if (max_chunks_per_lane >= 2) k_hot_detect<2><<<g, 256, 0, s>>>(a);
-    else k_hot_detect<1><<<g, 256, 0, s>>>(a);
+    const dim3 g((uint32_t)((a.total + DETECT_WAVES - 1) / DETECT_WAVES));
+    const uint32_t bs = 64u * DETECT_WAVES;
+    if (max_chunks_per_lane >= 8) k_hot_detect<8><<<g, bs, 0, s>>>(a);
+    else if (max_chunks_per_lane >= 4) k_hot_detect<4><<<g, bs, 0, s>>>(a);
+    else if (max_chunks_per_lane >= 2) k_hot_detect<2><<<g, bs, 0, s>>>(a);
+    else k_hot_detect<1><<<g, bs, 0, s>>>(a);
     return hipGetLastError();
 }
 

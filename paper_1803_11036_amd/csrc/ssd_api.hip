@@ -89,6 +89,53 @@ uint32_t hot_threshold(uint32_t eta, uint32_t theta)
     return (uint32_t)ceil((double)eta * (1.0 - exp(-(double)theta / (double)eta)));
 }
 
+// Binned scan geometry for a bin size request: bins of 2^shift bytes (at
+// least eta and 256 KiB, at most MAX_BINS of them), `pb` pairs per k_bin
+// workgroup (as many as its LDS holds).
+constexpr uint32_t MAX_BINS = 2048;
+constexpr uint64_t MIN_BIN_BYTES = 256ull << 10;
+constexpr uint64_t DEFAULT_BIN_BYTES = 2ull << 20;
+#ifndef SSD_BIN_CHUNK_MPAIRS
+#define SSD_BIN_CHUNK_MPAIRS 8
+#endif
+// Pairs binned per step, at most.  The stores of a bin are spread over the
+// workgroups of one XCD, so the work in flight is about (bins in flight) x
+// (items per bin): larger steps put more items in every bin.
+constexpr uint64_t BIN_CHUNK_PAIRS = (uint64_t)SSD_BIN_CHUNK_MPAIRS << 20;
+// k_bin segments one k_apply workgroup walks: with 2 MiB bins and about 2000
+// pairs per segment this puts about 500 workgroups on every bin, so the
+// workgroups resident on an XCD cover one or two bins (measured best of 2..64
+// on the core-link workload, 6M pairs per slice into 1.5 GiB of state)
+constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 4;
+// binned scan for states above this size (measured: faster on the 1.5 GiB
+// core-link state, slower on a 24 MiB state that the Infinity Cache holds)
+constexpr uint64_t AUTO_BINNED_ABOVE = 256ull << 20;
+constexpr uint32_t PHASE_SCAN_BIN = 8;
+struct BinPlan {
+    uint32_t shift = 0, n_bins = 0, pb = 0;
+};
+BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
+{
+    const uint64_t state = ((uint64_t)p.r << p.q) * p.eta;
+    BinPlan b;
+    b.shift = log2u(std::max<uint64_t>(std::max<uint64_t>(bin_bytes, MIN_BIN_BYTES), p.eta));
+    while (((state + (1ull << b.shift) - 1) >> b.shift) > MAX_BINS) b.shift++;
+    b.n_bins = (uint32_t)((state + (1ull << b.shift) - 1) >> b.shift);
+    b.pb = std::min<uint32_t>(BIN_PAIRS_PER_THREAD * 1024u, (BIN_LDS_WORDS - 2048u - b.n_bins - 1u) / p.r);
+    return b;
+}
+// Item and table words that every allowed bin size fits, for chunks of up to
+// BIN_CHUNK_PAIRS pairs (fewer for small states).
+void bin_capacity(const ssd_params& p, uint64_t* items_words, uint64_t* table_words)
+{
+    const uint64_t state = ((uint64_t)p.r << p.q) * p.eta;
+    const uint64_t chunk = std::min<uint64_t>(BIN_CHUNK_PAIRS, std::max<uint64_t>(1ull << 16, state >> 4));
+    const BinPlan worst = bin_plan(p, 0);     // the most bins, the fewest pairs per workgroup
+    const uint64_t blocks = (chunk + worst.pb - 1) / worst.pb;
+    *items_words = blocks * worst.pb * p.r;
+    *table_words = (uint64_t)(worst.n_bins + 1) * blocks;
+}
+
 uint32_t nw_of(const ssd_params& p) { return p.delta > 6 ? 1u << (p.delta - 6) : 1u; }
 uint64_t row_words(const ssd_params& p) { return p.q >= 6 ? (1ull << (p.q - 6)) : 1ull; }
 
@@ -101,13 +148,14 @@ struct Layout {
     uint64_t links = 0, se_prefix = 0, row_table = 0, level_prefix = 0, clock = 0, pack_offsets = 0, tiles = 0;
     uint64_t ctl = 0, hot_begin = 0, hot_end = 0, sort_tmp = 0, packed = 0, total = 0;
     uint64_t state_total = 0, pack_cap = 0, tile_cap = 0;
+    uint64_t bin_items = 0, bin_table = 0, bin_items_words = 0, bin_table_words = 0;   // single detectors
     std::vector<LinkLayout> link;
 };
 
 // Scratch layout of an engine: header (descriptors, prefix tables, clock,
 // scan tiles), tables, control blocks, the hot-bit pool (cleared by one fill
 // per close), then every link's own buffers; states are packed link after link.
-Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_cap)
+Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_cap, bool bins = false)
 {
     Layout L;
     L.link.resize(n);
@@ -154,6 +202,11 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     while (pw < maxres) pw <<= 1;
     L.sort_tmp = o; o = align_up(o + pw * 8);
     L.packed = o; o = align_up(o + pack_cap * sizeof(SuperPointDev));
+    if (bins) {
+        bin_capacity(p[0], &L.bin_items_words, &L.bin_table_words);
+        L.bin_items = o; o = align_up(o + L.bin_items_words * 4);
+        L.bin_table = o; o = align_up(o + L.bin_table_words * 4);
+    }
     L.total = o;
     uint64_t so = 0;
     for (uint32_t l = 0; l < n; l++) {
@@ -305,14 +358,14 @@ void engine_release(Engine* e)
 }
 
 int engine_query(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_cap, uint64_t* state_bytes,
-                 uint64_t* scratch_bytes)
+                 uint64_t* scratch_bytes, bool bins = false)
 {
     if (!p || n < 1 || n > MAX_LINKS) return fail(SSD_E_PARAM, "need 1..%u detectors", MAX_LINKS);
     for (uint32_t l = 0; l < n; l++) {
         int rc = validate(p + l);
         if (rc) return rc;
     }
-    Layout L = plan(p, n, pack_cap, tile_cap);
+    Layout L = plan(p, n, pack_cap, tile_cap, bins);
     if (state_bytes) *state_bytes = L.state_total;
     if (scratch_bytes) *scratch_bytes = L.total;
     return SSD_OK;
@@ -320,14 +373,14 @@ int engine_query(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t ti
 
 int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tables, void* state_dev,
                 uint64_t state_bytes, void* scratch_dev, uint64_t scratch_bytes, void* stream, uint64_t pack_cap,
-                uint64_t tile_cap, uint64_t stage_cap)
+                uint64_t tile_cap, uint64_t stage_cap, bool bins = false)
 {
-    int rc = engine_query(p, n, pack_cap, tile_cap, nullptr, nullptr);
+    int rc = engine_query(p, n, pack_cap, tile_cap, nullptr, nullptr, bins);
     if (rc) return rc;
     if (!tables) return fail(SSD_E_PARAM, "tables_host is NULL");
     e->n = n;
     e->p.assign(p, p + n);
-    e->L = plan(p, n, pack_cap, tile_cap);
+    e->L = plan(p, n, pack_cap, tile_cap, bins);
     if (!state_dev || state_bytes < e->L.state_total || ((uintptr_t)state_dev & 15u))
         return fail(SSD_E_NOMEM, "state buffer needs %llu bytes, 16-byte aligned", (unsigned long long)e->L.state_total);
     if (!scratch_dev || scratch_bytes < e->L.total || ((uintptr_t)scratch_dev & (ALIGN - 1)))
@@ -570,6 +623,9 @@ struct ssd_detector {
     Engine e;
     uint64_t id = g_next_detector_id.fetch_add(1);   // unique for the process: host addresses get reused
     uint64_t pass_bytes = DEFAULT_PASS_BYTES;
+    uint32_t scan_mode = SSD_SCAN_AUTO;
+    uint64_t bin_bytes = DEFAULT_BIN_BYTES;
+    uint32_t apply_segments = DEFAULT_APPLY_SEGMENTS;
     uint64_t last_reported = 0;
     const ssd_params& p() const { return e.p[0]; }
     const LinkDesc& D() const { return e.hl[0]; }
@@ -732,7 +788,7 @@ const char* ssd_last_error(void) { return g_last_error.c_str(); }
 int ssd_query_sizes(const ssd_params* p, uint64_t* state_bytes, uint64_t* scratch_bytes)
 {
     if (!p) return fail(SSD_E_PARAM, "params is NULL");
-    return engine_query(p, 1, 0, 0, state_bytes, scratch_bytes);
+    return engine_query(p, 1, 0, 0, state_bytes, scratch_bytes, true);
 }
 
 int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* state_dev, uint64_t state_bytes,
@@ -746,7 +802,7 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
     ssd_detector* d = new (std::nothrow) ssd_detector();
     if (!d) return fail(SSD_E_NOMEM, "host allocation failed");
     rc = engine_init(&d->e, p, 1, tables_host, state_dev, state_bytes, scratch_dev, scratch_bytes, stream, 0, 0,
-                     PREFIX_MAX);
+                     PREFIX_MAX, true);
     if (rc) {
         engine_release(&d->e);
         delete d;
@@ -769,6 +825,19 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     switch (knob) {
     case SSD_TUNE_SCAN_PASS_BYTES: d->pass_bytes = value; return SSD_OK;
     case SSD_TUNE_TIMING: d->e.timing = value != 0; return SSD_OK;
+    case SSD_TUNE_SCAN_MODE:
+        if (value != SSD_SCAN_PASSES && value != SSD_SCAN_BINNED && value != SSD_SCAN_AUTO)
+            return fail(SSD_E_PARAM, "unknown scan mode %llu", (unsigned long long)value);
+        d->scan_mode = (uint32_t)value;
+        return SSD_OK;
+    case SSD_TUNE_SCAN_BIN_BYTES:
+        if (!is_pow2(value)) return fail(SSD_E_PARAM, "bin bytes must be a power of two");
+        d->bin_bytes = value;
+        return SSD_OK;
+    case SSD_TUNE_SCAN_APPLY_SEGMENTS:
+        if (value < 1 || value > 4096) return fail(SSD_E_PARAM, "apply segments outside 1..4096");
+        d->apply_segments = (uint32_t)value;
+        return SSD_OK;
     case SSD_TUNE_SORT_BLOCK_LIMIT: {
         if (value > SORT_SMALL) return fail(SSD_E_PARAM, "sort block limit above %u", SORT_SMALL);
         int rc = usable(&d->e);
@@ -795,6 +864,44 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
     if (n == 0) return SSD_OK;
     if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
     const LinkDesc& D = d->D();
+    const uint64_t state_bytes = D.n_se << D.log2eta;
+    if (d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE)) {
+        const BinPlan bp = bin_plan(d->p(), d->bin_bytes);
+        const uint64_t seg = (uint64_t)bp.pb * D.r;
+        const uint64_t max_blocks = std::min(e->L.bin_items_words / seg, e->L.bin_table_words / (bp.n_bins + 1));
+        const uint64_t chunk = max_blocks * bp.pb;
+        if (chunk == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
+        BinArgs ba{};
+        ba.tables = D.tables;
+        ba.items = e->at<uint32_t>(e->L.bin_items);
+        ba.table = e->at<uint32_t>(e->L.bin_table);
+        ba.q = D.q; ba.r = D.r; ba.delta = D.delta; ba.log2eta = D.log2eta;
+        ba.bin_shift = bp.shift; ba.n_bins = bp.n_bins; ba.pb = bp.pb;
+        ApplyArgs aa{};
+        aa.items = ba.items;
+        aa.table = ba.table;
+        aa.state = D.state;
+        aa.n_bins = bp.n_bins;
+        aa.seg = (uint32_t)seg;
+        aa.bin_shift = bp.shift;
+        aa.per_part = d->apply_segments;
+        aa.stamp = stamp_of(e->clock);
+        for (uint64_t done = 0; done < n; done += chunk) {
+            const uint64_t m = std::min(chunk, n - done);
+            ba.pairs = reinterpret_cast<const uint2*>(pairs_dev) + done;
+            ba.n = m;
+            ba.blocks = (uint32_t)((m + bp.pb - 1) / bp.pb);
+            aa.blocks = ba.blocks;
+            aa.parts = (ba.blocks + aa.per_part - 1) / aa.per_part;
+            PhaseMark pm = phase_begin(e);
+            HIPCHK(e, launch_bin(ba, e->stream));
+            phase_end(e, pm, PHASE_SCAN_BIN, 1);
+            pm = phase_begin(e);
+            HIPCHK(e, launch_apply(aa, e->stream));
+            phase_end(e, pm, 0, 1);
+        }
+        return SSD_OK;
+    }
     ScanArgs a{};
     a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
     a.n = n;
@@ -802,15 +909,18 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
     a.tables = D.tables;
     a.q = D.q; a.r = D.r; a.delta = D.delta; a.log2eta = D.log2eta;
     a.stamp = stamp_of(e->clock);
-    // passes over estimator windows of about pass_bytes each
+    // passes over estimator windows of about pass_bytes each, highest window
+    // first: the last pass leaves the lowest estimators cache-resident, and hot
+    // detection reads them first
     const uint64_t n_se = D.n_se;
     uint64_t per_pass = n_se;
     if (d->pass_bytes) per_pass = std::max<uint64_t>(1, d->pass_bytes / D.eta);
+    const uint64_t n_pass = (n_se + per_pass - 1) / per_pass;
     PhaseMark pm = phase_begin(e);
     uint32_t launches = 0;
-    for (uint64_t lo = 0; lo < n_se; lo += per_pass) {
-        a.se_lo = lo;
-        a.se_hi = std::min(lo + per_pass, n_se);
+    for (uint64_t j = n_pass; j-- > 0;) {
+        a.se_lo = j * per_pass;
+        a.se_hi = std::min(a.se_lo + per_pass, n_se);
         HIPCHK(e, launch_scan(a, e->stream));
         launches++;
     }

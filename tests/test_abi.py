@@ -34,6 +34,19 @@ def test_binding_names_match_the_abi():
         assert hasattr(ssd, py), py
 
 
+def test_binding_constants_match_the_header():
+    """Every SSD_* integer the binding defines equals the header's #define,
+    and the binding names one timing phase per SSD_PHASES."""
+    with open(os.path.join(ROOT, "include", "ssd.h")) as f:
+        defs = {m.group(1): int(m.group(2), 0)
+                for m in re.finditer(r"#define\s+(SSD_[A-Z0-9_]+)\s+\(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?", f.read())}
+    shared = [n for n in defs if hasattr(ssd, n)]
+    assert len(shared) >= 10
+    for n in shared:
+        assert getattr(ssd, n) == defs[n], n
+    assert len(ssd.PHASES) == defs["SSD_PHASES"]
+
+
 def _p(**kw):
     base = dict(q=12, r=6, delta=5, eta=1024, k=4, theta=1024)
     base.update(kw)

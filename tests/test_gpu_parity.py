@@ -53,17 +53,21 @@ def test_tiny_config():
     assert np.all(np.isin(tr.planted_ips(), res["ip"]))
 
 
-@pytest.mark.parametrize("splits", [1, 3, 7])
-def test_ragged_batches_and_empty_slices(splits):
+@pytest.mark.parametrize("splits,mode", [(1, "passes"), (3, "passes"), (7, "passes"), (1, "binned"), (7, "binned")])
+def test_ragged_batches_and_empty_slices(splits, mode):
     """Pair counts that leave ragged tails (0, 1, 63, 64, 65, 257, odd sizes),
-    several scan calls per slice, and empty slices."""
+    several scan calls per slice, empty slices, and (binned scan) calls of
+    several binning chunks."""
     q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
     sizes = [0, 1, 63, 64, 65, 257, 10007, 0, 12345, 9999, 0, 10240]
     sl = _slices_small(5 + splits, len(sizes), kb, theta, q, sizes=sizes)
     sl = [s if sizes[i] else s[:0] for i, s in enumerate(sl)]
+    sl[9] = np.resize(sl[9], (150001, 2))      # the same pairs repeated: one call of several binning chunks
     g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(3), key_bits=kb)
+    if mode == "binned":
+        ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
     for t, p in enumerate(sl):
-        log(f"ragged splits={splits} slice {t} n={p.shape[0]}")
+        log(f"ragged splits={splits} {mode} slice {t} n={p.shape[0]}")
         scan_both(g, o, p, t, splits=splits if p.shape[0] >= splits else 1)
         compare_state(g, o)
         close_both(g, o)
@@ -146,6 +150,27 @@ def test_scan_pass_windows_do_not_change_state():
         scan_both(g, o, tr.pairs(0, t), t)
         compare_state(g, o)
         close_both(g, o, check_internals=False)
+
+
+@pytest.mark.parametrize("bin_kib", [256, 2048])
+def test_binned_scan_matches_oracle(bin_kib):
+    """The bin-sorted scan (96 or 12 bins over the 24 MiB state) gives the
+    oracle's state and lists, also for one call of 3.5M pairs (three binning
+    chunks, the last one ragged) and for a slice split over five calls."""
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_BIN_BYTES, bin_kib << 10)
+    for t in range(4):
+        pairs = tr.pairs(0, t)
+        if t == 1:
+            pairs = np.concatenate([pairs] * 4)[:3_500_001]
+        log(f"binned {bin_kib} KiB slice {t} n={pairs.shape[0]}")
+        scan_both(g, o, pairs, t, splits=5 if t == 2 else 1)
+        compare_state(g, o)
+        close_both(g, o, check_internals=(t == 3))
 
 
 def test_multi_kernel_sort_path():
