@@ -192,7 +192,7 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_TUNE_SORT_BLOCK_LIMIT 2u
 #define SSD_TUNE_TIMING 3u          /* 1: time every phase with HIP events */
 #define SSD_TUNE_SCAN_TILE_PAIRS 4u /* batches: pairs per scan work tile (default 4096) */
-#define SSD_TUNE_GRAPH 5u           /* batches: 1 (default) = replay the close as a HIP graph */
+#define SSD_TUNE_GRAPH 5u           /* 1 (default) = replay the close as a HIP graph (detectors, batches) */
 #define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = time the candidate (pass window, tile)
                                        pairs on the next scans and keep the fastest */
 /*   SSD_TUNE_SCAN_MODE (single detectors): SSD_SCAN_PASSES = pass windows as
@@ -212,9 +212,9 @@ int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
  * phase, measured with HIP events recorded on the detector's stream around
  * each phase's kernels, and the number of kernel launches per phase.
  * Phases: 0 scan stores, 1 hot detection, 2 hot lists, 3 candidate expansion,
- * 4 final test, 5 sort/report, 6 merge, 7 whole close replayed as a graph
- * (batches; its kernels are then not timed one by one), 8 scan binning (the
- * sort step of the binned scan).  Synchronises the stream; reset != 0 clears
+ * 4 final test, 5 sort/report, 6 merge, 7 the close after hot detection
+ * replayed as a graph (phases 2-5 are then timed as this one), 8 scan
+ * binning (the sort step of the binned scan).  Synchronises the stream; reset != 0 clears
  * the totals after reading. */
 #define SSD_PHASES 9u
 int ssd_read_timing(ssd_detector *d, double *ms_out, uint64_t *launches_out, int reset);

@@ -126,7 +126,6 @@ struct DetectArgs {
 struct LevelArgs {
     const LinkDesc* links;
     uint32_t n_links;
-    uint64_t* prefix;             // [n_links + 1] work items before each link (padded to 256)
     uint32_t level;               // 0 = rows 0..2, L = row L+2, LEVEL_VERIFY = final test
 };
 
@@ -147,9 +146,8 @@ struct PackArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
-hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, hipStream_t s);
+hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, bool clear_hot, hipStream_t s);
 hipError_t launch_advance(const LinkDesc* links, uint32_t n_links, hipStream_t s);
-hipError_t launch_clear_hot(const LinkDesc* links, uint32_t n_links, hipStream_t s);
 hipError_t launch_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s);
@@ -161,7 +159,6 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);
 hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
-hipError_t launch_level_prefix(const LevelArgs& a, hipStream_t s);
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s);
 hipError_t launch_extend(const LevelArgs& a, hipStream_t s);
 hipError_t launch_verify(const LevelArgs& a, hipStream_t s);

@@ -89,7 +89,8 @@ __device__ __forceinline__ uint32_t expire_word(uint32_t w, const LiveCfg& L)
 
 // Index of the link owning flattened item g: the largest l with prefix[l] <= g
 // (empty links have prefix[l] == prefix[l+1] and are skipped).
-__device__ __forceinline__ uint32_t find_link(const uint64_t* prefix, uint32_t n_links, uint64_t g)
+template <class U>
+__device__ __forceinline__ uint32_t find_link(const U* prefix, uint32_t n_links, uint64_t g)
 {
     uint32_t lo = 0, hi = n_links;
     while (hi - lo > 1) {
@@ -149,10 +150,18 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
 }
 
 // Per-slice constants of every link from its device clock (the open slice t).
-__global__ void k_prepare(LinkDesc* links, uint32_t n_links)
+// Per-slice constants of every link from its slot clock (grid: links x 16,
+// thread 0 of block (l, 0)), and the hot bitmasks cleared for this close.
+__global__ __launch_bounds__(256) void k_prepare(LinkDesc* links, uint32_t clear_hot)
 {
-    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n_links) return;
+    const uint32_t l = blockIdx.x;
+    if (clear_hot) {
+        const LinkDesc* D = links + l;
+        uint32_t* p = reinterpret_cast<uint32_t*>(D->hotbits);     // hotT follows hotbits
+        const uint64_t n = D->hot_words;
+        for (uint64_t i = blockIdx.y * 256u + threadIdx.x; i < n; i += 256u * gridDim.y) p[i] = 0u;
+    }
+    if (blockIdx.y != 0 || threadIdx.x != 0) return;
     const unsigned long long t = links[l].clock->t;
     const uint32_t k = links[l].k;
     const uint32_t cur = 1u + (uint32_t)(t % 255u);
@@ -183,13 +192,6 @@ __global__ void k_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst)
 }
 
 // Clear every link's hot bitmasks (grid: links x 16 blocks).
-__global__ __launch_bounds__(256) void k_clear_hot(const LinkDesc* links)
-{
-    const LinkDesc* D = links + blockIdx.x;
-    uint32_t* p = reinterpret_cast<uint32_t*>(D->hotbits);     // hotT follows hotbits
-    const uint64_t n = D->hot_words;
-    for (uint64_t i = blockIdx.y * 256u + threadIdx.x; i < n; i += 256u * gridDim.y) p[i] = 0u;
-}
 
 // ---------------------------------------------------------------- scan
 // Alg. 2 for every pair: one byte store per row.  `se_lo..se_hi` restricts
@@ -356,26 +358,18 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
     for (uint32_t i = threadIdx.x; i < np * r; i += 1024u) seg[i] = stage[i];
 }
 
-#ifndef SSD_APPLY_WAVES
-#define SSD_APPLY_WAVES 1
-#endif
-constexpr uint32_t APPLY_WAVES = SSD_APPLY_WAVES;   // waves (parts of one bin) per workgroup
-
-// Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w / blocks_per_bin)-th bin
-// from the top with w = g / 8; each wave takes one part of the bin, i.e.
-// segments [part * per_part, ...),
+// One wave per workgroup.  Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w /
+// parts)-th bin from the top with w = g / 8, segments [part * per_part, ...),
 // 64 segments per round: lane j holds segment j's run of the bin, and the
 // wave walks the concatenated runs 64 items at a time.
-__global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(ApplyArgs a)
+__global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 {
     const uint32_t g = blockIdx.x, w = g >> 3;
-    const uint32_t blocks_per_bin = (a.parts + APPLY_WAVES - 1) / APPLY_WAVES;
-    const uint32_t walk = (g & 7u) + 8u * (w / blocks_per_bin);
+    const uint32_t walk = (g & 7u) + 8u * (w / a.parts);
     if (walk >= a.n_bins) return;
     const uint32_t bin = a.n_bins - 1u - walk;     // highest bins first: the lowest stay cached for hot detection
-    const uint32_t part = (w % blocks_per_bin) * APPLY_WAVES + (threadIdx.x >> 6);
-    if (part >= a.parts) return;
-    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t part = w % a.parts;
+    const uint32_t lane = threadIdx.x;
     const uint32_t j0 = part * a.per_part;
     const uint32_t j1 = min(a.blocks, j0 + a.per_part);
     uint8_t* base = a.state + ((uint64_t)bin << a.bin_shift);
@@ -407,10 +401,7 @@ __global__ __launch_bounds__(64 * APPLY_WAVES) void k_apply(ApplyArgs a)
             }
             const uint32_t rs = __shfl(st, (int)lo, 64);
             const uint32_t re = __shfl(excl, (int)lo, 64);
-            if (t < total) {
-                const uint32_t off = a.items[(uint64_t)(jb + lo) * a.seg + rs + (t - re)];
-                base[off] = stamp;
-            }
+            if (t < total) base[a.items[(uint64_t)(jb + lo) * a.seg + rs + (t - re)]] = stamp;
         }
     }
 }
@@ -534,33 +525,64 @@ __global__ __launch_bounds__(1024) void k_hot_compact(const LinkDesc* links, con
 // Work items of one level for every link, prefix-summed; expansion levels pad
 // each link to whole 256-item blocks so that a block never spans two links.
 
-__global__ __launch_bounds__(1024) void k_level_prefix(LevelArgs a)
+// Work items of one link at a level: 0 = |HSE(0)| x |HSE(1)| pairs of rows
+// 0, 1; L = the tuples of level L-1 (extended by row L+2); LEVEL_VERIFY = the
+// full tuples.  Expansion items are padded to whole 256-item workgroups, so a
+// workgroup never spans two links and appends with one atomic.
+__device__ __forceinline__ unsigned long long level_items(const LinkDesc* D, uint32_t level)
 {
-    __shared__ unsigned long long lds[1024];
-    unsigned long long own = 0;
-    for (uint32_t base = 0; base < a.n_links; base += 1024u) {
-        const uint32_t l = base + threadIdx.x;
-        unsigned long long n = 0;
-        if (l < a.n_links) {
-            const LinkDesc* D = a.links + l;
-            const Ctl* c = D->ctl;
-            if (a.level == 0) {
-                n = (unsigned long long)c->hot_n[0] * c->hot_n[1];
-            } else if (a.level == LEVEL_VERIFY) {
-                const unsigned long long m = c->level_n[D->r - 3];
-                n = m < D->max_tuples ? m : D->max_tuples;
-            } else if (a.level + 2 < D->r) {
-                const unsigned long long m = c->level_n[a.level - 1];
-                n = m < D->max_tuples ? m : D->max_tuples;
-            }
-            if (a.level != LEVEL_VERIFY) n = (n + 255ull) & ~255ull;
-        }
-        unsigned long long excl, total;
-        block_exclusive_scan_u64_1024(n, lds, &excl, &total);
-        if (l < a.n_links) a.prefix[l] = own + excl;
-        own += total;
+    const Ctl* c = D->ctl;
+    unsigned long long n = 0;
+    if (level == 0) {
+        n = (unsigned long long)c->hot_n[0] * c->hot_n[1];
+    } else if (level == LEVEL_VERIFY) {
+        const unsigned long long m = c->level_n[D->r - 3];
+        return m < D->max_tuples ? m : D->max_tuples;
+    } else if (level + 2 < D->r) {
+        const unsigned long long m = c->level_n[level - 1];
+        n = m < D->max_tuples ? m : D->max_tuples;
     }
-    if (threadIdx.x == 0) a.prefix[a.n_links] = own;
+    return (n + 255ull) & ~255ull;
+}
+
+// Every 256-thread workgroup of a level kernel computes the level's prefix of
+// work items over the links into LDS (pre[0..n_links]) from the counters the
+// previous kernel left: no separate launch between levels.
+__device__ void level_prefix_lds(const LevelArgs& a, unsigned long long* pre)
+{
+    __shared__ unsigned long long part[256];
+    if (a.n_links == 1) {
+        if (threadIdx.x == 0) {
+            pre[0] = 0;
+            pre[1] = level_items(a.links, a.level);
+        }
+        __syncthreads();
+        return;
+    }
+    const uint32_t per = (a.n_links + 255u) / 256u;
+    const uint32_t l0 = min(a.n_links, threadIdx.x * per), l1 = min(a.n_links, l0 + per);
+    unsigned long long sum = 0;
+    for (uint32_t l = l0; l < l1; l++) {
+        const unsigned long long n = level_items(a.links + l, a.level);
+        pre[l] = n;
+        sum += n;
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256u; o <<= 1) {
+        const unsigned long long v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned long long run = part[threadIdx.x] - sum;
+    for (uint32_t l = l0; l < l1; l++) {
+        const unsigned long long n = pre[l];
+        pre[l] = run;
+        run += n;
+    }
+    if (threadIdx.x == 255u) pre[a.n_links] = part[255];
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- expansion
@@ -612,13 +634,15 @@ __device__ __forceinline__ uint32_t extend_one(const LinkDesc* D, uint32_t he0, 
 // Level 0: every (he_0, he_1) from HSE(0) x HSE(1), extended over row 2.
 __global__ __launch_bounds__(256) void k_expand0(LevelArgs a)
 {
-    const uint64_t total = a.prefix[a.n_links];
+    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    level_prefix_lds(a, pre);
+    const uint64_t total = pre[a.n_links];
     for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < total; base += (uint64_t)gridDim.x * 256u) {
-        const uint32_t l = uniform(find_link(a.prefix, a.n_links, base));
+        const uint32_t l = uniform(find_link(pre, a.n_links, base));
         const LinkDesc* D = a.links + l;
         const uint64_t n0 = D->ctl->hot_n[0], n1 = D->ctl->hot_n[1];
         const uint64_t Q = n0 * n1;
-        const uint64_t idx = base - a.prefix[l] + threadIdx.x;
+        const uint64_t idx = base - pre[l] + threadIdx.x;
         const uint32_t qmask = (1u << D->q) - 1u;
         uint32_t ok = idx < Q;
         uint32_t he0 = 0;
@@ -643,14 +667,16 @@ __global__ __launch_bounds__(256) void k_expand0(LevelArgs a)
 // Level L >= 1: extend the tuples of level L-1 over row L+2.
 __global__ __launch_bounds__(256) void k_extend(LevelArgs a)
 {
+    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    level_prefix_lds(a, pre);
     const uint32_t level = a.level, row = level + 2;
-    const uint64_t total = a.prefix[a.n_links];
+    const uint64_t total = pre[a.n_links];
     for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < total; base += (uint64_t)gridDim.x * 256u) {
-        const uint32_t l = uniform(find_link(a.prefix, a.n_links, base));
+        const uint32_t l = uniform(find_link(pre, a.n_links, base));
         const LinkDesc* D = a.links + l;
         const unsigned long long raw = D->ctl->level_n[level - 1];
         const uint64_t nin = raw < D->max_tuples ? raw : D->max_tuples;
-        const uint64_t idx = base - a.prefix[l] + threadIdx.x;
+        const uint64_t idx = base - pre[l] + threadIdx.x;
         const uint32_t valid = idx < nin;
         const uint64_t* ix = D->ctb_x[(level - 1) & 1];
         const uint32_t* ih = D->ctb_h0[(level - 1) & 1];
@@ -671,13 +697,15 @@ __global__ __launch_bounds__(256) void k_extend(LevelArgs a)
 
 __global__ __launch_bounds__(256) void k_verify(LevelArgs a)
 {
+    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    level_prefix_lds(a, pre);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves = (uint64_t)gridDim.x * 4u;
-    const uint64_t total = a.prefix[a.n_links];
+    const uint64_t total = pre[a.n_links];
     for (uint64_t t = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6); t < total; t += waves) {
-        const uint32_t l = uniform(find_link(a.prefix, a.n_links, t));
+        const uint32_t l = uniform(find_link(pre, a.n_links, t));
         const LinkDesc* D = a.links + l;
-        const uint64_t idx = t - a.prefix[l];
+        const uint64_t idx = t - pre[l];
         const uint32_t lf = D->r - 3;
         const uint32_t he0 = D->ctb_h0[lf & 1][idx];
         const uint64_t x = D->ctb_x[lf & 1][idx];
@@ -728,6 +756,7 @@ __global__ __launch_bounds__(1024) void k_sort_small(const LinkDesc* links)
     __shared__ unsigned long long s[SORT_SMALL];
     __shared__ uint32_t lds[16];
     const LinkDesc* D = links + blockIdx.x;
+    if (threadIdx.x == 0) D->clock->t += 1ull;       // the close's last kernel per link: the next slot opens
     const uint64_t nraw = D->ctl->n_acc;
     if (nraw > D->sort_limit || nraw > D->max_results) return;
     const uint32_t n = (uint32_t)(nraw < SORT_SMALL ? nraw : SORT_SMALL);
@@ -900,9 +929,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, hipStream_t s)
+hipError_t launch_prepare(const LinkDesc* links, uint32_t n_links, bool clear_hot, hipStream_t s)
 {
-    k_prepare<<<grid_for(n_links, 256, 64), 256, 0, s>>>(const_cast<LinkDesc*>(links), n_links);
+    k_prepare<<<dim3(n_links, clear_hot ? 16 : 1), 256, 0, s>>>(const_cast<LinkDesc*>(links), clear_hot ? 1u : 0u);
     return hipGetLastError();
 }
 
@@ -918,11 +947,7 @@ hipError_t launch_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst, 
     return hipGetLastError();
 }
 
-hipError_t launch_clear_hot(const LinkDesc* links, uint32_t n_links, hipStream_t s)
-{
-    k_clear_hot<<<dim3(n_links, 16), 256, 0, s>>>(links);
-    return hipGetLastError();
-}
+
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s)
 {
@@ -948,8 +973,7 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
 {
     if (a.parts == 0 || a.per_part == 0) return hipErrorInvalidValue;
     const uint64_t groups = (a.n_bins + 7u) / 8u;
-    const uint64_t blocks_per_bin = (a.parts + APPLY_WAVES - 1) / APPLY_WAVES;
-    k_apply<<<(uint32_t)(8ull * blocks_per_bin * groups), 64 * APPLY_WAVES, 0, s>>>(a);
+    k_apply<<<(uint32_t)(8ull * a.parts * groups), 64, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -970,11 +994,6 @@ hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, 
     return hipGetLastError();
 }
 
-hipError_t launch_level_prefix(const LevelArgs& a, hipStream_t s)
-{
-    k_level_prefix<<<1, 1024, 0, s>>>(a);
-    return hipGetLastError();
-}
 
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
 {

@@ -145,7 +145,7 @@ struct LinkLayout {
 };
 
 struct Layout {
-    uint64_t links = 0, se_prefix = 0, row_table = 0, level_prefix = 0, clock = 0, pack_offsets = 0, tiles = 0;
+    uint64_t links = 0, se_prefix = 0, row_table = 0, clock = 0, pack_offsets = 0, tiles = 0;
     uint64_t ctl = 0, hot_begin = 0, hot_end = 0, sort_tmp = 0, packed = 0, total = 0;
     uint64_t state_total = 0, pack_cap = 0, tile_cap = 0;
     uint64_t bin_items = 0, bin_table = 0, bin_items_words = 0, bin_table_words = 0;   // single detectors
@@ -170,7 +170,6 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     L.links = o; o = align_up(o + n * sizeof(LinkDesc));
     L.se_prefix = o; o = align_up(o + (n + 1) * 8);
     L.row_table = o; o = align_up(o + rows * 4);
-    L.level_prefix = o; o = align_up(o + (n + 1) * 8);
     L.clock = o; o = align_up(o + n * sizeof(Clock));       // one clock per link
     L.pack_offsets = o; o = align_up(o + (n + 1) * 8);
     L.tiles = o; o = align_up(o + 8 + tile_cap * sizeof(ScanWindow));
@@ -256,6 +255,8 @@ struct Engine {
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipStream_t capture_stream = nullptr;   // records the close graph (never runs work)
+    uint64_t graph_prefix = 0;              // result entries the graph copies to pinned memory
     // results of the last close
     std::vector<std::vector<ssd_super_point>> results;
     std::vector<int> status;
@@ -340,11 +341,21 @@ void phase_collect(Engine* e)
         if (hipEventElapsedTime(&ms, e->ev_pool[pd.a], e->ev_pool[pd.b]) == hipSuccess) {
             e->ph_ms[pd.phase] += ms;
             e->ph_launches[pd.phase] += pd.launches;
+        } else {
+            (void)hipGetLastError();     // a missing sample is not an error of the next call
         }
         e->ev_free.push_back(pd.a);
         e->ev_free.push_back(pd.b);
     }
     e->pending.clear();
+}
+
+void graph_reset(Engine* e)
+{
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->gexec = nullptr;
+    e->graph = nullptr;
 }
 
 void engine_release(Engine* e)
@@ -353,6 +364,7 @@ void engine_release(Engine* e)
     if (!e->broken && e->scratch) (void)hipStreamSynchronize(e->stream);
     if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
     if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
     if (e->pinned) (void)hipHostFree(e->pinned);
     for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
 }
@@ -460,43 +472,50 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
 // per-slice constants, hot bits cleared, hot detection, hot lists, the
 // candidate levels, the final test, sorting, then the control blocks (and, for
 // batches, the packed lists) to pinned memory, and the clock advance.
-int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
+// The close, first part: per-slice constants, hot bitmasks cleared, hot
+// detection over every estimator (one large launch, always eager and timed).
+int enqueue_close_head(Engine* e)
 {
     const hipStream_t s = e->stream;
     LinkDesc* links = e->dev_links();
-    const bool t = e->timing && !e->use_graph;
-    auto begin = [&]() { return t ? phase_begin(e) : PhaseMark(); };
-    auto end = [&](PhaseMark m, uint32_t ph, uint32_t nl) { if (t) phase_end(e, m, ph, nl); };
-    HIPCHK(e, launch_prepare(links, e->n, s));
-    HIPCHK(e, launch_clear_hot(links, e->n, s));
+    HIPCHK(e, launch_prepare(links, e->n, true, s));
     DetectArgs da{};
     da.links = links;
     da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
     da.n_links = e->n;
     da.total = e->se_total;
-    PhaseMark pm = begin();
+    PhaseMark pm = phase_begin(e);
     HIPCHK(e, launch_hot_detect(da, e->max_chunks, s));
-    end(pm, 1, 1);
-    pm = begin();
+    phase_end(e, pm, 1, 1);
+    return SSD_OK;
+}
+
+// The close, second part: hot lists, expansion levels, final test, sort, and
+// the copies to pinned memory -- many small launches, replayed as a graph
+// when the engine uses one (its phases are then timed as one).
+int enqueue_close_tail(Engine* e, bool pack, uint64_t single_prefix, bool capturing)
+{
+    const hipStream_t s = e->stream;
+    LinkDesc* links = e->dev_links();
+    const bool t = e->timing && !capturing;
+    auto begin = [&]() { return t ? phase_begin(e) : PhaseMark(); };
+    auto end = [&](PhaseMark m, uint32_t ph, uint32_t nl) { if (t) phase_end(e, m, ph, nl); };
+    PhaseMark pm = begin();
     HIPCHK(e, launch_hot_compact(links, e->at<uint32_t>(e->L.row_table), e->rows_total, s));
     end(pm, 2, 1);
     LevelArgs la{};
     la.links = links;
     la.n_links = e->n;
-    la.prefix = e->at<uint64_t>(e->L.level_prefix);
     la.level = 0;
     pm = begin();
-    HIPCHK(e, launch_level_prefix(la, s));
     HIPCHK(e, launch_expand0(la, s));
     for (uint32_t lvl = 1; lvl + 3 <= e->max_r; lvl++) {
         la.level = lvl;
-        HIPCHK(e, launch_level_prefix(la, s));
         HIPCHK(e, launch_extend(la, s));
     }
     end(pm, 3, e->max_r - 2);
     la.level = LEVEL_VERIFY;
     pm = begin();
-    HIPCHK(e, launch_level_prefix(la, s));
     HIPCHK(e, launch_verify(la, s));
     end(pm, 4, 1);
     pm = begin();
@@ -519,7 +538,48 @@ int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
         HIPCHK(e, hipMemcpyAsync(e->mb_stage, e->hl[0].out, single_prefix * sizeof(SuperPointDev),
                                  hipMemcpyDeviceToHost, s));
     }
-    HIPCHK(e, launch_advance(links, e->n, s));
+    return SSD_OK;     // k_sort_small advanced every link's clock
+}
+
+int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
+{
+    int rc = enqueue_close_head(e);
+    if (rc) return rc;
+    return enqueue_close_tail(e, pack, single_prefix, false);
+}
+
+// The close with its second part as a HIP graph: captured once on a stream
+// of our own (the caller's may be the legacy default stream, which cannot be
+// captured) and replayed on the caller's stream after the eager first part.
+// Recaptured when the result prefix it copies changes.
+int close_graph(Engine* e, bool pack, uint64_t prefix)
+{
+    int rc = enqueue_close_head(e);
+    if (rc) return rc;
+    if (e->gexec && e->graph_prefix != prefix) graph_reset(e);
+    if (!e->gexec) {
+        if (!e->capture_stream) HIPCHK(e, hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking));
+        const hipStream_t caller = e->stream;
+        e->stream = e->capture_stream;
+        hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal);
+        if (err != hipSuccess) {
+            e->stream = caller;
+            return dev_fail(e, err, "hipStreamBeginCapture");
+        }
+        rc = enqueue_close_tail(e, pack, prefix, true);
+        hipGraph_t g = nullptr;
+        err = hipStreamEndCapture(e->stream, &g);
+        e->stream = caller;
+        e->graph = g;
+        if (rc) { graph_reset(e); return rc; }
+        if (err != hipSuccess) { graph_reset(e); return dev_fail(e, err, "hipStreamEndCapture"); }
+        err = hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0);
+        if (err != hipSuccess) { graph_reset(e); return dev_fail(e, err, "hipGraphInstantiate"); }
+        e->graph_prefix = prefix;
+    }
+    PhaseMark pm = phase_begin(e);
+    HIPCHK(e, hipGraphLaunch(e->gexec, e->stream));
+    phase_end(e, pm, 7, 1);
     return SSD_OK;
 }
 
@@ -586,7 +646,7 @@ int enqueue_advance_only(Engine* e)
 {
     const hipStream_t s = e->stream;
     LinkDesc* links = e->dev_links();
-    HIPCHK(e, launch_prepare(links, e->n, s));
+    HIPCHK(e, launch_prepare(links, e->n, false, s));
     DetectArgs da{};
     da.links = links;
     da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
@@ -643,7 +703,6 @@ struct ssd_batch {
     bool tile_used[2] = {false, false};
     uint32_t tile_next = 0;
     uint32_t scan_blocks = 2048;
-    hipStream_t capture_stream = nullptr;   // records the close graph (never runs work)
     // autotuner: candidate (pass window, tile pairs), each scan timed with events
     struct Cand { uint64_t pass, tile; double ns_per_pair; };
     std::vector<Cand> cands;
@@ -702,7 +761,6 @@ Layout plan_group(uint32_t max_members)
     L.links = o; o = align_up(o + max_members * sizeof(LinkDesc));
     L.se_prefix = o; o = align_up(o + (max_members + 1) * 8);
     L.row_table = o; o = align_up(o + (uint64_t)max_members * MAX_ROWS * 4);
-    L.level_prefix = o; o = align_up(o + (max_members + 1) * 8);
     L.pack_offsets = o; o = align_up(o + (max_members + 1) * 8);
     L.tiles = o; o = align_up(o + 8 + MAX_WINDOWS * sizeof(ScanWindow));
     L.ctl = o; o = align_up(o + max_members * sizeof(Ctl));    // unused: members' own blocks are read
@@ -808,6 +866,7 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
         delete d;
         return rc;
     }
+    d->e.use_graph = true;
     *out = d;
     return SSD_OK;
 }
@@ -825,6 +884,7 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     switch (knob) {
     case SSD_TUNE_SCAN_PASS_BYTES: d->pass_bytes = value; return SSD_OK;
     case SSD_TUNE_TIMING: d->e.timing = value != 0; return SSD_OK;
+    case SSD_TUNE_GRAPH: d->e.use_graph = value != 0; return SSD_OK;
     case SSD_TUNE_SCAN_MODE:
         if (value != SSD_SCAN_PASSES && value != SSD_SCAN_BINNED && value != SSD_SCAN_AUTO)
             return fail(SSD_E_PARAM, "unknown scan mode %llu", (unsigned long long)value);
@@ -945,9 +1005,20 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
         return SSD_OK;
     }
     const ssd_params& p = d->p();
-    const uint64_t prefix =
-        std::min<uint64_t>(std::min<uint64_t>(2 * d->last_reported + 64, PREFIX_MAX), p.max_results);
-    rc = enqueue_close(e, false, prefix);
+    // result entries copied to pinned memory with the control block (longer
+    // lists take a second copy); a replayed graph keeps its prefix until a
+    // list outgrows it
+    const uint64_t cap_prefix = std::min<uint64_t>(PREFIX_MAX, p.max_results);
+    const uint64_t need = std::min<uint64_t>(2 * d->last_reported + 64, cap_prefix);
+    uint64_t prefix = need;
+    if (e->use_graph) {
+        uint64_t up = 64;
+        while (up < need) up <<= 1;
+        prefix = e->gexec && e->graph_prefix >= need ? e->graph_prefix : std::min(up, cap_prefix);
+        rc = close_graph(e, false, prefix);
+    } else {
+        rc = enqueue_close(e, false, prefix);
+    }
     if (rc) return rc;
     HIPCHK(e, hipStreamSynchronize(e->stream));
     phase_collect(e);
@@ -1171,7 +1242,6 @@ void ssd_batch_destroy(ssd_batch* b)
 {
     if (!b) return;
     engine_release(&b->e);
-    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     for (auto& ev : b->tune_events) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
@@ -1309,32 +1379,8 @@ int ssd_batch_close(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint6
     Engine* e = &b->e;
     int rc = usable(e);
     if (rc) return rc;
-    if (e->use_graph) {
-        if (!e->gexec) {
-            // record on a stream of our own (the caller's may be the legacy
-            // default stream, which cannot be captured); replay on the caller's
-            if (!b->capture_stream)
-                HIPCHK(e, hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
-            const hipStream_t caller = e->stream;
-            e->stream = b->capture_stream;
-            hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal);
-            if (err != hipSuccess) { e->stream = caller; return dev_fail(e, err, "hipStreamBeginCapture"); }
-            rc = enqueue_close(e, true, 0);
-            hipGraph_t g = nullptr;
-            err = hipStreamEndCapture(e->stream, &g);
-            e->stream = caller;
-            if (rc) return rc;
-            if (err != hipSuccess) return dev_fail(e, err, "hipStreamEndCapture");
-            e->graph = g;
-            HIPCHK(e, hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0));
-        }
-        PhaseMark pm = phase_begin(e);
-        HIPCHK(e, hipGraphLaunch(e->gexec, e->stream));
-        phase_end(e, pm, 7, 1);
-    } else {
-        rc = enqueue_close(e, true, 0);
-        if (rc) return rc;
-    }
+    rc = e->use_graph ? close_graph(e, true, 0) : enqueue_close(e, true, 0);
+    if (rc) return rc;
     HIPCHK(e, hipStreamSynchronize(e->stream));
     phase_collect(e);
     autotune_collect(b);

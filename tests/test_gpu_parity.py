@@ -37,20 +37,29 @@ def _slices_small(seed, n_slices, key_bits, theta, q, sizes=None, heavy=20, heav
     return out
 
 
-def test_tiny_config():
+@pytest.mark.parametrize("graph,timing", [(1, 1), (0, 0), (1, 0)])
+def test_tiny_config(graph, timing):
     """1 router, 8 slices of 1M pairs, k = 4, 2^12 x 6 estimators of 1024
-    cells: every product compared at every slice, full window state."""
+    cells: every product compared at every slice, full window state; the
+    close replayed as a graph (with and without timing event nodes) between
+    eager scans and reads, or run eagerly."""
     cfg = tg.config("tiny")
     tr = tg.Trace(cfg)
     tabs = tg.hash_tables(cfg.hash_seed)
     g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    ssd.set_tuning(g, ssd.SSD_TUNE_GRAPH, graph)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, timing)
     for t in range(cfg.n_slices):
-        log(f"tiny slice {t}")
+        log(f"tiny graph={graph} timing={timing} slice {t}")
         scan_both(g, o, tr.pairs(0, t), t)
         compare_state(g, o)
         res = close_both(g, o)
     assert len(res) > 100
     assert np.all(np.isin(tr.planted_ips(), res["ip"]))
+    tm = ssd.read_timing(g)
+    if timing:
+        assert tm["hot_detect"][1] == cfg.n_slices and tm["hot_detect"][0] > 0
+        assert tm["close_graph"][1] == (cfg.n_slices if graph else 0)
 
 
 @pytest.mark.parametrize("splits,mode", [(1, "passes"), (3, "passes"), (7, "passes"), (1, "binned"), (7, "binned")])
