@@ -333,12 +333,17 @@ def main() -> int:
     n_timed = 0
     torch.cuda.synchronize()
     start = time.perf_counter()
+    # pipelined: slice t+1's scan is enqueued before slice t's list is
+    # collected, so the host's collection overlaps device work
     for i in range(args.steps):
         s = slices[args.warmup + i]
         ssd.scan_slice(det, s, t)
-        res = ssd.close_slice(det)
+        if i > 0:
+            res = ssd.close_end(det)
+        ssd.close_begin(det)
         t += 1
         n_timed += s.shape[0]
+    res = ssd.close_end(det)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - start
     timing = ssd.read_timing(det, reset=True)

@@ -146,6 +146,19 @@ int ssd_scan_slice(ssd_detector *d, const uint32_t *pairs_dev, uint64_t n, uint6
 int ssd_close_slice(ssd_detector *d, uint32_t flags, ssd_super_point *out_host,
                     uint64_t cap, uint64_t *n_out);
 
+/* The same close in two halves, so that the next slice's scans can be
+ * enqueued while this close runs and its list is collected (pipelining).
+ * ssd_close_begin enqueues the close of the open slice t on the detector's
+ * stream and opens slice t+1 at once; it does not wait.  ssd_close_end waits
+ * for that close only (not for work enqueued after it) and returns its list
+ * exactly as ssd_close_slice would, with the same errors.  At most one close
+ * may be pending: ssd_close_begin, ssd_close_slice, merges and group closes
+ * of a detector with a pending close fail with SSD_E_ORDER, as does
+ * ssd_close_end with none pending.  Scans of slice t+1 are allowed while the
+ * close of t is pending. */
+int ssd_close_begin(ssd_detector *d);
+int ssd_close_end(ssd_detector *d, ssd_super_point *out_host, uint64_t cap, uint64_t *n_out);
+
 /* The list of the last close again (host copy). */
 int ssd_get_results(ssd_detector *d, ssd_super_point *out_host, uint64_t cap, uint64_t *n_out);
 

@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "SSD_VERIFY_REHASH", "SSD_ADVANCE_ONLY", "SSDError", "Params", "make_params",
-    "query_sizes", "Detector", "init_detector", "scan_slice", "close_slice",
+    "query_sizes", "Detector", "init_detector", "scan_slice", "close_slice", "close_begin", "close_end",
     "get_results", "merge_router_state", "read_canonical_state", "read_rk",
     "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
     "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
@@ -92,6 +92,8 @@ def _lib():
         L.ssd_scan_slice.argtypes = [vp, vp, u64, u64]
         L.ssd_close_slice.argtypes = [vp, u32, vp, u64, u64p]
         L.ssd_get_results.argtypes = [vp, vp, u64, u64p]
+        L.ssd_close_begin.argtypes = [vp]
+        L.ssd_close_end.argtypes = [vp, vp, u64, u64p]
         L.ssd_merge_router_state.argtypes = [vp, C.POINTER(vp), u32]
         L.ssd_read_canonical_state.argtypes = [vp, vp, u64]
         L.ssd_read_rk.argtypes = [vp, vp, u64]
@@ -231,6 +233,16 @@ def _results(det: Detector, fn, *args) -> np.ndarray:
 def close_slice(det: Detector, advance_only: bool = False) -> np.ndarray:
     """Close the open slice; returns the SSP list (structured array ip, rk, est)."""
     return _results(det, _lib().ssd_close_slice, SSD_ADVANCE_ONLY if advance_only else 0)
+
+
+def close_begin(det: Detector) -> None:
+    """Enqueue the close of the open slice and open the next one (no wait)."""
+    _check(_lib().ssd_close_begin(det.handle), "close_begin")
+
+
+def close_end(det: Detector) -> np.ndarray:
+    """Wait for the pending close and return its SSP list."""
+    return _results(det, _lib().ssd_close_end)
 
 
 def get_results(det: Detector) -> np.ndarray:

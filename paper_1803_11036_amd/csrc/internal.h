@@ -160,6 +160,7 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);
 hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s);
+hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s);
 hipError_t launch_extend(const LevelArgs& a, hipStream_t s);
 hipError_t launch_verify(const LevelArgs& a, hipStream_t s);
 hipError_t launch_sort_small(const LinkDesc* links, uint32_t n_links, hipStream_t s);

@@ -690,6 +690,150 @@ __global__ __launch_bounds__(256) void k_extend(LevelArgs a)
     }
 }
 
+// ---------------------------------------------------------------- depth-first expansion
+// The same candidate tuples as the level-by-level kernels above, in one
+// launch: each thread takes one (HSE(0), HSE(1)) pair and extends it row by
+// row depth first; rows are template levels, so the loop state of every row
+// lives in registers.  A count pass reserves the workgroup's slots in the
+// full-tuple buffer, a second pass writes them.  Every level's tuple count
+// still goes to level_n (capacity checks and diagnostics).
+
+template <int RMAX>
+struct DfsCtx {
+    uint32_t lv[RMAX];            // tuples accepted per level, this thread
+    uint32_t full;                // full tuples, this thread
+    uint64_t slot;                // write pass: first slot of this thread
+    uint64_t* out_x;
+    uint32_t* out_h0;
+};
+
+// rows ROW..r-1 still to choose (r <= RMAX, a compile-time bound that keeps
+// every row's loop state in registers)
+template <int ROW, int RMAX, bool EMIT>
+__device__ __forceinline__ void dfs_row(const LinkDesc* D, uint32_t he0, uint64_t x, DfsCtx<RMAX>& c)
+{
+    if (ROW == RMAX || (uint32_t)ROW >= D->r) {             // rows 0..r-1 all chosen: a full tuple
+        if (EMIT) {
+            const uint64_t i = c.slot + c.full;
+            if (i < D->max_tuples) {
+                c.out_x[i] = x;
+                c.out_h0[i] = he0;
+            }
+        }
+        c.full++;
+        return;
+    }
+    if constexpr (ROW < RMAX) {
+        const uint32_t q = D->q, delta = D->delta, nw = D->nw, key_bits = D->key_bits;
+        const uint32_t qmask = (1u << q) - 1u;
+        const uint32_t sh = q - delta;
+        const uint32_t bprev = (uint32_t)(x >> ((ROW - 2) * delta)) & qmask;     // B(ROW-1)
+        const uint32_t key = ((bprev >> delta) ^ he0) & ((1u << sh) - 1u);
+        const uint64_t* w = D->hotT + ((uint64_t)ROW * (1ull << sh) + key) * nw;
+        const uint32_t newpos = (ROW - 2) * delta + q;                           // first host bit B(ROW) adds
+        const uint32_t top0 = he0 >> sh;
+        for (uint32_t wi = 0; wi < nw; wi++) {
+            uint64_t bits = w[wi];
+            while (bits) {
+                const uint32_t j = (uint32_t)__ffsll((long long)bits) - 1u + wi * 64u;
+                bits &= bits - 1;
+                const uint64_t nx = x | ((uint64_t)((top0 ^ j) & ((1u << delta) - 1u)) << newpos);
+                if ((nx >> key_bits) != 0) continue;                              // bits beyond the key width
+                c.lv[ROW - 2]++;
+                dfs_row<ROW + 1, RMAX, EMIT>(D, he0, nx, c);
+            }
+        }
+    }
+}
+
+// Level-0 pair idx of link D: (he0, B(1)); false if idx is padding or B(1)
+// has bits beyond the key width.
+__device__ __forceinline__ bool level0_pair(const LinkDesc* D, uint64_t idx, uint32_t* he0, uint64_t* x)
+{
+    const uint64_t n0 = D->ctl->hot_n[0], n1 = D->ctl->hot_n[1];
+    const uint64_t Q = n0 * n1;
+    if (idx >= Q) return false;
+    uint64_t ia, ib;
+    if (Q <= 0xFFFFFFFFull) { ia = (uint32_t)idx / (uint32_t)n1; ib = (uint32_t)idx - (uint32_t)ia * (uint32_t)n1; }
+    else { ia = idx / n1; ib = idx % n1; }
+    *he0 = D->hot_list[ia];
+    const uint32_t he1 = D->hot_list[(1ull << D->q) + ib];
+    *x = (uint64_t)((*he0 ^ he1) & ((1u << D->q) - 1u));                 // B(1): host bits 0..q-1
+    return (*x >> D->key_bits) == 0;
+}
+
+// Grid-stride over every link's level-0 pairs.  Pass 1 counts (per level and
+// full tuples) in registers; the workgroup then reserves its slots for each
+// link once, with one atomic per link and level; pass 2 repeats the walk and
+// writes.  A workgroup's 256-item chunks never span two links (padding), and
+// a workgroup handles chunks of one link at a time, so per-link totals are
+// flushed whenever the link changes.
+template <int RMAX>
+__global__ __launch_bounds__(256) void k_expand_dfs(LevelArgs a)
+{
+    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    __shared__ uint32_t wsum[4][RMAX];
+    __shared__ unsigned long long base_slot;
+    level_prefix_lds(a, pre);
+    const uint64_t total = pre[a.n_links];
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    uint64_t chunk = blockIdx.x;
+    const uint64_t n_chunks = total / 256u;
+    while (chunk < n_chunks) {
+        // the run of this workgroup's chunks that belong to one link
+        const uint32_t l = uniform(find_link(pre, a.n_links, chunk * 256u));
+        const LinkDesc* D = a.links + l;
+        const uint64_t link_end = pre[l + 1] / 256u;
+        const uint32_t lf = D->r - 3;
+        DfsCtx<RMAX> c{};
+        c.out_x = D->ctb_x[lf & 1];
+        c.out_h0 = D->ctb_h0[lf & 1];
+        uint64_t ch = chunk;
+        for (; ch < link_end; ch += gridDim.x) {
+            uint32_t he0;
+            uint64_t x;
+            if (level0_pair(D, ch * 256u - pre[l] + threadIdx.x, &he0, &x)) dfs_row<2, RMAX, false>(D, he0, x, c);
+        }
+        // workgroup totals per level; the last level is the full tuples
+#pragma unroll
+        for (uint32_t L = 0; L < (uint32_t)RMAX; L++) {
+            const uint32_t v = wave_sum(L + 3 <= D->r ? (L + 3 == D->r ? c.full : c.lv[L]) : 0u);
+            if (lane == 0) wsum[wid][L] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)RMAX && threadIdx.x + 3 <= D->r) {
+            const uint32_t L = threadIdx.x;
+            const unsigned long long v = (unsigned long long)wsum[0][L] + wsum[1][L] + wsum[2][L] + wsum[3][L];
+            if (L + 3 == D->r) base_slot = v ? atomicAdd(&D->ctl->level_n[L], v) : 0ull;
+            else if (v) atomicAdd(&D->ctl->level_n[L], v);
+        }
+        // this thread's first slot: the workgroup's base plus the full
+        // tuples of the lanes and waves before it
+        uint32_t incl = c.full;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (lane >= (uint32_t)o) incl += v;
+        }
+        __syncthreads();
+        uint64_t before = 0;
+        for (uint32_t w = 0; w < wid; w++) before += wsum[w][lf];
+        if (c.full) {
+            DfsCtx<RMAX> e{};
+            e.out_x = c.out_x;
+            e.out_h0 = c.out_h0;
+            e.slot = base_slot + before + (incl - c.full);
+            for (uint64_t cw = chunk; cw < link_end; cw += gridDim.x) {
+                uint32_t he0;
+                uint64_t x;
+                if (level0_pair(D, cw * 256u - pre[l] + threadIdx.x, &he0, &x)) dfs_row<2, RMAX, true>(D, he0, x, e);
+            }
+        }
+        __syncthreads();
+        chunk = ch;
+    }
+}
+
 // ---------------------------------------------------------------- verify
 // Final test of every full tuple (end of Alg. 4, Sec. 4.2 last pass): optional
 // re-hash check, then the UnionSE of Alg. 1 -- a cell counts only when it is
@@ -998,6 +1142,17 @@ hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, 
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
 {
     k_expand0<<<2048, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+#ifndef SSD_DFS_BLOCKS
+#define SSD_DFS_BLOCKS 512
+#endif
+hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s)
+{
+    if (max_r <= 6) k_expand_dfs<6><<<SSD_DFS_BLOCKS, 256, 0, s>>>(a);
+    else if (max_r <= 8) k_expand_dfs<8><<<SSD_DFS_BLOCKS, 256, 0, s>>>(a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

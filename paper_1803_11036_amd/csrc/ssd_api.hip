@@ -111,6 +111,9 @@ constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 4;
 // core-link state, slower on a 24 MiB state that the Infinity Cache holds)
 constexpr uint64_t AUTO_BINNED_ABOVE = 256ull << 20;
 constexpr uint32_t PHASE_SCAN_BIN = 8;
+// Candidate expansion: depth first in one launch up to this many rows (its
+// per-row loop state is held in registers), level by level above.
+constexpr uint32_t DFS_MAX_ROWS = 8;
 struct BinPlan {
     uint32_t shift = 0, n_bins = 0, pb = 0;
 };
@@ -336,7 +339,13 @@ void phase_end(Engine* e, PhaseMark m, uint32_t phase, uint32_t launches)
 // after the stream passed every pending stop event
 void phase_collect(Engine* e)
 {
+    std::vector<Engine::Pending> later;
     for (const auto& pd : e->pending) {
+        if (hipEventQuery(e->ev_pool[pd.b]) != hipSuccess) {   // work enqueued after the waited-for point
+            (void)hipGetLastError();
+            later.push_back(pd);
+            continue;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, e->ev_pool[pd.a], e->ev_pool[pd.b]) == hipSuccess) {
             e->ph_ms[pd.phase] += ms;
@@ -347,7 +356,7 @@ void phase_collect(Engine* e)
         e->ev_free.push_back(pd.a);
         e->ev_free.push_back(pd.b);
     }
-    e->pending.clear();
+    e->pending.swap(later);
 }
 
 void graph_reset(Engine* e)
@@ -508,12 +517,18 @@ int enqueue_close_tail(Engine* e, bool pack, uint64_t single_prefix, bool captur
     la.n_links = e->n;
     la.level = 0;
     pm = begin();
-    HIPCHK(e, launch_expand0(la, s));
-    for (uint32_t lvl = 1; lvl + 3 <= e->max_r; lvl++) {
-        la.level = lvl;
-        HIPCHK(e, launch_extend(la, s));
+    if (e->max_r <= DFS_MAX_ROWS) {
+        // one depth-first launch for all levels
+        HIPCHK(e, launch_expand_dfs(la, e->max_r, s));
+        end(pm, 3, 1);
+    } else {
+        HIPCHK(e, launch_expand0(la, s));
+        for (uint32_t lvl = 1; lvl + 3 <= e->max_r; lvl++) {
+            la.level = lvl;
+            HIPCHK(e, launch_extend(la, s));
+        }
+        end(pm, 3, e->max_r - 2);
     }
-    end(pm, 3, e->max_r - 2);
     la.level = LEVEL_VERIFY;
     pm = begin();
     HIPCHK(e, launch_verify(la, s));
@@ -687,6 +702,9 @@ struct ssd_detector {
     uint64_t bin_bytes = DEFAULT_BIN_BYTES;
     uint32_t apply_segments = DEFAULT_APPLY_SEGMENTS;
     uint64_t last_reported = 0;
+    bool pending = false;               // a close begun and not yet ended
+    uint64_t pending_prefix = 0;
+    hipEvent_t close_done = nullptr;    // recorded after the pending close
     const ssd_params& p() const { return e.p[0]; }
     const LinkDesc& D() const { return e.hl[0]; }
 };
@@ -875,6 +893,7 @@ void ssd_destroy(ssd_detector* d)
 {
     if (!d) return;
     engine_release(&d->e);
+    if (d->close_done) (void)hipEventDestroy(d->close_done);
     delete d;
 }
 
@@ -988,22 +1007,13 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
     return SSD_OK;
 }
 
-int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, uint64_t cap, uint64_t* n_out)
+int ssd_close_begin(ssd_detector* d)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
-    if (flags & ~SSD_ADVANCE_ONLY) return fail(SSD_E_PARAM, "unknown close flags 0x%x", flags);
-    if (n_out) *n_out = 0;
-    if (flags & SSD_ADVANCE_ONLY) {
-        rc = enqueue_advance_only(e);
-        if (rc) return rc;
-        e->clock++;
-        e->results[0].clear();
-        e->have_last = false;
-        return SSD_OK;
-    }
+    if (d->pending) return fail(SSD_E_ORDER, "a close is already pending (ssd_close_end first)");
     const ssd_params& p = d->p();
     // result entries copied to pinned memory with the control block (longer
     // lists take a second copy); a replayed graph keeps its prefix until a
@@ -1020,11 +1030,28 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
         rc = enqueue_close(e, false, prefix);
     }
     if (rc) return rc;
-    HIPCHK(e, hipStreamSynchronize(e->stream));
-    phase_collect(e);
+    if (!d->close_done) HIPCHK(e, hipEventCreateWithFlags(&d->close_done, hipEventDisableTiming));
+    HIPCHK(e, hipEventRecord(d->close_done, e->stream));
+    d->pending = true;
+    d->pending_prefix = prefix;
     e->clock++;
-    rc = collect_results(e, false, prefix);
+    return SSD_OK;
+}
+
+int ssd_close_end(ssd_detector* d, ssd_super_point* out_host, uint64_t cap, uint64_t* n_out)
+{
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
     if (rc) return rc;
+    if (n_out) *n_out = 0;
+    if (!d->pending) return fail(SSD_E_ORDER, "no close is pending");
+    d->pending = false;
+    HIPCHK(e, hipEventSynchronize(d->close_done));
+    phase_collect(e);
+    rc = collect_results(e, false, d->pending_prefix);
+    if (rc) return rc;
+    const ssd_params& p = d->p();
     if (e->status[0] != SSD_OK) {
         d->last_reported = 0;
         const Ctl& c = e->last[0];
@@ -1035,6 +1062,28 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     }
     d->last_reported = e->results[0].size();
     return ssd_get_results(d, out_host, cap, n_out);
+}
+
+int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, uint64_t cap, uint64_t* n_out)
+{
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (flags & ~SSD_ADVANCE_ONLY) return fail(SSD_E_PARAM, "unknown close flags 0x%x", flags);
+    if (n_out) *n_out = 0;
+    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    if (flags & SSD_ADVANCE_ONLY) {
+        rc = enqueue_advance_only(e);
+        if (rc) return rc;
+        e->clock++;
+        e->results[0].clear();
+        e->have_last = false;
+        return SSD_OK;
+    }
+    rc = ssd_close_begin(d);
+    if (rc) return rc;
+    return ssd_close_end(d, out_host, cap, n_out);
 }
 
 int ssd_get_results(ssd_detector* d, ssd_super_point* out_host, uint64_t cap, uint64_t* n_out)
@@ -1055,6 +1104,7 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
     if (!g) return fail(SSD_E_PARAM, "detector is NULL");
     int rc = usable(&g->e);
     if (rc) return rc;
+    if (g->pending) return fail(SSD_E_ORDER, "the global detector has a close pending");
     if (!routers || n < 1) return fail(SSD_E_PARAM, "need at least one router");
     const ssd_params& gp = g->p();
     for (uint32_t j = 0; j < n; j++) {
@@ -1062,6 +1112,7 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
         if (!r) return fail(SSD_E_PARAM, "router %u is NULL", j);
         if (r == g) return fail(SSD_E_PARAM, "router %u is the global detector", j);
         if (r->e.broken) return fail(SSD_E_STATE, "router %u is unusable", j);
+        if (r->pending) return fail(SSD_E_ORDER, "router %u has a close pending", j);
         const ssd_params& rp = r->p();
         if (rp.q != gp.q || rp.r != gp.r || rp.delta != gp.delta || rp.eta != gp.eta || rp.k != gp.k ||
             rp.key_bits != gp.key_bits || r->e.tables != g->e.tables)
@@ -1544,6 +1595,8 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
     if (rc) return rc;
     rc = group_bind(g, members, n);
     if (rc) return rc;
+    for (uint32_t i = 0; i < n; i++)
+        if (members[i]->pending) return fail(SSD_E_ORDER, "member %u has a close pending", i);
     rc = enqueue_close(e, true, 0);
     if (rc) return rc;
     HIPCHK(e, hipStreamSynchronize(e->stream));

@@ -101,6 +101,20 @@ def test_stamp_wrap_and_expiry(k):
     log(f"wrap k={k} done")
 
 
+def test_many_rows_level_expansion():
+    """r = 10 rows (q = 8, delta = 3): above the depth-first bound, so the
+    candidates are expanded level by level (nine launches); every product
+    compared with the oracle."""
+    q, r, delta, eta, k, theta, kb = 8, 10, 3, 1024, 3, 200, 32
+    sl = _slices_small(77, 5, kb, theta, q, sizes=[3000] * 5)
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(9), key_bits=kb)
+    for t, p in enumerate(sl):
+        scan_both(g, o, p, t)
+        compare_state(g, o)
+        res = close_both(g, o)
+    assert len(res) > 0
+
+
 def test_rehash_mode():
     cfg = tg.config("tiny")
     tr = tg.Trace(cfg)
@@ -180,6 +194,37 @@ def test_binned_scan_matches_oracle(bin_kib):
         scan_both(g, o, pairs, t, splits=5 if t == 2 else 1)
         compare_state(g, o)
         close_both(g, o, check_internals=(t == 3))
+
+
+def test_pipelined_close_matches_oracle():
+    """close_begin / close_end with the next slice's scans enqueued between
+    them give the oracle's lists and state; misuse is rejected."""
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.close_end(g)
+    assert e.value.status == -3
+    o.scan(tr.pairs(0, 0))
+    ssd.scan_slice(g, to_dev(tr.pairs(0, 0)), 0)
+    for t in range(1, 6):
+        ssd.close_begin(g)
+        with pytest.raises(ssd.SSDError) as e:
+            ssd.close_begin(g)
+        assert e.value.status == -3
+        with pytest.raises(ssd.SSDError) as e:
+            ssd.close_slice(g)
+        assert e.value.status == -3
+        ip, rk, est = o.close()                    # reconstruct, then age
+        nxt = tr.pairs(0, t)
+        ssd.scan_slice(g, to_dev(nxt), t)          # slice t while close t-1 is pending
+        res = ssd.close_end(g)
+        assert np.array_equal(res["ip"], ip) and np.array_equal(res["rk"], rk)
+        assert np.all(np.abs(res["est"] - est) <= 1e-6 * np.abs(est))
+        o.scan(nxt)
+        compare_state(g, o)
+    close_both(g, o)
 
 
 def test_multi_kernel_sort_path():
