@@ -215,7 +215,7 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       SSD_SCAN_AUTO (default) = binned for states above 256 MiB, else passes. */
 #define SSD_TUNE_SCAN_MODE 7u
 #define SSD_TUNE_SCAN_BIN_BYTES 8u
-#define SSD_TUNE_SCAN_APPLY_SEGMENTS 9u   /* binned: binning segments per store workgroup (default 4) */
+#define SSD_TUNE_SCAN_APPLY_SEGMENTS 9u   /* binned: binning segments per store workgroup (default 2) */
 #define SSD_SCAN_PASSES 0u
 #define SSD_SCAN_BINNED 1u
 #define SSD_SCAN_AUTO 2u

@@ -48,6 +48,9 @@ struct LinkDesc {
     uint32_t* rk;                 // [r][2^q]
     uint64_t* hotbits;            // [r][max(1, 2^q / 64)] row bitmasks of hot estimators
     uint64_t* hotT;               // [r][2^(q-delta)][nw] key-transposed hot bits
+    Ctl* host_ctl;                // mapped pinned mailbox of a single detector (else null):
+    SuperPointDev* host_out;      //   the control block and the first host_cap results
+    uint64_t host_cap;            //   are written there by the close's last kernel
     uint32_t* hot_list;           // [r][2^q]
     uint64_t* ctb_x[2];           // candidate buffers: regained bits
     uint32_t* ctb_h0[2];          //                    and he_0
@@ -153,8 +156,7 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s);
 // LDS words k_bin needs, and the launches of the two binned scan steps
 inline uint32_t bin_lds_words(uint32_t n_bins, uint32_t pb, uint32_t r) { return 2048u + n_bins + 1u + pb * r; }
-constexpr uint32_t BIN_PAIRS_PER_THREAD = 2;   // k_bin: at most 2048 pairs per 1024-thread workgroup
-constexpr uint32_t BIN_LDS_WORDS = 16384 - 32;   // dynamic LDS of k_bin: 64 KiB per workgroup less its static words
+constexpr uint32_t BIN_LDS_WORDS = 40960 - 32;   // dynamic LDS of k_bin: 160 KiB per workgroup less its static words
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);

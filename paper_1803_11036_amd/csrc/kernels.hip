@@ -12,6 +12,7 @@
 // are rebased so that live stamps map to [0, K') and tested in 16-bit slots
 // (see LiveCfg); the rebasing constants are computed on the host per slot.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "internal.h"
@@ -294,6 +295,10 @@ __device__ __forceinline__ uint64_t cell_addr(uint2 pr, uint32_t i, uint32_t h0,
 }
 
 
+// Up to 160 KiB of LDS per workgroup: about 6000 pairs, so that the run of
+// one bin in one segment is long (about 50 offsets at 2 MiB bins) and
+// k_apply's reads of the runs are dense.  Pass 1 counts the bins' offsets,
+// pass 2 hashes again and places each offset at its bin's next free slot.
 __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
 {
     extern __shared__ uint32_t lds[];
@@ -308,28 +313,13 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
     const uint32_t np = (uint32_t)min((uint64_t)a.pb, a.n - p0);
     const uint32_t q = a.q, r = a.r, delta = a.delta, log2eta = a.log2eta, bs = a.bin_shift;
     const uint32_t bmask = (1u << bs) - 1u;
-    // hash once: every item's bin-local offset, and its bin and rank within
-    // the bin (from the LDS counter), stay in registers until the bins' starts
-    // are known
-    uint32_t off[BIN_PAIRS_PER_THREAD][MAX_ROWS], key[BIN_PAIRS_PER_THREAD][MAX_ROWS];
-#pragma unroll
-    for (uint32_t u = 0; u < BIN_PAIRS_PER_THREAD; u++) {
-        const uint32_t p = threadIdx.x + u * 1024u;
-        if (p >= np) continue;
+    for (uint32_t p = threadIdx.x; p < np; p += 1024u) {
         const uint2 pr = a.pairs[p0 + p];
         uint32_t h0, d;
         pair_hashes(tab, pr, q, log2eta, &h0, &d);
-#pragma unroll
-        for (uint32_t i = 0; i < MAX_ROWS; i++) {
-            if (i >= r) continue;
-            const uint64_t addr = cell_addr(pr, i, h0, d, q, delta, log2eta);
-            const uint32_t bin = (uint32_t)(addr >> bs);
-            off[u][i] = (uint32_t)addr & bmask;
-            key[u][i] = (bin << 16) | atomicAdd(&hist[bin], 1u);
-        }
+        for (uint32_t i = 0; i < r; i++) atomicAdd(&hist[(uint32_t)(cell_addr(pr, i, h0, d, q, delta, log2eta) >> bs)], 1u);
     }
     __syncthreads();
-    // bin starts within the segment (exclusive scan, consecutive bins per thread)
     const uint32_t per = (a.n_bins + 1023u) / 1024u;
     const uint32_t b0 = min(a.n_bins, threadIdx.x * per), b1 = min(a.n_bins, b0 + per);
     uint32_t sum = 0;
@@ -344,13 +334,13 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
     }
     if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + blockIdx.x] = np * r;
     __syncthreads();
-#pragma unroll
-    for (uint32_t u = 0; u < BIN_PAIRS_PER_THREAD; u++) {
-        if (threadIdx.x + u * 1024u >= np) continue;
-#pragma unroll
-        for (uint32_t i = 0; i < MAX_ROWS; i++) {
-            if (i >= r) continue;
-            stage[hist[key[u][i] >> 16] + (key[u][i] & 0xFFFFu)] = off[u][i];
+    for (uint32_t p = threadIdx.x; p < np; p += 1024u) {
+        const uint2 pr = a.pairs[p0 + p];
+        uint32_t h0, d;
+        pair_hashes(tab, pr, q, log2eta, &h0, &d);
+        for (uint32_t i = 0; i < r; i++) {
+            const uint64_t addr = cell_addr(pr, i, h0, d, q, delta, log2eta);
+            stage[atomicAdd(&hist[(uint32_t)(addr >> bs)], 1u)] = (uint32_t)addr & bmask;
         }
     }
     __syncthreads();
@@ -412,10 +402,7 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 // estimators of this slot's expiry phase clear their dead cells.  Up to CH
 // 1 KiB wave loads in flight per group.
 
-#ifndef SSD_DETECT_WAVES
-#define SSD_DETECT_WAVES 4
-#endif
-constexpr uint32_t DETECT_WAVES = SSD_DETECT_WAVES;   // waves (estimators) per workgroup
+constexpr uint32_t DETECT_WAVES = 4;   // waves (estimators) per workgroup (4, 8, 16 measured: 4 best)
 
 template <int CH>
 __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
@@ -892,6 +879,24 @@ __device__ __forceinline__ double estimate(uint32_t eta, uint32_t R)
     return -(double)eta * log(z0 / (double)eta);
 }
 
+// Links whose host mailbox is mapped (single detectors) get the control
+// block written into it by the close's last kernel, instead of a copy.
+__device__ __forceinline__ void ctl_to_host(const LinkDesc* D, unsigned long long n_out)
+{
+    if (!D->host_ctl) return;
+    __syncthreads();
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(D->ctl);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(D->host_ctl);
+    constexpr uint32_t words = sizeof(Ctl) / 4;
+    constexpr uint32_t nout_word = offsetof(Ctl, n_out) / 4;
+    if (threadIdx.x < words) {
+        uint32_t v = src[threadIdx.x];
+        if (threadIdx.x == nout_word) v = (uint32_t)n_out;
+        if (threadIdx.x == nout_word + 1) v = (uint32_t)(n_out >> 32);
+        dst[threadIdx.x] = v;
+    }
+}
+
 // One block per link: up to SORT_SMALL keys sorted in LDS (bitonic),
 // de-duplicated by ip and written as the result list.  Lists above the link's
 // limit are left to the multi-kernel sort.
@@ -902,7 +907,10 @@ __global__ __launch_bounds__(1024) void k_sort_small(const LinkDesc* links)
     const LinkDesc* D = links + blockIdx.x;
     if (threadIdx.x == 0) D->clock->t += 1ull;       // the close's last kernel per link: the next slot opens
     const uint64_t nraw = D->ctl->n_acc;
-    if (nraw > D->sort_limit || nraw > D->max_results) return;
+    if (nraw > D->sort_limit || nraw > D->max_results) {
+        ctl_to_host(D, D->ctl->n_out);               // the host finishes this list
+        return;
+    }
     const uint32_t n = (uint32_t)(nraw < SORT_SMALL ? nraw : SORT_SMALL);
     const unsigned long long* keys = D->acc;
     uint32_t N = 1;
@@ -933,10 +941,12 @@ __global__ __launch_bounds__(1024) void k_sort_small(const LinkDesc* links)
             const uint32_t R = 0xFFFFFFFFu - (uint32_t)s[i];
             SuperPointDev sp;
             sp.ip = (uint32_t)(s[i] >> 32); sp.rk = R; sp.est = estimate(D->eta, R);
+            if (off < D->host_cap) D->host_out[off] = sp;     // straight into the host's pinned mailbox
             D->out[off++] = sp;
         }
     }
     if (threadIdx.x == 0) D->ctl->n_out = total;
+    ctl_to_host(D, total);
 }
 
 // Global bitonic step over N (power of two) keys, for lists above SORT_SMALL.
@@ -1108,7 +1118,14 @@ hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t
 hipError_t launch_bin(const BinArgs& a, hipStream_t s)
 {
     const uint32_t words = bin_lds_words(a.n_bins, a.pb, a.r);
-    if (words > BIN_LDS_WORDS || a.blocks == 0) return hipErrorInvalidValue;
+    if (a.blocks == 0 || words > BIN_LDS_WORDS) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bin),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
     k_bin<<<a.blocks, 1024, words * 4u, s>>>(a);
     return hipGetLastError();
 }
@@ -1145,13 +1162,14 @@ hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-#ifndef SSD_DFS_BLOCKS
-#define SSD_DFS_BLOCKS 512
-#endif
+// workgroups of the depth-first expansion: each flushes its counts with one
+// atomic per level, so fewer is better until the grid stops filling the chip
+// (512 and 1024 measured equal, 2048 slower)
+constexpr uint32_t DFS_BLOCKS = 512;
 hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s)
 {
-    if (max_r <= 6) k_expand_dfs<6><<<SSD_DFS_BLOCKS, 256, 0, s>>>(a);
-    else if (max_r <= 8) k_expand_dfs<8><<<SSD_DFS_BLOCKS, 256, 0, s>>>(a);
+    if (max_r <= 6) k_expand_dfs<6><<<DFS_BLOCKS, 256, 0, s>>>(a);
+    else if (max_r <= 8) k_expand_dfs<8><<<DFS_BLOCKS, 256, 0, s>>>(a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

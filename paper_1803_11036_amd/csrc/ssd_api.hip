@@ -95,18 +95,16 @@ uint32_t hot_threshold(uint32_t eta, uint32_t theta)
 constexpr uint32_t MAX_BINS = 2048;
 constexpr uint64_t MIN_BIN_BYTES = 256ull << 10;
 constexpr uint64_t DEFAULT_BIN_BYTES = 2ull << 20;
-#ifndef SSD_BIN_CHUNK_MPAIRS
-#define SSD_BIN_CHUNK_MPAIRS 8
-#endif
 // Pairs binned per step, at most.  The stores of a bin are spread over the
 // workgroups of one XCD, so the work in flight is about (bins in flight) x
-// (items per bin): larger steps put more items in every bin.
-constexpr uint64_t BIN_CHUNK_PAIRS = (uint64_t)SSD_BIN_CHUNK_MPAIRS << 20;
-// k_bin segments one k_apply workgroup walks: with 2 MiB bins and about 2000
-// pairs per segment this puts about 500 workgroups on every bin, so the
-// workgroups resident on an XCD cover one or two bins (measured best of 2..64
-// on the core-link workload, 6M pairs per slice into 1.5 GiB of state)
-constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 4;
+// (items per bin): larger steps put more items in every bin (8M and 16M
+// measured equal, 4M slower on 6M-pair calls).
+constexpr uint64_t BIN_CHUNK_PAIRS = 8ull << 20;
+// k_bin segments one k_apply workgroup walks: with 2 MiB bins and about 6000
+// pairs per segment this puts about 500 workgroups on every bin of a 6M-pair
+// step, so the workgroups resident on an XCD cover one or two bins (measured
+// best of 1..64 on the core-link workload, 6M pairs per slice into 1.5 GiB)
+constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 2;
 // binned scan for states above this size (measured: faster on the 1.5 GiB
 // core-link state, slower on a 24 MiB state that the Infinity Cache holds)
 constexpr uint64_t AUTO_BINNED_ABOVE = 256ull << 20;
@@ -124,7 +122,7 @@ BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
     b.shift = log2u(std::max<uint64_t>(std::max<uint64_t>(bin_bytes, MIN_BIN_BYTES), p.eta));
     while (((state + (1ull << b.shift) - 1) >> b.shift) > MAX_BINS) b.shift++;
     b.n_bins = (uint32_t)((state + (1ull << b.shift) - 1) >> b.shift);
-    b.pb = std::min<uint32_t>(BIN_PAIRS_PER_THREAD * 1024u, (BIN_LDS_WORDS - 2048u - b.n_bins - 1u) / p.r);
+    b.pb = (BIN_LDS_WORDS - 2048u - b.n_bins - 1u) / p.r;
     return b;
 }
 // Item and table words that every allowed bin size fits, for chunks of up to
@@ -254,6 +252,7 @@ struct Engine {
     double ph_ms[N_PHASES] = {};
     uint64_t ph_launches[N_PHASES] = {};
     bool gather_ctl = false;           // control blocks live with their links (groups)
+    bool direct_mailbox = false;       // the sort kernel writes control block and list to pinned memory
     // graph replay of the close
     bool use_graph = false;
     hipGraph_t graph = nullptr;
@@ -460,6 +459,18 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     e->mb_ctl = static_cast<Ctl*>(e->pinned);
     e->mb_stage = reinterpret_cast<SuperPointDev*>(e->mb_ctl + n);
     e->mb_offsets = reinterpret_cast<unsigned long long*>(e->mb_stage + stage_cap);
+    if (bins && n == 1) {
+        // a single detector's close writes its control block and list into
+        // the mailbox directly (no copies after the sort)
+        void* dctl = nullptr;
+        void* dout = nullptr;
+        HIPCHK(e, hipHostGetDevicePointer(&dctl, e->mb_ctl, 0));
+        HIPCHK(e, hipHostGetDevicePointer(&dout, e->mb_stage, 0));
+        e->hl[0].host_ctl = static_cast<Ctl*>(dctl);
+        e->hl[0].host_out = static_cast<SuperPointDev*>(dout);
+        e->hl[0].host_cap = std::min<uint64_t>(stage_cap, p[0].max_results);
+        e->direct_mailbox = true;
+    }
     // every cell starts empty (Sec. 3.2: initialised once); scratch and clock zero
     HIPCHK(e, launch_fill_u32(reinterpret_cast<uint32_t*>(e->state), e->L.state_total / 4, 0u, e->stream));
     HIPCHK(e, launch_fill_u32(e->at<uint32_t>(0), e->L.total / 4, 0u, e->stream));
@@ -536,6 +547,7 @@ int enqueue_close_tail(Engine* e, bool pack, uint64_t single_prefix, bool captur
     pm = begin();
     HIPCHK(e, launch_sort_small(links, e->n, s));
     end(pm, 5, 1);
+    if (e->direct_mailbox) return SSD_OK;   // k_sort_small wrote the mailbox and advanced the clock
     if (e->gather_ctl) HIPCHK(e, launch_gather_ctl(links, e->n, e->at<Ctl>(e->L.ctl), s));
     HIPCHK(e, hipMemcpyAsync(e->mb_ctl, e->at<Ctl>(e->L.ctl), e->n * sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (pack) {
@@ -701,7 +713,6 @@ struct ssd_detector {
     uint32_t scan_mode = SSD_SCAN_AUTO;
     uint64_t bin_bytes = DEFAULT_BIN_BYTES;
     uint32_t apply_segments = DEFAULT_APPLY_SEGMENTS;
-    uint64_t last_reported = 0;
     bool pending = false;               // a close begun and not yet ended
     uint64_t pending_prefix = 0;
     hipEvent_t close_done = nullptr;    // recorded after the pending close
@@ -817,6 +828,9 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
         e->p[i] = m[i]->e.p[0];
         e->T[i] = m[i]->e.T[0];
         e->hl[i] = m[i]->e.hl[0];
+        e->hl[i].host_ctl = nullptr;         // the group collects its members' lists itself
+        e->hl[i].host_out = nullptr;
+        e->hl[i].host_cap = 0;
         se_prefix[i + 1] = se_prefix[i] + e->hl[i].n_se;
         for (uint32_t r = 0; r < e->p[i].r; r++) row_table.push_back((i << 8) | r);
         e->max_r = std::max(e->max_r, e->p[i].r);
@@ -1014,21 +1028,10 @@ int ssd_close_begin(ssd_detector* d)
     int rc = usable(e);
     if (rc) return rc;
     if (d->pending) return fail(SSD_E_ORDER, "a close is already pending (ssd_close_end first)");
-    const ssd_params& p = d->p();
-    // result entries copied to pinned memory with the control block (longer
-    // lists take a second copy); a replayed graph keeps its prefix until a
-    // list outgrows it
-    const uint64_t cap_prefix = std::min<uint64_t>(PREFIX_MAX, p.max_results);
-    const uint64_t need = std::min<uint64_t>(2 * d->last_reported + 64, cap_prefix);
-    uint64_t prefix = need;
-    if (e->use_graph) {
-        uint64_t up = 64;
-        while (up < need) up <<= 1;
-        prefix = e->gexec && e->graph_prefix >= need ? e->graph_prefix : std::min(up, cap_prefix);
-        rc = close_graph(e, false, prefix);
-    } else {
-        rc = enqueue_close(e, false, prefix);
-    }
+    // the sort kernel writes the first host_cap entries of the list into the
+    // pinned mailbox; longer lists take a second copy when collected
+    const uint64_t prefix = e->hl[0].host_cap;
+    rc = e->use_graph ? close_graph(e, false, prefix) : enqueue_close(e, false, prefix);
     if (rc) return rc;
     if (!d->close_done) HIPCHK(e, hipEventCreateWithFlags(&d->close_done, hipEventDisableTiming));
     HIPCHK(e, hipEventRecord(d->close_done, e->stream));
@@ -1053,14 +1056,12 @@ int ssd_close_end(ssd_detector* d, ssd_super_point* out_host, uint64_t cap, uint
     if (rc) return rc;
     const ssd_params& p = d->p();
     if (e->status[0] != SSD_OK) {
-        d->last_reported = 0;
         const Ctl& c = e->last[0];
         if (c.n_acc > p.max_results)
             return fail(SSD_E_OVERFLOW, "%llu accepted hosts > max_results %llu", (unsigned long long)c.n_acc,
                         (unsigned long long)p.max_results);
         return fail(SSD_E_OVERFLOW, "a candidate level exceeded max_tuples %llu", (unsigned long long)p.max_tuples);
     }
-    d->last_reported = e->results[0].size();
     return ssd_get_results(d, out_host, cap, n_out);
 }
 
@@ -1611,7 +1612,6 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
         me.status[0] = e->status[i];
         me.last[0] = e->last[i];
         me.have_last = true;
-        members[i]->last_reported = e->results[i].size();
         if (counts_host) counts_host[i] = e->results[i].size();
         if (status_host) status_host[i] = e->status[i];
         total += e->results[i].size();
