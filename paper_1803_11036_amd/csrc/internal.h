@@ -52,6 +52,7 @@ struct LinkDesc {
     SuperPointDev* host_out;      //   the control block and the first host_cap results
     uint64_t host_cap;            //   are written there by the close's last kernel
     uint32_t* hot_list;           // [r][2^q]
+    uint16_t* live16;             // [r][2^q][eta / 16] live-cell bits of hot estimators (written at hot detection)
     uint64_t* ctb_x[2];           // candidate buffers: regained bits
     uint32_t* ctb_h0[2];          //                    and he_0
     unsigned long long* acc;      // accepted keys

@@ -76,6 +76,14 @@ __device__ __forceinline__ uint32_t live_bits(uint32_t w, const LiveCfg& L)
     return live;
 }
 
+// The live cells of a 16-byte chunk as a 16-bit mask (bit i = cell i).
+__device__ __forceinline__ uint32_t live_mask16(const uint4& v, const LiveCfg& L)
+{
+    auto nib = [](uint32_t x) { return ((x >> 8) & 3u) | ((x >> 22) & 12u); };
+    return nib(live_bits(v.x, L)) | (nib(live_bits(v.y, L)) << 4) | (nib(live_bits(v.z, L)) << 8) |
+           (nib(live_bits(v.w, L)) << 12);
+}
+
 // The word with every dead non-empty cell cleared (distance >= k).
 __device__ __forceinline__ uint32_t expire_word(uint32_t w, const LiveCfg& L)
 {
@@ -454,6 +462,13 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
     }
     if (count) {
         live = wave_sum(live);
+        if (live >= D->T) {
+            // a hot estimator: snapshot its live cells, one bit each, for the
+            // final test (which then no longer reads the state)
+            const uint32_t chunks = 1u << (log2eta - 4);
+            uint16_t* snap = D->live16 + s * chunks;
+            for (uint32_t c = lane; c < chunks; c += 64u) snap[c] = (uint16_t)live_mask16(se[c], L);
+        }
         if (lane == 0) {
             D->rk[s] = live;
             if (live >= D->T) {
@@ -842,22 +857,18 @@ __global__ __launch_bounds__(256) void k_verify(LevelArgs a)
         const uint64_t x = D->ctb_x[lf & 1][idx];
         const uint32_t q = D->q, qmask = (1u << q) - 1u;
         if (D->rehash && (tab_hash(D->tables, (uint32_t)x) & qmask) != he0) continue;
-        const LiveCfg L = D->L;
-        const uint4* se[MAX_ROWS];
-        for (uint32_t i = 0; i < D->r; i++) {
-            const uint32_t col = i == 0 ? he0 : (((uint32_t)(x >> ((i - 1) * D->delta)) & qmask) ^ he0);
-            se[i] = reinterpret_cast<const uint4*>(D->state + ((((uint64_t)i << q) | col) << D->log2eta));
-        }
-        const uint32_t chunks = D->eta >> 4;
+        // UnionSE (Alg. 1): a cell counts when it is live in all r estimators,
+        // from the live-cell snapshots hot detection took of these (hot) estimators
+        const uint32_t words = D->eta >> 6;                  // 64 cells per word
+        const uint64_t* snap = reinterpret_cast<const uint64_t*>(D->live16);
         uint32_t cnt = 0;
-        for (uint32_t c = lane; c < chunks; c += 64u) {
-            uint32_t m0 = ~0u, m1 = ~0u, m2 = ~0u, m3 = ~0u;
+        for (uint32_t w = lane; w < words; w += 64u) {
+            uint64_t m = ~0ull;
             for (uint32_t i = 0; i < D->r; i++) {
-                const uint4 v = se[i][c];
-                m0 &= live_bits(v.x, L); m1 &= live_bits(v.y, L);
-                m2 &= live_bits(v.z, L); m3 &= live_bits(v.w, L);
+                const uint32_t col = i == 0 ? he0 : (((uint32_t)(x >> ((i - 1) * D->delta)) & qmask) ^ he0);
+                m &= snap[((((uint64_t)i << q) | col) * words) + w];
             }
-            cnt += __popc(m0) + __popc(m1) + __popc(m2) + __popc(m3);
+            cnt += __popcll(m);
         }
         const uint32_t R = wave_sum(cnt);
         if (lane == 0 && R >= D->T) {

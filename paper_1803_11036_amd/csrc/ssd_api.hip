@@ -142,7 +142,7 @@ uint64_t row_words(const ssd_params& p) { return p.q >= 6 ? (1ull << (p.q - 6)) 
 
 struct LinkLayout {
     uint64_t state_off, state_bytes;
-    uint64_t tables, ctl, rk, hot_list, hotbits, hotT, ctb_x[2], ctb_h0[2], acc, out;
+    uint64_t tables, ctl, rk, hot_list, live16, hotbits, hotT, ctb_x[2], ctb_h0[2], acc, out;
 };
 
 struct Layout {
@@ -193,6 +193,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
         LinkLayout& K = L.link[l];
         K.rk = o; o = align_up(o + n_se * 4);
         K.hot_list = o; o = align_up(o + n_se * 4);
+        K.live16 = o; o = align_up(o + n_se * (q.eta / 16) * 2);
         for (int b = 0; b < 2; b++) { K.ctb_x[b] = o; o = align_up(o + q.max_tuples * 8); }
         for (int b = 0; b < 2; b++) { K.ctb_h0[b] = o; o = align_up(o + q.max_tuples * 4); }
         K.acc = o; o = align_up(o + q.max_results * 8);
@@ -424,6 +425,7 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
         D.hotbits = e->at<uint64_t>(K.hotbits);
         D.hotT = e->at<uint64_t>(K.hotT);
         D.hot_list = e->at<uint32_t>(K.hot_list);
+        D.live16 = e->at<uint16_t>(K.live16);
         for (int b = 0; b < 2; b++) {
             D.ctb_x[b] = e->at<uint64_t>(K.ctb_x[b]);
             D.ctb_h0[b] = e->at<uint32_t>(K.ctb_h0[b]);
@@ -579,10 +581,9 @@ int enqueue_close(Engine* e, bool pack, uint64_t single_prefix)
 // of our own (the caller's may be the legacy default stream, which cannot be
 // captured) and replayed on the caller's stream after the eager first part.
 // Recaptured when the result prefix it copies changes.
-int close_graph(Engine* e, bool pack, uint64_t prefix)
+int close_graph_tail(Engine* e, bool pack, uint64_t prefix)
 {
-    int rc = enqueue_close_head(e);
-    if (rc) return rc;
+    int rc = SSD_OK;
     if (e->gexec && e->graph_prefix != prefix) graph_reset(e);
     if (!e->gexec) {
         if (!e->capture_stream) HIPCHK(e, hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking));
@@ -608,6 +609,13 @@ int close_graph(Engine* e, bool pack, uint64_t prefix)
     HIPCHK(e, hipGraphLaunch(e->gexec, e->stream));
     phase_end(e, pm, 7, 1);
     return SSD_OK;
+}
+
+int close_graph(Engine* e, bool pack, uint64_t prefix)
+{
+    int rc = enqueue_close_head(e);
+    if (rc) return rc;
+    return close_graph_tail(e, pack, prefix);
 }
 
 // After the close's synchronisation: check every link's capacities, finish
@@ -716,6 +724,8 @@ struct ssd_detector {
     bool pending = false;               // a close begun and not yet ended
     uint64_t pending_prefix = 0;
     hipEvent_t close_done = nullptr;    // recorded after the pending close
+    hipEvent_t head_done = nullptr;     // hot detection of the pending close done
+    hipStream_t tail_stream = nullptr;  // runs the close after hot detection
     const ssd_params& p() const { return e.p[0]; }
     const LinkDesc& D() const { return e.hl[0]; }
 };
@@ -906,8 +916,14 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
 void ssd_destroy(ssd_detector* d)
 {
     if (!d) return;
+    (void)hipSetDevice(d->e.device);
+    if (d->tail_stream) {
+        if (!d->e.broken) (void)hipStreamSynchronize(d->tail_stream);
+        (void)hipStreamDestroy(d->tail_stream);
+    }
     engine_release(&d->e);
     if (d->close_done) (void)hipEventDestroy(d->close_done);
+    if (d->head_done) (void)hipEventDestroy(d->head_done);
     delete d;
 }
 
@@ -933,6 +949,7 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
         return SSD_OK;
     case SSD_TUNE_SORT_BLOCK_LIMIT: {
         if (value > SORT_SMALL) return fail(SSD_E_PARAM, "sort block limit above %u", SORT_SMALL);
+        if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
         int rc = usable(&d->e);
         if (rc) return rc;
         d->e.hl[0].sort_limit = value;
@@ -1031,10 +1048,27 @@ int ssd_close_begin(ssd_detector* d)
     // the sort kernel writes the first host_cap entries of the list into the
     // pinned mailbox; longer lists take a second copy when collected
     const uint64_t prefix = e->hl[0].host_cap;
-    rc = e->use_graph ? close_graph(e, false, prefix) : enqueue_close(e, false, prefix);
-    if (rc) return rc;
     if (!d->close_done) HIPCHK(e, hipEventCreateWithFlags(&d->close_done, hipEventDisableTiming));
-    HIPCHK(e, hipEventRecord(d->close_done, e->stream));
+    if (!d->head_done) HIPCHK(e, hipEventCreateWithFlags(&d->head_done, hipEventDisableTiming));
+    if (!d->tail_stream) HIPCHK(e, hipStreamCreateWithFlags(&d->tail_stream, hipStreamNonBlocking));
+    // hot detection reuses the hot bitmasks and snapshots of the previous
+    // close: its second part must have finished
+    HIPCHK(e, hipStreamWaitEvent(e->stream, d->close_done, 0));
+    rc = enqueue_close_head(e);
+    if (rc) return rc;
+    // the rest of the close reads no state, so it runs on the second stream
+    // while the caller's stream goes on with the next slice's scans
+    HIPCHK(e, hipEventRecord(d->head_done, e->stream));
+    HIPCHK(e, hipStreamWaitEvent(d->tail_stream, d->head_done, 0));
+    const hipStream_t caller = e->stream;
+    e->stream = d->tail_stream;
+    rc = e->use_graph ? close_graph_tail(e, false, prefix) : enqueue_close_tail(e, false, prefix, false);
+    if (rc == SSD_OK) {
+        hipError_t err = hipEventRecord(d->close_done, e->stream);
+        if (err != hipSuccess) rc = dev_fail(e, err, "hipEventRecord");
+    }
+    e->stream = caller;
+    if (rc) return rc;
     d->pending = true;
     d->pending_prefix = prefix;
     e->clock++;
@@ -1161,6 +1195,7 @@ int ssd_read_rk(ssd_detector* d, uint32_t* out_host, uint64_t n)
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
+    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
     const uint64_t n_se = d->D().n_se;
     if (!out_host || n < n_se) return fail(SSD_E_NOMEM, "R_k needs %llu entries", (unsigned long long)n_se);
@@ -1175,6 +1210,7 @@ int ssd_read_hot(ssd_detector* d, uint32_t* counts_host, uint32_t* lists_host, u
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
+    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
     if (!counts_host) return fail(SSD_E_PARAM, "counts_host is NULL");
     const Ctl& c = e->last[0];
@@ -1198,6 +1234,7 @@ int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t*
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
+    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
     const ssd_params& p = d->p();
     const uint32_t lf = p.r - 3;
@@ -1225,6 +1262,7 @@ int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t*
 int ssd_read_timing(ssd_detector* d, double* ms_out, uint64_t* launches_out, int reset)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    if (d->tail_stream && !d->e.broken) HIPCHK(&d->e, hipStreamSynchronize(d->tail_stream));
     return read_timing(&d->e, ms_out, launches_out, reset);
 }
 
