@@ -157,7 +157,10 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t s);
 // LDS words k_bin needs, and the launches of the two binned scan steps
 inline uint32_t bin_lds_words(uint32_t n_bins, uint32_t pb, uint32_t r) { return 2048u + n_bins + 1u + pb * r; }
-constexpr uint32_t BIN_LDS_WORDS = 40960 - 32;   // dynamic LDS of k_bin: 160 KiB per workgroup less its static words
+// dynamic LDS of k_bin: 160 KiB per workgroup less its static words (128 and
+// 144 KiB, which leave room for the overlapped close's workgroups, measured
+// the same)
+constexpr uint32_t BIN_LDS_WORDS = 40960u - 32u;
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);

@@ -636,7 +636,7 @@ __device__ __forceinline__ uint32_t extend_one(const LinkDesc* D, uint32_t he0, 
 // Level 0: every (he_0, he_1) from HSE(0) x HSE(1), extended over row 2.
 __global__ __launch_bounds__(256) void k_expand0(LevelArgs a)
 {
-    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    extern __shared__ unsigned long long pre[];      // [n_links + 1], sized at launch
     level_prefix_lds(a, pre);
     const uint64_t total = pre[a.n_links];
     for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < total; base += (uint64_t)gridDim.x * 256u) {
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(256) void k_expand0(LevelArgs a)
 // Level L >= 1: extend the tuples of level L-1 over row L+2.
 __global__ __launch_bounds__(256) void k_extend(LevelArgs a)
 {
-    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    extern __shared__ unsigned long long pre[];      // [n_links + 1], sized at launch
     level_prefix_lds(a, pre);
     const uint32_t level = a.level, row = level + 2;
     const uint64_t total = pre[a.n_links];
@@ -773,7 +773,7 @@ __device__ __forceinline__ bool level0_pair(const LinkDesc* D, uint64_t idx, uin
 template <int RMAX>
 __global__ __launch_bounds__(256) void k_expand_dfs(LevelArgs a)
 {
-    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    extern __shared__ unsigned long long pre[];      // [n_links + 1], sized at launch
     __shared__ uint32_t wsum[4][RMAX];
     __shared__ unsigned long long base_slot;
     level_prefix_lds(a, pre);
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(256) void k_expand_dfs(LevelArgs a)
 
 __global__ __launch_bounds__(256) void k_verify(LevelArgs a)
 {
-    __shared__ unsigned long long pre[MAX_LINKS + 1];
+    extern __shared__ unsigned long long pre[];      // [n_links + 1], sized at launch
     level_prefix_lds(a, pre);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves = (uint64_t)gridDim.x * 4u;
@@ -1167,9 +1167,12 @@ hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, 
 }
 
 
+// dynamic LDS of the level kernels: the work prefix over the links
+static inline size_t prefix_lds(const LevelArgs& a) { return ((size_t)a.n_links + 1) * 8u; }
+
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
 {
-    k_expand0<<<2048, 256, 0, s>>>(a);
+    k_expand0<<<2048, 256, prefix_lds(a), s>>>(a);
     return hipGetLastError();
 }
 
@@ -1179,21 +1182,21 @@ hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
 constexpr uint32_t DFS_BLOCKS = 512;
 hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s)
 {
-    if (max_r <= 6) k_expand_dfs<6><<<DFS_BLOCKS, 256, 0, s>>>(a);
-    else if (max_r <= 8) k_expand_dfs<8><<<DFS_BLOCKS, 256, 0, s>>>(a);
+    if (max_r <= 6) k_expand_dfs<6><<<DFS_BLOCKS, 256, prefix_lds(a), s>>>(a);
+    else if (max_r <= 8) k_expand_dfs<8><<<DFS_BLOCKS, 256, prefix_lds(a), s>>>(a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_extend(const LevelArgs& a, hipStream_t s)
 {
-    k_extend<<<2048, 256, 0, s>>>(a);
+    k_extend<<<2048, 256, prefix_lds(a), s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_verify(const LevelArgs& a, hipStream_t s)
 {
-    k_verify<<<2048, 256, 0, s>>>(a);
+    k_verify<<<2048, 256, prefix_lds(a), s>>>(a);
     return hipGetLastError();
 }
 
