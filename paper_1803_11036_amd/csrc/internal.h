@@ -121,7 +121,7 @@ struct ApplyArgs {
 
 struct DetectArgs {
     const LinkDesc* links;
-    const uint64_t* se_prefix;    // [n_links + 1] estimators before each link
+    const uint64_t* se_prefix;    // [n_links + 1] waves before each link (a wave covers >= 4 KiB of state)
     uint32_t n_links;
     uint64_t total;               // waves launched
     uint32_t expire_only;         // link 0 only: visit the estimators of this slot's expiry phase
@@ -163,7 +163,7 @@ inline uint32_t bin_lds_words(uint32_t n_bins, uint32_t pb, uint32_t r) { return
 constexpr uint32_t BIN_LDS_WORDS = 40960u - 32u;
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
-hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s);
+hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, bool small, hipStream_t s);
 hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s);
 hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s);

@@ -412,29 +412,105 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 
 constexpr uint32_t DETECT_WAVES = 4;   // waves (estimators) per workgroup (4, 8, 16 measured: 4 best)
 
-template <int CH>
+// The end of one estimator's test: R_k, and if hot, its live-cell snapshot
+// (for the final test, which then reads no state) and its bits in the row
+// and key-transposed bitmasks.
+__device__ __forceinline__ void hot_finish(const LinkDesc* D, uint64_t s, uint32_t live, const uint4* se, uint32_t lane)
+{
+    const uint32_t log2eta = D->log2eta;
+    if (live >= D->T) {
+        const uint32_t chunks = 1u << (log2eta - 4);
+        uint16_t* snap = D->live16 + s * chunks;
+        for (uint32_t c = lane; c < chunks; c += 64u) snap[c] = (uint16_t)live_mask16(se[c], D->L);
+    }
+    if (lane == 0) {
+        D->rk[s] = live;
+        if (live >= D->T) {
+            const uint32_t q = D->q;
+            const uint32_t row = (uint32_t)(s >> q), c = (uint32_t)s & ((1u << q) - 1u);
+            const uint32_t sh = q - D->delta;
+            const uint32_t key = c & ((1u << sh) - 1u), j = c >> sh;
+            const uint32_t rw = q >= 6 ? (1u << (q - 6)) : 1u;    // words per row bitmask
+            atomicOr(reinterpret_cast<unsigned long long*>(D->hotbits) + (uint64_t)row * rw + (c >> 6),
+                     1ull << (c & 63u));
+            atomicOr(reinterpret_cast<unsigned long long*>(D->hotT) + ((uint64_t)row * (1ull << sh) + key) * D->nw +
+                         (j >> 6),
+                     1ull << (j & 63u));
+        }
+    }
+}
+
+// A wave covers 4 KiB of state at least: one estimator when eta >= 4096, else
+// 4096 / eta consecutive estimators (load round c of the wave's four belongs
+// to estimator c / (eta / 1024)), so that small estimators still give every
+// wave four 1 KiB loads in flight.
+template <int CH, bool SMALL>
 __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t g = (uint64_t)blockIdx.x * DETECT_WAVES + (threadIdx.x >> 6);
+    // batches of up to 256 links search the wave prefix in LDS (one coalesced
+    // load per workgroup instead of a chain of dependent loads per wave)
+    __shared__ unsigned long long pre_lds[SMALL ? 257 : 1];
+    const bool lds_prefix = SMALL && a.n_links > 1 && a.n_links <= 256u && !a.expire_only;
+    if (lds_prefix) {
+        for (uint32_t i = threadIdx.x; i <= a.n_links; i += blockDim.x) pre_lds[i] = a.se_prefix[i];
+        __syncthreads();
+    }
     if (g >= a.total) return;
     uint32_t l;
-    uint64_t s;
+    uint64_t s;                                         // first estimator of the wave
     if (a.expire_only) {
         l = 0;
         s = a.links[0].expire_phase + g * a.links[0].expire_period;
         if (s >= a.links[0].n_se) return;
     } else {
-        l = uniform(find_link(a.se_prefix, a.n_links, g));
-        s = g - a.se_prefix[l];
+        const unsigned long long* pre = lds_prefix ? pre_lds : reinterpret_cast<const unsigned long long*>(a.se_prefix);
+        l = uniform(find_link(pre, a.n_links, g));
+        const uint32_t lg = a.links[l].log2eta;
+        s = (g - pre[l]) << (lg < 12u ? 12u - lg : 0u);
     }
     const LinkDesc* D = a.links + l;
     const uint32_t log2eta = D->log2eta;
     const LiveCfg L = D->L;
+    const bool count = !a.expire_only;
+    if (SMALL && log2eta < 12u && count) {
+        // several estimators per wave: four rounds of 1 KiB, one estimator per
+        // 2^(log2eta-10) rounds; every estimator is whole in this wave
+        const uint32_t rpe = 1u << (log2eta - 10);       // rounds per estimator (1 or 2)
+        const uint32_t ne = 4u / rpe;                    // estimators of the wave
+        uint4* base = reinterpret_cast<uint4*>(D->state + (s << log2eta));
+        uint4 v[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) v[c] = base[c * 64u + lane];
+        uint32_t cnt[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            cnt[c] = __popc(live_bits(v[c].x, L)) + __popc(live_bits(v[c].y, L)) + __popc(live_bits(v[c].z, L)) +
+                     __popc(live_bits(v[c].w, L));
+        for (uint32_t e = 0; e < ne; e++) {
+            const uint64_t se_idx = s + e;
+            const bool expire = (se_idx % D->expire_period) == D->expire_phase;
+            uint32_t live = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                if ((uint32_t)c / rpe != e) continue;
+                live += cnt[c];
+                if (expire) {
+                    uint4 n;
+                    n.x = expire_word(v[c].x, L); n.y = expire_word(v[c].y, L);
+                    n.z = expire_word(v[c].z, L); n.w = expire_word(v[c].w, L);
+                    if (n.x != v[c].x || n.y != v[c].y || n.z != v[c].z || n.w != v[c].w) base[c * 64u + lane] = n;
+                }
+            }
+            live = wave_sum(live);
+            hot_finish(D, se_idx, live, base + (uint64_t)e * rpe * 64u, lane);
+        }
+        return;
+    }
     uint4* se = reinterpret_cast<uint4*>(D->state + (s << log2eta));
     const uint32_t per_lane = (1u << log2eta) >> 10;    // uint4 chunks per lane (eta >= 1024)
     const bool expire = (s % D->expire_period) == D->expire_phase;
-    const bool count = !a.expire_only;
     uint32_t live = 0;
     for (uint32_t g0 = 0; g0 < per_lane; g0 += CH) {
         uint4 v[CH];
@@ -460,31 +536,7 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
             }
         }
     }
-    if (count) {
-        live = wave_sum(live);
-        if (live >= D->T) {
-            // a hot estimator: snapshot its live cells, one bit each, for the
-            // final test (which then no longer reads the state)
-            const uint32_t chunks = 1u << (log2eta - 4);
-            uint16_t* snap = D->live16 + s * chunks;
-            for (uint32_t c = lane; c < chunks; c += 64u) snap[c] = (uint16_t)live_mask16(se[c], L);
-        }
-        if (lane == 0) {
-            D->rk[s] = live;
-            if (live >= D->T) {
-                const uint32_t q = D->q;
-                const uint32_t row = (uint32_t)(s >> q), c = (uint32_t)s & ((1u << q) - 1u);
-                const uint32_t sh = q - D->delta;
-                const uint32_t key = c & ((1u << sh) - 1u), j = c >> sh;
-                const uint32_t rw = q >= 6 ? (1u << (q - 6)) : 1u;    // words per row bitmask
-                atomicOr(reinterpret_cast<unsigned long long*>(D->hotbits) + (uint64_t)row * rw + (c >> 6),
-                         1ull << (c & 63u));
-                atomicOr(reinterpret_cast<unsigned long long*>(D->hotT) +
-                             ((uint64_t)row * (1ull << sh) + key) * D->nw + (j >> 6),
-                         1ull << (j & 63u));
-            }
-        }
-    }
+    if (count) hot_finish(D, s, wave_sum(live), se, lane);
 }
 
 // ---------------------------------------------------------------- hot lists
@@ -1149,14 +1201,22 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, hipStream_t s)
+hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, bool small, hipStream_t s)
 {
+    // SMALL: some link has eta < 4096 (several estimators per wave) or the
+    // engine has several links (link prefix in LDS); the plain variant keeps
+    // half the registers, so more waves stream the state
     const dim3 g((uint32_t)((a.total + DETECT_WAVES - 1) / DETECT_WAVES));
     const uint32_t bs = 64u * DETECT_WAVES;
-    if (max_chunks_per_lane >= 8) k_hot_detect<8><<<g, bs, 0, s>>>(a);
-    else if (max_chunks_per_lane >= 4) k_hot_detect<4><<<g, bs, 0, s>>>(a);
-    else if (max_chunks_per_lane >= 2) k_hot_detect<2><<<g, bs, 0, s>>>(a);
-    else k_hot_detect<1><<<g, bs, 0, s>>>(a);
+    if (small) {
+        if (max_chunks_per_lane >= 8) k_hot_detect<8, true><<<g, bs, 0, s>>>(a);
+        else k_hot_detect<4, true><<<g, bs, 0, s>>>(a);
+    } else {
+        if (max_chunks_per_lane >= 8) k_hot_detect<8, false><<<g, bs, 0, s>>>(a);
+        else if (max_chunks_per_lane >= 4) k_hot_detect<4, false><<<g, bs, 0, s>>>(a);
+        else if (max_chunks_per_lane >= 2) k_hot_detect<2, false><<<g, bs, 0, s>>>(a);
+        else k_hot_detect<1, false><<<g, bs, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -1179,7 +1239,11 @@ hipError_t launch_expand0(const LevelArgs& a, hipStream_t s)
 // workgroups of the depth-first expansion: each flushes its counts with one
 // atomic per level, so fewer is better until the grid stops filling the chip
 // (512 and 1024 measured equal, 2048 slower)
+// Grids of the close's small kernels (fewer workgroups, which would leave
+// more of the chip to the overlapping scan, made them slower than the scan:
+// 128/256 and 256/512 workgroups measured worse than 512/2048)
 constexpr uint32_t DFS_BLOCKS = 512;
+constexpr uint32_t VERIFY_BLOCKS = 2048;
 hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s)
 {
     if (max_r <= 6) k_expand_dfs<6><<<DFS_BLOCKS, 256, prefix_lds(a), s>>>(a);
@@ -1196,7 +1260,7 @@ hipError_t launch_extend(const LevelArgs& a, hipStream_t s)
 
 hipError_t launch_verify(const LevelArgs& a, hipStream_t s)
 {
-    k_verify<<<2048, 256, prefix_lds(a), s>>>(a);
+    k_verify<<<VERIFY_BLOCKS, 256, prefix_lds(a), s>>>(a);
     return hipGetLastError();
 }
 

@@ -138,6 +138,10 @@ void bin_capacity(const ssd_params& p, uint64_t* items_words, uint64_t* table_wo
 }
 
 uint32_t nw_of(const ssd_params& p) { return p.delta > 6 ? 1u << (p.delta - 6) : 1u; }
+
+// Hot detection waves of a link: one per estimator from eta = 4096 up, one
+// per 4 KiB of state below (k_hot_detect).
+uint64_t detect_waves(const LinkDesc& D) { return D.log2eta >= 12 ? D.n_se : D.n_se >> (12 - D.log2eta); }
 uint64_t row_words(const ssd_params& p) { return p.q >= 6 ? (1ull << (p.q - 6)) : 1ull; }
 
 struct LinkLayout {
@@ -236,6 +240,7 @@ struct Engine {
     bool broken = false;
     uint64_t se_total = 0;
     uint32_t rows_total = 0, max_r = 0, max_chunks = 1;
+    bool detect_small = false;          // a link with eta < 4096, or several links (k_hot_detect SMALL)
     std::vector<LinkDesc> hl;          // host copies of the device descriptors
     std::vector<uint32_t> tables;      // n x 2048
     // pinned host mailbox: control blocks, staged result entries, pack offsets
@@ -445,10 +450,11 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
         D.nw = nw_of(q);
         D.key_bits = q.key_bits;
         D.rehash = (q.flags & SSD_VERIFY_REHASH) ? 1u : 0u;
-        se_prefix[l + 1] = se_prefix[l] + D.n_se;
+        se_prefix[l + 1] = se_prefix[l] + detect_waves(D);
         for (uint32_t i = 0; i < q.r; i++) row_table.push_back((l << 8) | i);
         e->max_r = std::max(e->max_r, q.r);
         e->max_chunks = std::max(e->max_chunks, q.eta >> 10);
+        e->detect_small = e->detect_small || q.eta < 4096 || n > 1;
     }
     e->se_total = se_prefix[n];
     e->rows_total = (uint32_t)row_table.size();
@@ -507,7 +513,7 @@ int enqueue_close_head(Engine* e)
     da.n_links = e->n;
     da.total = e->se_total;
     PhaseMark pm = phase_begin(e);
-    HIPCHK(e, launch_hot_detect(da, e->max_chunks, s));
+    HIPCHK(e, launch_hot_detect(da, e->max_chunks, e->detect_small, s));
     phase_end(e, pm, 1, 1);
     return SSD_OK;
 }
@@ -689,7 +695,7 @@ int enqueue_advance_only(Engine* e)
     da.expire_only = 1;
     const uint64_t period = 255u - e->p[0].k;
     da.total = (e->hl[0].n_se + period - 1) / period;
-    HIPCHK(e, launch_hot_detect(da, e->max_chunks, s));
+    HIPCHK(e, launch_hot_detect(da, e->max_chunks, e->detect_small, s));
     HIPCHK(e, launch_advance(links, e->n, s));
     return SSD_OK;
 }
@@ -723,12 +729,27 @@ struct ssd_detector {
     uint32_t apply_segments = DEFAULT_APPLY_SEGMENTS;
     bool pending = false;               // a close begun and not yet ended
     uint64_t pending_prefix = 0;
-    hipEvent_t close_done = nullptr;    // recorded after the pending close
-    hipEvent_t head_done = nullptr;     // hot detection of the pending close done
-    hipStream_t tail_stream = nullptr;  // runs the close after hot detection
+    hipStream_t close_stream = nullptr; // runs the close after hot detection
+    hipEvent_t detect_done = nullptr;   // hot detection of the last close done
+    hipEvent_t close_done = nullptr;    // the last close done
     const ssd_params& p() const { return e.p[0]; }
     const LinkDesc& D() const { return e.hl[0]; }
 };
+
+namespace {
+
+// The second stream of a single detector and its events (created on first use).
+int detector_streams(ssd_detector* d)
+{
+    Engine* e = &d->e;
+    if (!d->detect_done) HIPCHK(e, hipEventCreateWithFlags(&d->detect_done, hipEventDisableTiming));
+    if (!d->close_done) HIPCHK(e, hipEventCreateWithFlags(&d->close_done, hipEventDisableTiming));
+    if (!d->close_stream) HIPCHK(e, hipStreamCreateWithFlags(&d->close_stream, hipStreamNonBlocking));
+    return SSD_OK;
+}
+
+
+}  // namespace
 
 // ---------------------------------------------------------------- batch
 
@@ -832,6 +853,7 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
     e->hl.resize(n);
     e->max_r = 0;
     e->max_chunks = 1;
+    e->detect_small = n > 1;
     std::vector<uint64_t> se_prefix(n + 1, 0);
     std::vector<uint32_t> row_table;
     for (uint32_t i = 0; i < n; i++) {
@@ -841,10 +863,11 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
         e->hl[i].host_ctl = nullptr;         // the group collects its members' lists itself
         e->hl[i].host_out = nullptr;
         e->hl[i].host_cap = 0;
-        se_prefix[i + 1] = se_prefix[i] + e->hl[i].n_se;
+        se_prefix[i + 1] = se_prefix[i] + detect_waves(e->hl[i]);
         for (uint32_t r = 0; r < e->p[i].r; r++) row_table.push_back((i << 8) | r);
         e->max_r = std::max(e->max_r, e->p[i].r);
         e->max_chunks = std::max(e->max_chunks, e->p[i].eta >> 10);
+        e->detect_small = e->detect_small || e->p[i].eta < 4096;
     }
     e->se_total = se_prefix[n];
     e->rows_total = (uint32_t)row_table.size();
@@ -917,13 +940,13 @@ void ssd_destroy(ssd_detector* d)
 {
     if (!d) return;
     (void)hipSetDevice(d->e.device);
-    if (d->tail_stream) {
-        if (!d->e.broken) (void)hipStreamSynchronize(d->tail_stream);
-        (void)hipStreamDestroy(d->tail_stream);
+    if (d->close_stream) {
+        if (!d->e.broken) (void)hipStreamSynchronize(d->close_stream);
+        (void)hipStreamDestroy(d->close_stream);
     }
     engine_release(&d->e);
-    if (d->close_done) (void)hipEventDestroy(d->close_done);
-    if (d->head_done) (void)hipEventDestroy(d->head_done);
+    for (hipEvent_t ev : {d->detect_done, d->close_done})
+        if (ev) (void)hipEventDestroy(ev);
     delete d;
 }
 
@@ -1045,23 +1068,25 @@ int ssd_close_begin(ssd_detector* d)
     int rc = usable(e);
     if (rc) return rc;
     if (d->pending) return fail(SSD_E_ORDER, "a close is already pending (ssd_close_end first)");
+    rc = detector_streams(d);
+    if (rc) return rc;
     // the sort kernel writes the first host_cap entries of the list into the
     // pinned mailbox; longer lists take a second copy when collected
     const uint64_t prefix = e->hl[0].host_cap;
-    if (!d->close_done) HIPCHK(e, hipEventCreateWithFlags(&d->close_done, hipEventDisableTiming));
-    if (!d->head_done) HIPCHK(e, hipEventCreateWithFlags(&d->head_done, hipEventDisableTiming));
-    if (!d->tail_stream) HIPCHK(e, hipStreamCreateWithFlags(&d->tail_stream, hipStreamNonBlocking));
-    // hot detection reuses the hot bitmasks and snapshots of the previous
-    // close: its second part must have finished
+    // hot detection on the caller's stream, after the slice's scans; it
+    // reuses the hot bitmasks and snapshots of the previous close, whose
+    // second part must have finished.  (Run on the second stream instead, hot
+    // detection overlapped with the next slice's binning and both slowed:
+    // 0.764 ms per core-link step against 0.714.)
     HIPCHK(e, hipStreamWaitEvent(e->stream, d->close_done, 0));
     rc = enqueue_close_head(e);
     if (rc) return rc;
-    // the rest of the close reads no state, so it runs on the second stream
+    HIPCHK(e, hipEventRecord(d->detect_done, e->stream));
+    // the rest of the close reads no state: it runs on the second stream
     // while the caller's stream goes on with the next slice's scans
-    HIPCHK(e, hipEventRecord(d->head_done, e->stream));
-    HIPCHK(e, hipStreamWaitEvent(d->tail_stream, d->head_done, 0));
+    HIPCHK(e, hipStreamWaitEvent(d->close_stream, d->detect_done, 0));
     const hipStream_t caller = e->stream;
-    e->stream = d->tail_stream;
+    e->stream = d->close_stream;
     rc = e->use_graph ? close_graph_tail(e, false, prefix) : enqueue_close_tail(e, false, prefix, false);
     if (rc == SSD_OK) {
         hipError_t err = hipEventRecord(d->close_done, e->stream);
@@ -1262,7 +1287,7 @@ int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t*
 int ssd_read_timing(ssd_detector* d, double* ms_out, uint64_t* launches_out, int reset)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    if (d->tail_stream && !d->e.broken) HIPCHK(&d->e, hipStreamSynchronize(d->tail_stream));
+    if (d->close_stream && !d->e.broken) HIPCHK(&d->e, hipStreamSynchronize(d->close_stream));
     return read_timing(&d->e, ms_out, launches_out, reset);
 }
 
