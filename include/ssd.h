@@ -208,11 +208,14 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_TUNE_GRAPH 5u           /* 1 (default) = replay the close as a HIP graph (detectors, batches) */
 #define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = time the candidate (pass window, tile)
                                        pairs on the next scans and keep the fastest */
-/*   SSD_TUNE_SCAN_MODE (single detectors): SSD_SCAN_PASSES = pass windows as
- *       above; SSD_SCAN_BINNED = each call's pairs are first sorted by state
- *       bin (SSD_TUNE_SCAN_BIN_BYTES, a power of two, default 2 MiB), then each
+/*   SSD_TUNE_SCAN_MODE: SSD_SCAN_PASSES = pass windows as above;
+ *       SSD_SCAN_BINNED = each call's pairs are first sorted by state bin
+ *       (SSD_TUNE_SCAN_BIN_BYTES, a power of two, default 2 MiB), then each
  *       bin's stores are made by workgroups of one XCD, inside its L2;
- *       SSD_SCAN_AUTO (default) = binned for states above 256 MiB, else passes. */
+ *       SSD_SCAN_AUTO (default) = binned for states above 256 MiB, else passes
+ *       (batches: the links above 256 MiB with at least 2^20 pairs in the call
+ *       are scanned binned, the others in the tile scan; batches take
+ *       SSD_SCAN_PASSES or SSD_SCAN_AUTO). */
 #define SSD_TUNE_SCAN_MODE 7u
 #define SSD_TUNE_SCAN_BIN_BYTES 8u
 #define SSD_TUNE_SCAN_APPLY_SEGMENTS 9u   /* binned: binning segments per store workgroup (default 2) */

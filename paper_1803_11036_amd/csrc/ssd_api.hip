@@ -109,6 +109,8 @@ constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 2;
 // core-link state, slower on a 24 MiB state that the Infinity Cache holds)
 constexpr uint64_t AUTO_BINNED_ABOVE = 256ull << 20;
 constexpr uint32_t PHASE_SCAN_BIN = 8;
+// batch links scanned binned: a large state and at least this many pairs
+constexpr uint64_t BATCH_BINNED_MIN_PAIRS = 1ull << 20;
 // Candidate expansion: depth first in one launch up to this many rows (its
 // per-row loop state is held in registers), level by level above.
 constexpr uint32_t DFS_MAX_ROWS = 8;
@@ -208,7 +210,14 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     L.sort_tmp = o; o = align_up(o + pw * 8);
     L.packed = o; o = align_up(o + pack_cap * sizeof(SuperPointDev));
     if (bins) {
-        bin_capacity(p[0], &L.bin_items_words, &L.bin_table_words);
+        // shared by the links scanned binned, one after another: the largest
+        for (uint32_t l = 0; l < n; l++) {
+            if (n > 1 && ((uint64_t)p[l].r << p[l].q) * p[l].eta <= AUTO_BINNED_ABOVE) continue;
+            uint64_t iw = 0, tw = 0;
+            bin_capacity(p[l], &iw, &tw);
+            L.bin_items_words = std::max(L.bin_items_words, iw);
+            L.bin_table_words = std::max(L.bin_table_words, tw);
+        }
         L.bin_items = o; o = align_up(o + L.bin_items_words * 4);
         L.bin_table = o; o = align_up(o + L.bin_table_words * 4);
     }
@@ -399,7 +408,7 @@ int engine_query(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t ti
 
 int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tables, void* state_dev,
                 uint64_t state_bytes, void* scratch_dev, uint64_t scratch_bytes, void* stream, uint64_t pack_cap,
-                uint64_t tile_cap, uint64_t stage_cap, bool bins = false)
+                uint64_t tile_cap, uint64_t stage_cap, bool bins = false, bool single = false)
 {
     int rc = engine_query(p, n, pack_cap, tile_cap, nullptr, nullptr, bins);
     if (rc) return rc;
@@ -467,7 +476,7 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     e->mb_ctl = static_cast<Ctl*>(e->pinned);
     e->mb_stage = reinterpret_cast<SuperPointDev*>(e->mb_ctl + n);
     e->mb_offsets = reinterpret_cast<unsigned long long*>(e->mb_stage + stage_cap);
-    if (bins && n == 1) {
+    if (single) {
         // a single detector's close writes its control block and list into
         // the mailbox directly (no copies after the sort)
         void* dctl = nullptr;
@@ -500,6 +509,49 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
 // per-slice constants, hot bits cleared, hot detection, hot lists, the
 // candidate levels, the final test, sorting, then the control blocks (and, for
 // batches, the packed lists) to pinned memory, and the clock advance.
+// Binned scan (k_bin, then k_apply) of n pairs of link l, in steps that fit
+// the engine's bin buffers (shared by every binned link of a batch: the steps
+// run one after another on the engine's stream).
+int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs)
+{
+    const LinkDesc& D = e->hl[l];
+    const BinPlan bp = bin_plan(e->p[l], bin_bytes);
+    const uint64_t seg = (uint64_t)bp.pb * D.r;
+    const uint64_t max_blocks = std::min(e->L.bin_items_words / seg, e->L.bin_table_words / (bp.n_bins + 1));
+    const uint64_t chunk = max_blocks * bp.pb;
+    if (chunk == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
+    BinArgs ba{};
+    ba.tables = D.tables;
+    ba.items = e->at<uint32_t>(e->L.bin_items);
+    ba.table = e->at<uint32_t>(e->L.bin_table);
+    ba.q = D.q; ba.r = D.r; ba.delta = D.delta; ba.log2eta = D.log2eta;
+    ba.bin_shift = bp.shift; ba.n_bins = bp.n_bins; ba.pb = bp.pb;
+    ApplyArgs aa{};
+    aa.items = ba.items;
+    aa.table = ba.table;
+    aa.state = D.state;
+    aa.n_bins = bp.n_bins;
+    aa.seg = (uint32_t)seg;
+    aa.bin_shift = bp.shift;
+    aa.per_part = segs;
+    aa.stamp = stamp_of(e->clock);
+    for (uint64_t done = 0; done < n; done += chunk) {
+        const uint64_t m = std::min(chunk, n - done);
+        ba.pairs = pairs + done;
+        ba.n = m;
+        ba.blocks = (uint32_t)((m + bp.pb - 1) / bp.pb);
+        aa.blocks = ba.blocks;
+        aa.parts = (ba.blocks + aa.per_part - 1) / aa.per_part;
+        PhaseMark pm = phase_begin(e);
+        HIPCHK(e, launch_bin(ba, e->stream));
+        phase_end(e, pm, PHASE_SCAN_BIN, 1);
+        pm = phase_begin(e);
+        HIPCHK(e, launch_apply(aa, e->stream));
+        phase_end(e, pm, 0, 1);
+    }
+    return SSD_OK;
+}
+
 // The close, first part: per-slice constants, hot bitmasks cleared, hot
 // detection over every estimator (one large launch, always eager and timed).
 int enqueue_close_head(Engine* e)
@@ -755,6 +807,7 @@ int detector_streams(ssd_detector* d)
 
 struct ssd_batch {
     Engine e;
+    uint32_t scan_mode = SSD_SCAN_AUTO;   // SSD_SCAN_PASSES: every link in the tile scan
     uint64_t pass_bytes = DEFAULT_PASS_BYTES;
     uint64_t tile_pairs = DEFAULT_TILE_PAIRS;
     // pinned double-buffered window lists for the persistent scan
@@ -925,7 +978,7 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
     ssd_detector* d = new (std::nothrow) ssd_detector();
     if (!d) return fail(SSD_E_NOMEM, "host allocation failed");
     rc = engine_init(&d->e, p, 1, tables_host, state_dev, state_bytes, scratch_dev, scratch_bytes, stream, 0, 0,
-                     PREFIX_MAX, true);
+                     PREFIX_MAX, true, true);
     if (rc) {
         engine_release(&d->e);
         delete d;
@@ -998,43 +1051,8 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
     if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
     const LinkDesc& D = d->D();
     const uint64_t state_bytes = D.n_se << D.log2eta;
-    if (d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE)) {
-        const BinPlan bp = bin_plan(d->p(), d->bin_bytes);
-        const uint64_t seg = (uint64_t)bp.pb * D.r;
-        const uint64_t max_blocks = std::min(e->L.bin_items_words / seg, e->L.bin_table_words / (bp.n_bins + 1));
-        const uint64_t chunk = max_blocks * bp.pb;
-        if (chunk == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
-        BinArgs ba{};
-        ba.tables = D.tables;
-        ba.items = e->at<uint32_t>(e->L.bin_items);
-        ba.table = e->at<uint32_t>(e->L.bin_table);
-        ba.q = D.q; ba.r = D.r; ba.delta = D.delta; ba.log2eta = D.log2eta;
-        ba.bin_shift = bp.shift; ba.n_bins = bp.n_bins; ba.pb = bp.pb;
-        ApplyArgs aa{};
-        aa.items = ba.items;
-        aa.table = ba.table;
-        aa.state = D.state;
-        aa.n_bins = bp.n_bins;
-        aa.seg = (uint32_t)seg;
-        aa.bin_shift = bp.shift;
-        aa.per_part = d->apply_segments;
-        aa.stamp = stamp_of(e->clock);
-        for (uint64_t done = 0; done < n; done += chunk) {
-            const uint64_t m = std::min(chunk, n - done);
-            ba.pairs = reinterpret_cast<const uint2*>(pairs_dev) + done;
-            ba.n = m;
-            ba.blocks = (uint32_t)((m + bp.pb - 1) / bp.pb);
-            aa.blocks = ba.blocks;
-            aa.parts = (ba.blocks + aa.per_part - 1) / aa.per_part;
-            PhaseMark pm = phase_begin(e);
-            HIPCHK(e, launch_bin(ba, e->stream));
-            phase_end(e, pm, PHASE_SCAN_BIN, 1);
-            pm = phase_begin(e);
-            HIPCHK(e, launch_apply(aa, e->stream));
-            phase_end(e, pm, 0, 1);
-        }
-        return SSD_OK;
-    }
+    if (d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE))
+        return enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes, d->apply_segments);
     ScanArgs a{};
     a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
     a.n = n;
@@ -1313,9 +1331,19 @@ int ssd_get_info(ssd_detector* d, ssd_info* out)
 
 // ---- batch
 
+// a batch keeps bin buffers when some link's state is large enough for the
+// binned scan
+bool batch_bins(const ssd_params* p, uint32_t n)
+{
+    if (!p) return false;
+    for (uint32_t l = 0; l < n && l < MAX_LINKS; l++)
+        if (((uint64_t)p[l].r << p[l].q) * p[l].eta > AUTO_BINNED_ABOVE) return true;
+    return false;
+}
+
 int ssd_batch_query_sizes(const ssd_params* p, uint32_t n, uint64_t* state_bytes, uint64_t* scratch_bytes)
 {
-    return engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, state_bytes, scratch_bytes);
+    return engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, state_bytes, scratch_bytes, batch_bins(p, n));
 }
 
 int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host, void* state_dev,
@@ -1323,12 +1351,13 @@ int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host,
 {
     if (!out) return fail(SSD_E_PARAM, "out is NULL");
     *out = nullptr;
-    int rc = engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, nullptr, nullptr);
+    const bool bins = batch_bins(p, n);
+    int rc = engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, nullptr, nullptr, bins);
     if (rc) return rc;
     ssd_batch* b = new (std::nothrow) ssd_batch();
     if (!b) return fail(SSD_E_NOMEM, "host allocation failed");
     rc = engine_init(&b->e, p, n, tables_host, state_dev, state_bytes, scratch_dev, scratch_bytes, stream,
-                     BATCH_STAGE, MAX_WINDOWS, BATCH_STAGE);
+                     BATCH_STAGE, MAX_WINDOWS, BATCH_STAGE, bins);
     if (rc == SSD_OK) {
         b->e.use_graph = true;
         for (int i = 0; i < 2 && rc == SSD_OK; i++) {
@@ -1379,6 +1408,11 @@ int ssd_batch_set_tuning(ssd_batch* b, uint32_t knob, uint64_t value)
         return SSD_OK;
     case SSD_TUNE_TIMING: b->e.timing = value != 0; return SSD_OK;
     case SSD_TUNE_GRAPH: b->e.use_graph = value != 0; return SSD_OK;
+    case SSD_TUNE_SCAN_MODE:
+        if (value != SSD_SCAN_PASSES && value != SSD_SCAN_AUTO)
+            return fail(SSD_E_PARAM, "batches take SSD_SCAN_PASSES or SSD_SCAN_AUTO");
+        b->scan_mode = (uint32_t)value;
+        return SSD_OK;
     case SSD_TUNE_AUTOTUNE:
         if (!value) { b->tune_idx = -1; return SSD_OK; }
         b->cands.clear();
@@ -1425,65 +1459,86 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
         pass = b->cands[cand].pass;
         tile = b->cands[cand].tile;
     }
-    // windows of every link's state, ordered by address; tiles are implicit
+    // links with a large state and enough pairs take the binned scan (as a
+    // separate detector would); the others share one persistent tile scan
+    std::vector<uint32_t> binned;
+    if (b->scan_mode != SSD_SCAN_PASSES && e->L.bin_items_words) {
+        for (uint32_t l = 0; l < e->n; l++)
+            if ((e->hl[l].n_se << e->hl[l].log2eta) > AUTO_BINNED_ABOVE &&
+                offsets_host[l + 1] - offsets_host[l] >= BATCH_BINNED_MIN_PAIRS)
+                binned.push_back(l);
+    }
+    auto is_binned = [&](uint32_t l) { return std::find(binned.begin(), binned.end(), l) != binned.end(); };
+    // windows of every other link's state, ordered by address; tiles are implicit
     struct Win { uint64_t at; uint32_t link; uint64_t lo, hi; };
     std::vector<Win> wins;
     for (uint32_t l = 0; l < e->n; l++) {
-        if (offsets_host[l + 1] == offsets_host[l]) continue;
+        if (offsets_host[l + 1] == offsets_host[l] || is_binned(l)) continue;
         const LinkDesc& D = e->hl[l];
         const uint64_t per = pass ? std::max<uint64_t>(1, pass / D.eta) : D.n_se;
         for (uint64_t lo = 0; lo < D.n_se; lo += per)
             wins.push_back({e->L.link[l].state_off + lo * D.eta, l, lo, std::min(lo + per, D.n_se)});
     }
     if (wins.size() > MAX_WINDOWS) return fail(SSD_E_PARAM, "scan pass window too small: %zu windows", wins.size());
+    if (wins.empty()) cand = -1;
     std::sort(wins.begin(), wins.end(), [](const Win& a, const Win& c) { return a.at < c.at; });
-    const uint32_t buf = b->tile_next;
-    b->tile_next ^= 1u;
-    if (b->tile_used[buf]) HIPCHK(e, hipEventSynchronize(b->tile_done[buf]));   // its last copy has run
-    unsigned long long* counter = static_cast<unsigned long long*>(b->tile_pinned[buf]);
-    ScanWindow* ws = reinterpret_cast<ScanWindow*>(counter + 1);
-    *counter = 0;
-    uint64_t tiles = 0;
-    for (size_t i = 0; i < wins.size(); i++) {
-        const Win& w = wins[i];
-        ScanWindow& W = ws[i];
-        W.link = w.link;
-        W.pad = 0;
-        W.start = offsets_host[w.link];
-        W.n = offsets_host[w.link + 1] - W.start;
-        W.se_lo = w.lo;
-        W.se_hi = w.hi;
-        W.tile_base = tiles;
-        W.stamp = stamp_of(e->clock);
-        W.pad2 = 0;
-        tiles += (W.n + tile - 1) / tile;
+    uint64_t tile_pairs_total = 0;
+    for (uint32_t l = 0; l < e->n; l++)
+        if (!is_binned(l)) tile_pairs_total += offsets_host[l + 1] - offsets_host[l];
+    if (!wins.empty()) {
+        const uint32_t buf = b->tile_next;
+        b->tile_next ^= 1u;
+        if (b->tile_used[buf]) HIPCHK(e, hipEventSynchronize(b->tile_done[buf]));   // its last copy has run
+        unsigned long long* counter = static_cast<unsigned long long*>(b->tile_pinned[buf]);
+        ScanWindow* ws = reinterpret_cast<ScanWindow*>(counter + 1);
+        *counter = 0;
+        uint64_t tiles = 0;
+        for (size_t i = 0; i < wins.size(); i++) {
+            const Win& w = wins[i];
+            ScanWindow& W = ws[i];
+            W.link = w.link;
+            W.pad = 0;
+            W.start = offsets_host[w.link];
+            W.n = offsets_host[w.link + 1] - W.start;
+            W.se_lo = w.lo;
+            W.se_hi = w.hi;
+            W.tile_base = tiles;
+            W.stamp = stamp_of(e->clock);
+            W.pad2 = 0;
+            tiles += (W.n + tile - 1) / tile;
+        }
+        unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
+        HIPCHK(e, hipMemcpyAsync(dcounter, counter, 8 + wins.size() * sizeof(ScanWindow), hipMemcpyHostToDevice,
+                                 e->stream));
+        HIPCHK(e, hipEventRecord(b->tile_done[buf], e->stream));
+        b->tile_used[buf] = true;
+        TileScanArgs a{};
+        a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
+        a.links = e->dev_links();
+        a.wins = reinterpret_cast<const ScanWindow*>(dcounter + 1);
+        a.counter = dcounter;
+        a.n_wins = (uint32_t)wins.size();
+        a.n_tiles = tiles;
+        a.tile = tile;
+        hipEvent_t ta = nullptr, tb = nullptr;
+        if (cand >= 0) {
+            HIPCHK(e, hipEventCreate(&ta));
+            HIPCHK(e, hipEventCreate(&tb));
+            HIPCHK(e, hipEventRecord(ta, e->stream));
+        }
+        PhaseMark pm = phase_begin(e);
+        HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(b->scan_blocks, tiles), e->stream));
+        phase_end(e, pm, 0, 1);
+        if (cand >= 0) {
+            HIPCHK(e, hipEventRecord(tb, e->stream));
+            b->tune_pending.push_back({cand, tile_pairs_total});
+            b->tune_events.push_back({ta, tb});
+        }
     }
-    unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
-    HIPCHK(e, hipMemcpyAsync(dcounter, counter, 8 + wins.size() * sizeof(ScanWindow), hipMemcpyHostToDevice,
-                             e->stream));
-    HIPCHK(e, hipEventRecord(b->tile_done[buf], e->stream));
-    b->tile_used[buf] = true;
-    TileScanArgs a{};
-    a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
-    a.links = e->dev_links();
-    a.wins = reinterpret_cast<const ScanWindow*>(dcounter + 1);
-    a.counter = dcounter;
-    a.n_wins = (uint32_t)wins.size();
-    a.n_tiles = tiles;
-    a.tile = tile;
-    hipEvent_t ta = nullptr, tb = nullptr;
-    if (cand >= 0) {
-        HIPCHK(e, hipEventCreate(&ta));
-        HIPCHK(e, hipEventCreate(&tb));
-        HIPCHK(e, hipEventRecord(ta, e->stream));
-    }
-    PhaseMark pm = phase_begin(e);
-    HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(b->scan_blocks, tiles), e->stream));
-    phase_end(e, pm, 0, 1);
-    if (cand >= 0) {
-        HIPCHK(e, hipEventRecord(tb, e->stream));
-        b->tune_pending.push_back({cand, total_pairs});
-        b->tune_events.push_back({ta, tb});
+    for (uint32_t l : binned) {
+        rc = enqueue_binned_scan(e, l, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[l],
+                                 offsets_host[l + 1] - offsets_host[l], DEFAULT_BIN_BYTES, DEFAULT_APPLY_SEGMENTS);
+        if (rc) return rc;
     }
     return SSD_OK;
 }

@@ -66,6 +66,34 @@ def test_batch_equals_separate_detectors(graph, autotune):
         d.destroy()
 
 
+def test_batch_binned_links_equal_separate_detectors():
+    """Links with a state above 256 MiB and at least 2^20 pairs in the call
+    take the binned scan inside the batch (the rest the tile scan); every
+    link's list equals its separate detector's."""
+    cfgs = tg.batch_configs(n_links=12, pairs_scale=0.5)
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    b = ssd.batch_init([_params(c) for c in cfgs], tabs, device="cuda:0")
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_TIMING, 1)
+    plain = [ssd.init_detector(_params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    big = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > 256 << 20 and c.pairs_lo >= 1 << 20]
+    assert big, "no link takes the binned scan"
+    for t in range(4):
+        per, offs, dev = _slice_pairs(traces, t)
+        ssd.batch_scan(b, dev, offs, t)
+        lists, status = ssd.batch_close(b)
+        assert np.all(status == 0)
+        for i in range(len(cfgs)):
+            ssd.scan_slice(plain[i], dev[int(offs[i]):int(offs[i + 1])], t)
+            res = ssd.close_slice(plain[i])
+            assert np.array_equal(lists[i], res), f"slice {t} link {i}: batch and separate detector differ"
+        log(f"batch binned slice {t}: {sum(len(x) for x in lists)} hosts, binned links {big}")
+    assert ssd.batch_read_timing(b)["scan_bin"][1] >= 4 * len(big)
+    b.destroy()
+    for d in plain:
+        d.destroy()
+
+
 def test_batch_overflow_is_per_link():
     """Links whose candidate capacity is exceeded report SSD_E_OVERFLOW and
     nothing else; every other link still matches its separate detector."""
