@@ -356,6 +356,66 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
     for (uint32_t i = threadIdx.x; i < np * r; i += 1024u) seg[i] = stage[i];
 }
 
+// The same sort for the common row counts with every item kept in registers
+// between the two passes (R rows, up to PPT pairs per thread): the pairs are
+// hashed once, and each offset's rank in its bin comes from the count pass.
+template <int R, int PPT>
+__global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wsum[16];
+    uint32_t* tab = lds;
+    uint32_t* hist = lds + 2048;
+    uint32_t* stage = hist + a.n_bins + 1;
+    for (uint32_t i = threadIdx.x; i < 2048u; i += 1024u) tab[i] = a.tables[i];
+    for (uint32_t i = threadIdx.x; i <= a.n_bins; i += 1024u) hist[i] = 0u;
+    __syncthreads();
+    const uint64_t p0 = (uint64_t)blockIdx.x * a.pb;
+    const uint32_t np = (uint32_t)min((uint64_t)a.pb, a.n - p0);
+    const uint32_t q = a.q, delta = a.delta, log2eta = a.log2eta, bs = a.bin_shift;
+    const uint32_t bmask = (1u << bs) - 1u;
+    uint32_t off[PPT][R], key[PPT][R];
+#pragma unroll
+    for (int u = 0; u < PPT; u++) {
+        const uint32_t p = threadIdx.x + u * 1024u;
+        if (p >= np) continue;
+        const uint2 pr = a.pairs[p0 + p];
+        uint32_t h0, d;
+        pair_hashes(tab, pr, q, log2eta, &h0, &d);
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const uint64_t addr = cell_addr(pr, i, h0, d, q, delta, log2eta);
+            const uint32_t bin = (uint32_t)(addr >> bs);
+            off[u][i] = (uint32_t)addr & bmask;
+            key[u][i] = (bin << 16) | atomicAdd(&hist[bin], 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t per = (a.n_bins + 1023u) / 1024u;
+    const uint32_t b0 = min(a.n_bins, threadIdx.x * per), b1 = min(a.n_bins, b0 + per);
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; b++) sum += hist[b];
+    uint32_t total;
+    uint32_t start = block_exclusive_scan_1024(sum, wsum, &total);
+    for (uint32_t b = b0; b < b1; b++) {
+        const uint32_t c = hist[b];
+        hist[b] = start;
+        a.table[(uint64_t)b * a.blocks + blockIdx.x] = start;
+        start += c;
+    }
+    if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + blockIdx.x] = np * R;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PPT; u++) {
+        if (threadIdx.x + u * 1024u >= np) continue;
+#pragma unroll
+        for (int i = 0; i < R; i++) stage[hist[key[u][i] >> 16] + (key[u][i] & 0xFFFFu)] = off[u][i];
+    }
+    __syncthreads();
+    uint32_t* seg = a.items + (uint64_t)blockIdx.x * a.pb * R;
+    for (uint32_t i = threadIdx.x; i < np * R; i += 1024u) seg[i] = stage[i];
+}
+
 // One wave per workgroup.  Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w /
 // parts)-th bin from the top with w = g / 8, segments [part * per_part, ...),
 // 64 segments per round: lane j holds segment j's run of the bin, and the
@@ -1184,12 +1244,16 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t s)
     if (a.blocks == 0 || words > BIN_LDS_WORDS) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bin),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
-        if (e != hipSuccess) return e;
+        for (const void* f : {reinterpret_cast<const void*>(&k_bin), reinterpret_cast<const void*>(&k_bin_reg<6, 6>),
+                              reinterpret_cast<const void*>(&k_bin_reg<5, 7>)}) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
+            if (e != hipSuccess) return e;
+        }
         attr = true;
     }
-    k_bin<<<a.blocks, 1024, words * 4u, s>>>(a);
+    if (a.r == 6 && a.pb <= 6u * 1024u) k_bin_reg<6, 6><<<a.blocks, 1024, words * 4u, s>>>(a);
+    else if (a.r == 5 && a.pb <= 7u * 1024u) k_bin_reg<5, 7><<<a.blocks, 1024, words * 4u, s>>>(a);
+    else k_bin<<<a.blocks, 1024, words * 4u, s>>>(a);
     return hipGetLastError();
 }
 

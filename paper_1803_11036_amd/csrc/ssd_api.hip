@@ -125,6 +125,10 @@ BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
     while (((state + (1ull << b.shift) - 1) >> b.shift) > MAX_BINS) b.shift++;
     b.n_bins = (uint32_t)((state + (1ull << b.shift) - 1) >> b.shift);
     b.pb = (BIN_LDS_WORDS - 2048u - b.n_bins - 1u) / p.r;
+    // rows 5 and 6 keep every pair's offsets in registers (k_bin_reg): at
+    // most 7 and 6 pairs per thread
+    if (p.r == 6) b.pb = std::min<uint32_t>(b.pb, 6u * 1024u);
+    if (p.r == 5) b.pb = std::min<uint32_t>(b.pb, 7u * 1024u);
     return b;
 }
 // Item and table words that every allowed bin size fits, for chunks of up to
