@@ -107,6 +107,7 @@ struct BinArgs {
     uint32_t* table;              // [n_bins + 1][blocks] start of bin b in segment j; row n_bins = item count
     uint32_t q, r, delta, log2eta;
     uint32_t bin_shift, n_bins, pb, blocks;
+    uint32_t pack, pad;           // 1: three 21-bit offsets per 8-byte word (bins of at most 2 MiB)
 };
 
 // binned scan, step 2: the stores of every bin
@@ -116,7 +117,7 @@ struct ApplyArgs {
     uint8_t* state;
     uint32_t n_bins, blocks, seg, bin_shift;
     uint32_t parts, per_part;     // workgroups per bin, segments per workgroup
-    uint32_t stamp, pad;
+    uint32_t stamp, pack;         // pack: as BinArgs::pack
 };
 
 struct DetectArgs {

@@ -303,6 +303,36 @@ __device__ __forceinline__ uint64_t cell_addr(uint2 pr, uint32_t i, uint32_t h0,
 }
 
 
+// A workgroup's sorted offsets out to its segment, coalesced: 4 bytes each, or
+// (bins of at most 2 MiB) three 21-bit offsets per 8-byte word.
+__device__ __forceinline__ void write_segment(const BinArgs& a, const uint32_t* stage, uint32_t n)
+{
+    const uint64_t seg_items = (uint64_t)a.pb * a.r;
+    if (a.pack) {
+        uint64_t* seg = reinterpret_cast<uint64_t*>(a.items) + (uint64_t)blockIdx.x * ((seg_items + 2) / 3);
+        for (uint32_t w = threadIdx.x; w * 3u < n; w += 1024u) {
+            const uint32_t i = w * 3u;
+            uint64_t v = stage[i];
+            if (i + 1 < n) v |= (uint64_t)stage[i + 1] << 21;
+            if (i + 2 < n) v |= (uint64_t)stage[i + 2] << 42;
+            seg[w] = v;
+        }
+    } else {
+        uint32_t* seg = a.items + (uint64_t)blockIdx.x * seg_items;
+        for (uint32_t i = threadIdx.x; i < n; i += 1024u) seg[i] = stage[i];
+    }
+}
+
+// Item i of segment j as written by write_segment.
+__device__ __forceinline__ uint32_t read_item(const ApplyArgs& a, uint32_t j, uint32_t i)
+{
+    if (a.pack) {
+        const uint64_t w = reinterpret_cast<const uint64_t*>(a.items)[(uint64_t)j * ((a.seg + 2u) / 3u) + i / 3u];
+        return (uint32_t)(w >> (21u * (i % 3u))) & 0x1FFFFFu;
+    }
+    return a.items[(uint64_t)j * a.seg + i];
+}
+
 // Up to 160 KiB of LDS per workgroup: about 6000 pairs, so that the run of
 // one bin in one segment is long (about 50 offsets at 2 MiB bins) and
 // k_apply's reads of the runs are dense.  Pass 1 counts the bins' offsets,
@@ -352,8 +382,7 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
         }
     }
     __syncthreads();
-    uint32_t* seg = a.items + (uint64_t)blockIdx.x * a.pb * r;
-    for (uint32_t i = threadIdx.x; i < np * r; i += 1024u) seg[i] = stage[i];
+    write_segment(a, stage, np * r);
 }
 
 // The same sort for the common row counts with every item kept in registers
@@ -412,8 +441,7 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
         for (int i = 0; i < R; i++) stage[hist[key[u][i] >> 16] + (key[u][i] & 0xFFFFu)] = off[u][i];
     }
     __syncthreads();
-    uint32_t* seg = a.items + (uint64_t)blockIdx.x * a.pb * R;
-    for (uint32_t i = threadIdx.x; i < np * R; i += 1024u) seg[i] = stage[i];
+    write_segment(a, stage, np * R);
 }
 
 // One wave per workgroup.  Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w /
@@ -459,7 +487,7 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
             }
             const uint32_t rs = __shfl(st, (int)lo, 64);
             const uint32_t re = __shfl(excl, (int)lo, 64);
-            if (t < total) base[a.items[(uint64_t)(jb + lo) * a.seg + rs + (t - re)]] = stamp;
+            if (t < total) base[read_item(a, jb + lo, rs + (t - re))] = stamp;
         }
     }
 }

@@ -530,7 +530,9 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
     ba.table = e->at<uint32_t>(e->L.bin_table);
     ba.q = D.q; ba.r = D.r; ba.delta = D.delta; ba.log2eta = D.log2eta;
     ba.bin_shift = bp.shift; ba.n_bins = bp.n_bins; ba.pb = bp.pb;
+    ba.pack = bp.shift <= 21 ? 1u : 0u;
     ApplyArgs aa{};
+    aa.pack = ba.pack;
     aa.items = ba.items;
     aa.table = ba.table;
     aa.state = D.state;

@@ -175,10 +175,11 @@ def test_scan_pass_windows_do_not_change_state():
         close_both(g, o, check_internals=False)
 
 
-@pytest.mark.parametrize("bin_kib", [256, 2048])
+@pytest.mark.parametrize("bin_kib", [256, 2048, 4096])
 def test_binned_scan_matches_oracle(bin_kib):
-    """The bin-sorted scan (96 or 12 bins over the 24 MiB state) gives the
-    oracle's state and lists, also for one call of 3.5M pairs (three binning
+    """The bin-sorted scan (96, 12 or 6 bins over the 24 MiB state; offsets
+    packed three to a word up to 2 MiB bins, 4 bytes each above) gives the
+    oracle's state and lists, also for one call of 3.5M pairs (several binning
     chunks, the last one ragged) and for a slice split over five calls."""
     cfg = tg.config("tiny")
     tr = tg.Trace(cfg)
