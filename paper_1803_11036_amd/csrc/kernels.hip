@@ -503,10 +503,11 @@ constexpr uint32_t DETECT_WAVES = 4;   // waves (estimators) per workgroup (4, 8
 // The end of one estimator's test: R_k, and if hot, its live-cell snapshot
 // (for the final test, which then reads no state) and its bits in the row
 // and key-transposed bitmasks.
+template <bool SNAP>
 __device__ __forceinline__ void hot_finish(const LinkDesc* D, uint64_t s, uint32_t live, const uint4* se, uint32_t lane)
 {
     const uint32_t log2eta = D->log2eta;
-    if (live >= D->T) {
+    if (SNAP && live >= D->T) {
         const uint32_t chunks = 1u << (log2eta - 4);
         uint16_t* snap = D->live16 + s * chunks;
         for (uint32_t c = lane; c < chunks; c += 64u) snap[c] = (uint16_t)live_mask16(se[c], D->L);
@@ -592,7 +593,7 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
                 }
             }
             live = wave_sum(live);
-            hot_finish(D, se_idx, live, base + (uint64_t)e * rpe * 64u, lane);
+            hot_finish<true>(D, se_idx, live, base + (uint64_t)e * rpe * 64u, lane);
         }
         return;
     }
@@ -600,8 +601,8 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
     const uint32_t per_lane = (1u << log2eta) >> 10;    // uint4 chunks per lane (eta >= 1024)
     const bool expire = (s % D->expire_period) == D->expire_phase;
     uint32_t live = 0;
+    uint4 v[CH];                                        // the last group stays for the snapshot
     for (uint32_t g0 = 0; g0 < per_lane; g0 += CH) {
-        uint4 v[CH];
 #pragma unroll
         for (int c = 0; c < CH; c++)
             v[c] = (g0 + c < per_lane) ? se[(g0 + c) * 64u + lane] : make_uint4(0u, 0u, 0u, 0u);
@@ -624,7 +625,19 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
             }
         }
     }
-    if (count) hot_finish(D, s, wave_sum(live), se, lane);
+    if (count) {
+        live = wave_sum(live);
+        if (per_lane <= (uint32_t)CH && live >= D->T) {
+            // the whole estimator is still in registers: snapshot from there
+            uint16_t* snap = D->live16 + s * (per_lane * 64u);
+#pragma unroll
+            for (int c = 0; c < CH; c++)
+                if ((uint32_t)c < per_lane) snap[c * 64u + lane] = (uint16_t)live_mask16(v[c], L);
+            hot_finish<false>(D, s, live, se, lane);
+        } else {
+            hot_finish<true>(D, s, live, se, lane);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- hot lists
