@@ -868,6 +868,7 @@ void autotune_collect(ssd_batch* b)
 struct ssd_group {
     Engine e;                          // header-only engine over the bound members
     uint32_t max_members = 0;
+    uint32_t scan_blocks = 2048;       // tile-scan workgroups: 8 per compute unit
     std::vector<uint64_t> bound;       // ids of the members whose descriptors are on the device
 };
 
@@ -1633,6 +1634,8 @@ int ssd_group_init(uint32_t max_members, void* scratch_dev, uint64_t scratch_byt
     e->mb_ctl = static_cast<Ctl*>(e->pinned);
     e->mb_stage = reinterpret_cast<SuperPointDev*>(e->mb_ctl + max_members);
     e->mb_offsets = reinterpret_cast<unsigned long long*>(e->mb_stage + BATCH_STAGE);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, e->device) == hipSuccess) g->scan_blocks = (uint32_t)prop.multiProcessorCount * 8u;
     *out = g;
     return SSD_OK;
 }
@@ -1662,14 +1665,26 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     }
     if (offsets_host[n] == offsets_host[0]) return SSD_OK;
     if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
-    // windows of every member's state (its own pass window), in member order
+    // members that a call of their own would scan binned (large state, enough
+    // pairs) are scanned binned here too, with their own bin buffers, after
+    // the tile scan of the others -- when they were set up on the group's
+    // stream, so that the group's close stays ordered after their scan
+    auto binned = [&](uint32_t i) {
+        const ssd_detector* m = members[i];
+        if (m->e.stream != e->stream) return false;
+        const uint64_t np = offsets_host[i + 1] - offsets_host[i];
+        const uint64_t sb = e->hl[i].n_se << e->hl[i].log2eta;
+        return m->scan_mode != SSD_SCAN_PASSES && np >= BATCH_BINNED_MIN_PAIRS &&
+               (m->scan_mode == SSD_SCAN_BINNED || sb > AUTO_BINNED_ABOVE);
+    };
+    // windows of every other member's state (its own pass window), in member order
     std::vector<ScanWindow> ws;
     uint64_t tiles = 0;
     const uint64_t tile = DEFAULT_TILE_PAIRS;
     ws.push_back({});   // slot for the counter (8 bytes) ahead of the windows
     for (uint32_t i = 0; i < n; i++) {
         const uint64_t np = offsets_host[i + 1] - offsets_host[i];
-        if (!np) continue;
+        if (!np || binned(i)) continue;
         const LinkDesc& D = e->hl[i];
         const uint64_t pass = members[i]->pass_bytes;
         const uint64_t per = pass ? std::max<uint64_t>(1, pass / D.eta) : D.n_se;
@@ -1688,26 +1703,32 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     }
     const uint64_t n_wins = ws.size() - 1;
     if (n_wins > MAX_WINDOWS) return fail(SSD_E_PARAM, "too many scan windows (%llu)", (unsigned long long)n_wins);
-    // the device block is [counter (8 bytes)][windows]; the first vector entry only supplies the zero counter
-    unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
-    const unsigned long long zero = 0;
-    HIPCHK(e, hipMemcpyAsync(dcounter, &zero, 8, hipMemcpyHostToDevice, e->stream));
-    HIPCHK(e, hipMemcpyAsync(dcounter + 1, ws.data() + 1, n_wins * sizeof(ScanWindow), hipMemcpyHostToDevice,
-                             e->stream));
-    TileScanArgs a{};
-    a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
-    a.links = e->dev_links();
-    a.wins = reinterpret_cast<const ScanWindow*>(dcounter + 1);
-    a.counter = dcounter;
-    a.n_wins = (uint32_t)n_wins;
-    a.n_tiles = tiles;
-    a.tile = tile;
-    hipDeviceProp_t prop;
-    uint32_t blocks = 2048;
-    if (hipGetDeviceProperties(&prop, e->device) == hipSuccess) blocks = (uint32_t)prop.multiProcessorCount * 8u;
-    PhaseMark pm = phase_begin(e);
-    HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(blocks, tiles), e->stream));
-    phase_end(e, pm, 0, 1);
+    if (n_wins) {
+        // the device block is [counter (8 bytes)][windows]; the first vector entry only supplies the zero counter
+        unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
+        const unsigned long long zero = 0;
+        HIPCHK(e, hipMemcpyAsync(dcounter, &zero, 8, hipMemcpyHostToDevice, e->stream));
+        HIPCHK(e, hipMemcpyAsync(dcounter + 1, ws.data() + 1, n_wins * sizeof(ScanWindow), hipMemcpyHostToDevice,
+                                 e->stream));
+        TileScanArgs a{};
+        a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
+        a.links = e->dev_links();
+        a.wins = reinterpret_cast<const ScanWindow*>(dcounter + 1);
+        a.counter = dcounter;
+        a.n_wins = (uint32_t)n_wins;
+        a.n_tiles = tiles;
+        a.tile = tile;
+        PhaseMark pm = phase_begin(e);
+        HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(g->scan_blocks, tiles), e->stream));
+        phase_end(e, pm, 0, 1);
+    }
+    for (uint32_t i = 0; i < n; i++) {
+        if (!binned(i)) continue;
+        ssd_detector* m = members[i];
+        rc = enqueue_binned_scan(&m->e, 0, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[i],
+                                 offsets_host[i + 1] - offsets_host[i], m->bin_bytes, m->apply_segments);
+        if (rc) return rc;
+    }
     return SSD_OK;
 }
 

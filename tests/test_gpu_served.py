@@ -8,7 +8,7 @@ import pytest
 
 import paper_1803_11036_amd as ssd
 import tracegen as tg
-from _parity import log
+from _parity import log, to_dev
 from paper_1803_11036_amd import serve
 
 pytestmark = pytest.mark.gpu
@@ -49,3 +49,49 @@ def test_served_admission_by_memory_budget():
     assert rep.max_admitted <= 3
     assert max(rep.admit_wait_s) > 0
     _check_equal(inputs, rep)
+
+
+def test_group_binned_members_equal_separate_detectors():
+    """Members with a state above 256 MiB and at least 2^20 pairs in the call
+    are scanned binned inside the group scan (the rest share the tile scan);
+    each member's list equals that of a detector of its own fed the same pairs."""
+    cfgs = tg.batch_configs(n_links=12, pairs_scale=0.5)
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+
+    def params(c):
+        return ssd.make_params(q=c.q, r=c.r, delta=c.delta, eta=c.eta, k=c.k, theta=c.theta)
+
+    members = [ssd.init_detector(params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    alone = [ssd.init_detector(params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    for d in members:
+        ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
+    g = ssd.group_init(len(cfgs), device="cuda:0")
+    big = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > 256 << 20 and c.pairs_lo >= 1 << 20]
+    assert big, "no member takes the binned scan"
+    clock = [0] * len(cfgs)           # open slice of member i and of its own detector
+    for t in range(3):
+        per = [tr.pairs(0, t % tr.cfg.n_slices) for tr in traces]
+        offs = np.zeros(len(per) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([p.shape[0] for p in per])
+        dev = to_dev(np.concatenate(per))
+        # every member in the first slice; a subset (one binned, some tiled) after
+        pick = list(range(len(cfgs))) if t == 0 else sorted({big[t % len(big)], 0, 1, 5})
+        sub = np.concatenate([per[i] for i in pick])
+        soffs = np.zeros(len(pick) + 1, dtype=np.uint64)
+        soffs[1:] = np.cumsum([per[i].shape[0] for i in pick])
+        sdev = to_dev(sub)
+        ms = [members[i] for i in pick]
+        ssd.group_scan(g, ms, sdev, soffs, [clock[i] for i in pick])
+        lists, status = ssd.group_close(g, ms)
+        assert np.all(status == 0)
+        for j, i in enumerate(pick):
+            ssd.scan_slice(alone[i], dev[int(offs[i]):int(offs[i + 1])], clock[i])
+            res = ssd.close_slice(alone[i])
+            clock[i] += 1
+            assert np.array_equal(lists[j], res), f"slice {t} member {i}: group and own detector differ"
+        log(f"group binned slice {t}: members {pick}, {sum(len(x) for x in lists)} hosts, binned {big}")
+    assert sum(ssd.read_timing(members[i])["scan_bin"][1] for i in big) >= len(big) + 2
+    g.destroy()
+    for d in members + alone:
+        d.destroy()
