@@ -335,6 +335,8 @@ def main() -> int:
                     help="single-detector scan: pass windows or bin-sorted stores (default: library)")
     ap.add_argument("--bin-kib", type=int, default=None, help="binned scan: bin size in KiB (power of two)")
     ap.add_argument("--apply-segments", type=int, default=None, help="binned scan: segments per store workgroup")
+    ap.add_argument("--no-counted", action="store_true",
+                    help="hot detection scans the whole state (no per-slot counters)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (PMC calibration)")
     ap.add_argument("--links", type=int, default=64, help="batched workload: number of links")
@@ -397,6 +399,8 @@ def main() -> int:
         ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_BIN_BYTES, args.bin_kib << 10)
     if args.apply_segments is not None:
         ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_APPLY_SEGMENTS, args.apply_segments)
+    if args.no_counted:
+        ssd.set_tuning(det, ssd.SSD_TUNE_COUNTED, 0)
     ssd.set_tuning(det, ssd.SSD_TUNE_TIMING, 1)
     state_bytes = det.state.numel()
 
@@ -465,19 +469,31 @@ def main() -> int:
     # algorithmic bytes per scan call (the unit of the scan kernels):
     #   pass scan k_scan: 8 B pair read + r cell bytes written per pair;
     #   binned scan k_bin: 8 B pair read + r 4-byte offsets written per pair,
-    #               k_apply: r 4-byte offsets read + r cell bytes written per pair;
-    # hot detection reads the whole state once per close
-    stores = "k_apply" if binned else "k_scan"
-    cand = {
-        stores: (timing["scan"][0], avg_pairs * (5 * cfg.r if binned else 8 + cfg.r), timing["scan"][0] / args.steps),
-        "k_hot_detect": (timing["hot_detect"][0], float(state_bytes), det_ms),
-    }
+    #               k_apply: r 4-byte offsets read + r cell bytes written per pair,
+    #               k_apply_counted: the same + r cell bytes read per pair;
+    # hot detection reads the whole state once per close; counted detection
+    # (k_count) reads k 4-byte counters and writes R_k and the next slot's
+    # counter per estimator, and reads the cells of the hot estimators
+    # (writing their 2-bit-per-16-cell snapshots) and of this slot's expiry
+    # phase (1 / (255 - k) of the estimators)
+    counted = timing["count_detect"][1] > 0
+    stores = ("k_apply_counted" if counted else "k_apply") if binned else "k_scan"
+    per_pair = (6 * cfg.r if counted else 5 * cfg.r) if binned else 8 + cfg.r
+    cand = {stores: (timing["scan"][0], avg_pairs * per_pair, timing["scan"][0] / args.steps)}
+    if timing["hot_detect"][1]:
+        cand["k_hot_detect"] = (timing["hot_detect"][0], float(state_bytes), det_ms)
+    if counted:
+        n_se = cfg.r << cfg.q
+        n_hot = sum(info["hot_counts"][:cfg.r])
+        count_bytes = n_se * (4 * cfg.k + 8) + n_hot * (cfg.eta + cfg.eta // 8) + n_se / (255 - cfg.k) * cfg.eta
+        cand["k_count"] = (timing["count_detect"][0], float(count_bytes),
+                           timing["count_detect"][0] / timing["count_detect"][1])
     if binned:
         cand["k_bin"] = (timing["scan_bin"][0], avg_pairs * (8 + 4 * cfg.r), timing["scan_bin"][0] / args.steps)
     dom = max(cand, key=lambda k: cand[k][0])
     _, bytes_per_launch, ms_per_launch = cand[dom]
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
-    launches_per_unit = {"k_hot_detect": 1, "k_bin": timing["scan_bin"][1] // args.steps}.get(
+    launches_per_unit = {"k_hot_detect": 1, "k_count": 1, "k_bin": timing["scan_bin"][1] // args.steps}.get(
         dom, timing["scan"][1] // args.steps)
     traffic = load_traffic(dom, cfg.name)
     if traffic is not None:

@@ -222,6 +222,20 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_SCAN_PASSES 0u
 #define SSD_SCAN_BINNED 1u
 #define SSD_SCAN_AUTO 2u
+/*   SSD_TUNE_COUNTED: 1 (default) = while a detector's scans are binned, it
+ *       keeps for every estimator and every slice of the window the number of
+ *       cells that hold that slice's stamp, updated by the scan's stores (bins
+ *       of 1 MiB, 512 KiB or 256 KiB: the largest not above 512 KiB, or
+ *       above SSD_TUNE_SCAN_BIN_BYTES once set, that fits; each stored by one
+ *       workgroup that marks the cells it has visited).  Its close then takes R_k from these
+ *       counters and reads only the cells of hot estimators and of the
+ *       estimators whose expiry phase it is, instead of the whole state.
+ *       Possible when eta >= 32 k and the state fits 4096 bins; the
+ *       counters take r * 2^q * k * 4 bytes of scratch (included in
+ *       ssd_query_sizes).  A router merge into the detector, an advance-only
+ *       close, a pass scan or a group call leaves them stale: the close that
+ *       follows the next binned scan rebuilds them from the state. */
+#define SSD_TUNE_COUNTED 10u
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 
 /* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per
@@ -230,9 +244,11 @@ int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
  * Phases: 0 scan stores, 1 hot detection, 2 hot lists, 3 candidate expansion,
  * 4 final test, 5 sort/report, 6 merge, 7 the close after hot detection
  * replayed as a graph (phases 2-5 are then timed as this one), 8 scan
- * binning (the sort step of the binned scan).  Synchronises the stream; reset != 0 clears
+ * binning (the sort step of the binned scan), 9 hot detection from the
+ * per-slot counters (SSD_TUNE_COUNTED; two launches when the counters are
+ * rebuilt from the state first).  Synchronises the stream; reset != 0 clears
  * the totals after reading. */
-#define SSD_PHASES 9u
+#define SSD_PHASES 10u
 int ssd_read_timing(ssd_detector *d, double *ms_out, uint64_t *launches_out, int reset);
 
 void ssd_destroy(ssd_detector *d);

@@ -53,6 +53,7 @@ struct LinkDesc {
     uint64_t host_cap;            //   are written there by the close's last kernel
     uint32_t* hot_list;           // [r][2^q]
     uint16_t* live16;             // [r][2^q][eta / 16] live-cell bits of hot estimators (written at hot detection)
+    uint32_t* counts;             // [r][2^q][k] live cells per estimator and slot t mod k (counted detectors, else null)
     uint64_t* ctb_x[2];           // candidate buffers: regained bits
     uint32_t* ctb_h0[2];          //                    and he_0
     unsigned long long* acc;      // accepted keys
@@ -118,7 +119,19 @@ struct ApplyArgs {
     uint32_t n_bins, blocks, seg, bin_shift;
     uint32_t parts, per_part;     // workgroups per bin, segments per workgroup
     uint32_t stamp, pack;         // pack: as BinArgs::pack
+    // counted apply only: the link's per-slot counters, its window, the open
+    // slice's slot (t mod k) and the estimator size
+    uint32_t* counts;
+    uint32_t k, slot, log2eta, pad;
 };
+
+// LDS of the counted apply: a bit per cell of the bin, then a signed counter
+// per estimator of the bin and slot
+inline uint64_t counted_lds_bytes(uint32_t bin_shift, uint32_t log2eta, uint32_t k)
+{
+    return (1ull << (bin_shift - 3)) + (1ull << (bin_shift - log2eta)) * k * 4ull;
+}
+constexpr uint32_t COUNTED_LDS_BYTES = 151u * 1024u;   // 160 KiB less the kernel's static list of marked words
 
 struct DetectArgs {
     const LinkDesc* links;
@@ -164,6 +177,9 @@ inline uint32_t bin_lds_words(uint32_t n_bins, uint32_t pb, uint32_t r) { return
 constexpr uint32_t BIN_LDS_WORDS = 40960u - 32u;
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s);
+hipError_t launch_recount(const LinkDesc* link, uint64_t n_se, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, bool small, hipStream_t s);
 hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s);

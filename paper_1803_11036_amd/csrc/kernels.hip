@@ -448,8 +448,12 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
 // parts)-th bin from the top with w = g / 8, segments [part * per_part, ...),
 // 64 segments per round: lane j holds segment j's run of the bin, and the
 // wave walks the concatenated runs 64 items at a time.
+constexpr uint32_t APPLY_UNROLL = 2;      // items per lane in flight
+
+template <bool PACK>
 __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 {
+    const uint64_t seg_words = PACK ? (a.seg + 2u) / 3u : a.seg;   // item words per segment
     const uint32_t g = blockIdx.x, w = g >> 3;
     const uint32_t walk = (g & 7u) + 8u * (w / a.parts);
     if (walk >= a.n_bins) return;
@@ -476,19 +480,204 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
         }
         const uint32_t excl = incl - c;
         const uint32_t total = __shfl(incl, 63, 64);
-        for (uint32_t t0 = 0; t0 < total; t0 += 64u) {
-            const uint32_t t = t0 + lane;
-            // the run holding item t: the largest lane whose run starts at or before t
-            uint32_t lo = 0;
+        for (uint32_t t0 = 0; t0 < total; t0 += 64u * APPLY_UNROLL) {
+            // every lane loads (past the end: the first word of segment jb),
+            // so that the loads issue back to back and are waited for once
+            uint32_t it[APPLY_UNROLL], sg[APPLY_UNROLL];
+            bool ok[APPLY_UNROLL];
 #pragma unroll
-            for (uint32_t sft = 32; sft > 0; sft >>= 1) {
-                const uint32_t e = __shfl(excl, (int)(lo + sft), 64);
-                if (e <= t) lo += sft;
+            for (int u = 0; u < (int)APPLY_UNROLL; u++) {
+                const uint32_t t = t0 + (uint32_t)u * 64u + lane;
+                // the run holding item t: the largest lane whose run starts at or before t
+                uint32_t lo = 0;
+#pragma unroll
+                for (uint32_t sft = 32; sft > 0; sft >>= 1) {
+                    const uint32_t e = __shfl(excl, (int)(lo + sft), 64);
+                    if (e <= t) lo += sft;
+                }
+                const uint32_t rs = __shfl(st, (int)lo, 64);
+                const uint32_t re = __shfl(excl, (int)lo, 64);
+                ok[u] = t < total;
+                it[u] = ok[u] ? rs + (t - re) : 0u;
+                sg[u] = ok[u] ? jb + lo : jb;
             }
-            const uint32_t rs = __shfl(st, (int)lo, 64);
-            const uint32_t re = __shfl(excl, (int)lo, 64);
-            if (t < total) base[read_item(a, jb + lo, rs + (t - re))] = stamp;
+            uint64_t raw[APPLY_UNROLL];
+#pragma unroll
+            for (int u = 0; u < (int)APPLY_UNROLL; u++) {
+                const uint64_t w = (uint64_t)sg[u] * seg_words + (PACK ? it[u] / 3u : it[u]);
+                raw[u] = PACK ? reinterpret_cast<const uint64_t*>(a.items)[w] : (uint64_t)a.items[w];
+            }
+            // offsets taken on every lane and pinned before the first store (an
+            // empty asm reading them), so that no load sinks into a store's
+            // branch and waits for the stores before it
+            uint32_t off[APPLY_UNROLL];
+#pragma unroll
+            for (int u = 0; u < (int)APPLY_UNROLL; u++) {
+                off[u] = PACK ? (uint32_t)(raw[u] >> (21u * (it[u] % 3u))) & 0x1FFFFFu : (uint32_t)raw[u];
+                asm volatile("" : : "v"(off[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < (int)APPLY_UNROLL; u++)
+                if (ok[u]) base[off[u]] = stamp;
         }
+    }
+}
+
+// Counted variant: one workgroup per bin.  The walk over the bin's items only
+// marks their cells in an LDS bitmap (a bit per cell); then every marked cell
+// is visited once, 16-byte chunk by chunk: a cell whose stamp is not the open
+// slice's yet takes it and moves in its estimator's per-slot counters (+1 for
+// the open slot, -1 for the slot of an old stamp still in the window).
+// Stamps of earlier launches into the same slice are recognised by their
+// value, so every cell is counted once per slice.  The workgroup owns its
+// bin's cells and estimators: chunks are written back whole and the counters,
+// summed in LDS, are added to memory without atomics.
+constexpr uint32_t CAPPLY_WAVES = 16;
+constexpr uint32_t CAPPLY_UNROLL = 4;     // items per lane in flight in the walk
+constexpr uint32_t CAPPLY_CHUNKS = 4;     // bitmap words per thread in flight in the visit
+constexpr uint32_t CAPPLY_LIST = 4096;    // marked words listed for the visit (more: the whole bitmap is swept)
+
+// The marked cells of one 4-byte word: new stamps and counter moves.
+__device__ __forceinline__ uint32_t stamp_word(uint32_t x, uint32_t m, uint32_t stamp, uint32_t k, uint32_t slot,
+                                               int* ce, uint32_t& changed)
+{
+    while (m) {
+        const uint32_t i = (uint32_t)__ffs(m) - 1u;
+        m &= m - 1u;
+        const uint32_t b = (x >> (8u * i)) & 0xFFu;
+        if (b == stamp) continue;
+        x = (x & ~(0xFFu << (8u * i))) | (stamp << (8u * i));
+        changed++;
+        if (b != 0u) {
+            const uint32_t d = (stamp + 255u - b) % 255u;      // slices since the old stamp
+            if (d < k) atomicSub(&ce[slot >= d ? slot - d : slot + k - d], 1);
+        }
+    }
+    return x;
+}
+
+template <bool PACK>
+__global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t bin = a.n_bins - 1u - blockIdx.x;
+    const uint32_t bm_words = 1u << (a.bin_shift - 5u);
+    const uint32_t n_est = 1u << (a.bin_shift - a.log2eta);
+    const uint32_t k = a.k, slot = a.slot;
+    const uint32_t n_words = bm_words + n_est * k;
+    uint32_t* bm = lds;
+    int* cnt = reinterpret_cast<int*>(lds + bm_words);
+    // the words that received their first mark, in order of marking
+    __shared__ uint16_t list[CAPPLY_LIST];
+    __shared__ uint32_t n_list;
+    for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) lds[i] = 0u;
+    if (threadIdx.x == 0) n_list = 0u;
+    __syncthreads();
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
+    const uint64_t seg_words = PACK ? (a.seg + 2u) / 3u : a.seg;   // item words per segment
+    for (uint32_t jb = wave * 64u; jb < a.blocks; jb += 64u * CAPPLY_WAVES) {
+        const uint32_t j = jb + lane;
+        uint32_t st = 0, c = 0;
+        if (j < a.blocks) {
+            st = row[j];
+            c = row[a.blocks + j] - st;
+        }
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (lane >= (uint32_t)o) incl += v;
+        }
+        const uint32_t excl = incl - c;
+        const uint32_t total = __shfl(incl, 63, 64);
+        for (uint32_t t0 = 0; t0 < total; t0 += 64u * CAPPLY_UNROLL) {
+            // every lane loads (past the end: the first word of segment jb),
+            // so that the loads issue back to back and are waited for once
+            uint64_t addr[CAPPLY_UNROLL];
+            uint32_t sub[CAPPLY_UNROLL];
+#pragma unroll
+            for (int u = 0; u < (int)CAPPLY_UNROLL; u++) {
+                const uint32_t t = t0 + (uint32_t)u * 64u + lane;
+                uint32_t lo = 0;
+#pragma unroll
+                for (uint32_t sft = 32; sft > 0; sft >>= 1) {
+                    const uint32_t e = __shfl(excl, (int)(lo + sft), 64);
+                    if (e <= t) lo += sft;
+                }
+                const uint32_t rs = __shfl(st, (int)lo, 64);
+                const uint32_t re = __shfl(excl, (int)lo, 64);
+                const bool ok = t < total;
+                const uint32_t i = ok ? rs + (t - re) : 0u;
+                const uint32_t sg = ok ? jb + lo : jb;
+                addr[u] = (uint64_t)sg * seg_words + (PACK ? i / 3u : i);
+                sub[u] = ok ? (PACK ? 21u * (i % 3u) : 0u) : 0xFFu;
+            }
+            uint64_t raw[CAPPLY_UNROLL];
+#pragma unroll
+            for (int u = 0; u < (int)CAPPLY_UNROLL; u++)
+                raw[u] = PACK ? reinterpret_cast<const uint64_t*>(a.items)[addr[u]] : (uint64_t)a.items[addr[u]];
+#pragma unroll
+            for (int u = 0; u < (int)CAPPLY_UNROLL; u++) {
+                if (sub[u] == 0xFFu) continue;
+                const uint32_t off = PACK ? (uint32_t)(raw[u] >> sub[u]) & 0x1FFFFFu : (uint32_t)raw[u];
+                if (atomicOr(&bm[off >> 5], 1u << (off & 31u)) == 0u) {
+                    const uint32_t at = atomicAdd(&n_list, 1u);
+                    if (at < CAPPLY_LIST) list[at] = (uint16_t)(off >> 5);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // visit: bitmap word w covers the 32 cells of 16-byte chunks 2w and 2w + 1;
+    // unmarked halves load the bin's first chunk instead (one line, cached),
+    // so that the loads issue back to back
+    uint4* chunk = reinterpret_cast<uint4*>(a.state + ((uint64_t)bin << a.bin_shift));
+    const uint32_t stamp = a.stamp;
+    // the listed words when they all fit the list, else every word of the bitmap
+    const bool listed = n_list <= CAPPLY_LIST;
+    const uint32_t n_visit = listed ? n_list : bm_words;
+    for (uint32_t w0 = threadIdx.x; w0 < n_visit; w0 += blockDim.x * CAPPLY_CHUNKS) {
+        uint32_t m[CAPPLY_CHUNKS], wd[CAPPLY_CHUNKS];
+        uint4 v[2 * CAPPLY_CHUNKS];
+#pragma unroll
+        for (int u = 0; u < (int)CAPPLY_CHUNKS; u++) {
+            const uint32_t i = w0 + (uint32_t)u * blockDim.x;
+            wd[u] = i < n_visit ? (listed ? (uint32_t)list[i] : i) : 0u;
+            m[u] = i < n_visit ? bm[wd[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < (int)CAPPLY_CHUNKS; u++) {
+            const uint32_t w = wd[u];
+            v[2 * u] = chunk[(m[u] & 0xFFFFu) ? 2u * w : 0u];
+            v[2 * u + 1] = chunk[(m[u] >> 16) ? 2u * w + 1u : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < (int)CAPPLY_CHUNKS; u++) {
+            if (!m[u]) continue;
+            const uint32_t w = wd[u];
+            int* ce = cnt + ((w << 5) >> a.log2eta) * k;
+            uint32_t changed = 0;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const uint32_t mh = (m[u] >> (16 * h)) & 0xFFFFu;
+                if (!mh) continue;
+                uint4 x = v[2 * u + h];
+                const uint32_t before = changed;
+                x.x = stamp_word(x.x, mh & 0xFu, stamp, k, slot, ce, changed);
+                x.y = stamp_word(x.y, (mh >> 4) & 0xFu, stamp, k, slot, ce, changed);
+                x.z = stamp_word(x.z, (mh >> 8) & 0xFu, stamp, k, slot, ce, changed);
+                x.w = stamp_word(x.w, (mh >> 12) & 0xFu, stamp, k, slot, ce, changed);
+                if (changed != before) chunk[2 * w + h] = x;
+            }
+            if (changed) atomicAdd(&ce[slot], (int)changed);
+        }
+    }
+    __syncthreads();
+    uint32_t* dst = a.counts + (uint64_t)bin * n_est * k;
+    for (uint32_t i = threadIdx.x; i < n_est * k; i += blockDim.x) {
+        const int v = cnt[i];
+        if (v) dst[i] += (uint32_t)v;
     }
 }
 
@@ -637,6 +826,95 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
         } else {
             hot_finish<true>(D, s, live, se, lane);
         }
+    }
+}
+
+// ---------------------------------------------------------------- counted detection
+// R_k of every estimator from its per-slot counters (one thread per
+// estimator): the same live-cell count as a scan of the state, since every
+// live cell carries the stamp of exactly one slice of the window.  The wave
+// then visits only the estimators that need their cells: hot ones (snapshot
+// and bitmask bits) and those of this slot's expiry phase (dead cells
+// cleared).  The slot of the next slice is zeroed for its scans.
+__global__ __launch_bounds__(256) void k_count(const LinkDesc* link, uint64_t n_se)
+{
+    const LinkDesc* D = link;
+    const uint64_t s = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t k = D->k;
+    const uint32_t next = (uint32_t)((D->clock->t + 1ull) % k);
+    uint32_t live = 0;
+    bool hot = false, expire = false;
+    if (s < n_se) {
+        uint32_t* c = D->counts + s * k;
+        for (uint32_t j = 0; j < k; j++) live += c[j];
+        c[next] = 0u;
+        hot = live >= D->T;
+        expire = (s % D->expire_period) == D->expire_phase;
+        if (!hot) D->rk[s] = live;
+    }
+    unsigned long long m = __ballot(hot || expire);
+    if (!m) return;
+    const uint32_t log2eta = D->log2eta;
+    const uint32_t chunks = 1u << (log2eta - 4);
+    const LiveCfg L = D->L;
+    const uint64_t s0 = s - lane;
+    while (m) {
+        const uint32_t i = (uint32_t)__ffsll((long long)m) - 1u;
+        m &= m - 1ull;
+        const uint64_t si = s0 + i;
+        const uint32_t li = __shfl(live, (int)i, 64);
+        const bool hi = __shfl((uint32_t)hot, (int)i, 64) != 0u;
+        const bool ei = __shfl((uint32_t)expire, (int)i, 64) != 0u;
+        uint4* se = reinterpret_cast<uint4*>(D->state + (si << log2eta));
+        uint16_t* snap = D->live16 + si * chunks;
+        for (uint32_t c = lane; c < chunks; c += 64u) {
+            const uint4 v = se[c];
+            if (hi) snap[c] = (uint16_t)live_mask16(v, L);
+            if (ei) {
+                uint4 n;
+                n.x = expire_word(v.x, L); n.y = expire_word(v.y, L);
+                n.z = expire_word(v.z, L); n.w = expire_word(v.w, L);
+                if (n.x != v.x || n.y != v.y || n.z != v.z || n.w != v.w) se[c] = n;
+            }
+        }
+        if (hi) hot_finish<false>(D, si, li, se, lane);
+    }
+}
+
+// Bytes of a word equal to stamp s.
+__device__ __forceinline__ uint32_t count_eq(uint32_t w, uint32_t s)
+{
+    const uint32_t x = w ^ (s * 0x01010101u);
+    const uint32_t nz = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+    return 4u - __popc(nz);
+}
+
+// The per-slot counters rebuilt from the state (one wave per estimator): for
+// every slice of the window, the cells holding its stamp.
+__global__ __launch_bounds__(256) void k_recount(const LinkDesc* link, uint64_t n_se)
+{
+    const LinkDesc* D = link;
+    const uint64_t s = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (s >= n_se) return;
+    const uint32_t k = D->k;
+    const unsigned long long t = D->clock->t;
+    const uint32_t slot = (uint32_t)(t % k);
+    const uint32_t chunks = 1u << (D->log2eta - 4);
+    const uint4* se = reinterpret_cast<const uint4*>(D->state + (s << D->log2eta));
+    for (uint32_t j = 0; j < k; j++) {
+        const uint32_t d = slot >= j ? slot - j : slot + k - j;   // slices back from t
+        uint32_t n = 0;
+        if (d <= t) {
+            const uint32_t st = 1u + (uint32_t)((t - d) % 255ull);
+            for (uint32_t c = lane; c < chunks; c += 64u) {
+                const uint4 v = se[c];
+                n += count_eq(v.x, st) + count_eq(v.y, st) + count_eq(v.z, st) + count_eq(v.w, st);
+            }
+        }
+        n = wave_sum(n);
+        if (lane == 0) D->counts[s * k + j] = n;
     }
 }
 
@@ -1302,7 +1580,42 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
 {
     if (a.parts == 0 || a.per_part == 0) return hipErrorInvalidValue;
     const uint64_t groups = (a.n_bins + 7u) / 8u;
-    k_apply<<<(uint32_t)(8ull * a.parts * groups), 64, 0, s>>>(a);
+    if (a.pack) k_apply<true><<<(uint32_t)(8ull * a.parts * groups), 64, 0, s>>>(a);
+    else k_apply<false><<<(uint32_t)(8ull * a.parts * groups), 64, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s)
+{
+    const uint64_t bytes = counted_lds_bytes(a.bin_shift, a.log2eta, a.k);
+    if (!a.counts || a.k == 0 || a.slot >= a.k || a.bin_shift < a.log2eta || a.bin_shift < 5 ||
+        bytes > COUNTED_LDS_BYTES || a.n_bins == 0)
+        return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        for (const void* f : {reinterpret_cast<const void*>(&k_apply_counted<true>),
+                              reinterpret_cast<const void*>(&k_apply_counted<false>)}) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)COUNTED_LDS_BYTES);
+            if (e != hipSuccess) return e;
+        }
+        attr = true;
+    }
+    if (a.pack) k_apply_counted<true><<<a.n_bins, 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
+    else k_apply_counted<false><<<a.n_bins, 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s)
+{
+    if (n_se == 0) return hipErrorInvalidValue;
+    k_count<<<(uint32_t)((n_se + 255u) / 256u), 256, 0, s>>>(link, n_se);
+    return hipGetLastError();
+}
+
+hipError_t launch_recount(const LinkDesc* link, uint64_t n_se, hipStream_t s)
+{
+    if (n_se == 0) return hipErrorInvalidValue;
+    k_recount<<<(uint32_t)((n_se + 3u) / 4u), 256, 0, s>>>(link, n_se);
     return hipGetLastError();
 }
 

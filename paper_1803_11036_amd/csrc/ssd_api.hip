@@ -92,9 +92,12 @@ uint32_t hot_threshold(uint32_t eta, uint32_t theta)
 // Binned scan geometry for a bin size request: bins of 2^shift bytes (at
 // least eta and 256 KiB, at most MAX_BINS of them), `pb` pairs per k_bin
 // workgroup (as many as its LDS holds).
-constexpr uint32_t MAX_BINS = 2048;
+constexpr uint32_t MAX_BINS = 4096;
 constexpr uint64_t MIN_BIN_BYTES = 256ull << 10;
 constexpr uint64_t DEFAULT_BIN_BYTES = 2ull << 20;
+// counted scans: 512 KiB bins let two workgroups share a compute unit (0.40 ms
+// per 6M-pair call into the 1.5 GiB core-link state against 0.55 ms at 1 MiB)
+constexpr uint64_t DEFAULT_COUNTED_BIN_BYTES = 512ull << 10;
 // Pairs binned per step, at most.  The stores of a bin are spread over the
 // workgroups of one XCD, so the work in flight is about (bins in flight) x
 // (items per bin): larger steps put more items in every bin (8M and 16M
@@ -131,6 +134,25 @@ BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
     if (p.r == 5) b.pb = std::min<uint32_t>(b.pb, 7u * 1024u);
     return b;
 }
+// Bin size of the counted scan (k_apply_counted) for a bin size request: of
+// 1 MiB, 512 KiB and 256 KiB, those whose cell bits and counters fit one
+// workgroup's LDS and that give at most MAX_BINS bins; the largest of them
+// not above the request, else the smallest.  0 when none does or when the
+// counters would exceed an eighth of the state (eta < 32 k): the link cannot
+// count.
+uint32_t counted_shift(const ssd_params& p, uint64_t want = 1ull << 20)
+{
+    if (32ull * p.k > p.eta) return 0;
+    const uint32_t le = log2u(p.eta);
+    uint32_t best = 0, smallest = 0;
+    for (uint32_t sh = 20; sh >= 18; sh--) {
+        if (sh < le || counted_lds_bytes(sh, le, p.k) > COUNTED_LDS_BYTES) continue;
+        if (bin_plan(p, 1ull << sh).shift != sh) break;   // more bins than MAX_BINS, and more below
+        smallest = sh;
+        if (!best && (1ull << sh) <= want) best = sh;
+    }
+    return best ? best : smallest;
+}
 // Item and table words that every allowed bin size fits, for chunks of up to
 // BIN_CHUNK_PAIRS pairs (fewer for small states).
 void bin_capacity(const ssd_params& p, uint64_t* items_words, uint64_t* table_words)
@@ -153,6 +175,7 @@ uint64_t row_words(const ssd_params& p) { return p.q >= 6 ? (1ull << (p.q - 6)) 
 struct LinkLayout {
     uint64_t state_off, state_bytes;
     uint64_t tables, ctl, rk, hot_list, live16, hotbits, hotT, ctb_x[2], ctb_h0[2], acc, out;
+    uint64_t counts;              // per-slot counters of a single detector that can count (else 0)
 };
 
 struct Layout {
@@ -208,6 +231,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
         for (int b = 0; b < 2; b++) { K.ctb_h0[b] = o; o = align_up(o + q.max_tuples * 4); }
         K.acc = o; o = align_up(o + q.max_results * 8);
         K.out = o; o = align_up(o + q.max_results * sizeof(SuperPointDev));
+        if (bins && n == 1 && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
     }
     uint64_t pw = 1;
     while (pw < maxres) pw <<= 1;
@@ -254,6 +278,12 @@ struct Engine {
     uint64_t se_total = 0;
     uint32_t rows_total = 0, max_r = 0, max_chunks = 1;
     bool detect_small = false;          // a link with eta < 4096, or several links (k_hot_detect SMALL)
+    // counted detection (single detectors): the counters are exact for the
+    // open slice's scans so far (count_valid), or a binned scan of this slice
+    // ran uncounted and the close rebuilds them (count_rebuild)
+    bool counting = false;
+    bool count_valid = false, count_rebuild = false;
+    uint64_t counted_bin_bytes = DEFAULT_COUNTED_BIN_BYTES;   // bin size request of counted scans
     std::vector<LinkDesc> hl;          // host copies of the device descriptors
     std::vector<uint32_t> tables;      // n x 2048
     // pinned host mailbox: control blocks, staged result entries, pack offsets
@@ -444,6 +474,7 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
         D.hotT = e->at<uint64_t>(K.hotT);
         D.hot_list = e->at<uint32_t>(K.hot_list);
         D.live16 = e->at<uint16_t>(K.live16);
+        D.counts = K.counts ? e->at<uint32_t>(K.counts) : nullptr;
         for (int b = 0; b < 2; b++) {
             D.ctb_x[b] = e->at<uint64_t>(K.ctb_x[b]);
             D.ctb_h0[b] = e->at<uint32_t>(K.ctb_h0[b]);
@@ -471,6 +502,11 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     }
     e->se_total = se_prefix[n];
     e->rows_total = (uint32_t)row_table.size();
+    if (n == 1 && e->hl[0].counts) {
+        // the counters start zero with the state: exact from the first slice
+        e->counting = true;
+        e->count_valid = true;
+    }
     hipError_t err = hipGetDevice(&e->device);
     if (err != hipSuccess) return dev_fail(e, err, "hipGetDevice");
     e->stage_cap = stage_cap;
@@ -519,7 +555,12 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
 int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs)
 {
     const LinkDesc& D = e->hl[l];
+    const bool counted = e->counting && e->count_valid;
+    if (e->counting && !counted) e->count_rebuild = true;
+    const uint32_t csh = counted ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
+    if (counted) bin_bytes = 1ull << csh;
     const BinPlan bp = bin_plan(e->p[l], bin_bytes);
+    if (counted && (!csh || bp.shift != csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
     const uint64_t seg = (uint64_t)bp.pb * D.r;
     const uint64_t max_blocks = std::min(e->L.bin_items_words / seg, e->L.bin_table_words / (bp.n_bins + 1));
     const uint64_t chunk = max_blocks * bp.pb;
@@ -541,6 +582,12 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
     aa.bin_shift = bp.shift;
     aa.per_part = segs;
     aa.stamp = stamp_of(e->clock);
+    if (counted) {
+        aa.counts = D.counts;
+        aa.k = D.k;
+        aa.slot = (uint32_t)(e->clock % D.k);
+        aa.log2eta = D.log2eta;
+    }
     for (uint64_t done = 0; done < n; done += chunk) {
         const uint64_t m = std::min(chunk, n - done);
         ba.pairs = pairs + done;
@@ -552,7 +599,7 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
         HIPCHK(e, launch_bin(ba, e->stream));
         phase_end(e, pm, PHASE_SCAN_BIN, 1);
         pm = phase_begin(e);
-        HIPCHK(e, launch_apply(aa, e->stream));
+        HIPCHK(e, counted ? launch_apply_counted(aa, e->stream) : launch_apply(aa, e->stream));
         phase_end(e, pm, 0, 1);
     }
     return SSD_OK;
@@ -565,6 +612,19 @@ int enqueue_close_head(Engine* e)
     const hipStream_t s = e->stream;
     LinkDesc* links = e->dev_links();
     HIPCHK(e, launch_prepare(links, e->n, true, s));
+    if (e->counting && (e->count_valid || e->count_rebuild)) {
+        // R_k from the per-slot counters (rebuilt from the state first when
+        // this slice's scans ran uncounted); the next slot starts at zero
+        PhaseMark pm = phase_begin(e);
+        if (!e->count_valid) HIPCHK(e, launch_recount(links, e->hl[0].n_se, s));
+        HIPCHK(e, launch_count(links, e->hl[0].n_se, s));
+        phase_end(e, pm, 9, e->count_valid ? 1 : 2);
+        e->count_valid = true;
+        e->count_rebuild = false;
+        return SSD_OK;
+    }
+    e->count_valid = false;
+    e->count_rebuild = false;
     DetectArgs da{};
     da.links = links;
     da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
@@ -744,6 +804,8 @@ int collect_results(Engine* e, bool packed, uint64_t single_prefix)
 int enqueue_advance_only(Engine* e)
 {
     const hipStream_t s = e->stream;
+    e->count_valid = false;           // the next slot's counters are not zeroed
+    e->count_rebuild = false;
     LinkDesc* links = e->dev_links();
     HIPCHK(e, launch_prepare(links, e->n, false, s));
     DetectArgs da{};
@@ -1025,10 +1087,21 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     case SSD_TUNE_SCAN_BIN_BYTES:
         if (!is_pow2(value)) return fail(SSD_E_PARAM, "bin bytes must be a power of two");
         d->bin_bytes = value;
+        d->e.counted_bin_bytes = value;
         return SSD_OK;
     case SSD_TUNE_SCAN_APPLY_SEGMENTS:
         if (value < 1 || value > 4096) return fail(SSD_E_PARAM, "apply segments outside 1..4096");
         d->apply_segments = (uint32_t)value;
+        return SSD_OK;
+    case SSD_TUNE_COUNTED:
+        if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
+        if (value && !d->e.hl[0].counts) return fail(SSD_E_PARAM, "this detector cannot count (eta < 32 k or too many bins)");
+        if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+        if (d->e.counting != (value != 0)) {
+            d->e.counting = value != 0;
+            d->e.count_valid = false;
+            d->e.count_rebuild = false;
+        }
         return SSD_OK;
     case SSD_TUNE_SORT_BLOCK_LIMIT: {
         if (value > SORT_SMALL) return fail(SSD_E_PARAM, "sort block limit above %u", SORT_SMALL);
@@ -1060,6 +1133,7 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
     const uint64_t state_bytes = D.n_se << D.log2eta;
     if (d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE))
         return enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes, d->apply_segments);
+    e->count_valid = false;           // pass scans store without counting
     ScanArgs a{};
     a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
     a.n = n;
@@ -1206,6 +1280,8 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
                                                   (unsigned long long)r->e.clock, (unsigned long long)g->e.clock);
         if (r->e.device != g->e.device) return fail(SSD_E_INCOMPAT, "router %u is on another device", j);
     }
+    g->e.count_valid = false;         // merged cells are not counted
+    g->e.count_rebuild = false;
     MergeArgs a{};
     a.dst = g->D().state;
     a.n16 = g->e.L.state_total / 16u;
@@ -1657,6 +1733,7 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     if (!offsets_host || !slice_ids_host) return fail(SSD_E_PARAM, "offsets or slice ids NULL");
     rc = group_bind(g, members, n);
     if (rc) return rc;
+    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid = false;   // the group's stores are not counted
     for (uint32_t i = 0; i < n; i++) {
         if (offsets_host[i + 1] < offsets_host[i]) return fail(SSD_E_PARAM, "offsets decrease at member %u", i);
         if (slice_ids_host[i] != members[i]->e.clock)
@@ -1743,6 +1820,11 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
     if (rc) return rc;
     for (uint32_t i = 0; i < n; i++)
         if (members[i]->pending) return fail(SSD_E_ORDER, "member %u has a close pending", i);
+    for (uint32_t i = 0; i < n; i++) {
+        // the group's close zeroes no member's next slot
+        members[i]->e.count_valid = false;
+        members[i]->e.count_rebuild = false;
+    }
     rc = enqueue_close(e, true, 0);
     if (rc) return rc;
     HIPCHK(e, hipStreamSynchronize(e->stream));

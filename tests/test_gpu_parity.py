@@ -62,43 +62,60 @@ def test_tiny_config(graph, timing):
         assert tm["close_graph"][1] == (cfg.n_slices if graph else 0)
 
 
-@pytest.mark.parametrize("splits,mode", [(1, "passes"), (3, "passes"), (7, "passes"), (1, "binned"), (7, "binned")])
+@pytest.mark.parametrize("splits,mode", [(1, "passes"), (3, "passes"), (7, "passes"), (1, "binned"), (7, "binned"),
+                                         (7, "binned_uncounted")])
 def test_ragged_batches_and_empty_slices(splits, mode):
     """Pair counts that leave ragged tails (0, 1, 63, 64, 65, 257, odd sizes),
     several scan calls per slice, empty slices, and (binned scan) calls of
-    several binning chunks."""
+    several binning chunks -- binned with per-slot counters (one 1 MiB bin;
+    the cells of one slice reach the counters through several launches) and
+    without."""
     q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
     sizes = [0, 1, 63, 64, 65, 257, 10007, 0, 12345, 9999, 0, 10240]
     sl = _slices_small(5 + splits, len(sizes), kb, theta, q, sizes=sizes)
     sl = [s if sizes[i] else s[:0] for i, s in enumerate(sl)]
     sl[9] = np.resize(sl[9], (150001, 2))      # the same pairs repeated: one call of several binning chunks
     g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(3), key_bits=kb)
-    if mode == "binned":
+    if mode != "passes":
         ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    if mode == "binned_uncounted":
+        ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED, 0)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
     for t, p in enumerate(sl):
         log(f"ragged splits={splits} {mode} slice {t} n={p.shape[0]}")
         scan_both(g, o, p, t, splits=splits if p.shape[0] >= splits else 1)
         compare_state(g, o)
         close_both(g, o)
+    tm = ssd.read_timing(g)
+    counted = mode == "binned"
+    assert (tm["count_detect"][1] == len(sl)) == counted and (tm["hot_detect"][1] == 0) == counted
 
 
-@pytest.mark.parametrize("k", [1, 3, 17, 254])
-def test_stamp_wrap_and_expiry(k):
+@pytest.mark.parametrize("k,mode", [(1, "passes"), (3, "passes"), (17, "passes"), (254, "passes"),
+                                    (1, "counted"), (3, "counted"), (17, "counted")])
+def test_stamp_wrap_and_expiry(k, mode):
     """300 slices: the 8-bit slot stamps wrap (255 slots) and the rotating
     expiry must keep every cell's distance exact, for the discrete window
-    (k = 1, Sec. 3.1), short and maximal windows."""
+    (k = 1, Sec. 3.1), short and maximal windows -- also for R_k taken from
+    the per-slot counters, whose slot of an old stamp rests on that
+    distance."""
     q, r, delta, eta, theta, kb = 8, 4, 4, 1024, 150, 16
     n = 300
     # about 0.15 * 2^q * theta distinct background pairs per window
     per_slice = max(20, int(0.15 * (1 << q) * theta / k))
     sl = _slices_small(40 + k, n, kb, theta, q, sizes=[per_slice] * n, heavy=60 if k < 100 else 8)
     g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(4), key_bits=kb)
+    if mode == "counted":
+        ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+        ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
     for t, p in enumerate(sl):
         scan_both(g, o, p, t)
         if t % 10 == 0 or t > 250:
             compare_state(g, o)
-        close_both(g, o, check_internals=(t % 25 == 0))
-    log(f"wrap k={k} done")
+        close_both(g, o, check_internals=(t % 25 == 0 or (mode == "counted" and t > 250)))
+    if mode == "counted":
+        assert ssd.read_timing(g)["count_detect"][1] == n
+    log(f"wrap k={k} {mode} done")
 
 
 def test_many_rows_level_expansion():
@@ -175,18 +192,21 @@ def test_scan_pass_windows_do_not_change_state():
         close_both(g, o, check_internals=False)
 
 
-@pytest.mark.parametrize("bin_kib", [256, 2048, 4096])
-def test_binned_scan_matches_oracle(bin_kib):
+@pytest.mark.parametrize("bin_kib,counted", [(256, 0), (2048, 0), (4096, 0), (1024, 1), (256, 1)])
+def test_binned_scan_matches_oracle(bin_kib, counted):
     """The bin-sorted scan (96, 12 or 6 bins over the 24 MiB state; offsets
-    packed three to a word up to 2 MiB bins, 4 bytes each above) gives the
-    oracle's state and lists, also for one call of 3.5M pairs (several binning
-    chunks, the last one ragged) and for a slice split over five calls."""
+    packed three to a word up to 2 MiB bins, 4 bytes each above; with
+    per-slot counters, 24 bins of 1 MiB or 96 of 256 KiB, whose marked words
+    overflow the visit list) gives the oracle's state and lists, also for one
+    call of 3.5M pairs (several binning chunks, the last one ragged) and for a
+    slice split over five calls."""
     cfg = tg.config("tiny")
     tr = tg.Trace(cfg)
     tabs = tg.hash_tables(cfg.hash_seed)
     g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
     ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
     ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_BIN_BYTES, bin_kib << 10)
+    ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED, counted)
     for t in range(4):
         pairs = tr.pairs(0, t)
         if t == 1:
@@ -195,6 +215,37 @@ def test_binned_scan_matches_oracle(bin_kib):
         scan_both(g, o, pairs, t, splits=5 if t == 2 else 1)
         compare_state(g, o)
         close_both(g, o, check_internals=(t == 3))
+
+
+def test_counted_detection_switches():
+    """R_k from the per-slot counters through every switch of the counted
+    path: counted from the first slice, stale after a pass scan (full hot
+    detection), rebuilt from the state at the close after the next binned
+    scan, counting switched off and on again, and slices split over several
+    calls -- every product equals the oracle's at every slice."""
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
+    # (scan mode, counted knob, calls): expected detection path and launches
+    plan = [(ssd.SSD_SCAN_BINNED, 1, 1, "count", 1), (ssd.SSD_SCAN_BINNED, 1, 3, "count", 1),
+            (ssd.SSD_SCAN_PASSES, 1, 1, "full", 1), (ssd.SSD_SCAN_BINNED, 1, 2, "count", 2),
+            (ssd.SSD_SCAN_BINNED, 1, 1, "count", 1), (ssd.SSD_SCAN_BINNED, 0, 1, "full", 1),
+            (ssd.SSD_SCAN_BINNED, 1, 1, "count", 2), (ssd.SSD_SCAN_BINNED, 1, 4, "count", 1)]
+    for t, (mode, counted, calls, path, launches) in enumerate(plan):
+        ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, mode)
+        ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED, counted)
+        log(f"counted switches slice {t}: mode {mode} counted {counted} calls {calls}")
+        scan_both(g, o, tr.pairs(0, t % cfg.n_slices), t, splits=calls)
+        close_both(g, o)
+        tm = ssd.read_timing(g, reset=True)
+        if path == "count":
+            assert tm["count_detect"][1] == launches and tm["hot_detect"][1] == 0, f"slice {t}: {tm}"
+        else:
+            assert tm["hot_detect"][1] == launches and tm["count_detect"][1] == 0, f"slice {t}: {tm}"
+    compare_state(g, o)
 
 
 def test_pipelined_close_matches_oracle():
