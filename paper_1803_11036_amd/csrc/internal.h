@@ -125,6 +125,11 @@ struct ApplyArgs {
     uint32_t k, slot, log2eta, pad;
 };
 
+// 8-byte words of one packed binning segment of n items (three 21-bit
+// offsets per word), rounded up to an even count so that every segment
+// starts 16-byte aligned
+__host__ __device__ inline uint64_t packed_seg_words(uint64_t n_items) { return ((n_items + 2) / 3 + 1) & ~1ull; }
+
 // LDS of the counted apply: a bit per cell of the bin, then a signed counter
 // per estimator of the bin and slot
 inline uint64_t counted_lds_bytes(uint32_t bin_shift, uint32_t log2eta, uint32_t k)

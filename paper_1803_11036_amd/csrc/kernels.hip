@@ -309,7 +309,7 @@ __device__ __forceinline__ void write_segment(const BinArgs& a, const uint32_t* 
 {
     const uint64_t seg_items = (uint64_t)a.pb * a.r;
     if (a.pack) {
-        uint64_t* seg = reinterpret_cast<uint64_t*>(a.items) + (uint64_t)blockIdx.x * ((seg_items + 2) / 3);
+        uint64_t* seg = reinterpret_cast<uint64_t*>(a.items) + (uint64_t)blockIdx.x * packed_seg_words(seg_items);
         for (uint32_t w = threadIdx.x; w * 3u < n; w += 1024u) {
             const uint32_t i = w * 3u;
             uint64_t v = stage[i];
@@ -327,7 +327,7 @@ __device__ __forceinline__ void write_segment(const BinArgs& a, const uint32_t* 
 __device__ __forceinline__ uint32_t read_item(const ApplyArgs& a, uint32_t j, uint32_t i)
 {
     if (a.pack) {
-        const uint64_t w = reinterpret_cast<const uint64_t*>(a.items)[(uint64_t)j * ((a.seg + 2u) / 3u) + i / 3u];
+        const uint64_t w = reinterpret_cast<const uint64_t*>(a.items)[(uint64_t)j * packed_seg_words(a.seg) + i / 3u];
         return (uint32_t)(w >> (21u * (i % 3u))) & 0x1FFFFFu;
     }
     return a.items[(uint64_t)j * a.seg + i];
@@ -453,7 +453,7 @@ constexpr uint32_t APPLY_UNROLL = 2;      // items per lane in flight
 template <bool PACK>
 __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 {
-    const uint64_t seg_words = PACK ? (a.seg + 2u) / 3u : a.seg;   // item words per segment
+    const uint64_t seg_words = PACK ? packed_seg_words(a.seg) : a.seg;   // item words per segment
     const uint32_t g = blockIdx.x, w = g >> 3;
     const uint32_t walk = (g & 7u) + 8u * (w / a.parts);
     if (walk >= a.n_bins) return;
@@ -533,7 +533,6 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 // bin's cells and estimators: chunks are written back whole and the counters,
 // summed in LDS, are added to memory without atomics.
 constexpr uint32_t CAPPLY_WAVES = 16;
-constexpr uint32_t CAPPLY_UNROLL = 4;     // items per lane in flight in the walk
 constexpr uint32_t CAPPLY_CHUNKS = 4;     // bitmap words per thread in flight in the visit
 constexpr uint32_t CAPPLY_LIST = 4096;    // marked words listed for the visit (more: the whole bitmap is swept)
 
@@ -556,11 +555,15 @@ __device__ __forceinline__ uint32_t stamp_word(uint32_t x, uint32_t m, uint32_t 
     return x;
 }
 
-template <bool PACK>
 __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a)
 {
     extern __shared__ uint32_t lds[];
-    const uint32_t bin = a.n_bins - 1u - blockIdx.x;
+    // workgroup g runs on XCD g mod 8, which takes a contiguous eighth of the
+    // bins in order: neighbouring bins, whose runs share cache lines in every
+    // segment, are read through the same L2 at about the same time
+    const uint32_t per_xcd = (a.n_bins + 7u) >> 3;
+    const uint32_t bin = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    if (bin >= a.n_bins) return;
     const uint32_t bm_words = 1u << (a.bin_shift - 5u);
     const uint32_t n_est = 1u << (a.bin_shift - a.log2eta);
     const uint32_t k = a.k, slot = a.slot;
@@ -570,60 +573,54 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
     // the words that received their first mark, in order of marking
     __shared__ uint16_t list[CAPPLY_LIST];
     __shared__ uint32_t n_list;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
+    // this lane's run (segment j) of the wave's first group, loaded before the
+    // LDS is cleared so that the two overlap
+    uint32_t j = wave * 64u + lane, st = 0, c = 0;
+    if (j < a.blocks) {
+        st = row[j];
+        c = row[a.blocks + j] - st;
+    }
     for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) lds[i] = 0u;
     if (threadIdx.x == 0) n_list = 0u;
     __syncthreads();
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
-    const uint64_t seg_words = PACK ? (a.seg + 2u) / 3u : a.seg;   // item words per segment
+    // walk: lane j reads run j itself, four aligned 16-byte loads (24 offsets)
+    // at a time; words past the segment's end are read from its last pair and
+    // fall outside the run
+    const uint64_t seg_words = packed_seg_words(a.seg);
+    const uint64_t* items = reinterpret_cast<const uint64_t*>(a.items);
+    const uint32_t last_pair = (uint32_t)(seg_words / 2u) - 1u;
     for (uint32_t jb = wave * 64u; jb < a.blocks; jb += 64u * CAPPLY_WAVES) {
-        const uint32_t j = jb + lane;
-        uint32_t st = 0, c = 0;
-        if (j < a.blocks) {
-            st = row[j];
-            c = row[a.blocks + j] - st;
-        }
-        uint32_t incl = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(incl, o, 64);
-            if (lane >= (uint32_t)o) incl += v;
-        }
-        const uint32_t excl = incl - c;
-        const uint32_t total = __shfl(incl, 63, 64);
-        for (uint32_t t0 = 0; t0 < total; t0 += 64u * CAPPLY_UNROLL) {
-            // every lane loads (past the end: the first word of segment jb),
-            // so that the loads issue back to back and are waited for once
-            uint64_t addr[CAPPLY_UNROLL];
-            uint32_t sub[CAPPLY_UNROLL];
-#pragma unroll
-            for (int u = 0; u < (int)CAPPLY_UNROLL; u++) {
-                const uint32_t t = t0 + (uint32_t)u * 64u + lane;
-                uint32_t lo = 0;
-#pragma unroll
-                for (uint32_t sft = 32; sft > 0; sft >>= 1) {
-                    const uint32_t e = __shfl(excl, (int)(lo + sft), 64);
-                    if (e <= t) lo += sft;
-                }
-                const uint32_t rs = __shfl(st, (int)lo, 64);
-                const uint32_t re = __shfl(excl, (int)lo, 64);
-                const bool ok = t < total;
-                const uint32_t i = ok ? rs + (t - re) : 0u;
-                const uint32_t sg = ok ? jb + lo : jb;
-                addr[u] = (uint64_t)sg * seg_words + (PACK ? i / 3u : i);
-                sub[u] = ok ? (PACK ? 21u * (i % 3u) : 0u) : 0xFFu;
+        if (jb != wave * 64u) {
+            j = jb + lane;
+            st = 0;
+            c = 0;
+            if (j < a.blocks) {
+                st = row[j];
+                c = row[a.blocks + j] - st;
             }
-            uint64_t raw[CAPPLY_UNROLL];
+        }
+        const uint32_t end = st + c;                                   // items [st, end)
+        const uint32_t w_end = (end + 2u) / 3u;
+        const uint4* seg = reinterpret_cast<const uint4*>(items + (uint64_t)min(j, a.blocks - 1u) * seg_words);
+        for (uint32_t base = (st / 3u) & ~1u; c && base < w_end; base += 8u) {
+            uint4 q[4];
 #pragma unroll
-            for (int u = 0; u < (int)CAPPLY_UNROLL; u++)
-                raw[u] = PACK ? reinterpret_cast<const uint64_t*>(a.items)[addr[u]] : (uint64_t)a.items[addr[u]];
+            for (int i = 0; i < 4; i++) q[i] = seg[min(base / 2u + (uint32_t)i, last_pair)];
 #pragma unroll
-            for (int u = 0; u < (int)CAPPLY_UNROLL; u++) {
-                if (sub[u] == 0xFFu) continue;
-                const uint32_t off = PACK ? (uint32_t)(raw[u] >> sub[u]) & 0x1FFFFFu : (uint32_t)raw[u];
-                if (atomicOr(&bm[off >> 5], 1u << (off & 31u)) == 0u) {
-                    const uint32_t at = atomicAdd(&n_list, 1u);
-                    if (at < CAPPLY_LIST) list[at] = (uint16_t)(off >> 5);
+            for (int i = 0; i < 8; i++) {
+                const uint64_t wd = (i & 1) ? ((uint64_t)q[i / 2].w << 32 | q[i / 2].z)
+                                            : ((uint64_t)q[i / 2].y << 32 | q[i / 2].x);
+                const uint32_t i0 = 3u * (base + (uint32_t)i);
+#pragma unroll
+                for (uint32_t sft = 0; sft < 3; sft++) {
+                    if (i0 + sft < st || i0 + sft >= end) continue;
+                    const uint32_t off = (uint32_t)(wd >> (21u * sft)) & 0x1FFFFFu;
+                    if (atomicOr(&bm[off >> 5], 1u << (off & 31u)) == 0u) {
+                        const uint32_t at = atomicAdd(&n_list, 1u);
+                        if (at < CAPPLY_LIST) list[at] = (uint16_t)(off >> 5);
+                    }
                 }
             }
         }
@@ -674,10 +671,11 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
         }
     }
     __syncthreads();
+    // counters added without waiting for them (atomics whose result is unused)
     uint32_t* dst = a.counts + (uint64_t)bin * n_est * k;
     for (uint32_t i = threadIdx.x; i < n_est * k; i += blockDim.x) {
         const int v = cnt[i];
-        if (v) dst[i] += (uint32_t)v;
+        if (v) atomicAdd(&dst[i], (uint32_t)v);
     }
 }
 
@@ -1591,17 +1589,16 @@ hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s)
     if (!a.counts || a.k == 0 || a.slot >= a.k || a.bin_shift < a.log2eta || a.bin_shift < 5 ||
         bytes > COUNTED_LDS_BYTES || a.n_bins == 0)
         return hipErrorInvalidValue;
+    if (!a.pack || a.seg < 6u) return hipErrorInvalidValue;     // counted bins are at most 2 MiB: always packed
     static bool attr = false;
     if (!attr) {
-        for (const void* f : {reinterpret_cast<const void*>(&k_apply_counted<true>),
-                              reinterpret_cast<const void*>(&k_apply_counted<false>)}) {
-            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)COUNTED_LDS_BYTES);
-            if (e != hipSuccess) return e;
-        }
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_counted),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)COUNTED_LDS_BYTES);
+        if (e != hipSuccess) return e;
         attr = true;
     }
-    if (a.pack) k_apply_counted<true><<<a.n_bins, 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
-    else k_apply_counted<false><<<a.n_bins, 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
+    const uint32_t grid = 8u * ((a.n_bins + 7u) / 8u);
+    k_apply_counted<<<grid, 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
     return hipGetLastError();
 }
 
