@@ -536,23 +536,37 @@ constexpr uint32_t CAPPLY_WAVES = 16;
 constexpr uint32_t CAPPLY_CHUNKS = 4;     // bitmap words per thread in flight in the visit
 constexpr uint32_t CAPPLY_LIST = 4096;    // marked words listed for the visit (more: the whole bitmap is swept)
 
-// The marked cells of one 4-byte word: new stamps and counter moves.
+// The marked cells of one 4-byte word (mask m, a bit per byte): the new
+// stamps, the count of cells restamped, and -1 on the slot of every old stamp
+// still in the window.  Byte masks are formed SWAR; only the restamped cells
+// with an old stamp are visited one by one.
 __device__ __forceinline__ uint32_t stamp_word(uint32_t x, uint32_t m, uint32_t stamp, uint32_t k, uint32_t slot,
                                                int* ce, uint32_t& changed)
 {
-    while (m) {
-        const uint32_t i = (uint32_t)__ffs(m) - 1u;
-        m &= m - 1u;
+    const uint32_t lanes = ((m * 0x00204081u) & 0x01010101u) * 0xFFu;       // bit i of m -> byte i
+    const uint32_t y = x ^ (stamp * 0x01010101u);
+    const uint32_t ne = ((((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u) >> 7;   // byte != stamp
+    const uint32_t nz = ((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u) >> 7;   // byte != 0
+    const uint32_t chg = lanes & (ne * 0xFFu);
+    changed += (uint32_t)__popc(chg) >> 3;
+    uint32_t old = (chg & (nz * 0xFFu)) & 0x01010101u;      // restamped cells with an old stamp
+    while (old) {
+        const uint32_t i = ((uint32_t)__ffs(old) - 1u) >> 3;
+        old &= old - 1u;
         const uint32_t b = (x >> (8u * i)) & 0xFFu;
-        if (b == stamp) continue;
-        x = (x & ~(0xFFu << (8u * i))) | (stamp << (8u * i));
-        changed++;
-        if (b != 0u) {
-            const uint32_t d = (stamp + 255u - b) % 255u;      // slices since the old stamp
-            if (d < k) atomicSub(&ce[slot >= d ? slot - d : slot + k - d], 1);
-        }
+        const uint32_t d = (stamp + 255u - b) % 255u;      // slices since the old stamp
+        if (d < k) atomicSub(&ce[slot >= d ? slot - d : slot + k - d], 1);
     }
-    return x;
+    return (x & ~chg) | ((stamp * 0x01010101u) & chg);
+}
+
+// Workgroup barrier that orders LDS only: global stores issued before it stay
+// in flight (a plain __syncthreads waits for their completion).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a)
@@ -634,9 +648,19 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
     // the listed words when they all fit the list, else every word of the bitmap
     const bool listed = n_list <= CAPPLY_LIST;
     const uint32_t n_visit = listed ? n_list : bm_words;
+    // new stamps and counter moves for every chunk of a pass first, then its
+    // stores; the last pass (the only one when the list holds every marked
+    // word) stores after the counters, at the kernel's end, so that no wait
+    // of the workgroup covers a store
+    uint4 v[2 * CAPPLY_CHUNKS];
+    uint32_t wd[CAPPLY_CHUNKS];
+    uint32_t dirty = 0;
     for (uint32_t w0 = threadIdx.x; w0 < n_visit; w0 += blockDim.x * CAPPLY_CHUNKS) {
-        uint32_t m[CAPPLY_CHUNKS], wd[CAPPLY_CHUNKS];
-        uint4 v[2 * CAPPLY_CHUNKS];
+#pragma unroll
+        for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++)
+            if (dirty & (1u << u)) chunk[2u * wd[u / 2] + (u & 1)] = v[u];
+        dirty = 0;
+        uint32_t m[CAPPLY_CHUNKS];
 #pragma unroll
         for (int u = 0; u < (int)CAPPLY_CHUNKS; u++) {
             const uint32_t i = w0 + (uint32_t)u * blockDim.x;
@@ -652,31 +676,41 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
 #pragma unroll
         for (int u = 0; u < (int)CAPPLY_CHUNKS; u++) {
             if (!m[u]) continue;
-            const uint32_t w = wd[u];
-            int* ce = cnt + ((w << 5) >> a.log2eta) * k;
+            int* ce = cnt + ((wd[u] << 5) >> a.log2eta) * k;
             uint32_t changed = 0;
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 const uint32_t mh = (m[u] >> (16 * h)) & 0xFFFFu;
                 if (!mh) continue;
-                uint4 x = v[2 * u + h];
+                uint4& x = v[2 * u + h];
                 const uint32_t before = changed;
                 x.x = stamp_word(x.x, mh & 0xFu, stamp, k, slot, ce, changed);
                 x.y = stamp_word(x.y, (mh >> 4) & 0xFu, stamp, k, slot, ce, changed);
                 x.z = stamp_word(x.z, (mh >> 8) & 0xFu, stamp, k, slot, ce, changed);
                 x.w = stamp_word(x.w, (mh >> 12) & 0xFu, stamp, k, slot, ce, changed);
-                if (changed != before) chunk[2 * w + h] = x;
+                if (changed != before) dirty |= 1u << (2 * u + h);
             }
             if (changed) atomicAdd(&ce[slot], (int)changed);
         }
     }
-    __syncthreads();
+    // every chunk load is waited for here, before any store or counter atomic
+    // is in flight (a wait after them would count them too)
+#pragma unroll
+    for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++) asm volatile("" : : "v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
+    lds_barrier();
     // counters added without waiting for them (atomics whose result is unused)
     uint32_t* dst = a.counts + (uint64_t)bin * n_est * k;
     for (uint32_t i = threadIdx.x; i < n_est * k; i += blockDim.x) {
-        const int v = cnt[i];
-        if (v) atomicAdd(&dst[i], (uint32_t)v);
+        const int c = cnt[i];
+        if (c) atomicAdd(&dst[i], (uint32_t)c);
     }
+#pragma unroll
+    for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++)
+        if (dirty & (1u << u)) chunk[2u * wd[u / 2] + (u & 1)] = v[u];
+    // the stored values stay live to here: no register of a store in flight
+    // is reused (which would wait for the store)
+#pragma unroll
+    for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++) asm volatile("" : : "v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
 }
 
 // ---------------------------------------------------------------- hot detection
