@@ -248,13 +248,67 @@ def test_counted_detection_switches():
     compare_state(g, o)
 
 
-def test_pipelined_close_matches_oracle():
+def test_counted_after_advance_and_merge():
+    """The per-slot counters go stale after an advance-only close and after a
+    router merge into the detector (Alg. 5); the close after the detector's
+    next binned scan rebuilds them from the state, a close with no scan of
+    its own detects from the whole state.  Every product equals the
+    oracle's, and counting cannot be switched on for a detector whose
+    counters would exceed an eighth of its state (eta < 32 k)."""
+    q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
+    tabs = tg.hash_tables(9)
+    g, o = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
+    gr, orr = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
+    sl = _slices_small(200, 8, kb, theta // 2, q, heavy=15)
+    # (own scan, router merged, advance only) -> detection path, launches
+    plan = [(1, 0, 0, "count", 1), (1, 0, 0, "count", 1), (1, 0, 1, None, 0), (1, 0, 0, "count", 2),
+            (1, 1, 0, "count", 2), (0, 1, 0, "full", 1), (1, 0, 0, "count", 2), (1, 0, 0, "count", 1)]
+    for t, (own, merged, adv, path, launches) in enumerate(plan):
+        half = sl[t].shape[0] // 2
+        mine, theirs = sl[t][:half], sl[t][half:]
+        scan_both(gr, orr, theirs, t)
+        if merged:
+            ssd.merge_router_state(g, [gr])
+            o.merge_from([orr])
+        if own:
+            scan_both(g, o, mine, t)
+        log(f"counted stale slice {t}: own {own} merged {merged} advance {adv}")
+        if adv:
+            assert len(ssd.close_slice(g, advance_only=True)) == 0
+            o.close(advance_only=True)
+        else:
+            close_both(g, o)
+        compare_state(g, o)
+        tm = ssd.read_timing(g, reset=True)
+        if path == "count":
+            assert tm["count_detect"][1] == launches and tm["hot_detect"][1] == 0, f"slice {t}: {tm}"
+        elif path == "full":
+            assert tm["hot_detect"][1] == launches and tm["count_detect"][1] == 0, f"slice {t}: {tm}"
+        assert len(ssd.close_slice(gr, advance_only=True)) == 0
+        orr.close(advance_only=True)
+    wide = ssd.init_detector(ssd.make_params(q=8, r=4, delta=4, eta=1024, k=254, theta=200, key_bits=16),
+                             tabs, device="cuda:0")
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.set_tuning(wide, ssd.SSD_TUNE_COUNTED, 1)
+    assert e.value.status == -1
+    ssd.set_tuning(wide, ssd.SSD_TUNE_COUNTED, 0)
+    wide.destroy()
+
+
+@pytest.mark.parametrize("mode", ["auto", "counted"])
+def test_pipelined_close_matches_oracle(mode):
     """close_begin / close_end with the next slice's scans enqueued between
-    them give the oracle's lists and state; misuse is rejected."""
+    them give the oracle's lists and state, also with the next slice's
+    counted scan moving the counters while the close's second part runs;
+    misuse is rejected."""
     cfg = tg.config("tiny")
     tr = tg.Trace(cfg)
     tabs = tg.hash_tables(cfg.hash_seed)
     g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    if mode == "counted":
+        ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
     with pytest.raises(ssd.SSDError) as e:
         ssd.close_end(g)
     assert e.value.status == -3
