@@ -53,7 +53,7 @@ struct LinkDesc {
     uint64_t host_cap;            //   are written there by the close's last kernel
     uint32_t* hot_list;           // [r][2^q]
     uint16_t* live16;             // [r][2^q][eta / 16] live-cell bits of hot estimators (written at hot detection)
-    uint32_t* counts;             // [r][2^q][k] live cells per estimator and slot t mod k (counted detectors, else null)
+    uint32_t* counts;             // [k][r][2^q] live cells per slot t mod k and estimator (counted detectors, else null)
     uint64_t* ctb_x[2];           // candidate buffers: regained bits
     uint32_t* ctb_h0[2];          //                    and he_0
     unsigned long long* acc;      // accepted keys
@@ -123,6 +123,7 @@ struct ApplyArgs {
     // slice's slot (t mod k) and the estimator size
     uint32_t* counts;
     uint32_t k, slot, log2eta, pad;
+    uint64_t n_se;                // estimators of the link (the counters' slot stride)
 };
 
 // 8-byte words of one packed binning segment of n items (three 21-bit

@@ -699,10 +699,12 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
     for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++) asm volatile("" : : "v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
     lds_barrier();
     // counters added without waiting for them (atomics whose result is unused)
-    uint32_t* dst = a.counts + (uint64_t)bin * n_est * k;
+    // (slot-major in memory: consecutive threads take consecutive estimators)
+    uint32_t* dst = a.counts + ((uint64_t)bin << (a.bin_shift - a.log2eta));
     for (uint32_t i = threadIdx.x; i < n_est * k; i += blockDim.x) {
-        const int c = cnt[i];
-        if (c) atomicAdd(&dst[i], (uint32_t)c);
+        const uint32_t j = i / n_est, e = i - j * n_est;
+        const int c = cnt[e * k + j];
+        if (c) atomicAdd(&dst[(uint64_t)j * a.n_se + e], (uint32_t)c);
     }
 #pragma unroll
     for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++)
@@ -864,40 +866,45 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
 // ---------------------------------------------------------------- counted detection
 // R_k of every estimator from its per-slot counters (one thread per
 // estimator): the same live-cell count as a scan of the state, since every
-// live cell carries the stamp of exactly one slice of the window.  The wave
-// then visits only the estimators that need their cells: hot ones (snapshot
-// and bitmask bits) and those of this slot's expiry phase (dead cells
-// cleared).  The slot of the next slice is zeroed for its scans.
+// live cell carries the stamp of exactly one slice of the window.  Only the
+// estimators that need their cells are then visited, by the workgroup's four
+// waves in turn: hot ones (snapshot and bitmask bits) and those of this
+// slot's expiry phase (dead cells cleared).  The slot of the next slice is
+// zeroed for its scans.
 __global__ __launch_bounds__(256) void k_count(const LinkDesc* link, uint64_t n_se)
 {
     const LinkDesc* D = link;
-    const uint64_t s = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-    const uint32_t lane = threadIdx.x & 63u;
+    __shared__ uint32_t todo[256];      // local estimator | 0x100 hot | 0x200 expiring
+    __shared__ uint32_t todo_live[256];
+    __shared__ uint32_t n_todo;
+    if (threadIdx.x == 0) n_todo = 0u;
+    __syncthreads();
+    const uint64_t s0 = (uint64_t)blockIdx.x * 256u;
+    const uint64_t s = s0 + threadIdx.x;
     const uint32_t k = D->k;
     const uint32_t next = (uint32_t)((D->clock->t + 1ull) % k);
-    uint32_t live = 0;
-    bool hot = false, expire = false;
     if (s < n_se) {
-        uint32_t* c = D->counts + s * k;
-        for (uint32_t j = 0; j < k; j++) live += c[j];
-        c[next] = 0u;
-        hot = live >= D->T;
-        expire = (s % D->expire_period) == D->expire_phase;
+        uint32_t live = 0;
+        for (uint32_t j = 0; j < k; j++) live += D->counts[(uint64_t)j * n_se + s];
+        D->counts[(uint64_t)next * n_se + s] = 0u;
+        const bool hot = live >= D->T;
+        const bool expire = (s % D->expire_period) == D->expire_phase;
         if (!hot) D->rk[s] = live;
+        if (hot || expire) {
+            const uint32_t at = atomicAdd(&n_todo, 1u);
+            todo[at] = threadIdx.x | (hot ? 0x100u : 0u) | (expire ? 0x200u : 0u);
+            todo_live[at] = live;
+        }
     }
-    unsigned long long m = __ballot(hot || expire);
-    if (!m) return;
+    __syncthreads();
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t log2eta = D->log2eta;
     const uint32_t chunks = 1u << (log2eta - 4);
     const LiveCfg L = D->L;
-    const uint64_t s0 = s - lane;
-    while (m) {
-        const uint32_t i = (uint32_t)__ffsll((long long)m) - 1u;
-        m &= m - 1ull;
-        const uint64_t si = s0 + i;
-        const uint32_t li = __shfl(live, (int)i, 64);
-        const bool hi = __shfl((uint32_t)hot, (int)i, 64) != 0u;
-        const bool ei = __shfl((uint32_t)expire, (int)i, 64) != 0u;
+    for (uint32_t i = wave; i < n_todo; i += 4u) {
+        const uint32_t e = todo[i];
+        const uint64_t si = s0 + (e & 0xFFu);
+        const bool hi = (e & 0x100u) != 0u, ei = (e & 0x200u) != 0u;
         uint4* se = reinterpret_cast<uint4*>(D->state + (si << log2eta));
         uint16_t* snap = D->live16 + si * chunks;
         for (uint32_t c = lane; c < chunks; c += 64u) {
@@ -910,7 +917,7 @@ __global__ __launch_bounds__(256) void k_count(const LinkDesc* link, uint64_t n_
                 if (n.x != v.x || n.y != v.y || n.z != v.z || n.w != v.w) se[c] = n;
             }
         }
-        if (hi) hot_finish<false>(D, si, li, se, lane);
+        if (hi) hot_finish<false>(D, si, todo_live[i], se, lane);
     }
 }
 
@@ -946,7 +953,7 @@ __global__ __launch_bounds__(256) void k_recount(const LinkDesc* link, uint64_t 
             }
         }
         n = wave_sum(n);
-        if (lane == 0) D->counts[s * k + j] = n;
+        if (lane == 0) D->counts[(uint64_t)j * n_se + s] = n;
     }
 }
 

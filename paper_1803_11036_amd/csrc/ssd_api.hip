@@ -587,6 +587,7 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
         aa.k = D.k;
         aa.slot = (uint32_t)(e->clock % D.k);
         aa.log2eta = D.log2eta;
+        aa.n_se = D.n_se;
     }
     for (uint64_t done = 0; done < n; done += chunk) {
         const uint64_t m = std::min(chunk, n - done);
