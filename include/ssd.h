@@ -234,7 +234,11 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       counters take r * 2^q * k * 4 bytes of scratch (included in
  *       ssd_query_sizes).  A router merge into the detector, an advance-only
  *       close, a pass scan or a group call leaves them stale: the close that
- *       follows the next binned scan rebuilds them from the state. */
+ *       follows the next binned scan rebuilds them from the state.  Batches:
+ *       the same for every link above 256 MiB that can count (reading 1 if
+ *       any link counts); a link scanned by the tile scan in a slice (fewer
+ *       than 2^20 pairs in the call, or SSD_SCAN_PASSES) leaves its counters
+ *       stale likewise. */
 #define SSD_TUNE_COUNTED 10u
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 

@@ -231,7 +231,10 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
         for (int b = 0; b < 2; b++) { K.ctb_h0[b] = o; o = align_up(o + q.max_tuples * 4); }
         K.acc = o; o = align_up(o + q.max_results * 8);
         K.out = o; o = align_up(o + q.max_results * sizeof(SuperPointDev));
-        if (bins && n == 1 && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
+        // per-slot counters for the links whose scans are binned (single
+        // detectors; batch links above the binned threshold) and can count
+        const bool binned = n == 1 || ((uint64_t)q.r << q.q) * q.eta > AUTO_BINNED_ABOVE;
+        if (bins && binned && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
     }
     uint64_t pw = 1;
     while (pw < maxres) pw <<= 1;
@@ -278,11 +281,11 @@ struct Engine {
     uint64_t se_total = 0;
     uint32_t rows_total = 0, max_r = 0, max_chunks = 1;
     bool detect_small = false;          // a link with eta < 4096, or several links (k_hot_detect SMALL)
-    // counted detection (single detectors): the counters are exact for the
-    // open slice's scans so far (count_valid), or a binned scan of this slice
-    // ran uncounted and the close rebuilds them (count_rebuild)
-    bool counting = false;
-    bool count_valid = false, count_rebuild = false;
+    // counted detection, per link: the counters are exact for the open
+    // slice's scans so far (count_valid), or a binned scan of this slice ran
+    // uncounted and the close rebuilds them (count_rebuild)
+    std::vector<uint8_t> counting, count_valid, count_rebuild;
+    std::vector<uint64_t> detect_prefix;   // the hot detection wave prefix on the device
     uint64_t counted_bin_bytes = DEFAULT_COUNTED_BIN_BYTES;   // bin size request of counted scans
     std::vector<LinkDesc> hl;          // host copies of the device descriptors
     std::vector<uint32_t> tables;      // n x 2048
@@ -502,11 +505,13 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     }
     e->se_total = se_prefix[n];
     e->rows_total = (uint32_t)row_table.size();
-    if (n == 1 && e->hl[0].counts) {
-        // the counters start zero with the state: exact from the first slice
-        e->counting = true;
-        e->count_valid = true;
-    }
+    // the counters start zero with the state: exact from the first slice
+    e->counting.assign(n, 0);
+    e->count_valid.assign(n, 0);
+    e->count_rebuild.assign(n, 0);
+    for (uint32_t l = 0; l < n; l++)
+        if (e->hl[l].counts) e->counting[l] = e->count_valid[l] = 1;
+    e->detect_prefix = se_prefix;
     hipError_t err = hipGetDevice(&e->device);
     if (err != hipSuccess) return dev_fail(e, err, "hipGetDevice");
     e->stage_cap = stage_cap;
@@ -555,8 +560,8 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
 int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs)
 {
     const LinkDesc& D = e->hl[l];
-    const bool counted = e->counting && e->count_valid;
-    if (e->counting && !counted) e->count_rebuild = true;
+    const bool counted = e->counting[l] && e->count_valid[l];
+    if (e->counting[l] && !counted) e->count_rebuild[l] = 1;
     const uint32_t csh = counted ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
     if (counted) bin_bytes = 1ull << csh;
     const BinPlan bp = bin_plan(e->p[l], bin_bytes);
@@ -613,27 +618,40 @@ int enqueue_close_head(Engine* e)
     const hipStream_t s = e->stream;
     LinkDesc* links = e->dev_links();
     HIPCHK(e, launch_prepare(links, e->n, true, s));
-    if (e->counting && (e->count_valid || e->count_rebuild)) {
-        // R_k from the per-slot counters (rebuilt from the state first when
-        // this slice's scans ran uncounted); the next slot starts at zero
-        PhaseMark pm = phase_begin(e);
-        if (!e->count_valid) HIPCHK(e, launch_recount(links, e->hl[0].n_se, s));
-        HIPCHK(e, launch_count(links, e->hl[0].n_se, s));
-        phase_end(e, pm, 9, e->count_valid ? 1 : 2);
-        e->count_valid = true;
-        e->count_rebuild = false;
-        return SSD_OK;
+    // per link: R_k from the per-slot counters (1), from counters rebuilt
+    // from the state first (2), or by reading the whole state (0)
+    const uint32_t n = e->n;
+    std::vector<uint8_t> mode(n, 0);
+    std::vector<uint64_t> pre(n + 1, 0);
+    for (uint32_t l = 0; l < n; l++) {
+        if (e->counting[l] && (e->count_valid[l] || e->count_rebuild[l])) mode[l] = e->count_valid[l] ? 1 : 2;
+        pre[l + 1] = pre[l] + (mode[l] ? 0 : detect_waves(e->hl[l]));      // counted links take no waves
     }
-    e->count_valid = false;
-    e->count_rebuild = false;
-    DetectArgs da{};
-    da.links = links;
-    da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
-    da.n_links = e->n;
-    da.total = e->se_total;
-    PhaseMark pm = phase_begin(e);
-    HIPCHK(e, launch_hot_detect(da, e->max_chunks, e->detect_small, s));
-    phase_end(e, pm, 1, 1);
+    if (pre != e->detect_prefix) {
+        HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), pre.data(), (n + 1) * 8, hipMemcpyHostToDevice, s));
+        e->detect_prefix = pre;
+    }
+    if (pre[n]) {
+        DetectArgs da{};
+        da.links = links;
+        da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
+        da.n_links = n;
+        da.total = pre[n];
+        PhaseMark pm = phase_begin(e);
+        HIPCHK(e, launch_hot_detect(da, e->max_chunks, e->detect_small, s));
+        phase_end(e, pm, 1, 1);
+    }
+    for (uint32_t l = 0; l < n; l++) {
+        if (mode[l]) {
+            // the next slot starts at zero
+            PhaseMark pm = phase_begin(e);
+            if (mode[l] == 2) HIPCHK(e, launch_recount(links + l, e->hl[l].n_se, s));
+            HIPCHK(e, launch_count(links + l, e->hl[l].n_se, s));
+            phase_end(e, pm, 9, mode[l]);
+        }
+        e->count_valid[l] = mode[l] != 0;
+        e->count_rebuild[l] = 0;
+    }
     return SSD_OK;
 }
 
@@ -805,8 +823,8 @@ int collect_results(Engine* e, bool packed, uint64_t single_prefix)
 int enqueue_advance_only(Engine* e)
 {
     const hipStream_t s = e->stream;
-    e->count_valid = false;           // the next slot's counters are not zeroed
-    e->count_rebuild = false;
+    e->count_valid[0] = 0;            // the next slot's counters are not zeroed
+    e->count_rebuild[0] = 0;
     LinkDesc* links = e->dev_links();
     HIPCHK(e, launch_prepare(links, e->n, false, s));
     DetectArgs da{};
@@ -994,6 +1012,10 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
     }
     e->se_total = se_prefix[n];
     e->rows_total = (uint32_t)row_table.size();
+    e->counting.assign(n, 0);              // a group's close reads every member's state
+    e->count_valid.assign(n, 0);
+    e->count_rebuild.assign(n, 0);
+    e->detect_prefix = se_prefix;
     HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
     HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice,
                              e->stream));
@@ -1098,10 +1120,10 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
         if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
         if (value && !d->e.hl[0].counts) return fail(SSD_E_PARAM, "this detector cannot count (eta < 32 k or too many bins)");
         if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
-        if (d->e.counting != (value != 0)) {
-            d->e.counting = value != 0;
-            d->e.count_valid = false;
-            d->e.count_rebuild = false;
+        if (d->e.counting[0] != (value != 0)) {
+            d->e.counting[0] = value != 0;
+            d->e.count_valid[0] = 0;
+            d->e.count_rebuild[0] = 0;
         }
         return SSD_OK;
     case SSD_TUNE_SORT_BLOCK_LIMIT: {
@@ -1134,7 +1156,7 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
     const uint64_t state_bytes = D.n_se << D.log2eta;
     if (d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE))
         return enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes, d->apply_segments);
-    e->count_valid = false;           // pass scans store without counting
+    e->count_valid[0] = 0;            // pass scans store without counting
     ScanArgs a{};
     a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
     a.n = n;
@@ -1281,8 +1303,8 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
                                                   (unsigned long long)r->e.clock, (unsigned long long)g->e.clock);
         if (r->e.device != g->e.device) return fail(SSD_E_INCOMPAT, "router %u is on another device", j);
     }
-    g->e.count_valid = false;         // merged cells are not counted
-    g->e.count_rebuild = false;
+    g->e.count_valid[0] = 0;          // merged cells are not counted
+    g->e.count_rebuild[0] = 0;
     MergeArgs a{};
     a.dst = g->D().state;
     a.n16 = g->e.L.state_total / 16u;
@@ -1497,6 +1519,18 @@ int ssd_batch_set_tuning(ssd_batch* b, uint32_t knob, uint64_t value)
             return fail(SSD_E_PARAM, "batches take SSD_SCAN_PASSES or SSD_SCAN_AUTO");
         b->scan_mode = (uint32_t)value;
         return SSD_OK;
+    case SSD_TUNE_COUNTED: {
+        // every link whose scans are binned and that can count (others: no effect)
+        if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
+        Engine& e = b->e;
+        for (uint32_t l = 0; l < e.n; l++) {
+            if (!e.hl[l].counts || e.counting[l] == (value != 0)) continue;
+            e.counting[l] = value != 0;
+            e.count_valid[l] = 0;
+            e.count_rebuild[l] = 0;
+        }
+        return SSD_OK;
+    }
     case SSD_TUNE_AUTOTUNE:
         if (!value) { b->tune_idx = -1; return SSD_OK; }
         b->cands.clear();
@@ -1517,6 +1551,10 @@ int ssd_batch_get_tuning(ssd_batch* b, uint32_t knob, uint64_t* value)
     case SSD_TUNE_TIMING: *value = b->e.timing; return SSD_OK;
     case SSD_TUNE_GRAPH: *value = b->e.use_graph; return SSD_OK;
     case SSD_TUNE_AUTOTUNE: *value = b->tune_idx >= 0; return SSD_OK;
+    case SSD_TUNE_COUNTED:
+        *value = 0;
+        for (uint32_t l = 0; l < b->e.n; l++) *value |= b->e.counting[l];
+        return SSD_OK;
     default: return fail(SSD_E_PARAM, "unknown tuning knob %u", knob);
     }
 }
@@ -1558,6 +1596,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
     std::vector<Win> wins;
     for (uint32_t l = 0; l < e->n; l++) {
         if (offsets_host[l + 1] == offsets_host[l] || is_binned(l)) continue;
+        e->count_valid[l] = 0;             // the tile scan stores without counting
         const LinkDesc& D = e->hl[l];
         const uint64_t per = pass ? std::max<uint64_t>(1, pass / D.eta) : D.n_se;
         for (uint64_t lo = 0; lo < D.n_se; lo += per)
@@ -1734,7 +1773,7 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     if (!offsets_host || !slice_ids_host) return fail(SSD_E_PARAM, "offsets or slice ids NULL");
     rc = group_bind(g, members, n);
     if (rc) return rc;
-    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid = false;   // the group's stores are not counted
+    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;    // the group's stores are not counted
     for (uint32_t i = 0; i < n; i++) {
         if (offsets_host[i + 1] < offsets_host[i]) return fail(SSD_E_PARAM, "offsets decrease at member %u", i);
         if (slice_ids_host[i] != members[i]->e.clock)
@@ -1823,8 +1862,8 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
         if (members[i]->pending) return fail(SSD_E_ORDER, "member %u has a close pending", i);
     for (uint32_t i = 0; i < n; i++) {
         // the group's close zeroes no member's next slot
-        members[i]->e.count_valid = false;
-        members[i]->e.count_rebuild = false;
+        members[i]->e.count_valid[0] = 0;
+        members[i]->e.count_rebuild[0] = 0;
     }
     rc = enqueue_close(e, true, 0);
     if (rc) return rc;

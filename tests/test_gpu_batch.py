@@ -68,8 +68,11 @@ def test_batch_equals_separate_detectors(graph, autotune):
 
 def test_batch_binned_links_equal_separate_detectors():
     """Links with a state above 256 MiB and at least 2^20 pairs in the call
-    take the binned scan inside the batch (the rest the tile scan); every
-    link's list equals its separate detector's."""
+    take the binned scan inside the batch, keeping per-slot counters (the rest
+    the tile scan, with hot detection over their states).  A large link that
+    gets fewer pairs in a slice is tile-scanned: its counters go stale, and
+    the close after its next binned scan rebuilds them; counting is switched
+    off and on.  Every link's list equals its separate detector's."""
     cfgs = tg.batch_configs(n_links=12, pairs_scale=0.5)
     traces = [tg.Trace(c) for c in cfgs]
     tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
@@ -78,8 +81,19 @@ def test_batch_binned_links_equal_separate_detectors():
     plain = [ssd.init_detector(_params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
     big = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > 256 << 20 and c.pairs_lo >= 1 << 20]
     assert big, "no link takes the binned scan"
-    for t in range(4):
-        per, offs, dev = _slice_pairs(traces, t)
+    assert ssd.batch_get_tuning(b, ssd.SSD_TUNE_COUNTED) == 1
+    # slice: (large links' pairs cut to 5000, counting knob) -> count launches expected
+    plan = [(False, None, len(big)), (False, None, len(big)), (True, None, 0), (False, None, 2 * len(big)),
+            (False, 0, 0), (False, 1, 2 * len(big))]
+    for t, (cut, knob, launches) in enumerate(plan):
+        per = [tr.pairs(0, t % tr.cfg.n_slices) for tr in traces]
+        if cut:
+            per = [p[:5000] if i in big else p for i, p in enumerate(per)]
+        offs = np.zeros(len(per) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([p.shape[0] for p in per])
+        dev = to_dev(np.concatenate(per))
+        if knob is not None:
+            ssd.batch_set_tuning(b, ssd.SSD_TUNE_COUNTED, knob)
         ssd.batch_scan(b, dev, offs, t)
         lists, status = ssd.batch_close(b)
         assert np.all(status == 0)
@@ -87,8 +101,12 @@ def test_batch_binned_links_equal_separate_detectors():
             ssd.scan_slice(plain[i], dev[int(offs[i]):int(offs[i + 1])], t)
             res = ssd.close_slice(plain[i])
             assert np.array_equal(lists[i], res), f"slice {t} link {i}: batch and separate detector differ"
-        log(f"batch binned slice {t}: {sum(len(x) for x in lists)} hosts, binned links {big}")
-    assert ssd.batch_read_timing(b)["scan_bin"][1] >= 4 * len(big)
+        tm = ssd.batch_read_timing(b, reset=True)
+        log(f"batch binned slice {t}: {sum(len(x) for x in lists)} hosts, binned links {big}, "
+            f"count launches {tm['count_detect'][1]}, bin launches {tm['scan_bin'][1]}")
+        assert tm["count_detect"][1] == launches, f"slice {t}: {tm}"
+        assert tm["hot_detect"][1] == 1                        # the other links' states (and uncounted ones)
+        assert tm["scan_bin"][1] >= (0 if cut else len(big))
     b.destroy()
     for d in plain:
         d.destroy()
