@@ -232,14 +232,19 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       estimators whose expiry phase it is, instead of the whole state.
  *       Possible when eta >= 32 k and the state fits 4096 bins; the
  *       counters take r * 2^q * k * 4 bytes of scratch (included in
- *       ssd_query_sizes).  A router merge into the detector, an advance-only
- *       close, a pass scan or a group call leaves them stale: the close that
- *       follows the next binned scan rebuilds them from the state.  Batches:
+ *       ssd_query_sizes).  A scan call with fewer cell offsets per bin on
+ *       average than SSD_TUNE_COUNTED_MIN_ITEMS (default 2048) stores
+ *       uncounted (the counted stores cost a workgroup per bin); it, a router
+ *       merge into the detector, an advance-only close, a pass scan or a
+ *       group call leaves the counters stale: the close reads the state,
+ *       or, when every binned call of the slice was large, rebuilds the
+ *       counters from it.  Batches:
  *       the same for every link above 256 MiB that can count (reading 1 if
  *       any link counts); a link scanned by the tile scan in a slice (fewer
  *       than 2^20 pairs in the call, or SSD_SCAN_PASSES) leaves its counters
  *       stale likewise. */
 #define SSD_TUNE_COUNTED 10u
+#define SSD_TUNE_COUNTED_MIN_ITEMS 11u   /* counted scans: offsets per bin a call needs (default 2048) */
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 
 /* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per

@@ -27,7 +27,7 @@ __all__ = [
     "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
     "SSD_TUNE_SCAN_TILE_PAIRS", "SSD_TUNE_GRAPH", "SSD_TUNE_AUTOTUNE", "PHASES",
     "SSD_TUNE_SCAN_MODE", "SSD_TUNE_SCAN_BIN_BYTES", "SSD_TUNE_SCAN_APPLY_SEGMENTS", "SSD_SCAN_PASSES",
-    "SSD_SCAN_BINNED", "SSD_SCAN_AUTO", "SSD_TUNE_COUNTED",
+    "SSD_SCAN_BINNED", "SSD_SCAN_AUTO", "SSD_TUNE_COUNTED", "SSD_TUNE_COUNTED_MIN_ITEMS",
     "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
     "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_destroy",
     "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_destroy",
@@ -310,6 +310,7 @@ SSD_TUNE_SCAN_MODE = 7
 SSD_TUNE_SCAN_BIN_BYTES = 8
 SSD_TUNE_SCAN_APPLY_SEGMENTS = 9
 SSD_TUNE_COUNTED = 10
+SSD_TUNE_COUNTED_MIN_ITEMS = 11
 SSD_SCAN_PASSES = 0
 SSD_SCAN_BINNED = 1
 SSD_SCAN_AUTO = 2

@@ -98,6 +98,12 @@ constexpr uint64_t DEFAULT_BIN_BYTES = 2ull << 20;
 // counted scans: 512 KiB bins let two workgroups share a compute unit (0.40 ms
 // per 6M-pair call into the 1.5 GiB core-link state against 0.55 ms at 1 MiB)
 constexpr uint64_t DEFAULT_COUNTED_BIN_BYTES = 512ull << 10;
+// A counted scan costs a workgroup per bin whatever the call's size: calls
+// with fewer offsets per bin on average store uncounted (and leave the
+// counters stale); many small calls per slice then close with the
+// full-state hot detection instead (the served streams' 64K-4M-pair calls:
+// counting at 256 slowed their per-stream closes eightfold).
+constexpr uint64_t DEFAULT_COUNTED_MIN_ITEMS = 2048;
 // Pairs binned per step, at most.  The stores of a bin are spread over the
 // workgroups of one XCD, so the work in flight is about (bins in flight) x
 // (items per bin): larger steps put more items in every bin (8M and 16M
@@ -287,6 +293,8 @@ struct Engine {
     std::vector<uint8_t> counting, count_valid, count_rebuild;
     std::vector<uint64_t> detect_prefix;   // the hot detection wave prefix on the device
     uint64_t counted_bin_bytes = DEFAULT_COUNTED_BIN_BYTES;   // bin size request of counted scans
+    uint64_t counted_min_items = DEFAULT_COUNTED_MIN_ITEMS;   // offsets per bin a call needs to count
+    std::vector<uint8_t> count_small;      // a call of this slice stored uncounted for being small
     std::vector<LinkDesc> hl;          // host copies of the device descriptors
     std::vector<uint32_t> tables;      // n x 2048
     // pinned host mailbox: control blocks, staged result entries, pack offsets
@@ -509,6 +517,7 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     e->counting.assign(n, 0);
     e->count_valid.assign(n, 0);
     e->count_rebuild.assign(n, 0);
+    e->count_small.assign(n, 0);
     for (uint32_t l = 0; l < n; l++)
         if (e->hl[l].counts) e->counting[l] = e->count_valid[l] = 1;
     e->detect_prefix = se_prefix;
@@ -560,9 +569,17 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
 int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs)
 {
     const LinkDesc& D = e->hl[l];
-    const bool counted = e->counting[l] && e->count_valid[l];
-    if (e->counting[l] && !counted) e->count_rebuild[l] = 1;
-    const uint32_t csh = counted ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
+    uint32_t csh = e->counting[l] ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
+    const bool large = csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << csh).n_bins;
+    const bool counted = e->counting[l] && e->count_valid[l] && large;
+    if (e->counting[l] && !counted) {
+        e->count_valid[l] = 0;                 // these stores are not counted
+        // the close rebuilds the counters from the state after large calls
+        // only; with a small call in the slice it reads the state once
+        if (!large) e->count_small[l] = 1;
+        e->count_rebuild[l] = large && !e->count_small[l];
+    }
+    if (!counted) csh = 0;
     if (counted) bin_bytes = 1ull << csh;
     const BinPlan bp = bin_plan(e->p[l], bin_bytes);
     if (counted && (!csh || bp.shift != csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
@@ -651,6 +668,7 @@ int enqueue_close_head(Engine* e)
         }
         e->count_valid[l] = mode[l] != 0;
         e->count_rebuild[l] = 0;
+        e->count_small[l] = 0;
     }
     return SSD_OK;
 }
@@ -825,6 +843,7 @@ int enqueue_advance_only(Engine* e)
     const hipStream_t s = e->stream;
     e->count_valid[0] = 0;            // the next slot's counters are not zeroed
     e->count_rebuild[0] = 0;
+    e->count_small[0] = 0;
     LinkDesc* links = e->dev_links();
     HIPCHK(e, launch_prepare(links, e->n, false, s));
     DetectArgs da{};
@@ -1012,9 +1031,10 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
     }
     e->se_total = se_prefix[n];
     e->rows_total = (uint32_t)row_table.size();
-    e->counting.assign(n, 0);              // a group's close reads every member's state
+    e->counting.assign(n, 0);              // set from the members at every close
     e->count_valid.assign(n, 0);
     e->count_rebuild.assign(n, 0);
+    e->count_small.assign(n, 0);
     e->detect_prefix = se_prefix;
     HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
     HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice,
@@ -1115,6 +1135,9 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     case SSD_TUNE_SCAN_APPLY_SEGMENTS:
         if (value < 1 || value > 4096) return fail(SSD_E_PARAM, "apply segments outside 1..4096");
         d->apply_segments = (uint32_t)value;
+        return SSD_OK;
+    case SSD_TUNE_COUNTED_MIN_ITEMS:
+        d->e.counted_min_items = value;
         return SSD_OK;
     case SSD_TUNE_COUNTED:
         if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
@@ -1519,6 +1542,9 @@ int ssd_batch_set_tuning(ssd_batch* b, uint32_t knob, uint64_t value)
             return fail(SSD_E_PARAM, "batches take SSD_SCAN_PASSES or SSD_SCAN_AUTO");
         b->scan_mode = (uint32_t)value;
         return SSD_OK;
+    case SSD_TUNE_COUNTED_MIN_ITEMS:
+        b->e.counted_min_items = value;
+        return SSD_OK;
     case SSD_TUNE_COUNTED: {
         // every link whose scans are binned and that can count (others: no effect)
         if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
@@ -1773,7 +1799,6 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     if (!offsets_host || !slice_ids_host) return fail(SSD_E_PARAM, "offsets or slice ids NULL");
     rc = group_bind(g, members, n);
     if (rc) return rc;
-    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;    // the group's stores are not counted
     for (uint32_t i = 0; i < n; i++) {
         if (offsets_host[i + 1] < offsets_host[i]) return fail(SSD_E_PARAM, "offsets decrease at member %u", i);
         if (slice_ids_host[i] != members[i]->e.clock)
@@ -1839,6 +1864,7 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(g->scan_blocks, tiles), e->stream));
         phase_end(e, pm, 0, 1);
     }
+    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;   // group scans store uncounted
     for (uint32_t i = 0; i < n; i++) {
         if (!binned(i)) continue;
         ssd_detector* m = members[i];
@@ -1860,8 +1886,10 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
     if (rc) return rc;
     for (uint32_t i = 0; i < n; i++)
         if (members[i]->pending) return fail(SSD_E_ORDER, "member %u has a close pending", i);
+    // a group's close reads every member's state (served streams' calls are
+    // mostly too small to count; counted group closes measured slower) and
+    // zeroes no member's next slot
     for (uint32_t i = 0; i < n; i++) {
-        // the group's close zeroes no member's next slot
         members[i]->e.count_valid[0] = 0;
         members[i]->e.count_rebuild[0] = 0;
     }

@@ -67,8 +67,9 @@ def test_tiny_config(graph, timing):
 def test_ragged_batches_and_empty_slices(splits, mode):
     """Pair counts that leave ragged tails (0, 1, 63, 64, 65, 257, odd sizes),
     several scan calls per slice, empty slices, and (binned scan) calls of
-    several binning chunks -- binned with per-slot counters (one 1 MiB bin;
-    the cells of one slice reach the counters through several launches) and
+    several binning chunks -- binned with per-slot counters (two 512 KiB
+    bins; the cells of one slice reach the counters through several launches,
+    and calls with too few pairs store uncounted and leave them stale) and
     without."""
     q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
     sizes = [0, 1, 63, 64, 65, 257, 10007, 0, 12345, 9999, 0, 10240]
@@ -87,8 +88,15 @@ def test_ragged_batches_and_empty_slices(splits, mode):
         compare_state(g, o)
         close_both(g, o)
     tm = ssd.read_timing(g)
-    counted = mode == "binned"
-    assert (tm["count_detect"][1] == len(sl)) == counted and (tm["hot_detect"][1] == 0) == counted
+    # counted closes need the slice's calls large enough (256 offsets per bin on
+    # average); the others read the state.  The counters are exact until the
+    # first uncounted store, so a pass-scan detector's first close (an empty
+    # slice here) still counts.
+    if mode == "binned":
+        assert tm["count_detect"][1] > 1
+    else:
+        assert tm["count_detect"][1] <= (1 if mode == "passes" else 0)
+    assert tm["count_detect"][1] + tm["hot_detect"][1] >= len(sl)
 
 
 @pytest.mark.parametrize("k,mode", [(1, "passes"), (3, "passes"), (17, "passes"), (254, "passes"),
@@ -107,6 +115,7 @@ def test_stamp_wrap_and_expiry(k, mode):
     g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(4), key_bits=kb)
     if mode == "counted":
         ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+        ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED_MIN_ITEMS, 0)       # count every call, however small
         ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
     for t, p in enumerate(sl):
         scan_both(g, o, p, t)
@@ -221,8 +230,10 @@ def test_counted_detection_switches():
     """R_k from the per-slot counters through every switch of the counted
     path: counted from the first slice, stale after a pass scan (full hot
     detection), rebuilt from the state at the close after the next binned
-    scan, counting switched off and on again, and slices split over several
-    calls -- every product equals the oracle's at every slice."""
+    scan, counting switched off and on again, slices split over several
+    calls, and a slice of one small call (too few offsets per bin to count:
+    full hot detection, no rebuild) -- every product equals the oracle's at
+    every slice."""
     cfg = tg.config("tiny")
     tr = tg.Trace(cfg)
     tabs = tg.hash_tables(cfg.hash_seed)
@@ -233,12 +244,16 @@ def test_counted_detection_switches():
     plan = [(ssd.SSD_SCAN_BINNED, 1, 1, "count", 1), (ssd.SSD_SCAN_BINNED, 1, 3, "count", 1),
             (ssd.SSD_SCAN_PASSES, 1, 1, "full", 1), (ssd.SSD_SCAN_BINNED, 1, 2, "count", 2),
             (ssd.SSD_SCAN_BINNED, 1, 1, "count", 1), (ssd.SSD_SCAN_BINNED, 0, 1, "full", 1),
-            (ssd.SSD_SCAN_BINNED, 1, 1, "count", 2), (ssd.SSD_SCAN_BINNED, 1, 4, "count", 1)]
+            (ssd.SSD_SCAN_BINNED, 1, 1, "count", 2), (ssd.SSD_SCAN_BINNED, 1, 4, "count", 1),
+            (ssd.SSD_SCAN_BINNED, 1, 0, "full", 1), (ssd.SSD_SCAN_BINNED, 1, 1, "count", 2)]
     for t, (mode, counted, calls, path, launches) in enumerate(plan):
         ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, mode)
         ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED, counted)
         log(f"counted switches slice {t}: mode {mode} counted {counted} calls {calls}")
-        scan_both(g, o, tr.pairs(0, t % cfg.n_slices), t, splits=calls)
+        pairs = tr.pairs(0, t % cfg.n_slices)
+        if calls == 0:                                  # one call of 1000 pairs: about 125 offsets per bin
+            pairs, calls = pairs[:1000], 1
+        scan_both(g, o, pairs, t, splits=calls)
         close_both(g, o)
         tm = ssd.read_timing(g, reset=True)
         if path == "count":
@@ -260,6 +275,7 @@ def test_counted_after_advance_and_merge():
     g, o = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
     gr, orr = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
     ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED_MIN_ITEMS, 0)           # count every call, however small
     ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
     sl = _slices_small(200, 8, kb, theta // 2, q, heavy=15)
     # (own scan, router merged, advance only) -> detection path, launches
