@@ -303,13 +303,22 @@ __device__ __forceinline__ uint64_t cell_addr(uint2 pr, uint32_t i, uint32_t h0,
 }
 
 
+// The segment (chunk of pairs) of this binning workgroup: workgroup g runs on
+// XCD g mod 8, which takes a contiguous eighth of the segments, so that the
+// bin table entries of neighbouring segments, which share sectors, are
+// written through one L2 and leave it merged.  At least the segment count.
+__device__ __forceinline__ uint32_t bin_segment(uint32_t blocks)
+{
+    return (blockIdx.x & 7u) * ((blocks + 7u) >> 3) + (blockIdx.x >> 3);
+}
+
 // A workgroup's sorted offsets out to its segment, coalesced: 4 bytes each, or
 // (bins of at most 2 MiB) three 21-bit offsets per 8-byte word.
-__device__ __forceinline__ void write_segment(const BinArgs& a, const uint32_t* stage, uint32_t n)
+__device__ __forceinline__ void write_segment(const BinArgs& a, uint32_t sg, const uint32_t* stage, uint32_t n)
 {
     const uint64_t seg_items = (uint64_t)a.pb * a.r;
     if (a.pack) {
-        uint64_t* seg = reinterpret_cast<uint64_t*>(a.items) + (uint64_t)blockIdx.x * packed_seg_words(seg_items);
+        uint64_t* seg = reinterpret_cast<uint64_t*>(a.items) + (uint64_t)sg * packed_seg_words(seg_items);
         for (uint32_t w = threadIdx.x; w * 3u < n; w += 1024u) {
             const uint32_t i = w * 3u;
             uint64_t v = stage[i];
@@ -318,7 +327,7 @@ __device__ __forceinline__ void write_segment(const BinArgs& a, const uint32_t* 
             seg[w] = v;
         }
     } else {
-        uint32_t* seg = a.items + (uint64_t)blockIdx.x * seg_items;
+        uint32_t* seg = a.items + (uint64_t)sg * seg_items;
         for (uint32_t i = threadIdx.x; i < n; i += 1024u) seg[i] = stage[i];
     }
 }
@@ -341,13 +350,15 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
 {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t wsum[16];
+    const uint32_t sg = bin_segment(a.blocks);
+    if (sg >= a.blocks) return;
     uint32_t* tab = lds;
     uint32_t* hist = lds + 2048;
     uint32_t* stage = hist + a.n_bins + 1;
     for (uint32_t i = threadIdx.x; i < 2048u; i += 1024u) tab[i] = a.tables[i];
     for (uint32_t i = threadIdx.x; i <= a.n_bins; i += 1024u) hist[i] = 0u;
     __syncthreads();
-    const uint64_t p0 = (uint64_t)blockIdx.x * a.pb;
+    const uint64_t p0 = (uint64_t)sg * a.pb;
     const uint32_t np = (uint32_t)min((uint64_t)a.pb, a.n - p0);
     const uint32_t q = a.q, r = a.r, delta = a.delta, log2eta = a.log2eta, bs = a.bin_shift;
     const uint32_t bmask = (1u << bs) - 1u;
@@ -367,10 +378,10 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
     for (uint32_t b = b0; b < b1; b++) {
         const uint32_t c = hist[b];
         hist[b] = start;
-        a.table[(uint64_t)b * a.blocks + blockIdx.x] = start;
+        a.table[(uint64_t)b * a.blocks + sg] = start;
         start += c;
     }
-    if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + blockIdx.x] = np * r;
+    if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + sg] = np * r;
     __syncthreads();
     for (uint32_t p = threadIdx.x; p < np; p += 1024u) {
         const uint2 pr = a.pairs[p0 + p];
@@ -382,7 +393,7 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
         }
     }
     __syncthreads();
-    write_segment(a, stage, np * r);
+    write_segment(a, sg, stage, np * r);
 }
 
 // The same sort for the common row counts with every item kept in registers
@@ -393,13 +404,15 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
 {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t wsum[16];
+    const uint32_t sg = bin_segment(a.blocks);
+    if (sg >= a.blocks) return;
     uint32_t* tab = lds;
     uint32_t* hist = lds + 2048;
     uint32_t* stage = hist + a.n_bins + 1;
     for (uint32_t i = threadIdx.x; i < 2048u; i += 1024u) tab[i] = a.tables[i];
     for (uint32_t i = threadIdx.x; i <= a.n_bins; i += 1024u) hist[i] = 0u;
     __syncthreads();
-    const uint64_t p0 = (uint64_t)blockIdx.x * a.pb;
+    const uint64_t p0 = (uint64_t)sg * a.pb;
     const uint32_t np = (uint32_t)min((uint64_t)a.pb, a.n - p0);
     const uint32_t q = a.q, delta = a.delta, log2eta = a.log2eta, bs = a.bin_shift;
     const uint32_t bmask = (1u << bs) - 1u;
@@ -429,10 +442,10 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
     for (uint32_t b = b0; b < b1; b++) {
         const uint32_t c = hist[b];
         hist[b] = start;
-        a.table[(uint64_t)b * a.blocks + blockIdx.x] = start;
+        a.table[(uint64_t)b * a.blocks + sg] = start;
         start += c;
     }
-    if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + blockIdx.x] = np * R;
+    if (threadIdx.x == 0) a.table[(uint64_t)a.n_bins * a.blocks + sg] = np * R;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PPT; u++) {
@@ -441,7 +454,7 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
         for (int i = 0; i < R; i++) stage[hist[key[u][i] >> 16] + (key[u][i] & 0xFFFFu)] = off[u][i];
     }
     __syncthreads();
-    write_segment(a, stage, np * R);
+    write_segment(a, sg, stage, np * R);
 }
 
 // One wave per workgroup.  Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w /
@@ -1609,9 +1622,10 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t s)
         }
         attr = true;
     }
-    if (a.r == 6 && a.pb <= 6u * 1024u) k_bin_reg<6, 6><<<a.blocks, 1024, words * 4u, s>>>(a);
-    else if (a.r == 5 && a.pb <= 7u * 1024u) k_bin_reg<5, 7><<<a.blocks, 1024, words * 4u, s>>>(a);
-    else k_bin<<<a.blocks, 1024, words * 4u, s>>>(a);
+    const uint32_t grid = 8u * ((a.blocks + 7u) / 8u);      // segments dealt to XCDs in contiguous eighths
+    if (a.r == 6 && a.pb <= 6u * 1024u) k_bin_reg<6, 6><<<grid, 1024, words * 4u, s>>>(a);
+    else if (a.r == 5 && a.pb <= 7u * 1024u) k_bin_reg<5, 7><<<grid, 1024, words * 4u, s>>>(a);
+    else k_bin<<<grid, 1024, words * 4u, s>>>(a);
     return hipGetLastError();
 }
 
