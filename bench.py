@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -39,10 +40,17 @@ def log(msg: str) -> None:
 
 
 def kernel_source_sha() -> str:
+    """Hash of the kernel sources' code: comments and blank lines are left
+    out, so that a comment edit does not void traffic measured on the same
+    kernels."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1803_11036_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1803_11036_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -543,8 +543,9 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 // the open slot, -1 for the slot of an old stamp still in the window).
 // Stamps of earlier launches into the same slice are recognised by their
 // value, so every cell is counted once per slice.  The workgroup owns its
-// bin's cells and estimators: chunks are written back whole and the counters,
-// summed in LDS, are added to memory without atomics.
+// bin's cells and estimators: chunks are written back whole, and the
+// counters, summed in LDS, are added to memory by atomics whose result is
+// unused (so that nothing waits for a read of the old values).
 constexpr uint32_t CAPPLY_WAVES = 16;
 constexpr uint32_t CAPPLY_CHUNKS = 4;     // bitmap words per thread in flight in the visit
 constexpr uint32_t CAPPLY_LIST = 4096;    // marked words listed for the visit (more: the whole bitmap is swept)

@@ -559,13 +559,11 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     return SSD_OK;
 }
 
-// The close of every link as one fixed launch sequence (recordable in a graph):
-// per-slice constants, hot bits cleared, hot detection, hot lists, the
-// candidate levels, the final test, sorting, then the control blocks (and, for
-// batches, the packed lists) to pinned memory, and the clock advance.
-// Binned scan (k_bin, then k_apply) of n pairs of link l, in steps that fit
-// the engine's bin buffers (shared by every binned link of a batch: the steps
-// run one after another on the engine's stream).
+// Binned scan (k_bin, then k_apply_counted or k_apply) of n pairs of link l,
+// in steps that fit the engine's bin buffers (shared by every binned link of a
+// batch: the steps run one after another on the engine's stream).  The
+// stores keep the link's per-slot counters when they are exact and the call
+// is large enough; otherwise they leave them stale.
 int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs)
 {
     const LinkDesc& D = e->hl[l];
@@ -628,8 +626,13 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
     return SSD_OK;
 }
 
-// The close, first part: per-slice constants, hot bitmasks cleared, hot
-// detection over every estimator (one large launch, always eager and timed).
+// The close of every link: per-slice constants, hot bitmasks cleared, hot
+// detection (this first part, eager and timed), then hot lists, the
+// candidate levels, the final test, sorting, the control blocks (and, for
+// batches, the packed lists) to pinned memory and the clock advance (the
+// second part, recordable in a graph).  Hot detection takes R_k from the
+// per-slot counters of the links where they are exact or rebuilt, and reads
+// the state of the others.
 int enqueue_close_head(Engine* e)
 {
     const hipStream_t s = e->stream;
