@@ -39,6 +39,33 @@ def test_core_link_full_size():
     assert len(res) > 500
 
 
+def test_core_link_full_size_split_calls_pipelined():
+    """The core link with every slice split over three counted scan calls
+    (2M pairs, about 3,900 offsets per 512 KiB bin each) and the close
+    pipelined behind the next slice's scans (close_begin / close_end): lists
+    equal the oracle's at every slice, R_k at the last."""
+    cfg = tg.config("core_link")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs,
+                     max_tuples=1 << 22, max_results=1 << 20)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
+    n = 5
+    scan_both(g, o, tr.pairs(0, 0), 0, splits=3)
+    for t in range(1, n + 1):
+        ssd.close_begin(g)
+        ip, rk, est = o.close()
+        if t < n:
+            scan_both(g, o, tr.pairs(0, t), t, splits=3)      # slice t while close t-1 is pending
+        res = ssd.close_end(g)
+        assert np.array_equal(res["ip"], ip) and np.array_equal(res["rk"], rk), f"slice {t - 1}: lists differ"
+        assert np.all(np.abs(res["est"] - est) <= 1e-6 * np.abs(est))
+        log(f"core_link split pipelined slice {t - 1}: {len(res)} hosts")
+    assert np.array_equal(ssd.read_rk(g), o.rk())
+    tm = ssd.read_timing(g)
+    assert tm["count_detect"][1] == n and tm["hot_detect"][1] == 0, tm
+
+
 def _run_distributed(cfg, tr, tabs, n_slices, with_union=True, with_oracle=False, distinct_only=False):
     R = cfg.n_streams
     params = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
