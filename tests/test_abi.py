@@ -107,3 +107,16 @@ def test_init_rejects_before_touching_the_device():
     assert lib.ssd_init_detector(C.addressof(p), C.addressof(tabs), None, 0, None, 0, None,
                                  C.addressof(out)) == -2
     assert out.value is None
+
+
+def test_counter_scratch_only_for_detectors_that_can_count():
+    """The per-slot counters (u32 per estimator and window slice) are part of
+    the scratch exactly when they take at most an eighth of the state
+    (eta >= 32 k); the knob and the phase that use them are exported."""
+    def scratch(k):
+        return ssd.query_sizes(_p(k=k))[1]
+    n_se = 6 << 12
+    assert scratch(4) - scratch(40) == n_se * 4 * 4            # k = 4: counted; k = 40 > 1024 / 32: not
+    assert scratch(32) - scratch(40) == n_se * 32 * 4          # k = 32: the largest window that counts at eta 1024
+    assert scratch(33) == scratch(40)
+    assert "count_detect" in ssd.PHASES and ssd.SSD_TUNE_COUNTED == 10
