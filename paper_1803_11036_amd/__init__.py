@@ -219,7 +219,7 @@ def _results(det: Detector, fn, *args) -> np.ndarray:
     n = C.c_uint64()
     cap = 4096
     while True:
-        out = np.zeros(cap, dtype=RESULT_DTYPE)
+        out = np.empty(cap, dtype=RESULT_DTYPE)     # only the first n entries are filled and returned
         st = fn(det.handle, *args, out.ctypes.data, cap, C.byref(n))
         if st == SSD_E_TRUNC and n.value > cap:
             cap = int(n.value)
