@@ -1289,8 +1289,21 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
         e->have_last = false;
         return SSD_OK;
     }
-    rc = ssd_close_begin(d);
+    // a synchronous close: both parts on the caller's stream (nothing is
+    // enqueued between them, so the second stream would only add its event
+    // hand-over)
+    rc = detector_streams(d);
     if (rc) return rc;
+    const uint64_t prefix = e->hl[0].host_cap;
+    HIPCHK(e, hipStreamWaitEvent(e->stream, d->close_done, 0));     // a pipelined close before it
+    rc = enqueue_close_head(e);
+    if (rc) return rc;
+    rc = e->use_graph ? close_graph_tail(e, false, prefix) : enqueue_close_tail(e, false, prefix, false);
+    if (rc) return rc;
+    HIPCHK(e, hipEventRecord(d->close_done, e->stream));
+    d->pending = true;
+    d->pending_prefix = prefix;
+    e->clock++;
     return ssd_close_end(d, out_host, cap, n_out);
 }
 
