@@ -366,7 +366,7 @@ void orc_hse(const orc_rsea *s, uint32_t *counts, uint32_t *out)
     uint64_t o = 0;
     for (uint32_t i = 0; i < s->r; i++) {
         counts[i] = s->hse_n[i];
-        memcpy(out + o, s->hse + ((uint64_t)i << s->q), s->hse_n[i] * sizeof(uint32_t));
+        if (s->hse_n[i]) memcpy(out + o, s->hse + ((uint64_t)i << s->q), s->hse_n[i] * sizeof(uint32_t));
         o += s->hse_n[i];
     }
 }
@@ -374,7 +374,7 @@ void orc_hse(const orc_rsea *s, uint32_t *counts, uint32_t *out)
 uint64_t orc_tuples(const orc_rsea *s, uint32_t *out, uint64_t cap)
 {
     uint64_t n = s->n_tuples < cap ? s->n_tuples : cap;
-    memcpy(out, s->tuples, n * s->r * sizeof(uint32_t));
+    if (n) memcpy(out, s->tuples, n * s->r * sizeof(uint32_t));   /* out may be NULL when cap is 0 */
     return s->n_tuples;
 }
 

@@ -463,3 +463,140 @@ def test_oracle_finds_planted_super_points():
         ip, rk, est = o.close()
     assert np.all(np.isin(tr.planted_ips(), ip))
     assert np.all(est[np.isin(ip, tr.planted_ips())] > 1024 * 0.8)
+
+
+# ------------------------------------------- Eq. 1 as the C oracle reports it
+
+def _host_with_cells(o, host, n_cells, rng):
+    """Pairs (host, oip) whose cell hashes H1 cover exactly n_cells distinct
+    cells (one peer per cell).  H1 is pinned by the golden vectors above."""
+    seen, peers = set(), []
+    while len(seen) < n_cells:
+        oip = int(rng.integers(0, 2 ** 32))
+        d = o.h1(oip)
+        if d not in seen:
+            seen.add(d)
+            peers.append(oip)
+    return np.array([[host, p] for p in peers], dtype=np.uint32)
+
+
+def test_c_oracle_estimate_at_controlled_R():
+    """A lone host whose peers fill exactly R cells: its r estimators and their
+    union hold exactly those cells, so the C oracle reports R itself, and its
+    Eq. 1 estimate must (i) reach theta exactly from the hot threshold T on
+    (the inverse relation of Sec. 3.3), (ii) grow with R, and (iii) at
+    saturation (R = eta, where Eq. 1 has ln 0) equal the estimate at
+    R = eta - 1, eta * ln(eta) (reading R6: z0 at least 1)."""
+    eta, theta = 1024, 700
+    rng = np.random.default_rng(91)
+    tabs = _tables(2)
+    T = oracle.RSEA(8, 4, 4, eta, 2, theta, tabs, key_bits=16).T
+    got = {}
+    for R in (T - 1, T, T + 1, eta - 1, eta):
+        o = oracle.RSEA(8, 4, 4, eta, 2, theta, tabs, key_bits=16, verify_rehash=True)
+        o.scan(_host_with_cells(o, 0x1234, R, rng))
+        ip, rk, est = o.close()
+        if R < T:
+            assert len(ip) == 0                      # below the hot threshold: not reported
+            continue
+        assert list(ip) == [0x1234] and list(rk) == [R]
+        got[R] = float(est[0])
+    assert got[T] >= theta and got[T] < theta + eta / (eta - T) + 1e-9
+    assert got[T] < got[T + 1] < got[eta - 1]
+    assert got[eta] == got[eta - 1] == pytest.approx(eta * math.log(eta), rel=1e-15)
+    # the pinned Python Eq. 1 (special values, inverse of the threshold) agrees
+    for R, e in got.items():
+        assert e == pytest.approx(float(oracle.estimate(eta, np.array([R]))[0]), rel=4e-16)
+
+
+def test_c_oracle_estimate_is_unbiased():
+    """Linear counting (Sec. 3.2, Eq. 1): for hosts with n distinct peers and
+    no collisions, the C oracle's estimates average n.  With eta = 4096 and
+    n = 1500 one estimate has a standard deviation of about 18, so the mean of
+    48 hosts lies within 15 of n; a wrong logarithm base (log10: about 650,
+    log2: about 2160) or a wrong sign fails this by far."""
+    eta, n, H = 4096, 1500, 48
+    tabs = _tables(13)
+    o = oracle.RSEA(10, 5, 8, eta, 1, 1024, tabs, verify_rehash=True)
+    rng = np.random.default_rng(17)
+    hosts = rng.choice(2 ** 32, H, replace=False).astype(np.uint32)
+    pairs = np.concatenate([np.stack([np.full(n, h, np.uint32),
+                                      rng.choice(2 ** 32, n, replace=False).astype(np.uint32)], 1)
+                            for h in hosts])
+    o.scan(pairs)
+    ip, rk, est = o.close()
+    mine = np.isin(ip, hosts)
+    assert mine.sum() == H
+    assert abs(est[mine].mean() - n) < 15
+    # every reported estimate equals the pinned Python Eq. 1 of its R
+    assert np.allclose(est, oracle.estimate(eta, rk), rtol=4e-16, atol=0)
+
+
+def test_c_oracle_estimate_equals_pinned_eq1_on_trace():
+    """Every host the C oracle reports on the tiny trace carries the pinned
+    Eq. 1 estimate of its R."""
+    cfg = tg.config("tiny")
+    tr = tg.Trace(cfg)
+    o = oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tg.hash_tables(cfg.hash_seed))
+    n = 0
+    for s in range(cfg.k):
+        o.scan(tr.pairs(0, s))
+        ip, rk, est = o.close()
+        assert np.allclose(est, oracle.estimate(cfg.eta, rk), rtol=4e-16, atol=0)
+        n += len(ip)
+    assert n > 1000
+
+
+# ------------------------------------ P8 at the paper geometry, 2^32 hosts
+
+def _paper_geometry_state(rehash):
+    """q=14, r=5, delta=6, eta=2048 (Sec. 5), theta 1024, k = 1: random
+    background well below the hot load plus 40 heavy hosts of 1500 peers."""
+    q, r, delta, eta, theta = 14, 5, 6, 2048, 1024
+    o = oracle.RSEA(q, r, delta, eta, 1, theta, _tables(31), verify_rehash=rehash)
+    rng = np.random.default_rng(31)
+    n_bg = int(0.1 * (1 << q) * theta)
+    bg = np.stack([rng.integers(0, 2 ** 32, n_bg, dtype=np.uint64).astype(np.uint32),
+                   rng.integers(0, 2 ** 32, n_bg, dtype=np.uint64).astype(np.uint32)], 1)
+    heavy = rng.choice(2 ** 32, 40, replace=False).astype(np.uint32)
+    hv = np.concatenate([np.stack([np.full(1500, h, np.uint32),
+                                   rng.integers(0, 2 ** 32, 1500, dtype=np.uint64).astype(np.uint32)], 1)
+                         for h in heavy])
+    o.scan(np.concatenate([bg, hv]))
+    return o, heavy
+
+
+def _bruteforce_all(o):
+    """Forward brute force over all 2^32 hosts, in threads (the C routine
+    releases the interpreter lock)."""
+    nthreads = min(8, os.cpu_count() or 1)
+    step = (1 << 32) // nthreads
+    parts = [None] * nthreads
+
+    def work(j):
+        parts[j] = o.bruteforce(j * step, (j + 1) * step if j < nthreads - 1 else 1 << 32)
+
+    th = [threading.Thread(target=work, args=(j,)) for j in range(nthreads)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
+def test_rehash_output_equals_bruteforce_paper_geometry():
+    """P8 at 32-bit keys and the paper's geometry: with the re-hash check the
+    regained set equals the forward brute force over all 2^32 IPv4 hosts, with
+    the same R values; in paper mode the regained set contains it, each
+    brute-force host with at least its own R."""
+    o, heavy = _paper_geometry_state(True)
+    o.reconstruct()
+    ip, rk, _ = o.results()
+    bip, brk = _bruteforce_all(o)
+    assert np.array_equal(ip, bip) and np.array_equal(rk, brk)
+    assert np.isin(heavy, ip).all()
+    p, _ = _paper_geometry_state(False)
+    p.reconstruct()
+    pip, prk, _ = p.results()
+    assert np.all(np.isin(bip, pip))
+    assert np.all(prk[np.searchsorted(pip, bip)] >= brk)
