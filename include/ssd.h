@@ -60,7 +60,14 @@ extern "C" {
  *       3 <= r <= 16, 4 <= q <= 20, 1 <= delta < q, delta <= 12,
  *       key_bits <= (r-2)*delta + q <= 64.
  *   eta: cells per sliding estimator, a power of two, 1024..65536 (Sec. 3.2).
- *   k: window length in slots, 1..254 (cells are 8-bit slot stamps).
+ *   k: window length in slots: 1..254 with 8-bit cells, 1..65534 with 16-bit
+ *       cells (the paper's 16-bit distance recorders allow k < 65535,
+ *       Sec. 3.2).
+ *   cell_bits: 8 (or 0) or 16, the width of a cell's slot stamp.  8-bit
+ *       cells halve the state; windows above 254 slots need 16-bit cells.
+ *       Detectors with 16-bit cells scan with pass windows or binned stores
+ *       and read the whole state at hot detection (no per-slot counters);
+ *       batches and groups take 8-bit cells only (SSD_E_PARAM).
  *   theta: super point threshold on the opposite number (Def. 2), >= 1.  An
  *       estimator is hot when its in-window cell count reaches
  *       T = ceil(eta * (1 - exp(-theta/eta))) (Sec. 3.3).
@@ -78,7 +85,7 @@ typedef struct {
     uint32_t theta;
     uint32_t key_bits;
     uint32_t flags;
-    uint32_t reserved; /* = 0 */
+    uint32_t cell_bits; /* 8 (0 = 8) or 16 */
     uint64_t max_tuples;
     uint64_t max_results;
 } ssd_params;
@@ -99,7 +106,7 @@ typedef struct {
     uint64_t open_slice;     /* slice that scans currently write               */
     uint32_t hot_threshold;  /* T                                              */
     uint32_t r;
-    uint64_t state_bytes;    /* r * 2^q * eta                                  */
+    uint64_t state_bytes;    /* r * 2^q * eta * cell_bits / 8                  */
     uint64_t level_counts[16]; /* tuples per candidate level at the last close
                                   (level 0 = rows 0..2, level L = row L+2)      */
     uint32_t hot_counts[16]; /* |HSE(i)| at the last close                     */
@@ -174,9 +181,9 @@ int ssd_merge_router_state(ssd_detector *global, ssd_detector *const *routers, u
 /* Parity and inspection. */
 
 /* Canonical window state of the open slice t, after its scans and before its
- * close: out_dev[i] (device, uint16, n_cells = r*2^q*eta entries in
- * [row][column][cell] order) = t - (slot of the cell's latest hit) when that
- * is below k, else 0xFFFF.  Synchronous. */
+ * close (the same for 8- and 16-bit cells): out_dev[i] (device, uint16,
+ * n_cells = r*2^q*eta entries in [row][column][cell] order) = t - (slot of
+ * the cell's latest hit) when that is below k, else 0xFFFF.  Synchronous. */
 int ssd_read_canonical_state(ssd_detector *d, uint16_t *out_dev, uint64_t n_cells);
 
 /* R_k of every estimator at the last close, uint32[r][2^q] (host). */
@@ -255,9 +262,10 @@ int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
  * replayed as a graph (phases 2-5 are then timed as this one), 8 scan
  * binning (the sort step of the binned scan), 9 hot detection from the
  * per-slot counters (SSD_TUNE_COUNTED; two launches when the counters are
- * rebuilt from the state first).  Synchronises the stream; reset != 0 clears
- * the totals after reading. */
-#define SSD_PHASES 10u
+ * rebuilt from the state first), 10 the persistent tile scan of batches and
+ * groups (phase 0 then holds their binned links' stores).  Synchronises the
+ * stream; reset != 0 clears the totals after reading. */
+#define SSD_PHASES 11u
 int ssd_read_timing(ssd_detector *d, double *ms_out, uint64_t *launches_out, int reset);
 
 void ssd_destroy(ssd_detector *d);
@@ -310,6 +318,10 @@ int ssd_batch_get_results(ssd_batch *b, ssd_super_point *out_host, uint64_t cap,
 int ssd_batch_set_tuning(ssd_batch *b, uint32_t knob, uint64_t value);
 int ssd_batch_get_tuning(ssd_batch *b, uint32_t knob, uint64_t *value);
 int ssd_batch_read_timing(ssd_batch *b, double *ms_out, uint64_t *launches_out, int reset);
+/* Inspection of link `link` at the last close, as ssd_read_rk and
+ * ssd_read_hot for a single detector (R_k per estimator; hot lists). */
+int ssd_batch_read_rk(ssd_batch *b, uint32_t link, uint32_t *out_host, uint64_t n);
+int ssd_batch_read_hot(ssd_batch *b, uint32_t link, uint32_t *counts_host, uint32_t *lists_host, uint64_t cap);
 void ssd_batch_destroy(ssd_batch *b);
 
 /* ---- Groups: continuous batching over independent detectors ---------------

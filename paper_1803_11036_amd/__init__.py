@@ -29,7 +29,7 @@ __all__ = [
     "SSD_TUNE_SCAN_MODE", "SSD_TUNE_SCAN_BIN_BYTES", "SSD_TUNE_SCAN_APPLY_SEGMENTS", "SSD_SCAN_PASSES",
     "SSD_SCAN_BINNED", "SSD_SCAN_AUTO", "SSD_TUNE_COUNTED", "SSD_TUNE_COUNTED_MIN_ITEMS",
     "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
-    "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_destroy",
+    "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_read_rk", "batch_read_hot", "batch_destroy",
     "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_destroy",
     "library_path", "RESULT_DTYPE",
 ]
@@ -49,7 +49,7 @@ class Params(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("q", C.c_uint32), ("r", C.c_uint32),
                 ("delta", C.c_uint32), ("eta", C.c_uint32), ("k", C.c_uint32),
                 ("theta", C.c_uint32), ("key_bits", C.c_uint32), ("flags", C.c_uint32),
-                ("reserved", C.c_uint32), ("max_tuples", C.c_uint64), ("max_results", C.c_uint64)]
+                ("cell_bits", C.c_uint32), ("max_tuples", C.c_uint64), ("max_results", C.c_uint64)]
 
 
 class _SuperPoint(C.Structure):
@@ -110,6 +110,8 @@ def _lib():
         L.ssd_batch_set_tuning.argtypes = [vp, u32, u64]
         L.ssd_batch_get_tuning.argtypes = [vp, u32, u64p]
         L.ssd_batch_read_timing.argtypes = [vp, vp, vp, C.c_int]
+        L.ssd_batch_read_rk.argtypes = [vp, u32, vp, u64]
+        L.ssd_batch_read_hot.argtypes = [vp, u32, vp, vp, u64]
         L.ssd_batch_destroy.argtypes = [vp]
         L.ssd_batch_destroy.restype = None
         L.ssd_group_query_sizes.argtypes = [u32, u64p]
@@ -124,12 +126,14 @@ def _lib():
         L.ssd_strerror.restype = C.c_char_p
         L.ssd_last_error.argtypes = []
         L.ssd_last_error.restype = C.c_char_p
-        for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice", "ssd_close_slice",
+        for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice",
+                     "ssd_close_slice",
                      "ssd_get_results", "ssd_merge_router_state", "ssd_read_canonical_state",
                      "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
                      "ssd_set_tuning", "ssd_read_timing", "ssd_batch_query_sizes", "ssd_batch_init",
                      "ssd_batch_scan", "ssd_batch_close", "ssd_batch_get_results", "ssd_batch_set_tuning",
-                     "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_group_query_sizes",
+                     "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_batch_read_rk", "ssd_batch_read_hot",
+                     "ssd_group_query_sizes",
                      "ssd_group_init", "ssd_group_scan", "ssd_group_close"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
@@ -143,9 +147,10 @@ def _check(status: int, where: str) -> None:
 
 
 def make_params(q: int, r: int, delta: int, eta: int, k: int, theta: int, key_bits: int = 32,
-                verify_rehash: bool = False, max_tuples: int = 1 << 22, max_results: int = 1 << 20) -> Params:
+                verify_rehash: bool = False, max_tuples: int = 1 << 22, max_results: int = 1 << 20,
+                cell_bits: int = 8) -> Params:
     return Params(SSD_ABI_VERSION, q, r, delta, eta, k, theta, key_bits,
-                  SSD_VERIFY_REHASH if verify_rehash else 0, 0, max_tuples, max_results)
+                  SSD_VERIFY_REHASH if verify_rehash else 0, cell_bits, max_tuples, max_results)
 
 
 def query_sizes(params: Params) -> Tuple[int, int]:
@@ -315,7 +320,7 @@ SSD_SCAN_PASSES = 0
 SSD_SCAN_BINNED = 1
 SSD_SCAN_AUTO = 2
 PHASES = ("scan", "hot_detect", "hot_lists", "expand", "verify", "report", "merge", "close_graph", "scan_bin",
-          "count_detect")
+          "count_detect", "scan_tiles")
 
 
 def read_timing(det: Detector, reset: bool = False) -> Dict[str, Tuple[float, int]]:
@@ -447,6 +452,26 @@ def batch_read_timing(b: Batch, reset: bool = False) -> Dict[str, Tuple[float, i
     n = np.zeros(len(PHASES), dtype=np.uint64)
     _check(_lib().ssd_batch_read_timing(b.handle, ms.ctypes.data, n.ctypes.data, int(reset)), "batch_read_timing")
     return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(PHASES)}
+
+
+def batch_read_rk(b: Batch, link: int) -> np.ndarray:
+    p = b.params[link]
+    out = np.zeros((p.r, 1 << p.q), dtype=np.uint32)
+    _check(_lib().ssd_batch_read_rk(b.handle, link, out.ctypes.data, out.size), "batch_read_rk")
+    return out
+
+
+def batch_read_hot(b: Batch, link: int) -> List[np.ndarray]:
+    p = b.params[link]
+    counts = np.zeros(p.r, dtype=np.uint32)
+    flat = np.zeros(p.r << p.q, dtype=np.uint32)
+    _check(_lib().ssd_batch_read_hot(b.handle, link, counts.ctypes.data, flat.ctypes.data, flat.size),
+           "batch_read_hot")
+    out, o = [], 0
+    for c in counts.tolist():
+        out.append(flat[o:o + c].copy())
+        o += c
+    return out
 
 
 # ---------------------------------------------------------------- groups

@@ -26,10 +26,12 @@ struct SuperPointDev {
     double est;
 };
 
-// Liveness constants for the close of slot t (stamp(t) = 1 + t mod 255):
-// a cell is live iff (cell - lo) mod 256 < K' and, when the live stamps wrap
-// past 255, the cell is not empty.  c1 = (256 - lo) and c2 = (256 - K') are
-// replicated into both 16-bit halves.
+// Liveness constants for the close of slot t.  8-bit cells (stamp(t) = 1 +
+// t mod 255): a cell is live iff (cell - lo) mod 256 < K' and, when the live
+// stamps wrap past 255, the cell is not empty; c1 = (256 - lo) and c2 = (256
+// - K') are replicated into both 16-bit halves.  16-bit cells (stamp(t) = 1 +
+// t mod 65535): live iff (cell - lo) mod 65536 < K' and, when the live stamps
+// wrap past 65535, not empty; c1 = lo and c2 = K'.
 struct LiveCfg {
     uint32_t c1, c2, wrap;
 };
@@ -63,6 +65,7 @@ struct LinkDesc {
     uint64_t n_se, max_tuples, max_results, sort_limit;
     uint64_t hot_words;           // u32 words of hotbits + hotT (cleared before every close)
     uint32_t q, r, delta, eta, log2eta, k, T, nw, key_bits, rehash;
+    uint32_t cell16, pad;         // 1: 16-bit cells (stamp 1 + t mod 65535), else 8-bit
     // per slice
     LiveCfg L;
     uint32_t expire_period, expire_phase;
@@ -77,6 +80,7 @@ struct ScanArgs {
     uint32_t q, r, delta, log2eta;
     uint64_t se_lo, se_hi;        // estimator window of this pass
     uint32_t stamp;
+    uint32_t cell16;              // 1: 16-bit cells
 };
 
 // persistent batched scan: one estimator window of one link and that link's
@@ -122,7 +126,8 @@ struct ApplyArgs {
     // counted apply only: the link's per-slot counters, its window, the open
     // slice's slot (t mod k) and the estimator size
     uint32_t* counts;
-    uint32_t k, slot, log2eta, pad;
+    uint32_t k, slot, log2eta;
+    uint32_t cell16;              // 1: 16-bit cells (k_apply; bins and offsets count cells)
     uint64_t n_se;                // estimators of the link (the counters' slot stride)
 };
 
@@ -159,6 +164,7 @@ struct MergeArgs {
     uint8_t* dst;
     uint64_t n16;                 // uint4 chunks per state
     uint32_t cur, k;
+    uint32_t cell16;              // 1: 16-bit cells
 };
 
 struct PackArgs {
@@ -187,6 +193,8 @@ hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s);
 hipError_t launch_recount(const LinkDesc* link, uint64_t n_se, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, bool small, hipStream_t s);
+// hot detection (or, with expire_only, the rotating expiry) of one link of 16-bit cells
+hipError_t launch_hot_detect16(const DetectArgs& a, hipStream_t s);
 hipError_t launch_hot_compact(const LinkDesc* links, const uint32_t* row_table, uint32_t rows, hipStream_t s);
 hipError_t launch_expand0(const LevelArgs& a, hipStream_t s);
 hipError_t launch_expand_dfs(const LevelArgs& a, uint32_t max_r, hipStream_t s);
@@ -197,9 +205,10 @@ hipError_t launch_sort_large(const LinkDesc* link, const LinkDesc& host_copy, un
                              hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
-hipError_t launch_canonical(const uint8_t* state, uint16_t* out, uint64_t n, uint32_t cur, uint32_t k, hipStream_t s);
+hipError_t launch_canonical(const uint8_t* state, uint16_t* out, uint64_t n, uint32_t cur, uint32_t k, bool cell16,
+                            hipStream_t s);
 
 // host-side copies of the per-slice rules (also used by the merge and the canonical reader)
-inline uint32_t stamp_of(uint64_t t) { return 1u + (uint32_t)(t % 255u); }
+inline uint32_t stamp_of(uint64_t t, bool cell16) { return 1u + (uint32_t)(t % (cell16 ? 65535u : 255u)); }
 
 }  // namespace ssd

@@ -10,7 +10,10 @@
 //
 // Liveness test (distance < k) on four packed cells at once: the byte values
 // are rebased so that live stamps map to [0, K') and tested in 16-bit slots
-// (see LiveCfg); the rebasing constants are computed on the host per slot.
+// (see LiveCfg); the rebasing constants are computed per slot from the clock.
+//
+// Windows longer than 254 slots (the paper's k up to 65534, Sec. 3.2) take
+// 16-bit cells: stamp 1 + (s mod 65535), the same rules modulo 65535.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -96,6 +99,31 @@ __device__ __forceinline__ uint32_t expire_word(uint32_t w, const LiveCfg& L)
     return w & ~(de | dd);
 }
 
+// 16-bit cells: c is live iff (c - lo) mod 2^16 < K' and, when the live
+// stamps wrap past 65535, c is not empty (LiveCfg c1 = lo, c2 = K').
+__device__ __forceinline__ uint32_t live_cell16(uint32_t c, const LiveCfg& L)
+{
+    return (((c - L.c1) & 0xFFFFu) < L.c2 && (!L.wrap || c != 0u)) ? 1u : 0u;
+}
+
+// The live cells of a 16-byte chunk of eight 16-bit cells (bit i = cell i).
+__device__ __forceinline__ uint32_t live_mask8_c16(const uint4& v, const LiveCfg& L)
+{
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        m |= (live_cell16(w[i] & 0xFFFFu, L) << (2 * i)) | (live_cell16(w[i] >> 16, L) << (2 * i + 1));
+    return m;
+}
+
+// Two 16-bit cells with every dead non-empty one cleared (distance >= k).
+__device__ __forceinline__ uint32_t expire_word16(uint32_t w, const LiveCfg& L)
+{
+    const uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+    return (live_cell16(lo, L) ? lo : 0u) | ((live_cell16(hi, L) ? hi : 0u) << 16);
+}
+
 // Index of the link owning flattened item g: the largest l with prefix[l] <= g
 // (empty links have prefix[l] == prefix[l+1] and are skipped).
 template <class U>
@@ -173,6 +201,17 @@ __global__ __launch_bounds__(256) void k_prepare(LinkDesc* links, uint32_t clear
     if (blockIdx.y != 0 || threadIdx.x != 0) return;
     const unsigned long long t = links[l].clock->t;
     const uint32_t k = links[l].k;
+    if (links[l].cell16) {
+        // 16-bit cells: stamps 1 + t mod 65535, expiry period 65535 - k
+        const uint32_t cur = 1u + (uint32_t)(t % 65535u);
+        LiveCfg c;
+        if (cur >= k) { c.c1 = cur - k + 1u; c.c2 = k; c.wrap = 0u; }
+        else { c.c1 = cur + 65536u - k; c.c2 = k + 1u; c.wrap = 1u; }
+        links[l].L = c;
+        links[l].expire_period = 65535u - k;
+        links[l].expire_phase = (uint32_t)(t % (65535u - k));
+        return;
+    }
     const uint32_t cur = 1u + (uint32_t)(t % 255u);
     uint32_t lo, kp, wrap;
     if (cur >= k) { lo = cur - k + 1u; kp = k; wrap = 0u; }
@@ -207,9 +246,10 @@ __global__ void k_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst)
 // the stores to one estimator window so that a pass's random stores stay in
 // the last-level cache.
 
-__device__ __forceinline__ void scan_pair(const uint32_t* tab, uint2 pr, uint8_t* state, uint32_t q, uint32_t delta,
+template <class T>
+__device__ __forceinline__ void scan_pair(const uint32_t* tab, uint2 pr, T* state, uint32_t q, uint32_t delta,
                                           uint32_t log2eta, uint32_t row_lo, uint32_t row_hi, uint64_t se_lo,
-                                          uint64_t se_hi, uint8_t stamp)
+                                          uint64_t se_hi, T stamp)
 {
     const uint32_t qmask = (1u << q) - 1u;
     const uint32_t d = tab_hash(tab + 1024, pr.y) & ((1u << log2eta) - 1u);   // H1(oip)
@@ -221,6 +261,7 @@ __device__ __forceinline__ void scan_pair(const uint32_t* tab, uint2 pr, uint8_t
     }
 }
 
+template <class T>
 __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
 {
     __shared__ uint32_t tab[2048];
@@ -230,8 +271,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     const uint32_t row_hi = (uint32_t)((a.se_hi - 1) >> a.q) + 1u;
     const uint64_t stride = (uint64_t)gridDim.x * 256u;
     for (uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x; p < a.n; p += stride)
-        scan_pair(tab, a.pairs[p], a.state, a.q, a.delta, a.log2eta, row_lo, row_hi, a.se_lo, a.se_hi,
-                  (uint8_t)a.stamp);
+        scan_pair<T>(tab, a.pairs[p], reinterpret_cast<T*>(a.state), a.q, a.delta, a.log2eta, row_lo, row_hi,
+                     a.se_lo, a.se_hi, (T)a.stamp);
 }
 
 // Persistent scan over many links: workgroups pull tile numbers from a device
@@ -272,7 +313,8 @@ __global__ __launch_bounds__(256) void k_scan_tiles(TileScanArgs a)
         const uint32_t row_lo = (uint32_t)(W.se_lo >> q);
         const uint32_t row_hi = (uint32_t)((W.se_hi - 1) >> q) + 1u;
         for (uint64_t p = first + threadIdx.x; p < last; p += 256u)
-            scan_pair(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, W.se_lo, W.se_hi, (uint8_t)W.stamp);
+            scan_pair<uint8_t>(tab, a.pairs[p], state, q, delta, log2eta, row_lo, row_hi, W.se_lo, W.se_hi,
+                               (uint8_t)W.stamp);
     }
 }
 
@@ -463,7 +505,7 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
 // wave walks the concatenated runs 64 items at a time.
 constexpr uint32_t APPLY_UNROLL = 2;      // items per lane in flight
 
-template <bool PACK>
+template <bool PACK, class T>
 __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
 {
     const uint64_t seg_words = PACK ? packed_seg_words(a.seg) : a.seg;   // item words per segment
@@ -475,8 +517,8 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
     const uint32_t lane = threadIdx.x;
     const uint32_t j0 = part * a.per_part;
     const uint32_t j1 = min(a.blocks, j0 + a.per_part);
-    uint8_t* base = a.state + ((uint64_t)bin << a.bin_shift);
-    const uint8_t stamp = (uint8_t)a.stamp;
+    T* base = reinterpret_cast<T*>(a.state) + ((uint64_t)bin << a.bin_shift);    // bins count cells
+    const T stamp = (T)a.stamp;
     const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
     for (uint32_t jb = j0; jb < j1; jb += 64u) {
         const uint32_t j = jb + lane;
@@ -740,15 +782,10 @@ constexpr uint32_t DETECT_WAVES = 4;   // waves (estimators) per workgroup (4, 8
 // The end of one estimator's test: R_k, and if hot, its live-cell snapshot
 // (for the final test, which then reads no state) and its bits in the row
 // and key-transposed bitmasks.
-template <bool SNAP>
-__device__ __forceinline__ void hot_finish(const LinkDesc* D, uint64_t s, uint32_t live, const uint4* se, uint32_t lane)
+// R_k of estimator s and, if it is hot, its bits in the row and
+// key-transposed bitmasks (lane 0 writes).
+__device__ __forceinline__ void hot_mark(const LinkDesc* D, uint64_t s, uint32_t live, uint32_t lane)
 {
-    const uint32_t log2eta = D->log2eta;
-    if (SNAP && live >= D->T) {
-        const uint32_t chunks = 1u << (log2eta - 4);
-        uint16_t* snap = D->live16 + s * chunks;
-        for (uint32_t c = lane; c < chunks; c += 64u) snap[c] = (uint16_t)live_mask16(se[c], D->L);
-    }
     if (lane == 0) {
         D->rk[s] = live;
         if (live >= D->T) {
@@ -764,6 +801,18 @@ __device__ __forceinline__ void hot_finish(const LinkDesc* D, uint64_t s, uint32
                      1ull << (j & 63u));
         }
     }
+}
+
+template <bool SNAP>
+__device__ __forceinline__ void hot_finish(const LinkDesc* D, uint64_t s, uint32_t live, const uint4* se, uint32_t lane)
+{
+    const uint32_t log2eta = D->log2eta;
+    if (SNAP && live >= D->T) {
+        const uint32_t chunks = 1u << (log2eta - 4);
+        uint16_t* snap = D->live16 + s * chunks;
+        for (uint32_t c = lane; c < chunks; c += 64u) snap[c] = (uint16_t)live_mask16(se[c], D->L);
+    }
+    hot_mark(D, s, live, lane);
 }
 
 // A wave covers 4 KiB of state at least: one estimator when eta >= 4096, else
@@ -875,6 +924,80 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect(DetectArgs a)
             hot_finish<true>(D, s, live, se, lane);
         }
     }
+}
+
+// 16-bit cells (windows above 254 slots), one link: one wave per estimator;
+// in round c lane j takes the 16 cells of snapshot word c * 64 + j (two
+// 16-byte chunks, so a wave reads 2 KiB in one go).  Up to CH rounds stay in
+// registers for the snapshot of a hot estimator; larger estimators are read
+// again.  With expire_only, only the estimators of this slot's expiry phase
+// are visited (and not counted).
+template <int CH>
+__global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect16(DetectArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t g = (uint64_t)blockIdx.x * DETECT_WAVES + (threadIdx.x >> 6);
+    if (g >= a.total) return;
+    const LinkDesc* D = a.links;
+    uint64_t s = g;
+    if (a.expire_only) {
+        s = D->expire_phase + g * D->expire_period;
+        if (s >= D->n_se) return;
+    }
+    const uint32_t log2eta = D->log2eta;
+    const LiveCfg L = D->L;
+    const uint32_t rounds = (1u << log2eta) >> 10;      // 1024 cells per wave round (eta >= 1024)
+    uint4* se = reinterpret_cast<uint4*>(D->state + (s << (log2eta + 1)));
+    const bool expire = (s % D->expire_period) == D->expire_phase;
+    const bool count = !a.expire_only;
+    uint32_t live = 0;
+    uint32_t snap[CH];
+    for (uint32_t g0 = 0; g0 < rounds; g0 += CH) {
+        uint4 v[2 * CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            const uint64_t w = 2ull * ((g0 + (uint32_t)c) * 64u + lane);
+            if (g0 + (uint32_t)c < rounds) {
+                v[2 * c] = se[w];
+                v[2 * c + 1] = se[w + 1];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            if (g0 + (uint32_t)c >= rounds) continue;
+            const uint32_t m = live_mask8_c16(v[2 * c], L) | (live_mask8_c16(v[2 * c + 1], L) << 8);
+            snap[c] = m;
+            live += __popc(m);
+            if (expire) {
+                const uint64_t w = 2ull * ((g0 + (uint32_t)c) * 64u + lane);
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const uint4 x = v[2 * c + h];
+                    uint4 n;
+                    n.x = expire_word16(x.x, L); n.y = expire_word16(x.y, L);
+                    n.z = expire_word16(x.z, L); n.w = expire_word16(x.w, L);
+                    if (n.x != x.x || n.y != x.y || n.z != x.z || n.w != x.w) se[w + h] = n;
+                }
+            }
+        }
+    }
+    if (!count) return;
+    live = wave_sum(live);
+    if (live >= D->T) {
+        uint16_t* out = D->live16 + s * (1u << (log2eta - 4));
+        if (rounds <= (uint32_t)CH) {
+#pragma unroll
+            for (int c = 0; c < CH; c++)
+                if ((uint32_t)c < rounds) out[c * 64u + lane] = (uint16_t)snap[c];
+        } else {
+            // liveness is unchanged by the expiry writes above (dead cells only)
+            for (uint32_t c = 0; c < rounds; c++) {
+                const uint64_t w = 2ull * (c * 64u + lane);
+                out[c * 64u + lane] = (uint16_t)(live_mask8_c16(se[w], L) | (live_mask8_c16(se[w + 1], L) << 8));
+            }
+        }
+    }
+    hot_mark(D, s, live, lane);
 }
 
 // ---------------------------------------------------------------- counted detection
@@ -1545,17 +1668,52 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a)
     }
 }
 
+// The same for 16-bit cells: eight per chunk, distances modulo 65535.
+__global__ __launch_bounds__(256) void k_merge16(MergeArgs a)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < a.n16; i += stride) {
+        uint32_t best[8];
+        uint32_t code[8];
+#pragma unroll
+        for (int b = 0; b < 8; b++) { best[b] = 65535u; code[b] = 0u; }
+        for (uint32_t j = 0; j < a.n_src; j++) {
+            const uint4 v = reinterpret_cast<const uint4*>(a.src[j])[i];
+            if ((v.x | v.y | v.z | v.w) == 0u) continue;
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const uint32_t c = (w[b >> 1] >> ((b & 1) * 16)) & 0xFFFFu;
+                if (c) {
+                    int age = (int)a.cur - (int)c;
+                    if (age < 0) age += 65535;
+                    if ((uint32_t)age < best[b]) { best[b] = (uint32_t)age; code[b] = c; }
+                }
+            }
+        }
+        uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int b = 0; b < 8; b++)
+            if (best[b] < a.k) o[b >> 1] |= code[b] << ((b & 1) * 16);
+        reinterpret_cast<uint4*>(a.dst)[i] = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
 // ---------------------------------------------------------------- canonical
 
+// Distance of every cell (t - slot of its latest hit) where it is below k,
+// else 0xFFFF; stamps modulo M = 255 (8-bit cells) or 65535 (16-bit).
+template <class T, int M>
 __global__ __launch_bounds__(256) void k_canonical(const uint8_t* state, uint16_t* out, uint64_t n, uint32_t cur, uint32_t k)
 {
     const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    const T* cells = reinterpret_cast<const T*>(state);
     for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += stride) {
-        const uint32_t c = state[i];
+        const uint32_t c = cells[i];
         uint32_t v = 0xFFFFu;
         if (c) {
             int age = (int)cur - (int)c;
-            if (age < 0) age += 255;
+            if (age < 0) age += M;
             if ((uint32_t)age < k) v = (uint32_t)age;
         }
         out[i] = (uint16_t)v;
@@ -1600,7 +1758,8 @@ hipError_t launch_gather_ctl(const LinkDesc* links, uint32_t n_links, Ctl* dst, 
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s)
 {
-    k_scan<<<grid_for(a.n, 256, 256 * 16), 256, 0, s>>>(a);
+    if (a.cell16) k_scan<uint16_t><<<grid_for(a.n, 256, 256 * 16), 256, 0, s>>>(a);
+    else k_scan<uint8_t><<<grid_for(a.n, 256, 256 * 16), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1634,8 +1793,14 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
 {
     if (a.parts == 0 || a.per_part == 0) return hipErrorInvalidValue;
     const uint64_t groups = (a.n_bins + 7u) / 8u;
-    if (a.pack) k_apply<true><<<(uint32_t)(8ull * a.parts * groups), 64, 0, s>>>(a);
-    else k_apply<false><<<(uint32_t)(8ull * a.parts * groups), 64, 0, s>>>(a);
+    const uint32_t grid = (uint32_t)(8ull * a.parts * groups);
+    if (a.cell16) {
+        if (a.pack) k_apply<true, uint16_t><<<grid, 64, 0, s>>>(a);
+        else k_apply<false, uint16_t><<<grid, 64, 0, s>>>(a);
+    } else {
+        if (a.pack) k_apply<true, uint8_t><<<grid, 64, 0, s>>>(a);
+        else k_apply<false, uint8_t><<<grid, 64, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -1646,6 +1811,7 @@ hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s)
         bytes > COUNTED_LDS_BYTES || a.n_bins == 0)
         return hipErrorInvalidValue;
     if (!a.pack || a.seg < 6u) return hipErrorInvalidValue;     // counted bins are at most 2 MiB: always packed
+    if (a.cell16) return hipErrorInvalidValue;                   // counters are kept for 8-bit cells only
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_counted),
@@ -1688,6 +1854,14 @@ hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, 
         else if (max_chunks_per_lane >= 2) k_hot_detect<2, false><<<g, bs, 0, s>>>(a);
         else k_hot_detect<1, false><<<g, bs, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_hot_detect16(const DetectArgs& a, hipStream_t s)
+{
+    if (a.n_links != 1 || a.total == 0) return hipErrorInvalidValue;
+    const dim3 g((uint32_t)((a.total + DETECT_WAVES - 1) / DETECT_WAVES));
+    k_hot_detect16<4><<<g, 64u * DETECT_WAVES, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1762,13 +1936,16 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s)
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s)
 {
-    k_merge<<<grid_for(a.n16, 256, 256 * 16), 256, 0, s>>>(a);
+    if (a.cell16) k_merge16<<<grid_for(a.n16, 256, 256 * 16), 256, 0, s>>>(a);
+    else k_merge<<<grid_for(a.n16, 256, 256 * 16), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_canonical(const uint8_t* state, uint16_t* out, uint64_t n, uint32_t cur, uint32_t k, hipStream_t s)
+hipError_t launch_canonical(const uint8_t* state, uint16_t* out, uint64_t n, uint32_t cur, uint32_t k, bool cell16,
+                            hipStream_t s)
 {
-    k_canonical<<<grid_for(n, 256, 256 * 16), 256, 0, s>>>(state, out, n, cur, k);
+    if (cell16) k_canonical<uint16_t, 65535><<<grid_for(n, 256, 256 * 16), 256, 0, s>>>(state, out, n, cur, k);
+    else k_canonical<uint8_t, 255><<<grid_for(n, 256, 256 * 16), 256, 0, s>>>(state, out, n, cur, k);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@
 
 using namespace ssd;
 
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -52,6 +53,11 @@ uint32_t log2u(uint64_t x)
     return l;
 }
 
+// 16-bit cells (windows above 254 slots) or 8-bit
+bool cell16(const ssd_params& p) { return p.cell_bits == 16; }
+uint64_t state_cells(const ssd_params& p) { return ((uint64_t)p.r << p.q) * p.eta; }
+uint64_t state_bytes_of(const ssd_params& p) { return state_cells(p) << (cell16(p) ? 1 : 0); }
+
 constexpr uint32_t PREFIX_MAX = SORT_SMALL;       // result entries staged in pinned memory per close
 // Scan pass window: random byte stores confined to 128 MiB of state stay in
 // the 256 MB Infinity Cache (measured best of 64..768 MiB on the core-link
@@ -70,14 +76,17 @@ int validate(const ssd_params* p)
     if (p->q < 4 || p->q > 20) return fail(SSD_E_PARAM, "q=%u outside 4..20", p->q);
     if (p->delta < 1 || p->delta >= p->q || p->delta > 12) return fail(SSD_E_PARAM, "delta=%u must satisfy 1 <= delta < q, delta <= 12", p->delta);
     if (!is_pow2(p->eta) || p->eta < 1024 || p->eta > 65536) return fail(SSD_E_PARAM, "eta=%u must be a power of two in 1024..65536", p->eta);
-    if (p->k < 1 || p->k > 254) return fail(SSD_E_PARAM, "k=%u outside 1..254", p->k);
+    if (p->cell_bits != 0 && p->cell_bits != 8 && p->cell_bits != 16)
+        return fail(SSD_E_PARAM, "cell_bits=%u must be 8 or 16 (0 = 8)", p->cell_bits);
+    const uint32_t kmax = p->cell_bits == 16 ? 65534u : 254u;
+    if (p->k < 1 || p->k > kmax)
+        return fail(SSD_E_PARAM, "k=%u outside 1..%u for %u-bit cells", p->k, kmax, p->cell_bits == 16 ? 16u : 8u);
     if (p->theta < 1) return fail(SSD_E_PARAM, "theta must be >= 1");
     if (p->key_bits < 8 || p->key_bits > 32) return fail(SSD_E_PARAM, "key_bits=%u outside 8..32", p->key_bits);
     const uint32_t cover = (p->r - 2) * p->delta + p->q;
     if (cover < p->key_bits) return fail(SSD_E_PARAM, "(r-2)*delta+q=%u does not cover key_bits=%u", cover, p->key_bits);
     if (cover > 64) return fail(SSD_E_PARAM, "(r-2)*delta+q=%u exceeds 64", cover);
     if (p->flags & ~SSD_VERIFY_REHASH) return fail(SSD_E_PARAM, "unknown flags 0x%x", p->flags);
-    if (p->reserved) return fail(SSD_E_PARAM, "reserved must be 0");
     if (p->max_tuples < 1 || p->max_tuples > (1ull << 32)) return fail(SSD_E_PARAM, "max_tuples outside 1..2^32");
     if (p->max_results < 1 || p->max_results > (1ull << 28)) return fail(SSD_E_PARAM, "max_results outside 1..2^28");
     return SSD_OK;
@@ -118,6 +127,7 @@ constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 2;
 // core-link state, slower on a 24 MiB state that the Infinity Cache holds)
 constexpr uint64_t AUTO_BINNED_ABOVE = 256ull << 20;
 constexpr uint32_t PHASE_SCAN_BIN = 8;
+constexpr uint32_t PHASE_SCAN_TILES = 10;
 // batch links scanned binned: a large state and at least this many pairs
 constexpr uint64_t BATCH_BINNED_MIN_PAIRS = 1ull << 20;
 // Candidate expansion: depth first in one launch up to this many rows (its
@@ -128,9 +138,10 @@ struct BinPlan {
 };
 BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
 {
-    const uint64_t state = ((uint64_t)p.r << p.q) * p.eta;
+    // bins and their offsets count cells (2 bytes each for 16-bit cells)
+    const uint64_t state = state_cells(p);
     BinPlan b;
-    b.shift = log2u(std::max<uint64_t>(std::max<uint64_t>(bin_bytes, MIN_BIN_BYTES), p.eta));
+    b.shift = log2u(std::max<uint64_t>(std::max<uint64_t>(bin_bytes, MIN_BIN_BYTES) >> (cell16(p) ? 1 : 0), p.eta));
     while (((state + (1ull << b.shift) - 1) >> b.shift) > MAX_BINS) b.shift++;
     b.n_bins = (uint32_t)((state + (1ull << b.shift) - 1) >> b.shift);
     b.pb = (BIN_LDS_WORDS - 2048u - b.n_bins - 1u) / p.r;
@@ -148,7 +159,7 @@ BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
 // count.
 uint32_t counted_shift(const ssd_params& p, uint64_t want = 1ull << 20)
 {
-    if (32ull * p.k > p.eta) return 0;
+    if (32ull * p.k > p.eta || cell16(p)) return 0;     // 16-bit cells keep no counters
     const uint32_t le = log2u(p.eta);
     uint32_t best = 0, smallest = 0;
     for (uint32_t sh = 20; sh >= 18; sh--) {
@@ -163,7 +174,7 @@ uint32_t counted_shift(const ssd_params& p, uint64_t want = 1ull << 20)
 // BIN_CHUNK_PAIRS pairs (fewer for small states).
 void bin_capacity(const ssd_params& p, uint64_t* items_words, uint64_t* table_words)
 {
-    const uint64_t state = ((uint64_t)p.r << p.q) * p.eta;
+    const uint64_t state = state_cells(p);
     const uint64_t chunk = std::min<uint64_t>(BIN_CHUNK_PAIRS, std::max<uint64_t>(1ull << 16, state >> 4));
     const BinPlan worst = bin_plan(p, 0);     // the most bins, the fewest pairs per workgroup
     const uint64_t blocks = (chunk + worst.pb - 1) / worst.pb;
@@ -175,7 +186,12 @@ uint32_t nw_of(const ssd_params& p) { return p.delta > 6 ? 1u << (p.delta - 6) :
 
 // Hot detection waves of a link: one per estimator from eta = 4096 up, one
 // per 4 KiB of state below (k_hot_detect).
-uint64_t detect_waves(const LinkDesc& D) { return D.log2eta >= 12 ? D.n_se : D.n_se >> (12 - D.log2eta); }
+// (16-bit cells: one wave per estimator, k_hot_detect16).
+uint64_t detect_waves(const LinkDesc& D)
+{
+    if (D.cell16) return D.n_se;
+    return D.log2eta >= 12 ? D.n_se : D.n_se >> (12 - D.log2eta);
+}
 uint64_t row_words(const ssd_params& p) { return p.q >= 6 ? (1ull << (p.q - 6)) : 1ull; }
 
 struct LinkLayout {
@@ -239,7 +255,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
         K.out = o; o = align_up(o + q.max_results * sizeof(SuperPointDev));
         // per-slot counters for the links whose scans are binned (single
         // detectors; batch links above the binned threshold) and can count
-        const bool binned = n == 1 || ((uint64_t)q.r << q.q) * q.eta > AUTO_BINNED_ABOVE;
+        const bool binned = n == 1 || state_bytes_of(q) > AUTO_BINNED_ABOVE;
         if (bins && binned && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
     }
     uint64_t pw = 1;
@@ -249,7 +265,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     if (bins) {
         // shared by the links scanned binned, one after another: the largest
         for (uint32_t l = 0; l < n; l++) {
-            if (n > 1 && ((uint64_t)p[l].r << p[l].q) * p[l].eta <= AUTO_BINNED_ABOVE) continue;
+            if (n > 1 && state_bytes_of(p[l]) <= AUTO_BINNED_ABOVE) continue;
             uint64_t iw = 0, tw = 0;
             bin_capacity(p[l], &iw, &tw);
             L.bin_items_words = std::max(L.bin_items_words, iw);
@@ -262,7 +278,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     uint64_t so = 0;
     for (uint32_t l = 0; l < n; l++) {
         L.link[l].state_off = so;
-        L.link[l].state_bytes = ((uint64_t)p[l].r << p[l].q) * p[l].eta;
+        L.link[l].state_bytes = state_bytes_of(p[l]);
         so += L.link[l].state_bytes;
     }
     L.state_total = so;
@@ -501,6 +517,7 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
         D.max_results = q.max_results;
         D.sort_limit = SORT_SMALL;
         D.q = q.q; D.r = q.r; D.delta = q.delta; D.eta = q.eta; D.log2eta = log2u(q.eta); D.k = q.k;
+        D.cell16 = cell16(q) ? 1u : 0u;
         D.T = e->T[l] = hot_threshold(q.eta, q.theta);
         D.nw = nw_of(q);
         D.key_bits = q.key_bits;
@@ -559,36 +576,67 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     return SSD_OK;
 }
 
+// The binned scan of a call of n pairs of link l: whether its stores keep
+// the link's per-slot counters (they are exact and the call is large enough)
+// and its bin geometry.
+struct BinnedCall {
+    bool large = false, counted = false;
+    uint32_t csh = 0;        // counted bin shift (0: the link cannot count)
+    BinPlan bp;
+    uint64_t seg = 0;        // offsets per binning workgroup (pb * r)
+};
+BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_bytes)
+{
+    BinnedCall c;
+    c.csh = e->counting[l] ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
+    c.large = c.csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << c.csh).n_bins;
+    c.counted = e->counting[l] && e->count_valid[l] && c.large;
+    c.bp = bin_plan(e->p[l], c.counted ? 1ull << c.csh : bin_bytes);
+    c.seg = (uint64_t)c.bp.pb * e->p[l].r;
+    return c;
+}
+
+// Staging of the binned scan: the binning workgroups' offset segments (4 *
+// seg bytes each at most) and the bin-major table (n_bins + 1 words each).
+struct BinBufs {
+    uint32_t* items = nullptr;
+    uint32_t* table = nullptr;
+    uint64_t items_words = 0, table_words = 0;
+};
+BinBufs engine_bins(const Engine* e)
+{
+    return {e->at<uint32_t>(e->L.bin_items), e->at<uint32_t>(e->L.bin_table), e->L.bin_items_words,
+            e->L.bin_table_words};
+}
+
 // Binned scan (k_bin, then k_apply_counted or k_apply) of n pairs of link l,
-// in steps that fit the engine's bin buffers (shared by every binned link of a
-// batch: the steps run one after another on the engine's stream).  The
-// stores keep the link's per-slot counters when they are exact and the call
-// is large enough; otherwise they leave them stale.
-int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs)
+// in steps that fit the staging buffers bb (the engine's own are shared by
+// every binned link of a batch: the steps run one after another on the
+// engine's stream).  The stores keep the link's per-slot counters when they
+// are exact and the call is large enough; otherwise they leave them stale.
+int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs,
+                        const BinBufs& bb)
 {
     const LinkDesc& D = e->hl[l];
-    uint32_t csh = e->counting[l] ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
-    const bool large = csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << csh).n_bins;
-    const bool counted = e->counting[l] && e->count_valid[l] && large;
+    const BinnedCall c = binned_call(e, l, n, bin_bytes);
+    const bool counted = c.counted;
     if (e->counting[l] && !counted) {
         e->count_valid[l] = 0;                 // these stores are not counted
         // the close rebuilds the counters from the state after large calls
         // only; with a small call in the slice it reads the state once
-        if (!large) e->count_small[l] = 1;
-        e->count_rebuild[l] = large && !e->count_small[l];
+        if (!c.large) e->count_small[l] = 1;
+        e->count_rebuild[l] = c.large && !e->count_small[l];
     }
-    if (!counted) csh = 0;
-    if (counted) bin_bytes = 1ull << csh;
-    const BinPlan bp = bin_plan(e->p[l], bin_bytes);
-    if (counted && (!csh || bp.shift != csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
-    const uint64_t seg = (uint64_t)bp.pb * D.r;
-    const uint64_t max_blocks = std::min(e->L.bin_items_words / seg, e->L.bin_table_words / (bp.n_bins + 1));
+    const BinPlan bp = c.bp;
+    if (counted && (!c.csh || bp.shift != c.csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
+    const uint64_t seg = c.seg;
+    const uint64_t max_blocks = std::min(bb.items_words / seg, bb.table_words / (bp.n_bins + 1));
     const uint64_t chunk = max_blocks * bp.pb;
     if (chunk == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
     BinArgs ba{};
     ba.tables = D.tables;
-    ba.items = e->at<uint32_t>(e->L.bin_items);
-    ba.table = e->at<uint32_t>(e->L.bin_table);
+    ba.items = bb.items;
+    ba.table = bb.table;
     ba.q = D.q; ba.r = D.r; ba.delta = D.delta; ba.log2eta = D.log2eta;
     ba.bin_shift = bp.shift; ba.n_bins = bp.n_bins; ba.pb = bp.pb;
     ba.pack = bp.shift <= 21 ? 1u : 0u;
@@ -601,7 +649,8 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
     aa.seg = (uint32_t)seg;
     aa.bin_shift = bp.shift;
     aa.per_part = segs;
-    aa.stamp = stamp_of(e->clock);
+    aa.stamp = stamp_of(e->clock, D.cell16);
+    aa.cell16 = D.cell16;
     if (counted) {
         aa.counts = D.counts;
         aa.k = D.k;
@@ -658,7 +707,8 @@ int enqueue_close_head(Engine* e)
         da.n_links = n;
         da.total = pre[n];
         PhaseMark pm = phase_begin(e);
-        HIPCHK(e, launch_hot_detect(da, e->max_chunks, e->detect_small, s));
+        // 16-bit cells only in single detectors (batches and groups take 8-bit links)
+        HIPCHK(e, e->hl[0].cell16 ? launch_hot_detect16(da, s) : launch_hot_detect(da, e->max_chunks, e->detect_small, s));
         phase_end(e, pm, 1, 1);
     }
     for (uint32_t l = 0; l < n; l++) {
@@ -854,9 +904,9 @@ int enqueue_advance_only(Engine* e)
     da.se_prefix = e->at<uint64_t>(e->L.se_prefix);
     da.n_links = 1;
     da.expire_only = 1;
-    const uint64_t period = 255u - e->p[0].k;
+    const uint64_t period = (e->hl[0].cell16 ? 65535u : 255u) - e->p[0].k;
     da.total = (e->hl[0].n_se + period - 1) / period;
-    HIPCHK(e, launch_hot_detect(da, e->max_chunks, e->detect_small, s));
+    HIPCHK(e, e->hl[0].cell16 ? launch_hot_detect16(da, s) : launch_hot_detect(da, e->max_chunks, e->detect_small, s));
     HIPCHK(e, launch_advance(links, e->n, s));
     return SSD_OK;
 }
@@ -872,6 +922,43 @@ int read_timing(Engine* e, double* ms_out, uint64_t* launches_out, int reset)
         if (launches_out) launches_out[i] = e->ph_launches[i];
         if (reset) { e->ph_ms[i] = 0; e->ph_launches[i] = 0; }
     }
+    return SSD_OK;
+}
+
+// R_k of link l at the last close (host copy).
+int engine_read_rk(Engine* e, uint32_t l, uint32_t* out_host, uint64_t n)
+{
+    int rc = usable(e);
+    if (rc) return rc;
+    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
+    const uint64_t n_se = e->hl[l].n_se;
+    if (!out_host || n < n_se) return fail(SSD_E_NOMEM, "R_k needs %llu entries", (unsigned long long)n_se);
+    HIPCHK(e, hipMemcpyAsync(out_host, e->hl[l].rk, n_se * 4, hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return SSD_OK;
+}
+
+// Hot lists HSE(0..r-1) of link l at the last close: counts, then the lists
+// packed row after row.
+int engine_read_hot(Engine* e, uint32_t l, uint32_t* counts_host, uint32_t* lists_host, uint64_t cap)
+{
+    int rc = usable(e);
+    if (rc) return rc;
+    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
+    if (!counts_host) return fail(SSD_E_PARAM, "counts_host is NULL");
+    const Ctl& c = e->last[l];
+    const ssd_params& p = e->p[l];
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < p.r; i++) { counts_host[i] = c.hot_n[i]; total += c.hot_n[i]; }
+    if (total > cap || (total && !lists_host)) return fail(SSD_E_TRUNC, "hot lists need %llu entries", (unsigned long long)total);
+    uint64_t o = 0;
+    for (uint32_t i = 0; i < p.r; i++) {
+        if (c.hot_n[i])
+            HIPCHK(e, hipMemcpyAsync(lists_host + o, e->hl[l].hot_list + ((uint64_t)i << p.q),
+                                     (uint64_t)c.hot_n[i] * 4, hipMemcpyDeviceToHost, e->stream));
+        o += c.hot_n[i];
+    }
+    HIPCHK(e, hipStreamSynchronize(e->stream));
     return SSD_OK;
 }
 
@@ -906,6 +993,61 @@ int detector_streams(ssd_detector* d)
     if (!d->detect_done) HIPCHK(e, hipEventCreateWithFlags(&d->detect_done, hipEventDisableTiming));
     if (!d->close_done) HIPCHK(e, hipEventCreateWithFlags(&d->close_done, hipEventDisableTiming));
     if (!d->close_stream) HIPCHK(e, hipStreamCreateWithFlags(&d->close_stream, hipStreamNonBlocking));
+    return SSD_OK;
+}
+
+// Argument and state checks shared by the scan calls.
+int scan_checks(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint64_t slice_id)
+{
+    Engine* e = &d->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (slice_id != e->clock)
+        return fail(SSD_E_ORDER, "scan of slice %llu while slice %llu is open", (unsigned long long)slice_id,
+                    (unsigned long long)e->clock);
+    if (n == 0) return SSD_OK;
+    if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
+    return SSD_OK;
+}
+
+// The detector's scans are binned: SSD_SCAN_BINNED, or SSD_SCAN_AUTO with a
+// state above AUTO_BINNED_ABOVE.
+bool scans_binned(const ssd_detector* d)
+{
+    const LinkDesc& D = d->D();
+    const uint64_t state_bytes = (D.n_se << D.log2eta) << D.cell16;
+    return d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE);
+}
+
+// Pass-window scan (k_scan): passes over estimator windows of about
+// pass_bytes each, highest window first: the last pass leaves the lowest
+// estimators cache-resident, and hot detection reads them first.
+int enqueue_pass_scan(ssd_detector* d, const uint2* pairs, uint64_t n)
+{
+    Engine* e = &d->e;
+    const LinkDesc& D = d->D();
+    e->count_valid[0] = 0;            // pass scans store without counting
+    ScanArgs a{};
+    a.pairs = pairs;
+    a.n = n;
+    a.state = D.state;
+    a.tables = D.tables;
+    a.q = D.q; a.r = D.r; a.delta = D.delta; a.log2eta = D.log2eta;
+    a.stamp = stamp_of(e->clock, D.cell16);
+    a.cell16 = D.cell16;
+    const uint64_t n_se = D.n_se;
+    uint64_t per_pass = n_se;
+    if (d->pass_bytes) per_pass = std::max<uint64_t>(1, d->pass_bytes / ((uint64_t)D.eta << D.cell16));
+    const uint64_t n_pass = (n_se + per_pass - 1) / per_pass;
+    PhaseMark pm = phase_begin(e);
+    uint32_t launches = 0;
+    for (uint64_t j = n_pass; j-- > 0;) {
+        a.se_lo = j * per_pass;
+        a.se_hi = std::min(a.se_lo + per_pass, n_se);
+        HIPCHK(e, launch_scan(a, e->stream));
+        launches++;
+    }
+    phase_end(e, pm, 0, launches);
     return SSD_OK;
 }
 
@@ -1005,6 +1147,7 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
         if (m[i]->e.broken) return fail(SSD_E_STATE, "member %u is unusable", i);
         if (m[i]->e.device != e->device) return fail(SSD_E_INCOMPAT, "member %u is on another device", i);
         if (m[i]->e.stream != e->stream) return fail(SSD_E_INCOMPAT, "member %u uses another stream", i);
+        if (m[i]->e.hl[0].cell16) return fail(SSD_E_PARAM, "member %u has 16-bit cells: groups take 8-bit members", i);
         for (uint32_t j = 0; j < i; j++)
             if (m[j] == m[i]) return fail(SSD_E_PARAM, "member %u appears twice", i);
         same = same && g->bound[i] == m[i]->id;
@@ -1171,42 +1314,12 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
     Engine* e = &d->e;
-    int rc = usable(e);
-    if (rc) return rc;
-    if (slice_id != e->clock)
-        return fail(SSD_E_ORDER, "scan of slice %llu while slice %llu is open", (unsigned long long)slice_id,
-                    (unsigned long long)e->clock);
-    if (n == 0) return SSD_OK;
-    if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
-    const LinkDesc& D = d->D();
-    const uint64_t state_bytes = D.n_se << D.log2eta;
-    if (d->scan_mode == SSD_SCAN_BINNED || (d->scan_mode == SSD_SCAN_AUTO && state_bytes > AUTO_BINNED_ABOVE))
-        return enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes, d->apply_segments);
-    e->count_valid[0] = 0;            // pass scans store without counting
-    ScanArgs a{};
-    a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
-    a.n = n;
-    a.state = D.state;
-    a.tables = D.tables;
-    a.q = D.q; a.r = D.r; a.delta = D.delta; a.log2eta = D.log2eta;
-    a.stamp = stamp_of(e->clock);
-    // passes over estimator windows of about pass_bytes each, highest window
-    // first: the last pass leaves the lowest estimators cache-resident, and hot
-    // detection reads them first
-    const uint64_t n_se = D.n_se;
-    uint64_t per_pass = n_se;
-    if (d->pass_bytes) per_pass = std::max<uint64_t>(1, d->pass_bytes / D.eta);
-    const uint64_t n_pass = (n_se + per_pass - 1) / per_pass;
-    PhaseMark pm = phase_begin(e);
-    uint32_t launches = 0;
-    for (uint64_t j = n_pass; j-- > 0;) {
-        a.se_lo = j * per_pass;
-        a.se_hi = std::min(a.se_lo + per_pass, n_se);
-        HIPCHK(e, launch_scan(a, e->stream));
-        launches++;
-    }
-    phase_end(e, pm, 0, launches);
-    return SSD_OK;
+    int rc = scan_checks(d, pairs_dev, n, slice_id);
+    if (rc || n == 0) return rc;
+    if (scans_binned(d))
+        return enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes, d->apply_segments,
+                                   engine_bins(e));
+    return enqueue_pass_scan(d, reinterpret_cast<const uint2*>(pairs_dev), n);
 }
 
 int ssd_close_begin(ssd_detector* d)
@@ -1336,6 +1449,7 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
         if (r->pending) return fail(SSD_E_ORDER, "router %u has a close pending", j);
         const ssd_params& rp = r->p();
         if (rp.q != gp.q || rp.r != gp.r || rp.delta != gp.delta || rp.eta != gp.eta || rp.k != gp.k ||
+            cell16(rp) != cell16(gp) ||
             rp.key_bits != gp.key_bits || r->e.tables != g->e.tables)
             return fail(SSD_E_INCOMPAT, "router %u differs in geometry or hash tables", j);
         if (r->e.clock != g->e.clock) return fail(SSD_E_INCOMPAT, "router %u is at slice %llu, global at %llu", j,
@@ -1347,8 +1461,9 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
     MergeArgs a{};
     a.dst = g->D().state;
     a.n16 = g->e.L.state_total / 16u;
-    a.cur = stamp_of(g->e.clock);
+    a.cur = stamp_of(g->e.clock, cell16(gp));
     a.k = gp.k;
+    a.cell16 = cell16(gp) ? 1u : 0u;
     // associative merge in batches; later batches fold the partial result in
     uint32_t done = 0, launches = 0;
     PhaseMark pm = phase_begin(&g->e);
@@ -1370,9 +1485,10 @@ int ssd_read_canonical_state(ssd_detector* d, uint16_t* out_dev, uint64_t n_cell
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
-    const uint64_t n = e->L.state_total;
+    const uint64_t n = state_cells(d->p());
     if (!out_dev || n_cells < n) return fail(SSD_E_NOMEM, "canonical state needs %llu cells", (unsigned long long)n);
-    HIPCHK(e, launch_canonical(d->D().state, out_dev, n, stamp_of(e->clock), d->p().k, e->stream));
+    const bool c16 = cell16(d->p());
+    HIPCHK(e, launch_canonical(d->D().state, out_dev, n, stamp_of(e->clock, c16), d->p().k, c16, e->stream));
     HIPCHK(e, hipStreamSynchronize(e->stream));
     return SSD_OK;
 }
@@ -1380,40 +1496,15 @@ int ssd_read_canonical_state(ssd_detector* d, uint16_t* out_dev, uint64_t n_cell
 int ssd_read_rk(ssd_detector* d, uint32_t* out_host, uint64_t n)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    Engine* e = &d->e;
-    int rc = usable(e);
-    if (rc) return rc;
     if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
-    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
-    const uint64_t n_se = d->D().n_se;
-    if (!out_host || n < n_se) return fail(SSD_E_NOMEM, "R_k needs %llu entries", (unsigned long long)n_se);
-    HIPCHK(e, hipMemcpyAsync(out_host, d->D().rk, n_se * 4, hipMemcpyDeviceToHost, e->stream));
-    HIPCHK(e, hipStreamSynchronize(e->stream));
-    return SSD_OK;
+    return engine_read_rk(&d->e, 0, out_host, n);
 }
 
 int ssd_read_hot(ssd_detector* d, uint32_t* counts_host, uint32_t* lists_host, uint64_t cap)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    Engine* e = &d->e;
-    int rc = usable(e);
-    if (rc) return rc;
     if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
-    if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
-    if (!counts_host) return fail(SSD_E_PARAM, "counts_host is NULL");
-    const Ctl& c = e->last[0];
-    uint64_t total = 0;
-    for (uint32_t i = 0; i < d->p().r; i++) { counts_host[i] = c.hot_n[i]; total += c.hot_n[i]; }
-    if (total > cap || (total && !lists_host)) return fail(SSD_E_TRUNC, "hot lists need %llu entries", (unsigned long long)total);
-    uint64_t o = 0;
-    for (uint32_t i = 0; i < d->p().r; i++) {
-        if (c.hot_n[i])
-            HIPCHK(e, hipMemcpyAsync(lists_host + o, d->D().hot_list + ((uint64_t)i << d->p().q),
-                                     (uint64_t)c.hot_n[i] * 4, hipMemcpyDeviceToHost, e->stream));
-        o += c.hot_n[i];
-    }
-    HIPCHK(e, hipStreamSynchronize(e->stream));
-    return SSD_OK;
+    return engine_read_hot(&d->e, 0, counts_host, lists_host, cap);
 }
 
 int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t* n_out)
@@ -1478,7 +1569,7 @@ int ssd_get_info(ssd_detector* d, ssd_info* out)
 
 // a batch keeps bin buffers when some link's state is large enough for the
 // binned scan
-bool batch_bins(const ssd_params* p, uint32_t n)
+static bool batch_bins(const ssd_params* p, uint32_t n)
 {
     if (!p) return false;
     for (uint32_t l = 0; l < n && l < MAX_LINKS; l++)
@@ -1486,8 +1577,18 @@ bool batch_bins(const ssd_params* p, uint32_t n)
     return false;
 }
 
+// batch links take 8-bit cells (the persistent tile scan and the batched hot
+// detection are written for them)
+static int batch_cells_ok(const ssd_params* p, uint32_t n)
+{
+    for (uint32_t l = 0; p && l < n && l < MAX_LINKS; l++)
+        if (p[l].cell_bits == 16) return fail(SSD_E_PARAM, "link %u: batches take 8-bit cells (k <= 254)", l);
+    return SSD_OK;
+}
+
 int ssd_batch_query_sizes(const ssd_params* p, uint32_t n, uint64_t* state_bytes, uint64_t* scratch_bytes)
 {
+    if (int rc = batch_cells_ok(p, n)) return rc;
     return engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, state_bytes, scratch_bytes, batch_bins(p, n));
 }
 
@@ -1496,6 +1597,7 @@ int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host,
 {
     if (!out) return fail(SSD_E_PARAM, "out is NULL");
     *out = nullptr;
+    if (int rc = batch_cells_ok(p, n)) return rc;
     const bool bins = batch_bins(p, n);
     int rc = engine_query(p, n, BATCH_STAGE, MAX_WINDOWS, nullptr, nullptr, bins);
     if (rc) return rc;
@@ -1668,7 +1770,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
             W.se_lo = w.lo;
             W.se_hi = w.hi;
             W.tile_base = tiles;
-            W.stamp = stamp_of(e->clock);
+            W.stamp = stamp_of(e->clock, false);
             W.pad2 = 0;
             tiles += (W.n + tile - 1) / tile;
         }
@@ -1693,7 +1795,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
         }
         PhaseMark pm = phase_begin(e);
         HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(b->scan_blocks, tiles), e->stream));
-        phase_end(e, pm, 0, 1);
+        phase_end(e, pm, PHASE_SCAN_TILES, 1);
         if (cand >= 0) {
             HIPCHK(e, hipEventRecord(tb, e->stream));
             b->tune_pending.push_back({cand, tile_pairs_total});
@@ -1702,7 +1804,8 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
     }
     for (uint32_t l : binned) {
         rc = enqueue_binned_scan(e, l, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[l],
-                                 offsets_host[l + 1] - offsets_host[l], DEFAULT_BIN_BYTES, DEFAULT_APPLY_SEGMENTS);
+                                 offsets_host[l + 1] - offsets_host[l], DEFAULT_BIN_BYTES, DEFAULT_APPLY_SEGMENTS,
+                                 engine_bins(e));
         if (rc) return rc;
     }
     return SSD_OK;
@@ -1752,6 +1855,20 @@ int ssd_batch_read_timing(ssd_batch* b, double* ms_out, uint64_t* launches_out, 
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
     return read_timing(&b->e, ms_out, launches_out, reset);
+}
+
+int ssd_batch_read_rk(ssd_batch* b, uint32_t link, uint32_t* out_host, uint64_t n)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    if (link >= b->e.n) return fail(SSD_E_PARAM, "link %u of %u", link, b->e.n);
+    return engine_read_rk(&b->e, link, out_host, n);
+}
+
+int ssd_batch_read_hot(ssd_batch* b, uint32_t link, uint32_t* counts_host, uint32_t* lists_host, uint64_t cap)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    if (link >= b->e.n) return fail(SSD_E_PARAM, "link %u of %u", link, b->e.n);
+    return engine_read_hot(&b->e, link, counts_host, lists_host, cap);
 }
 
 // ---- group
@@ -1854,7 +1971,7 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
             W.se_lo = lo;
             W.se_hi = std::min(lo + per, D.n_se);
             W.tile_base = tiles;
-            W.stamp = stamp_of(members[i]->e.clock);
+            W.stamp = stamp_of(members[i]->e.clock, false);
             tiles += (np + tile - 1) / tile;
             ws.push_back(W);
         }
@@ -1878,14 +1995,15 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         a.tile = tile;
         PhaseMark pm = phase_begin(e);
         HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(g->scan_blocks, tiles), e->stream));
-        phase_end(e, pm, 0, 1);
+        phase_end(e, pm, PHASE_SCAN_TILES, 1);
     }
     for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;   // group scans store uncounted
     for (uint32_t i = 0; i < n; i++) {
         if (!binned(i)) continue;
         ssd_detector* m = members[i];
         rc = enqueue_binned_scan(&m->e, 0, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[i],
-                                 offsets_host[i + 1] - offsets_host[i], m->bin_bytes, m->apply_segments);
+                                 offsets_host[i + 1] - offsets_host[i], m->bin_bytes, m->apply_segments,
+                                 engine_bins(&m->e));
         if (rc) return rc;
     }
     return SSD_OK;

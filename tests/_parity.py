@@ -20,9 +20,10 @@ def log(msg: str) -> None:
 
 
 def make_pair(q, r, delta, eta, k, theta, tables, key_bits=32, rehash=False, max_tuples=1 << 20,
-              max_results=1 << 18):
+              max_results=1 << 18, cell_bits=8):
     p = ssd.make_params(q=q, r=r, delta=delta, eta=eta, k=k, theta=theta, key_bits=key_bits,
-                        verify_rehash=rehash, max_tuples=max_tuples, max_results=max_results)
+                        verify_rehash=rehash, max_tuples=max_tuples, max_results=max_results,
+                        cell_bits=cell_bits)
     g = ssd.init_detector(p, tables, device="cuda:0")
     o = oracle.RSEA(q, r, delta, eta, k, theta, tables, key_bits=key_bits, verify_rehash=rehash)
     return g, o

@@ -11,19 +11,26 @@ import paper_1803_11036_amd as ssd
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    with open(os.path.join(ROOT, "include", "ssd.h")) as f:
+def _declared(header="ssd.h"):
+    with open(os.path.join(ROOT, "include", header)) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(ssd_[a-z_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_call():
-    names = _declared()
-    assert len(names) >= 15
+    """Every call of every header under include/ (the detector's ABI and the
+    memory-ceiling probes) is exported by the built library."""
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert "ssd.h" in headers and "ssd_probe.h" in headers
     lib = C.CDLL(ssd.library_path())
-    for n in names:
-        assert hasattr(lib, n), n
+    total = 0
+    for h in headers:
+        names = _declared(h)
+        total += len(names)
+        for n in names:
+            assert hasattr(lib, n), f"{h}: {n}"
+    assert len(_declared()) >= 15 and total >= len(_declared()) + 2
 
 
 def test_binding_names_match_the_abi():
@@ -81,17 +88,40 @@ def test_abi_version_and_flags_checked():
     p.flags = 0x10
     with pytest.raises(ssd.SSDError):
         ssd.query_sizes(p)
-    p = _p()
-    p.reserved = 1
-    with pytest.raises(ssd.SSDError):
-        ssd.query_sizes(p)
+    for bits in (1, 12, 32):
+        p = _p()
+        p.cell_bits = bits
+        with pytest.raises(ssd.SSDError):
+            ssd.query_sizes(p)
 
 
 def test_paper_parameter_set_is_valid():
-    """Sec. 5 runs eta = 2^11, q = 14, r = 5, delta = 6 (with 16-bit recorders;
-    here with k <= 254)."""
+    """Sec. 5 runs eta = 2^11, q = 14, r = 5, delta = 6 with windows of k =
+    300 slots on 16-bit recorders: valid with 16-bit cells (twice the bytes
+    of 8-bit cells), refused with 8-bit cells; 16-bit cells allow k up to
+    65534 (Sec. 3.2: k < 65535)."""
+    cells = 5 * (1 << 14) * 2048
+    state, _ = ssd.query_sizes(ssd.make_params(q=14, r=5, delta=6, eta=2048, k=300, theta=1024, cell_bits=16))
+    assert state == 2 * cells
     state, _ = ssd.query_sizes(ssd.make_params(q=14, r=5, delta=6, eta=2048, k=254, theta=1024))
-    assert state == 5 * (1 << 14) * 2048
+    assert state == cells
+    for k, bits in ((300, 8), (255, 8), (65535, 16), (0, 16)):
+        with pytest.raises(ssd.SSDError) as e:
+            ssd.query_sizes(ssd.make_params(q=14, r=5, delta=6, eta=2048, k=k, theta=1024, cell_bits=bits))
+        assert e.value.status == -1
+    ssd.query_sizes(ssd.make_params(q=14, r=5, delta=6, eta=2048, k=65534, theta=1024, cell_bits=16))
+    ssd.query_sizes(ssd.make_params(q=14, r=5, delta=6, eta=2048, k=200, theta=1024, cell_bits=0))
+
+
+def test_batches_take_8bit_cells():
+    """Batch links with 16-bit cells are refused (the batched scan and hot
+    detection are written for 8-bit cells)."""
+    ok = ssd.make_params(q=12, r=6, delta=5, eta=1024, k=4, theta=1024)
+    wide = ssd.make_params(q=12, r=6, delta=5, eta=1024, k=300, theta=1024, cell_bits=16)
+    ssd.batch_query_sizes([ok, ok])
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.batch_query_sizes([ok, wide])
+    assert e.value.status == -1
 
 
 def test_init_rejects_before_touching_the_device():

@@ -139,3 +139,49 @@ def test_batch_overflow_is_per_link():
     with pytest.raises(ssd.SSDError) as e:
         ssd.batch_scan(b, dev, offs, 99)
     assert e.value.status == -3
+
+
+def test_batch_links_match_oracle():
+    """Every link of a batch against the oracle, with the binned links at full
+    size: two large links of the 64-link workload at full rate -- a 1.5 GiB
+    (q=16, r=6, eta=4096) link and a 640 MiB (q=14, r=5, eta=8192) link,
+    both scanned binned inside the batch with per-slot counters (the second
+    through the five-row register binning) -- and six links of the tile scan
+    at 2% of their rate.  Lists, R_k and hot lists of every link equal the
+    oracle's at every slice, for k + 2 slices of the longest window."""
+    full = tg.batch_configs(n_links=64)
+    small = tg.batch_configs(n_links=64, pairs_scale=0.02)
+    big_ids, small_ids = [17, 34], [9, 14, 20, 32, 44, 1]
+    cfgs = [full[i] for i in big_ids] + [small[i] for i in small_ids]
+    assert [c.r for c in cfgs[:2]] == [6, 5]
+    assert all(c.r * (1 << c.q) * c.eta > 256 << 20 and c.pairs_lo >= 1 << 20 for c in cfgs[:2])
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    b = ssd.batch_init([_params(c) for c in cfgs], tabs, device="cuda:0")
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_TIMING, 1)
+    orcs = [oracle.RSEA(c.q, c.r, c.delta, c.eta, c.k, c.theta, tabs[i]) for i, c in enumerate(cfgs)]
+    n_slices = max(c.k for c in cfgs) + 2
+    total = 0
+    for t in range(n_slices):
+        per, offs, dev = _slice_pairs(traces, t)
+        ssd.batch_scan(b, dev, offs, t)
+        lists, status = ssd.batch_close(b)
+        assert np.all(status == 0)
+        for i, o in enumerate(orcs):
+            o.scan(per[i])
+            o.reconstruct()
+            ip, rk, est = o.results()
+            assert np.array_equal(lists[i]["ip"], ip) and np.array_equal(lists[i]["rk"], rk), \
+                f"slice {t} link {i}: lists differ from the oracle"
+            assert np.all(np.abs(lists[i]["est"] - est) <= 1e-6 * np.abs(est))
+            assert np.array_equal(ssd.batch_read_rk(b, i), o.rk()), f"slice {t} link {i}: R_k differs"
+            for row, (x, y) in enumerate(zip(ssd.batch_read_hot(b, i), o.hse())):
+                assert np.array_equal(x, y), f"slice {t} link {i}: HSE({row}) differs"
+            o.age()
+            total += len(ip)
+        tm = ssd.batch_read_timing(b, reset=True)
+        log(f"batch vs oracle slice {t}: {sum(len(x) for x in lists)} hosts, bin launches {tm['scan_bin'][1]}, "
+            f"count launches {tm['count_detect'][1]}")
+        assert tm["scan_bin"][1] >= 2 and tm["count_detect"][1] == 2
+    assert total > 0
+    b.destroy()

@@ -127,3 +127,44 @@ def test_distributed_16_routers_against_oracle():
     res = _run_distributed(cfg, tr, tg.hash_tables(cfg.hash_seed), cfg.k + 2, with_union=False,
                            with_oracle=True, distinct_only=True)
     assert len(res) > 20
+
+
+def test_distributed_paper_geometry_against_oracle():
+    """The distributed workload's geometry at full state size -- q = 14,
+    r = 5, delta = 6 (the paper's), 2^14 x 5 estimators of 4096 cells, 320 MiB
+    per router, so every router's scan is binned through the five-row
+    register binning -- with four routers at 0.5-1M pairs per slice, merged
+    into the global detector every slice (Alg. 5) and compared with the
+    oracle's merge: lists, R_k, hot lists and tuples every slice, the whole
+    window state every third slice, for k + 2 slices."""
+    cfg = tg.config("distributed", n_streams=4, pairs_lo=500_000, pairs_hi=1_000_000)
+    assert (cfg.q, cfg.r, cfg.delta, cfg.eta) == (14, 5, 6, 4096)
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    R = cfg.n_streams
+    params = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                             max_tuples=1 << 22, max_results=1 << 20)
+    routers = [ssd.init_detector(params, tabs, device="cuda:0") for _ in range(R)]
+    glob = ssd.init_detector(params, tabs, device="cuda:0")
+    for d in routers:
+        ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
+    orc_r = [oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs) for _ in range(R)]
+    orc_g = oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs)
+    for t in range(cfg.k + 2):
+        per = tr.pairs_all(t)
+        for j in range(R):
+            ssd.scan_slice(routers[j], to_dev(per[j]), t)
+            orc_r[j].scan(per[j])
+        ssd.merge_router_state(glob, routers)
+        orc_g.merge_from(orc_r)
+        if t % 3 == 2:
+            compare_state(glob, orc_g)
+        res = close_both(glob, orc_g)
+        for j in range(R):
+            assert len(ssd.close_slice(routers[j], advance_only=True)) == 0
+            orc_r[j].close(advance_only=True)
+        log(f"distributed paper geometry slice {t}: {len(res)} hosts")
+    assert len(res) > 20
+    assert all(ssd.read_timing(d)["scan_bin"][1] == cfg.k + 2 for d in routers)
+    for d in routers + [glob]:
+        d.destroy()

@@ -127,6 +127,73 @@ def test_stamp_wrap_and_expiry(k, mode):
     log(f"wrap k={k} {mode} done")
 
 
+@pytest.mark.parametrize("mode,n_slices", [("binned", 302), ("passes", 24)])
+def test_paper_parameter_set_16bit_cells(mode, n_slices):
+    """The paper's sliding-window parameter set (Sec. 5): windows of k = 300
+    one-second slots, eta = 2^11, q = 14, r = 5, delta = 6, theta = 1024,
+    which needs 16-bit cells.  A paper-shaped trace at a lighter load (300K
+    background hosts, 60 planted, 30K pairs per slot; about 140 hot
+    estimators per row in a full window, which keeps the oracle's literal
+    enumeration within seconds per slot) runs k + 2 slots with the default
+    (binned) scan, so that the first slots leave the window, and 24 slots
+    with pass windows.  Lists at every slot; R_k, hot lists and tuples every
+    25 slots and at the last three; the whole canonical state every 60 slots
+    and at the end."""
+    cfg = tg.config("paper", pairs_lo=30_000, pairs_hi=30_000, n_hosts=300_000, n_planted=60)
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs, cell_bits=16)
+    if mode == "passes":
+        ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_PASSES)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
+    reported = 0
+    for t in range(n_slices):
+        scan_both(g, o, tr.pairs(0, t), t, splits=2 if t % 7 == 3 else 1)
+        last = t >= n_slices - 3
+        if t % 60 == 59 or t == n_slices - 1:
+            log(f"paper k=300 {mode} slice {t}: comparing the whole canonical state")
+            compare_state(g, o)
+        elif t % 20 == 0:
+            log(f"paper k=300 {mode} slice {t}")
+        res = close_both(g, o, check_internals=(t % 25 == 0 or last))
+        reported = len(res)
+    assert reported > 0
+    tm = ssd.read_timing(g)
+    assert tm["hot_detect"][1] == n_slices and tm["count_detect"][1] == 0
+    assert (tm["scan_bin"][1] > 0) == (mode == "binned")
+    log(f"paper k=300 {mode}: {reported} hosts at slice {n_slices - 1}")
+
+
+def test_16bit_stamp_wrap_and_expiry():
+    """16-bit stamps repeat after 65535 slots: scans in the first slots and
+    again around slot 65535, advance-only closes in between on both sides.
+    The rotating expiry (period 65535 - k) must clear every old cell before
+    its stamp comes round again, so that each cell's distance stays exact
+    (a cell hit in slot s must not look live at slot s + 65535)."""
+    q, r, delta, eta, k, theta, kb = 6, 4, 4, 1024, 5, 150, 14
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(12), key_bits=kb, cell_bits=16)
+    early, late = range(0, 12), range(65527, 65546)
+    sl = _slices_small(61, len(early) + len(late), kb, theta, q, sizes=[600] * (len(early) + len(late)),
+                       heavy=12)
+    j = 0
+    for t in range(late.stop):
+        if t in early or t in late:
+            scan_both(g, o, sl[j], t)
+            j += 1
+            if t in late or t % 4 == 0:
+                compare_state(g, o)
+            close_both(g, o, check_internals=(t in late))
+        else:
+            assert len(ssd.close_slice(g, advance_only=True)) == 0
+            o.close(advance_only=True)
+        if t % 10000 == 0:
+            log(f"16-bit wrap: slot {t}")
+        if t == 65000:
+            compare_state(g, o)
+            log("16-bit wrap: slot 65000 state equal")
+    compare_state(g, o)
+
+
 def test_many_rows_level_expansion():
     """r = 10 rows (q = 8, delta = 3): above the depth-first bound, so the
     candidates are expanded level by level (nine launches); every product
@@ -164,15 +231,18 @@ def test_key_width_beyond_32_bits():
         close_both(g, o)
 
 
-def test_merge_routers():
+@pytest.mark.parametrize("k,cell_bits", [(3, 8), (300, 16)])
+def test_merge_routers(k, cell_bits):
     """Alg. 5: four router detectors merged into a global one every slot;
     the global close must match the oracle's merged RSEA, and routers only
-    advance their clocks."""
-    q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
+    advance their clocks (8-bit cells, and 16-bit cells with a 300-slot
+    window)."""
+    q, r, delta, eta, theta, kb = 8, 4, 4, 1024, 200, 16
     tabs = tg.hash_tables(9)
     nR = 4
-    gpu_r, orc_r = zip(*[make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb) for _ in range(nR)])
-    g, o = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
+    gpu_r, orc_r = zip(*[make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb, cell_bits=cell_bits)
+                         for _ in range(nR)])
+    g, o = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb, cell_bits=cell_bits)
     rng = np.random.default_rng(10)
     for t in range(8):
         sl = _slices_small(100 + t, 1, kb, theta // 2, q, heavy=15)[0]
@@ -224,6 +294,32 @@ def test_binned_scan_matches_oracle(bin_kib, counted):
         scan_both(g, o, pairs, t, splits=5 if t == 2 else 1)
         compare_state(g, o)
         close_both(g, o, check_internals=(t == 3))
+
+
+@pytest.mark.parametrize("q,r,delta,counted", [(12, 4, 10, 0), (12, 4, 10, 1), (14, 5, 6, 0), (14, 5, 6, 1),
+                                                (12, 6, 5, 0), (12, 6, 5, 1)])
+def test_binned_scan_rows_match_oracle(q, r, delta, counted):
+    """Every binning kernel against the oracle on small states with the
+    binned scan forced: four rows (the general binning), five rows (the
+    register binning of up to 7 pairs per thread, as in the paper's geometry
+    q = 14, delta = 6) and six rows (up to 6 pairs per thread), with per-slot
+    counters and without; canonical state, lists, R_k, hot lists and tuples
+    every slice, one slice split over three calls."""
+    eta, k, theta, kb = 1024, 3, 300, 32
+    sizes = [60_000, 90_001, 45_000, 120_000, 70_000]
+    sl = _slices_small(300 + r, len(sizes), kb, theta, q, sizes=sizes, heavy=24)
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(20 + r), key_bits=kb)
+    ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED, counted)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
+    for t, p in enumerate(sl):
+        log(f"binned rows r={r} counted={counted} slice {t} n={p.shape[0]}")
+        scan_both(g, o, p, t, splits=3 if t == 1 else 1)
+        compare_state(g, o)
+        close_both(g, o)
+    tm = ssd.read_timing(g)
+    assert tm["scan_bin"][1] >= len(sl)
+    assert (tm["count_detect"][1] > 0) == bool(counted)
 
 
 def test_counted_detection_switches():

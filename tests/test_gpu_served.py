@@ -6,6 +6,7 @@ to wait for admission."""
 import numpy as np
 import pytest
 
+import oracle
 import paper_1803_11036_amd as ssd
 import tracegen as tg
 from _parity import log, to_dev
@@ -32,13 +33,41 @@ def _check_equal(inputs, rep):
     return total
 
 
+def _oracle_slots(s):
+    """The oracle fed one served stream's batches slot by slot (scan every
+    batch that arrived in the slot, then close): its list per slot."""
+    p = s.params
+    o = oracle.RSEA(p.q, p.r, p.delta, p.eta, p.k, p.theta, s.tables)
+    slot_of = np.floor(s.arrivals / s.slot).astype(np.int64)
+    out = []
+    for t in range(s.n_slots):
+        for j in np.nonzero(slot_of == t)[0]:
+            o.scan(s.batch(int(j)).cpu().numpy().view(np.uint32))
+        out.append(o.close())
+    return out
+
+
 def test_served_mix_equals_alone():
+    """Every stream's list in every slot is the same alone and in the mix,
+    and, for the streams with states up to 512 MiB, equal to the oracle's
+    fed the same batches."""
     inputs = _inputs(8, 4, 0x5EED1)
     rep = serve.serve(inputs, budget_bytes=1 << 40, time_scale=4.0)
     log(f"served: {rep.pairs} pairs in {rep.wall_s:.2f} s, {rep.scan_calls} scans, {rep.close_calls} closes, "
         f"p50 {rep.latency(50):.2f} ms p99 {rep.latency(99):.2f} ms")
     assert rep.max_scan_members > 1          # batches of several streams shared scan launches
     assert _check_equal(inputs, rep) > 0
+    checked = 0
+    for i, s in enumerate(inputs):
+        if serve.stream_bytes(s.params) > 512 << 20:
+            continue
+        for t, (ip, rk, est) in enumerate(_oracle_slots(s)):
+            mixed = rep.results[(i, t)]
+            assert np.array_equal(mixed["ip"], ip) and np.array_equal(mixed["rk"], rk), \
+                f"stream {i} slot {t}: served list differs from the oracle"
+            assert np.all(np.abs(mixed["est"] - est) <= 1e-6 * np.abs(est))
+        checked += 1
+    assert checked >= 2
 
 
 def test_served_admission_by_memory_budget():
@@ -54,7 +83,9 @@ def test_served_admission_by_memory_budget():
 def test_group_binned_members_equal_separate_detectors():
     """Members with a state above 256 MiB and at least 2^20 pairs in the call
     are scanned binned inside the group scan (the rest share the tile scan);
-    each member's list equals that of a detector of its own fed the same pairs."""
+    each member's list equals that of a detector of its own fed the same
+    pairs, and the oracle's (lists, R_k and hot lists), slice by slice, also
+    when only a subset of the members scans and closes."""
     cfgs = tg.batch_configs(n_links=12, pairs_scale=0.5)
     traces = [tg.Trace(c) for c in cfgs]
     tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
@@ -66,6 +97,7 @@ def test_group_binned_members_equal_separate_detectors():
     alone = [ssd.init_detector(params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
     for d in members:
         ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
+    orcs = [oracle.RSEA(c.q, c.r, c.delta, c.eta, c.k, c.theta, tabs[i]) for i, c in enumerate(cfgs)]
     g = ssd.group_init(len(cfgs), device="cuda:0")
     big = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > 256 << 20 and c.pairs_lo >= 1 << 20]
     assert big, "no member takes the binned scan"
@@ -90,8 +122,42 @@ def test_group_binned_members_equal_separate_detectors():
             res = ssd.close_slice(alone[i])
             clock[i] += 1
             assert np.array_equal(lists[j], res), f"slice {t} member {i}: group and own detector differ"
+            o = orcs[i]
+            o.scan(per[i])
+            o.reconstruct()
+            ip, rk, est = o.results()
+            assert np.array_equal(lists[j]["ip"], ip) and np.array_equal(lists[j]["rk"], rk), \
+                f"slice {t} member {i}: group and oracle differ"
+            assert np.all(np.abs(lists[j]["est"] - est) <= 1e-6 * np.abs(est))
+            assert np.array_equal(ssd.read_rk(members[i]), o.rk()), f"slice {t} member {i}: R_k differs"
+            for row, (x, y) in enumerate(zip(ssd.read_hot(members[i]), o.hse())):
+                assert np.array_equal(x, y), f"slice {t} member {i}: HSE({row}) differs"
+            o.age()
         log(f"group binned slice {t}: members {pick}, {sum(len(x) for x in lists)} hosts, binned {big}")
     assert sum(ssd.read_timing(members[i])["scan_bin"][1] for i in big) >= len(big) + 2
     g.destroy()
     for d in members + alone:
         d.destroy()
+
+
+def test_group_refuses_16bit_members():
+    """Groups take 8-bit members only: a detector with 16-bit cells (windows
+    above 254 slots) in a group call is refused before any work."""
+    p8 = ssd.make_params(q=8, r=4, delta=4, eta=1024, k=3, theta=200, key_bits=16)
+    p16 = ssd.make_params(q=8, r=4, delta=4, eta=1024, k=300, theta=200, key_bits=16, cell_bits=16)
+    tabs = tg.hash_tables(5)
+    d8, d16 = ssd.init_detector(p8, tabs, device="cuda:0"), ssd.init_detector(p16, tabs, device="cuda:0")
+    g = ssd.group_init(2, device="cuda:0")
+    pairs = to_dev(np.arange(20, dtype=np.uint32).reshape(10, 2))
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.group_scan(g, [d8, d16], pairs, [0, 5, 10], [0, 0])
+    assert e.value.status == -1
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.group_close(g, [d16])
+    assert e.value.status == -1
+    ssd.group_scan(g, [d8], pairs, [0, 10], [0])
+    lists, status = ssd.group_close(g, [d8])
+    assert status[0] == 0
+    g.destroy()
+    d8.destroy()
+    d16.destroy()

@@ -175,6 +175,17 @@ CONFIGS: Dict[str, TraceConfig] = {
         multi_frac=0.3, multi_lo=2, multi_hi=4,
         n_planted=200, planted_lo=1500, planted_hi=12_000,
         planted_routers_lo=2, planted_routers_hi=8, seed=0x55D00002),
+    # the paper's sliding-window parameter set (Sec. 5: one-second slots,
+    # k = 300, eta = 2^11, q = 14, r = 5, delta = 6, theta = 1024) on a
+    # core-link-shaped trace of 6M pairs per slot (40 Gb/s at 800 B); a
+    # window of 300 slots carries about 6M distinct pairs (background plus
+    # planted).  Its cells need 16 bits (k > 254).
+    "paper": TraceConfig(
+        name="paper", n_streams=1, n_slices=360, pairs_lo=6_000_000, pairs_hi=6_000_000,
+        k=300, theta=1024, q=14, r=5, delta=6, eta=2048,
+        n_hosts=800_000, degree_law="pareto", pareto_alpha=1.2, degree_cap=100_000,
+        n_planted=150, planted_lo=1500, planted_hi=50_000, planted_transient=0.4,
+        seed=0x55D00005),
 }
 
 
@@ -384,14 +395,18 @@ class Trace:
         p = np.arange(tot, dtype=np.int64) - np.repeat(first, d)
         return self._rows(h, p)
 
-    def pairs_device(self, stream: int, s: int, device, n: Optional[int] = None):
+    def pairs_device(self, stream: int, s: int, device, n: Optional[int] = None,
+                     d: Optional[np.ndarray] = None):
         """The slice's N pairs built on a torch device: the same distinct pairs
         as ``pairs``, with the repeats and the shuffle drawn by a torch Philox
         generator keyed like ``pairs`` (fast; a different but equally seeded
-        arrangement).  Returns an int32 (N, 2) tensor on ``device``."""
+        arrangement).  ``d``: the slice's distinct pairs if already drawn
+        (``distinct`` / ``distinct_all``).  Returns an int32 (N, 2) tensor on
+        ``device``."""
         import torch
         c = self.cfg
-        d = self.distinct(stream, s)
+        if d is None:
+            d = self.distinct(stream, s)
         N = int(self.n_pairs[stream]) if n is None else int(n)
         D = d.shape[0]
         if D == 0 or N == 0:
