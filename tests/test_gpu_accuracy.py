@@ -66,3 +66,127 @@ def test_accuracy_core_link(rehash):
     assert fnr < 0.05
     if rehash:
         assert fpr < 0.10
+
+
+def _rates(rows):
+    n_true = sum(r[1] for r in rows)
+    return sum(r[3] for r in rows) / max(1, n_true), sum(r[4] for r in rows) / max(1, n_true)
+
+
+def _row(t, got, true):
+    tp = np.intersect1d(got, true).size
+    return (t, true.size, got.size, got.size - tp, true.size - tp)
+
+
+@pytest.mark.parametrize("rehash", [False, True])
+def test_accuracy_paper_shape(rehash):
+    """The paper's sliding-window experiment shape (Sec. 5): one-second slots,
+    k = 300, eta = 2^11, q = 14, r = 5, delta = 6, theta = 1024 (16-bit
+    cells), 360 slots of 6M pairs of a core-link-shaped trace: FPR, FNR and
+    TFR over the 61 full windows SW(0,300) ... SW(60,300), against exact
+    sliding opposite numbers."""
+    cfg = tg.config("paper")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    p = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                        verify_rehash=rehash, max_tuples=1 << 22, max_results=1 << 20, cell_bits=16)
+    det = ssd.init_detector(p, tabs, device="cuda:0")
+    exact = truth.SlidingWindowTruth(cfg.k, cfg.theta)
+    rows = []
+    for t in range(cfg.n_slices):
+        d = tr.distinct(0, t)
+        ssd.scan_slice(det, tr.pairs_device(0, t, "cuda:0", d=d), t)
+        res = ssd.close_slice(det)
+        true = exact.add(d)
+        if t >= cfg.k - 1:
+            rows.append(_row(t, res["ip"], true))
+        if t % 60 == 0:
+            log(f"paper shape slot {t}: {len(res)} reported")
+    det.destroy()
+    fpr, fnr = _rates(rows)
+    log(f"accuracy paper shape (k=300) rehash={rehash}: FPR {100 * fpr:.2f}% FNR {100 * fnr:.2f}% "
+        f"TFR {100 * (fpr + fnr):.2f}% over {len(rows)} windows; true per window "
+        f"{min(r[1] for r in rows)}..{max(r[1] for r in rows)}, reported {min(r[2] for r in rows)}.."
+        f"{max(r[2] for r in rows)}")
+    assert len(rows) == cfg.n_slices - cfg.k + 1
+    assert fnr < 0.05
+    if rehash:
+        assert fpr < 0.10
+
+
+@pytest.mark.parametrize("rehash", [False, True])
+def test_accuracy_distributed_merged(rehash):
+    """The distributed workload (16 routers, k = 8, theta = 2048): the global
+    detector after the per-slot merge (Alg. 5) against the exact sliding
+    opposite numbers of every router's pairs together, over the full
+    windows of 24 slots."""
+    cfg = tg.config("distributed")
+    tr = tg.Trace(cfg)
+    tabs = tg.hash_tables(cfg.hash_seed)
+    p = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                        verify_rehash=rehash, max_tuples=1 << 22, max_results=1 << 20)
+    routers = [ssd.init_detector(p, tabs, device="cuda:0") for _ in range(cfg.n_streams)]
+    glob = ssd.init_detector(p, tabs, device="cuda:0")
+    exact = truth.SlidingWindowTruth(cfg.k, cfg.theta)
+    rows = []
+    for t in range(cfg.n_slices):
+        per = tr.distinct_all(t)
+        for j, d in enumerate(routers):
+            ssd.scan_slice(d, tr.pairs_device(j, t, "cuda:0", d=per[j]), t)
+        ssd.merge_router_state(glob, routers)
+        res = ssd.close_slice(glob)
+        for d in routers:
+            ssd.close_slice(d, advance_only=True)
+        true = exact.add(np.concatenate(per))
+        if t >= cfg.k - 1:
+            rows.append(_row(t, res["ip"], true))
+    for d in routers + [glob]:
+        d.destroy()
+    fpr, fnr = _rates(rows)
+    log(f"accuracy distributed merged rehash={rehash}: FPR {100 * fpr:.2f}% FNR {100 * fnr:.2f}% "
+        f"TFR {100 * (fpr + fnr):.2f}% over {len(rows)} windows, true/reported per window "
+        f"{[(r[1], r[2]) for r in rows]}")
+    assert fnr < 0.05
+    if rehash:
+        assert fpr < 0.10
+
+
+@pytest.mark.parametrize("rehash", [False, True])
+def test_accuracy_batched_links(rehash):
+    """Batched links (the 64-link workload's links with k <= 32, at their full
+    rates; window distinct pairs capped at 1.5M per link so that the exact
+    counts stay cheap): every link's list from the batch against its own
+    exact sliding opposite numbers, over its full windows up to slot k + 7."""
+    allc = tg.batch_configs(n_links=64, max_window_distinct=1.5e6)
+    pick = [i for i, c in enumerate(allc) if c.k <= 32]
+    cfgs = [allc[i] for i in pick]
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    params = [ssd.make_params(q=c.q, r=c.r, delta=c.delta, eta=c.eta, k=c.k, theta=c.theta,
+                              verify_rehash=rehash, max_tuples=1 << 21, max_results=1 << 18) for c in cfgs]
+    b = ssd.batch_init(params, tabs, device="cuda:0")
+    exact = [truth.SlidingWindowTruth(c.k, c.theta) for c in cfgs]
+    rows = [[] for _ in cfgs]
+    n_slices = max(c.k for c in cfgs) + 8
+    for t in range(n_slices):
+        dist = [tr.distinct(0, t % tr.cfg.n_slices) for tr in traces]
+        parts = [tr.pairs_device(0, t % tr.cfg.n_slices, "cuda:0", d=dist[i]) for i, tr in enumerate(traces)]
+        offs = np.zeros(len(parts) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([int(x.shape[0]) for x in parts])
+        ssd.batch_scan(b, torch.cat(parts).contiguous(), offs, t)
+        lists, status = ssd.batch_close(b)
+        assert np.all(status == 0)
+        for i, c in enumerate(cfgs):
+            true = exact[i].add(dist[i])
+            if c.k - 1 <= t <= c.k + 7:
+                rows[i].append(_row(t, lists[i]["ip"], true))
+    b.destroy()
+    flat = [r for rs in rows for r in rs]
+    fpr, fnr = _rates(flat)
+    worst = max(_rates(rs)[1] for rs in rows)
+    log(f"accuracy batched ({len(cfgs)} links, k <= 32) rehash={rehash}: FPR {100 * fpr:.2f}% "
+        f"FNR {100 * fnr:.2f}% TFR {100 * (fpr + fnr):.2f}% over {len(flat)} link windows; "
+        f"worst link FNR {100 * worst:.2f}%")
+    assert fnr < 0.05
+    if rehash:
+        assert fpr < 0.10

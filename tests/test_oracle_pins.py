@@ -600,3 +600,22 @@ def test_rehash_output_equals_bruteforce_paper_geometry():
     pip, prk, _ = p.results()
     assert np.all(np.isin(bip, pip))
     assert np.all(prk[np.searchsorted(pip, bip)] >= brk)
+
+
+def test_sliding_window_truth_equals_window_recount():
+    """The incremental exact truth (last slot of every distinct pair) gives,
+    at every slot, the same sliding super points as counting the window's
+    slots afresh (Def. 4), including early windows, pairs that leave and
+    come back, and repeats."""
+    rng = np.random.default_rng(3)
+    for k in (1, 3, 7):
+        tr = truth.SlidingWindowTruth(k, 40)
+        slices = []
+        for t in range(20):
+            hosts = rng.integers(0, 30, 3000).astype(np.uint32)
+            peers = rng.integers(0, 200, 3000).astype(np.uint32)
+            p = np.stack([hosts, peers], 1)
+            slices.append(p)
+            got = tr.add(p)
+            want = truth.window_super_points(slices, t, k, 40)
+            assert np.array_equal(got, want), (k, t)
