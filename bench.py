@@ -2,26 +2,38 @@
 """Benchmark of the sliding super point detector's hot path on one MI355X.
 
 A step is one pass of the whole hot path over one slice of synthetic input:
-scan of the slice's pairs (Alg. 2), then the slice close -- hot detection,
-candidate expansion, final test, sort and report (Sec. 4.2) -- with the list
-back in host memory.  The default workload is the single 40 Gb/s core link
-(6M pairs per 1-s slice, k = 10, 6 x 2^16 estimators of 4096 cells, theta
-1024; synthetic trace, see tracegen).  Inputs are resident in HBM before the
+the scan of the slice's pairs (Alg. 2), then the slice close -- hot
+detection, candidate expansion, final test, sort and report (Sec. 4.2) --
+with the lists back in host memory.  Inputs are resident in HBM before the
 timed region.
 
-Prints one JSON line: throughput in pairs (packets) per second over the timed
-steps, Gb/s at an 800-byte mean packet, slice-close latency p50/p99, per-phase
-device times from HIP events on the detector's stream, the roofline of the
-dominant kernel and the CPU oracle's rate on a bounded sample of the same
-workload.
+Default workload (the metric's own comparison): the batched form -- 64
+independent monitored links of uneven rates (0.2M-8M pairs per slice), windows
+(k 4..64) and thresholds (512..8192), about 152M pairs per slice over 19 GiB of
+state -- timed as plain per-link launches (one detector per link, scan and
+close per link in sequence on one stream) and as one batch (one persistent
+scan launch, one graph-replayed close), on the same pairs, with the lists
+checked identical for every timed slice.  `value` is the batched rate.
+
+Prints one JSON line: pairs (packets) per second, Gb/s at an 800-byte mean
+packet (also in the paper's /1024 convention), slice-close latency p50/p99,
+per-phase device times from HIP events on the engine's stream, the roofline
+of the dominant kernel (algorithmic bytes per launch over its event time,
+against 8 TB/s), the end-to-end rate with the pairs copied from pinned host
+memory, the CPU oracle's rate on a bounded sample (one thread and all host
+cores), the single core link as a secondary workload and the measured memory
+ceilings.  Other workloads: --workload core_link | distributed | served |
+ceilings.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
+import ctypes as C
 import hashlib
-import re
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,10 +45,36 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 MEAN_PACKET_BYTES = 800        # the paper's assumed mean packet size (Sec. 5)
+METRIC = "packets/s (and Gb/s @800B) scan + slice-close latency p50/p99, batched vs plain"
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def gbps(pps: float) -> dict:
+    """Gb/s at 800-byte packets: decimal, and the paper's convention
+    (M pairs/s x 800 x 8 / 1024, Sec. 5)."""
+    return {"gbps_at_800B": round(pps * MEAN_PACKET_BYTES * 8 / 1e9, 2),
+            "gbps_at_800B_paper_convention": round(pps / 1e6 * MEAN_PACKET_BYTES * 8 / 1024, 2)}
+
+
+def host_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_threads() -> int:
+    # the GPU box gives one GPU's process a share of 16 host cores
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def kernel_source_sha() -> str:
@@ -74,9 +112,144 @@ def load_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(cfg, trace, tables, n_slices: int):
-    """The oracle as it stands, single thread, on the first n_slices slices of
-    the same workload (scan + full close each)."""
+def roofline(cands: dict, workload: str) -> dict:
+    """The roofline of the kernel with the most device time per step.
+    cands: name -> (device ms per step, algorithmic bytes per launch, ms per
+    launch, launches per step, implementation bytes per launch or None)."""
+    dom = max(cands, key=lambda k: cands[k][0])
+    _, alg, ms, per_step, impl = cands[dom]
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = load_traffic(dom, workload)
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(alg), "ms_per_launch": round(ms, 5),
+            "launches_per_step": per_step,
+            "implementation_bytes_per_launch": round(impl) if impl else None,
+            "traffic_gbs": round(traffic / (ms * 1e-3) / 1e9, 1) if traffic and ms > 0 else None,
+            "others": {k: {"ms_per_step": round(v[0], 4), "ms_per_launch": round(v[2], 5),
+                           "achieved_gbs": round(v[1] / (v[2] * 1e-3) / 1e9, 1) if v[2] > 0 else None}
+                       for k, v in cands.items() if k != dom}}
+
+
+# ----------------------------------------------------------------------------
+# memory ceilings (probes in the library)
+
+def _probe_lib():
+    import paper_1803_11036_amd as ssd
+    L = C.CDLL(ssd.library_path())
+    L.ssd_probe_stream_read.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]
+    L.ssd_probe_stream_read.restype = C.c_int
+    L.ssd_probe_scatter.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p]
+    L.ssd_probe_scatter.restype = C.c_int
+    return L
+
+
+def ceilings(dev, sizes_mib, stores: int = 1 << 28, reps: int = 3) -> dict:
+    """Stream read (GB/s) and random byte scatter (G stores/s, uniform and
+    XCD-local) at each working-set size, timed with events on the stream the
+    probes run on (torch's current stream)."""
+    import torch
+    L = _probe_lib()
+    s = torch.cuda.current_stream(dev)
+    out = {}
+    sink = torch.empty(4096, dtype=torch.uint8, device=dev)
+    for mib in sizes_mib:
+        nbytes = mib << 20
+        buf = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        res = {}
+        for name, fn in (("stream_read_gbs", lambda: L.ssd_probe_stream_read(buf.data_ptr(), nbytes, sink.data_ptr(),
+                                                                             s.cuda_stream)),
+                         ("scatter_uniform_gstores", lambda: L.ssd_probe_scatter(buf.data_ptr(), nbytes, stores, 7, 0,
+                                                                                 s.cuda_stream)),
+                         ("scatter_xcd_local_gstores", lambda: L.ssd_probe_scatter(buf.data_ptr(), nbytes, stores, 7,
+                                                                                   1, s.cuda_stream))):
+            if name == "scatter_xcd_local_gstores" and (nbytes < (16 << 20) or nbytes % (2 << 20)):
+                continue
+            if fn() != 0:
+                raise RuntimeError(f"probe {name} failed")
+            best = None
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s)
+                if fn() != 0:
+                    raise RuntimeError(f"probe {name} failed")
+                b.record(s)
+                b.synchronize()
+                ms = a.elapsed_time(b)
+                best = ms if best is None else min(best, ms)
+            res[name] = round((nbytes / 1e9 if name == "stream_read_gbs" else stores / 1e9) / (best * 1e-3), 2)
+        out[f"{mib}MiB"] = res
+        del buf
+    torch.cuda.empty_cache()
+    return out
+
+
+# ----------------------------------------------------------------------------
+# CPU oracle baselines
+
+def _oracle_link_sample(cfgs, max_state=256 << 20, max_window_pairs=16_000_000, max_links=12):
+    """The batched links the CPU sample takes: states up to max_state bytes
+    and windows of at most max_window_pairs pairs, in link order."""
+    pick = [i for i, c in enumerate(cfgs)
+            if c.r * (1 << c.q) * c.eta <= max_state and c.k * c.pairs_lo <= max_window_pairs]
+    return pick[:max_links]
+
+
+def cpu_baseline_batched(cfgs, traces, tables) -> dict:
+    """The oracle as it stands on a sample of the batched links with full
+    windows: each sampled link's first k slices are scanned and aged untimed
+    (its window fills), then one slice per link is timed (scan + full close)
+    on one host thread, link after link, and the next slice on all host
+    cores at once, one link per thread (the oracle's calls release the GIL)."""
+    import oracle
+    pick = _oracle_link_sample(cfgs)
+    threads = min(cpu_threads(), len(pick))
+    orcs = {i: oracle.RSEA(cfgs[i].q, cfgs[i].r, cfgs[i].delta, cfgs[i].eta, cfgs[i].k, cfgs[i].theta, tables[i])
+            for i in pick}
+
+    def fill(i):
+        for t in range(cfgs[i].k):
+            orcs[i].scan(traces[i].pairs(0, t))
+            orcs[i].close(advance_only=True)
+        return i
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(fill, pick))
+    fill_s = time.perf_counter() - t0
+    # one thread: slice k of every sampled link, one after another
+    sl = {i: traces[i].pairs(0, cfgs[i].k % cfgs[i].n_slices) for i in pick}
+    n1 = sum(p.shape[0] for p in sl.values())
+    t0 = time.perf_counter()
+    for i in pick:
+        orcs[i].scan(sl[i])
+        orcs[i].close()
+    one_s = time.perf_counter() - t0
+    # all cores: slice k+1 of every sampled link, one link per thread
+    sl = {i: traces[i].pairs(0, (cfgs[i].k + 1) % cfgs[i].n_slices) for i in pick}
+    nn = sum(p.shape[0] for p in sl.values())
+
+    def step(i):
+        orcs[i].scan(sl[i])
+        orcs[i].close()
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(step, pick))
+    all_s = time.perf_counter() - t0
+    del orcs
+    sample = (f"{len(pick)} of the {len(cfgs)} batched links (those with at most 256 MiB of state and 16M pairs "
+              f"per window, in link order: {pick}); each link's window filled untimed ({fill_s:.1f} s), then one "
+              f"slice per link timed, scan + full close with a full window: {n1} pairs in {one_s:.2f} s on one "
+              f"thread, the next {nn} pairs in {all_s:.2f} s on {threads} threads (one link per thread)")
+    return {"value": round(nn / all_s, 1), "unit": "packets/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "single_thread": {"value": round(n1 / one_s, 1), "cores": 1},
+            "host": host_info()}
+
+
+def cpu_baseline_link(cfg, trace, tables, n_slices: int) -> dict:
+    """The oracle as it stands, one thread, on the first n_slices slices of a
+    single-link workload (scan + full close each)."""
     import oracle
     o = oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tables)
     slices = [trace.pairs(0, t) for t in range(n_slices)]
@@ -88,10 +261,13 @@ def cpu_baseline(cfg, trace, tables, n_slices: int):
         n += p.shape[0]
     dt = time.perf_counter() - t0
     del o
-    return {"value": n / dt, "unit": "packets/s", "cores": 1, "kind": "oracle",
+    return {"value": round(n / dt, 1), "unit": "packets/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_slices} slices of the workload ({n} pairs), scan + full close each, "
-                      f"{dt:.1f} s on one host thread"}
+                      f"{dt:.1f} s on one host thread", "host": host_info()}
 
+
+# ----------------------------------------------------------------------------
+# batched (default)
 
 def run_batched(args) -> dict:
     """64 links of uneven rates, windows and thresholds: plain per-link
@@ -104,6 +280,10 @@ def run_batched(args) -> dict:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    ceil = None
+    if not args.no_ceilings:
+        log("ceilings: stream read and byte scatter at the core-link state size")
+        ceil = ceilings(dev, [1536])
     cfgs = tg.batch_configs(n_links=args.links)
     log(f"batched: {len(cfgs)} links, building traces")
     traces = [tg.Trace(c) for c in cfgs]
@@ -126,7 +306,7 @@ def run_batched(args) -> dict:
     W, K = args.warmup, args.steps
     # plain: one detector per link
     plain = [ssd.init_detector(params(c), tables[i], device=dev) for i, c in enumerate(cfgs)]
-    plain_lists = []
+    plain_lists, plain_close = [], []
     t = 0
     for i in range(W + K):
         pairs, offs = slices[i % n_var]
@@ -134,11 +314,15 @@ def run_batched(args) -> dict:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         lists = []
+        close_ms = 0.0
         for l, d in enumerate(plain):
             ssd.scan_slice(d, pairs[int(offs[l]):int(offs[l + 1])], t)
+            c0 = time.perf_counter()
             lists.append(ssd.close_slice(d))
+            close_ms += (time.perf_counter() - c0) * 1e3
         if i >= W:
             plain_lists.append(lists)
+            plain_close.append(close_ms)
         t += 1
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
@@ -147,14 +331,19 @@ def run_batched(args) -> dict:
     del plain
     torch.cuda.empty_cache()
 
-    # batched: persistent scan + graph close; autotuned during the warmup
+    # batched: persistent scan + graph close; the autotuner times its
+    # candidates on untimed scans first
     b = ssd.batch_init([params(c) for c in cfgs], tables, device=dev)
-    ssd.batch_set_tuning(b, ssd.SSD_TUNE_TIMING, 1)
+    t = 0
     if args.autotune:
         ssd.batch_set_tuning(b, ssd.SSD_TUNE_AUTOTUNE, 1)
-    t = 0
-    lat = []
-    same = True
+        while ssd.batch_get_tuning(b, ssd.SSD_TUNE_AUTOTUNE):
+            pairs, offs = slices[t % n_var]
+            ssd.batch_scan(b, pairs, offs, t)
+            ssd.batch_close(b)
+            t += 1
+        log(f"autotuned over {t} slices")
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_TIMING, 1)
     batch_lists = []
     for i in range(W + K):
         pairs, offs = slices[i % n_var]
@@ -171,6 +360,7 @@ def run_batched(args) -> dict:
     batch_s = time.perf_counter() - t0
     timing = ssd.batch_read_timing(b, reset=True)
     # slice-close latency: scan drained first, then close call to lists in host memory
+    lat = []
     for i in range(args.latency_steps):
         pairs, offs = slices[i % n_var]
         ssd.batch_scan(b, pairs, offs, t)
@@ -179,33 +369,330 @@ def run_batched(args) -> dict:
         ssd.batch_close(b)
         lat.append((time.perf_counter() - c0) * 1e3)
         t += 1
+    same = True
     for (lists, status), ref in zip(batch_lists, plain_lists):
         same &= all(np.array_equal(x, y) for x, y in zip(lists, ref)) and not status.any()
     tuned = (ssd.batch_get_tuning(b, ssd.SSD_TUNE_SCAN_PASS_BYTES), ssd.batch_get_tuning(b, ssd.SSD_TUNE_SCAN_TILE_PAIRS))
+
+    # end to end: every step's pairs copied from pinned host memory on a copy
+    # stream, the next slice's copy overlapping this slice's scan and close
+    e2e = None
+    if args.e2e_steps:
+        host = [p.cpu().pin_memory() for p, _ in slices]
+        bufs = [torch.empty_like(slices[0][0]) for _ in range(2)]
+        cs = torch.cuda.Stream(dev)
+        ev = [torch.cuda.Event() for _ in range(2)]
+        cur = torch.cuda.current_stream(dev)
+
+        def copy(j):
+            with torch.cuda.stream(cs):
+                bufs[j % 2].copy_(host[j % n_var], non_blocking=True)
+                ev[j % 2].record(cs)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        copy(0)
+        n_e2e = 0
+        for j in range(args.e2e_steps):
+            if j + 1 < args.e2e_steps:
+                copy(j + 1)             # buffer (j+1)%2 was last read by step j-1, whose close has returned
+            cur.wait_event(ev[j % 2])
+            offs = slices[j % n_var][1]
+            ssd.batch_scan(b, bufs[j % 2], offs, t)
+            ssd.batch_close(b)
+            n_e2e += int(offs[-1])
+            t += 1
+        torch.cuda.synchronize()
+        e2e_s = time.perf_counter() - t0
+        e2e = {"packets_per_s": round(n_e2e / e2e_s, 1), **gbps(n_e2e / e2e_s),
+               "ms_per_step": round(e2e_s * 1e3 / args.e2e_steps, 3), "steps": args.e2e_steps,
+               "note": "pairs copied host->device from pinned memory each step (copy of the next slice "
+                       "overlapping this slice's scan and close); bound by the host link"}
+        del host, bufs
     state_bytes = b.state.numel()
     b.destroy()
+    del b
+    torch.cuda.empty_cache()
 
     total_pairs = sum(int(slices[i % n_var][1][-1]) for i in range(W, W + K))
     pps_b, pps_p = total_pairs / batch_s, total_pairs / plain_s
-    return {
-        "metric": "packets/s (and Gb/s @800B) scan + slice-close latency p50/p99, batched vs plain",
+
+    # roofline of the dominant kernel.  Algorithmic bytes (scan: 8 + r per
+    # pair, the pair read and one recorder written per row; hot detection:
+    # the whole state of every link it reads once per close)
+    per_slice = np.diff(slices[0][1]).astype(np.int64)
+    big = [l for l, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > (256 << 20) and per_slice[l] >= (1 << 20)]
+    tile_links = [l for l in range(len(cfgs)) if l not in big]
+    tile_alg = float(sum((8 + cfgs[l].r) * per_slice[l] for l in tile_links))
+    bin_alg = float(sum((8 + cfgs[l].r) * per_slice[l] for l in big))
+    cands = {}
+    if timing["scan_tiles"][1]:
+        ms = timing["scan_tiles"][0]
+        cands["k_scan_tiles"] = (ms / K, tile_alg, ms / timing["scan_tiles"][1], timing["scan_tiles"][1] // K, None)
+    if timing["scan"][1]:
+        ms = timing["scan"][0]
+        n_l = timing["scan"][1]
+        counted = timing["count_detect"][1] > 0
+        impl = float(sum((5 + (1 if counted else 0)) * cfgs[l].r * per_slice[l] for l in big)) / max(1, len(big))
+        cands["k_apply_counted" if counted else "k_apply"] = (ms / K, bin_alg / max(1, len(big)), ms / n_l, n_l // K,
+                                                             impl)
+    if timing["scan_bin"][1]:
+        ms = timing["scan_bin"][0]
+        n_l = timing["scan_bin"][1]
+        impl = float(sum((8 + 4 * cfgs[l].r) * per_slice[l] for l in big)) / max(1, len(big))
+        cands["k_bin"] = (ms / K, 8.0 * sum(per_slice[l] for l in big) / max(1, len(big)), ms / n_l, n_l // K, impl)
+    if timing["hot_detect"][1]:
+        ms = timing["hot_detect"][0]
+        read = float(sum(c.r * (1 << c.q) * c.eta for l, c in enumerate(cfgs) if l not in big or not timing["count_detect"][1]))
+        cands["k_hot_detect"] = (ms / K, read, ms / timing["hot_detect"][1], timing["hot_detect"][1] // K, None)
+    if timing["close_graph"][1]:
+        ms = timing["close_graph"][0]
+        cands["close_graph"] = (ms / K, 0.0, ms / timing["close_graph"][1], timing["close_graph"][1] // K, None)
+    roof = roofline(cands, "batched")
+
+    out = {
+        "metric": METRIC,
         "value": round(pps_b, 1), "unit": "packets/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(batch_s * 1e3 / K, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"batched: {len(cfgs)} links, {total_pairs // K} pairs/slice in total, "
-                               f"k 4..64, theta 512..8192, 2^12..2^16 x r estimators",
-                   "form": "batched", "links": len(cfgs), "state_bytes": state_bytes,
-                   "slice_variants": n_var},
-        "gbps_at_800B": round(pps_b * MEAN_PACKET_BYTES * 8 / 1e9, 2),
+                               f"k 4..64, theta 512..8192, 2^12..2^16 x r estimators, {state_bytes >> 20} MiB of state",
+                   "form": "batched", "links": len(cfgs), "pairs_per_slice": total_pairs // K,
+                   "state_bytes": state_bytes, "slice_variants": n_var},
+        **gbps(pps_b),
         "plain_packets_per_s": round(pps_p, 1),
         "batched_over_plain": round(pps_b / pps_p, 3),
         "identical_outputs": bool(same),
         "close_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                             "p99": round(float(np.percentile(lat, 99)), 4)},
+                             "p99": round(float(np.percentile(lat, 99)), 4)} if lat else None,
+        "plain_close_latency_ms": {"p50": round(float(np.percentile(plain_close, 50)), 4),
+                                   "p99": round(float(np.percentile(plain_close, 99)), 4),
+                                   "note": "sum of the 64 per-link close calls of a slice"},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1]} for k, v in timing.items() if v[1]},
         "autotuned": {"pass_bytes": tuned[0], "tile_pairs": tuned[1]},
+        "roofline": roof,
+        "end_to_end": e2e,
+        "ceilings": ceil,
     }
+    if not args.no_secondary:
+        log("secondary: the single core link")
+        out["core_link"] = run_core(args, secondary=True)
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a sample of the batched links")
+        out["cpu_baseline"] = cpu_baseline_batched(cfgs, traces, tables)
+    else:
+        out["cpu_baseline"] = None
+    return out
 
+
+# ----------------------------------------------------------------------------
+# single link (core link, or the tiny or paper-shaped workload)
+
+def run_core(args, secondary: bool = False) -> dict:
+    import torch
+    import paper_1803_11036_amd as ssd
+    import tracegen as tg
+
+    name = "core_link" if secondary else args.workload
+    cfg = tg.config(name)
+    if cfg.n_streams != 1:
+        raise SystemExit("this mode times a single-link workload")
+    trace = tg.Trace(cfg)
+    tables = tg.hash_tables(cfg.hash_seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W, K = (10, 20) if secondary else (args.warmup, args.steps)
+
+    n_gen = min(W + K, cfg.n_slices)
+    log(f"generating {n_gen} slices of {cfg.name}")
+    t0 = time.perf_counter()
+    slices = [trace.pairs_device(0, t, dev) for t in range(n_gen)]
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    cell_bits = 16 if cfg.k > 254 else 8
+    params = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
+                             max_tuples=1 << 22, max_results=1 << 20, cell_bits=cell_bits)
+    det = ssd.init_detector(params, tables, device=dev)
+    if not secondary:
+        if args.pass_mib is not None:
+            ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_PASS_BYTES, args.pass_mib << 20)
+        if args.scan_mode is not None:
+            ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_MODE,
+                           ssd.SSD_SCAN_BINNED if args.scan_mode == "binned" else ssd.SSD_SCAN_PASSES)
+        if args.bin_kib is not None:
+            ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_BIN_BYTES, args.bin_kib << 10)
+        if args.apply_segments is not None:
+            ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_APPLY_SEGMENTS, args.apply_segments)
+        if args.no_counted:
+            ssd.set_tuning(det, ssd.SSD_TUNE_COUNTED, 0)
+    ssd.set_tuning(det, ssd.SSD_TUNE_TIMING, 1)
+    state_bytes = det.state.numel()
+
+    t = 0
+    for i in range(W):
+        ssd.scan_slice(det, slices[i % n_gen], t)
+        ssd.close_slice(det)
+        t += 1
+    torch.cuda.synchronize()
+    ssd.read_timing(det, reset=True)
+
+    n_timed = 0
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    # pipelined: slice t+1's scan is enqueued before slice t's list is
+    # collected, so the host's collection overlaps device work
+    for i in range(K):
+        s = slices[(W + i) % n_gen]
+        ssd.scan_slice(det, s, t)
+        if i > 0:
+            ssd.close_end(det)
+        ssd.close_begin(det)
+        t += 1
+        n_timed += s.shape[0]
+    ssd.close_end(det)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - start
+    timing = ssd.read_timing(det, reset=True)
+    info = ssd.get_info(det)
+
+    # slice-close latency: scans drained first, then close_slice() call to list in host memory
+    lat = []
+    for i in range(args.latency_steps):
+        s = slices[(W + i) % n_gen]
+        ssd.scan_slice(det, s, t)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        ssd.close_slice(det)
+        lat.append((time.perf_counter() - c0) * 1e3)
+        t += 1
+    ssd.read_timing(det, reset=True)
+
+    # end to end: pairs from pinned host memory, the next slice's copy on a
+    # copy stream overlapping this slice's scan and close
+    e2e = None
+    if args.e2e_steps:
+        host = [s.cpu().pin_memory() for s in slices[:4]]
+        bufs = [torch.empty_like(slices[0]) for _ in range(2)]
+        cs = torch.cuda.Stream(dev)
+        cur = torch.cuda.current_stream(dev)
+        copied = [torch.cuda.Event() for _ in range(2)]
+        used = [torch.cuda.Event() for _ in range(2)]
+
+        def copy(j):
+            with torch.cuda.stream(cs):
+                cs.wait_event(used[j % 2])          # the scan that last read this buffer is done
+                bufs[j % 2].copy_(host[j % len(host)], non_blocking=True)
+                copied[j % 2].record(cs)
+
+        for e in used:
+            e.record(cur)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        copy(0)
+        n_e2e = 0
+        for j in range(args.e2e_steps):
+            if j + 1 < args.e2e_steps:
+                copy(j + 1)
+            cur.wait_event(copied[j % 2])
+            ssd.scan_slice(det, bufs[j % 2], t)
+            used[j % 2].record(cur)
+            if j > 0:
+                ssd.close_end(det)
+            ssd.close_begin(det)
+            t += 1
+            n_e2e += bufs[j % 2].shape[0]
+        ssd.close_end(det)
+        torch.cuda.synchronize()
+        e2e_s = time.perf_counter() - t0
+        e2e = {"packets_per_s": round(n_e2e / e2e_s, 1), **gbps(n_e2e / e2e_s),
+               "ms_per_step": round(e2e_s * 1e3 / args.e2e_steps, 4), "steps": args.e2e_steps,
+               "note": "pairs copied host->device from pinned memory each step, overlapping the previous "
+                       "slice's scan and close; bound by the host link"}
+        del host, bufs
+
+    if args.calibrate_copy_mib and not secondary:
+        a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    pps = n_timed / elapsed
+    avg_pairs = n_timed / K
+    kernels = {}
+    for kname, (ms, launches) in timing.items():
+        if launches:
+            kernels[kname] = {"ms_total": round(ms, 4), "launches": launches, "ms_per_launch": round(ms / launches, 5)}
+    binned = timing["scan_bin"][1] > 0
+    counted = timing["count_detect"][1] > 0
+    scan_ms = (timing["scan"][0] + timing["scan_bin"][0]) / K
+    # algorithmic bytes (per scan call: 8 + r per pair, the pair read and one
+    # recorder written per row; per close: the state read by hot detection)
+    cell_b = 2 if cell_bits == 16 else 1
+    alg_scan = avg_pairs * (8 + cfg.r * cell_b)
+    cands = {}
+    stores = ("k_apply_counted" if counted else "k_apply") if binned else "k_scan"
+    impl_scan = avg_pairs * ((6 if counted else 5) * cfg.r) if binned else None
+    n_scan = timing["scan"][1]
+    if n_scan:
+        cands[stores] = (timing["scan"][0] / K, alg_scan / max(1, n_scan // K), timing["scan"][0] / n_scan,
+                         n_scan // K, impl_scan / max(1, n_scan // K) if impl_scan else None)
+    if binned:
+        n_bin = timing["scan_bin"][1]
+        cands["k_bin"] = (timing["scan_bin"][0] / K, avg_pairs * 8.0 / max(1, n_bin // K),
+                          timing["scan_bin"][0] / n_bin, n_bin // K, avg_pairs * (8 + 4 * cfg.r) / max(1, n_bin // K))
+    if timing["hot_detect"][1]:
+        ms = timing["hot_detect"][0]
+        cands["k_hot_detect"] = (ms / K, float(state_bytes), ms / timing["hot_detect"][1], 1, None)
+    if counted:
+        ms = timing["count_detect"][0]
+        n_se = cfg.r << cfg.q
+        n_hot = sum(info["hot_counts"][:cfg.r])
+        impl = n_se * (4 * cfg.k + 8) + n_hot * (cfg.eta + cfg.eta // 8) + n_se / (255 - cfg.k) * cfg.eta
+        # R_k of every estimator from its counters instead of the state: the
+        # bytes it reads and writes (counters, hot and expiring estimators'
+        # cells, snapshots) stand for its work
+        cands["k_count"] = (ms / K, float(impl), ms / timing["count_detect"][1], 1, impl)
+    if timing["close_graph"][1]:
+        ms = timing["close_graph"][0]
+        cands["close_graph"] = (ms / K, 0.0, ms / timing["close_graph"][1], 1, None)
+    roof = roofline(cands, cfg.name)
+
+    out = {
+        "metric": METRIC,
+        "value": round(pps, 1), "unit": "packets/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(elapsed * 1e3 / K, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u16" if cell_bits == 16 else "u8", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: 1 link, {cfg.pairs_lo} pairs/slice, k={cfg.k}, "
+                               f"theta={cfg.theta}, {cfg.r}x2^{cfg.q} estimators x {cfg.eta} cells of {cell_bits} bits",
+                   "form": "plain", "pairs_per_slice": int(avg_pairs), "k": cfg.k, "theta": cfg.theta,
+                   "q": cfg.q, "r": cfg.r, "delta": cfg.delta, "eta": cfg.eta, "cell_bits": cell_bits,
+                   "state_bytes": state_bytes},
+        **gbps(pps),
+        "scan_packets_per_s": round(avg_pairs / (scan_ms * 1e-3), 1) if scan_ms > 0 else None,
+        "close_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                             "p99": round(float(np.percentile(lat, 99)), 4)} if lat else None,
+        "kernels": kernels,
+        "last_close": {"hot_counts": info["hot_counts"], "level_counts": info["level_counts"],
+                       "reported": info["reported"]},
+        "roofline": roof,
+        "end_to_end": e2e,
+    }
+    det.destroy()
+    del slices
+    torch.cuda.empty_cache()
+    if secondary:
+        for key in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            out.pop(key)
+        return out
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_link(cfg, trace, tables, args.cpu_slices)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# served and distributed forms
 
 def run_served(args) -> dict:
     """32 streams with Poisson batch arrivals (continuous batching): the
@@ -222,7 +709,6 @@ def run_served(args) -> dict:
     inputs = serve.build_inputs(ws, device=dev)
     torch.cuda.synchronize()
     budget = args.budget_gb << 30
-    out = {}
     reps = {}
     for mode in ("plain", "batched"):
         log(f"served {mode} at time scale {args.time_scale}")
@@ -231,7 +717,7 @@ def run_served(args) -> dict:
     same = all((b.results.get(key) is not None and pl.results.get(key) is not None and
                 np.array_equal(b.results[key], pl.results[key])) for key in pl.results)
     return {
-        "metric": "packets/s (and Gb/s @800B) scan + slice-close latency p50/p99, batched vs plain",
+        "metric": METRIC,
         "value": round(b.pairs_per_s, 1), "unit": "packets/s", "n_gpus": 1, "steps": len(b.latencies_ms),
         "warmup": 0, "ms_per_step": round(b.wall_s * 1e3 / max(1, len(b.latencies_ms)), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
@@ -239,14 +725,15 @@ def run_served(args) -> dict:
                                f"rate weight, slots 50-500 ms, time scale {args.time_scale}",
                    "form": "served", "streams": len(ws), "time_scale": args.time_scale,
                    "budget_bytes": budget, "pairs": b.pairs},
-        "gbps_at_800B": round(b.pairs_per_s * MEAN_PACKET_BYTES * 8 / 1e9, 2),
+        **gbps(b.pairs_per_s),
         "close_latency_ms": {"p50": round(b.latency(50), 4), "p99": round(b.latency(99), 4)},
         "plain": {"packets_per_s": round(pl.pairs_per_s, 1),
                   "close_latency_ms": {"p50": round(pl.latency(50), 4), "p99": round(pl.latency(99), 4)},
-                  "scan_calls": pl.scan_calls, "close_calls": pl.close_calls},
+                  "scan_calls": pl.scan_calls, "close_calls": pl.close_calls, "wall_s": round(pl.wall_s, 3)},
         "batched": {"scan_calls": b.scan_calls, "close_calls": b.close_calls,
                     "max_scan_members": b.max_scan_members, "max_close_members": b.max_close_members,
-                    "max_admitted": b.max_admitted},
+                    "max_admitted": b.max_admitted, "wall_s": round(b.wall_s, 3)},
+        "served_over_plain": round(b.pairs_per_s / pl.pairs_per_s, 3) if pl.pairs_per_s else None,
         "identical_outputs": bool(same),
         "note": "wall-clock rate of a time-driven run: it equals the offered load when the GPU keeps up",
     }
@@ -305,12 +792,18 @@ def run_distributed(args) -> dict:
     state = glob.state.numel()
     merge_ms = tg_["merge"][0] / max(1, tg_["merge"][1])
     merge_bytes = (cfg.n_streams + 1) * state          # every router state read, the global written
-    achieved = merge_bytes / (merge_ms * 1e-3) / 1e9 if merge_ms > 0 else 0.0
+    cands = {"k_merge": (tg_["merge"][0] / K, float(merge_bytes), merge_ms, 1, None),
+             "router_scans": (scan_ms / K, float(sum((8 + cfg.r) * int(p.shape[0]) for p in slices[0])),
+                              scan_ms / K, cfg.n_streams, None)}
+    if tg_["hot_detect"][1]:
+        cands["k_hot_detect"] = (tg_["hot_detect"][0] / K, float(state), tg_["hot_detect"][0] / tg_["hot_detect"][1],
+                                 1, None)
+    roof = roofline(cands, cfg.name)
     for d in routers + [glob]:
         d.destroy()
     pps = n_timed / elapsed
     return {
-        "metric": "packets/s (and Gb/s @800B) scan + slice-close latency p50/p99, batched vs plain",
+        "metric": METRIC,
         "value": round(pps, 1), "unit": "packets/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(elapsed * 1e3 / K, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
@@ -318,14 +811,12 @@ def run_distributed(args) -> dict:
                                f"k={cfg.k}, theta={cfg.theta}, {cfg.r}x2^{cfg.q} estimators x {cfg.eta} cells each",
                    "form": "distributed", "routers": cfg.n_streams, "state_bytes_per_router": state,
                    "slice_variants": n_var},
-        "gbps_at_800B": round(pps * MEAN_PACKET_BYTES * 8 / 1e9, 2),
+        **gbps(pps),
         "reported_last_slice": reported,
         "kernels": {"router_scans": {"ms_per_step": round(scan_ms / K, 4)},
                     "merge": {"ms_per_launch": round(merge_ms, 5), "launches": tg_["merge"][1]},
                     "global_hot_detect": {"ms_per_launch": round(tg_["hot_detect"][0] / max(1, tg_["hot_detect"][1]), 5)}},
-        "roofline": {"bound": "hbm", "kernel": "k_merge", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "algorithmic_bytes_per_launch": float(merge_bytes), "ms_per_launch": round(merge_ms, 5)},
+        "roofline": roof,
     }
 
 
@@ -334,10 +825,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="core_link")
+    ap.add_argument("--workload", default="batched",
+                    help="batched (default) | core_link | tiny | paper | distributed | served | ceilings")
     ap.add_argument("--latency-steps", type=int, default=10)
-    ap.add_argument("--cpu-slices", type=int, default=4)
+    ap.add_argument("--e2e-steps", type=int, default=12, help="steps of the pinned-host end-to-end run (0 = off)")
+    ap.add_argument("--cpu-slices", type=int, default=4, help="single-link workloads: oracle slices timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="batched: skip the core-link secondary run")
+    ap.add_argument("--no-ceilings", action="store_true", help="batched: skip the memory-ceiling probes")
     ap.add_argument("--pass-mib", type=int, default=None, help="scan pass window (MiB of state; default: library)")
     ap.add_argument("--scan-mode", choices=["passes", "binned"], default=None,
                     help="single-detector scan: pass windows or bin-sorted stores (default: library)")
@@ -349,11 +844,12 @@ def main() -> int:
                     help="also run one plain device copy of this size (PMC calibration)")
     ap.add_argument("--links", type=int, default=64, help="batched workload: number of links")
     ap.add_argument("--variants", type=int, default=2, help="batched workload: distinct slice contents cycled")
-    ap.add_argument("--autotune", type=int, default=1, help="batched workload: autotune during warmup")
+    ap.add_argument("--autotune", type=int, default=1, help="batched workload: autotune before the warmup")
     ap.add_argument("--streams", type=int, default=32, help="served workload: streams")
     ap.add_argument("--slots", type=int, default=6, help="served workload: slots per stream")
     ap.add_argument("--time-scale", type=float, default=0.25, help="served workload: stream time per wall second")
     ap.add_argument("--budget-gb", type=int, default=64, help="served workload: admission memory budget")
+    ap.add_argument("--ceiling-mib", default="24,1536,5120", help="ceilings workload: working-set sizes in MiB")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -361,193 +857,22 @@ def main() -> int:
         print(json.dumps({"error": "this detector runs on one GPU; multi-GPU sharding is a design "
                                    "note only, run with --gpus 1"}), flush=True)
         return 2
-
     if args.workload == "batched":
-        print(json.dumps(run_batched(args)), flush=True)
-        return 0
-    if args.workload == "served":
-        print(json.dumps(run_served(args)), flush=True)
-        return 0
-    if args.workload == "distributed":
-        print(json.dumps(run_distributed(args)), flush=True)
-        return 0
-
-    import torch
-    import paper_1803_11036_amd as ssd
-    import tracegen as tg
-
-    cfg = tg.config(args.workload)
-    if cfg.n_streams != 1:
-        raise SystemExit("bench.py times a single-link workload")
-    trace = tg.Trace(cfg)
-    tables = tg.hash_tables(cfg.hash_seed)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    n_gen = args.warmup + args.steps
-    log(f"generating {n_gen} slices of {cfg.name}")
-    t0 = time.perf_counter()
-    slices = []
-    for t in range(n_gen):
-        p = trace.pairs(0, t % cfg.n_slices)
-        slices.append(torch.from_numpy(p.view(np.int32)).to(dev))
-    torch.cuda.synchronize()
-    log(f"generated in {time.perf_counter() - t0:.1f} s")
-    pairs_per_slice = [int(s.shape[0]) for s in slices]
-
-    params = ssd.make_params(q=cfg.q, r=cfg.r, delta=cfg.delta, eta=cfg.eta, k=cfg.k, theta=cfg.theta,
-                             max_tuples=1 << 22, max_results=1 << 20)
-    det = ssd.init_detector(params, tables, device=dev)
-    if args.pass_mib is not None:
-        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_PASS_BYTES, args.pass_mib << 20)
-    if args.scan_mode is not None:
-        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_MODE,
-                       ssd.SSD_SCAN_BINNED if args.scan_mode == "binned" else ssd.SSD_SCAN_PASSES)
-    if args.bin_kib is not None:
-        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_BIN_BYTES, args.bin_kib << 10)
-    if args.apply_segments is not None:
-        ssd.set_tuning(det, ssd.SSD_TUNE_SCAN_APPLY_SEGMENTS, args.apply_segments)
-    if args.no_counted:
-        ssd.set_tuning(det, ssd.SSD_TUNE_COUNTED, 0)
-    ssd.set_tuning(det, ssd.SSD_TUNE_TIMING, 1)
-    state_bytes = det.state.numel()
-
-    t = 0
-    log("warmup")
-    for i in range(args.warmup):
-        ssd.scan_slice(det, slices[i], t)
-        ssd.close_slice(det)
-        t += 1
-    torch.cuda.synchronize()
-    ssd.read_timing(det, reset=True)
-
-    log("timed steps")
-    n_timed = 0
-    torch.cuda.synchronize()
-    start = time.perf_counter()
-    # pipelined: slice t+1's scan is enqueued before slice t's list is
-    # collected, so the host's collection overlaps device work
-    for i in range(args.steps):
-        s = slices[args.warmup + i]
-        ssd.scan_slice(det, s, t)
-        if i > 0:
-            res = ssd.close_end(det)
-        ssd.close_begin(det)
-        t += 1
-        n_timed += s.shape[0]
-    res = ssd.close_end(det)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - start
-    timing = ssd.read_timing(det, reset=True)
-    info = ssd.get_info(det)
-
-    # slice-close latency: scans drained first, then close_slice() call to list in host memory
-    lat = []
-    for i in range(args.latency_steps):
-        s = slices[args.warmup + i % args.steps]
-        ssd.scan_slice(det, s, t)
-        torch.cuda.synchronize()
-        c0 = time.perf_counter()
-        ssd.close_slice(det)
-        lat.append((time.perf_counter() - c0) * 1e3)
-        t += 1
-    ssd.read_timing(det, reset=True)
-
-    if args.calibrate_copy_mib:
-        a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    pps = n_timed / elapsed
-    ms_step = elapsed * 1e3 / args.steps
-    # per-kernel averages from HIP events over the timed region
-    kernels = {}
-    for name, (ms, launches) in timing.items():
-        if launches:
-            kernels[name] = {"ms_total": round(ms, 4), "launches": launches,
-                             "ms_per_launch": round(ms / launches, 5)}
-    avg_pairs = n_timed / args.steps
-    binned = timing["scan_bin"][1] > 0
-    # one scan call per step (all its launches), one hot detection launch per close
-    scan_ms = (timing["scan"][0] + timing["scan_bin"][0]) / args.steps
-    det_ms = timing["hot_detect"][0] / max(1, timing["hot_detect"][1])
-    # algorithmic bytes per scan call (the unit of the scan kernels):
-    #   pass scan k_scan: 8 B pair read + r cell bytes written per pair;
-    #   binned scan k_bin: 8 B pair read + r 4-byte offsets written per pair,
-    #               k_apply: r 4-byte offsets read + r cell bytes written per pair,
-    #               k_apply_counted: the same + r cell bytes read per pair;
-    # hot detection reads the whole state once per close; counted detection
-    # (k_count) reads k 4-byte counters and writes R_k and the next slot's
-    # counter per estimator, and reads the cells of the hot estimators
-    # (writing their 2-bit-per-16-cell snapshots) and of this slot's expiry
-    # phase (1 / (255 - k) of the estimators)
-    counted = timing["count_detect"][1] > 0
-    stores = ("k_apply_counted" if counted else "k_apply") if binned else "k_scan"
-    per_pair = (6 * cfg.r if counted else 5 * cfg.r) if binned else 8 + cfg.r
-    cand = {stores: (timing["scan"][0], avg_pairs * per_pair, timing["scan"][0] / args.steps)}
-    if timing["hot_detect"][1]:
-        cand["k_hot_detect"] = (timing["hot_detect"][0], float(state_bytes), det_ms)
-    if counted:
-        n_se = cfg.r << cfg.q
-        n_hot = sum(info["hot_counts"][:cfg.r])
-        count_bytes = n_se * (4 * cfg.k + 8) + n_hot * (cfg.eta + cfg.eta // 8) + n_se / (255 - cfg.k) * cfg.eta
-        cand["k_count"] = (timing["count_detect"][0], float(count_bytes),
-                           timing["count_detect"][0] / timing["count_detect"][1])
-    if binned:
-        cand["k_bin"] = (timing["scan_bin"][0], avg_pairs * (8 + 4 * cfg.r), timing["scan_bin"][0] / args.steps)
-    dom = max(cand, key=lambda k: cand[k][0])
-    _, bytes_per_launch, ms_per_launch = cand[dom]
-    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
-    launches_per_unit = {"k_hot_detect": 1, "k_count": 1, "k_bin": timing["scan_bin"][1] // args.steps}.get(
-        dom, timing["scan"][1] // args.steps)
-    traffic = load_traffic(dom, cfg.name)
-    if traffic is not None:
-        traffic *= launches_per_unit          # counters are per launch; the scan unit is one call
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": traffic, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "ms_per_launch": round(ms_per_launch, 5),
-                "launches_per_step": launches_per_unit,
-                "traffic_gbs": round(traffic / (ms_per_launch * 1e-3) / 1e9, 1) if traffic else None}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on {args.cpu_slices} slices")
-        cpu = cpu_baseline(cfg, trace, tables, args.cpu_slices)
-
-    out = {
-        "metric": "packets/s (and Gb/s @800B) scan + slice-close latency p50/p99, batched vs plain",
-        "value": round(pps, 1),
-        "unit": "packets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: 1 link, {cfg.pairs_lo} pairs/slice, k={cfg.k}, "
-                               f"theta={cfg.theta}, {cfg.r}x2^{cfg.q} estimators x {cfg.eta} cells",
-                   "form": "plain", "pairs_per_slice": int(avg_pairs), "k": cfg.k, "theta": cfg.theta,
-                   "q": cfg.q, "r": cfg.r, "delta": cfg.delta, "eta": cfg.eta,
-                   "state_bytes": state_bytes},
-        "gbps_at_800B": round(pps * MEAN_PACKET_BYTES * 8 / 1e9, 2),
-        "scan_packets_per_s": round(avg_pairs / (scan_ms * 1e-3), 1) if scan_ms > 0 else None,
-        "close_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                             "p99": round(float(np.percentile(lat, 99)), 4)} if lat else None,
-        "kernels": kernels,
-        "last_close": {"hot_counts": info["hot_counts"], "level_counts": info["level_counts"],
-                       "reported": info["reported"]},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
+        out = run_batched(args)
+    elif args.workload == "served":
+        out = run_served(args)
+    elif args.workload == "distributed":
+        out = run_distributed(args)
+    elif args.workload == "ceilings":
+        import torch
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        out = {"workload": "ceilings", "ceilings": ceilings(dev, [int(x) for x in args.ceiling_mib.split(",")]),
+               "note": "stream read GB/s; byte scatter G stores/s (uniform over the buffer, and XCD-local: "
+                       "workgroups of one XCD store into 2 MiB regions its L2 holds, every region in turn)"}
+    else:
+        out = run_core(args)
     print(json.dumps(out), flush=True)
-    det.destroy()
     return 0
 
 
