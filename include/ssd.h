@@ -141,6 +141,26 @@ int ssd_init_detector(const ssd_params *p, const uint32_t *tables_host,
  * not depend on how pairs are split over calls or ordered.  n = 0 is a no-op. */
 int ssd_scan_slice(ssd_detector *d, const uint32_t *pairs_dev, uint64_t n, uint64_t slice_id);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * scan as ssd_scan_slice (same arguments, errors and resulting state; the
+ * scan mode is chosen the same way), but the staging of the binned scan (the
+ * binning's offset segments and bin-major table) is taken from a static
+ * device array of SSD_NOALLOC_SCRATCH_BYTES (64 MiB) instead of the
+ * detector's scratch.  The library holds one such array on every device it
+ * runs on, until the process ends.  The call allocates nothing (no
+ * hipMalloc, no host or pinned allocation, no event) and records no phase
+ * timing.  A binned call whose staging exceeds the array fails with
+ * SSD_E_NOMEM before any work is enqueued (about 2.8M pairs at r = 6 with
+ * the default bins): split the slice over smaller calls.  Every call on one
+ * device shares that device's array, which keeps the last call's contents
+ * (nothing in it needs to start at zero: each call writes all the staging
+ * it reads).  Calls that overlap on one device race: calls of detectors on
+ * different streams must be ordered by the caller (events or
+ * synchronisation). */
+#define SSD_NOALLOC_SCRATCH_BYTES 67108864ull   /* 64 MiB */
+int ssd_scan_slice_noalloc(ssd_detector *d, const uint32_t *pairs_dev, uint64_t n, uint64_t slice_id);
+
 /* Close the open slice t.  Without flags: estimate every sliding estimator
  * over slots max(0, t-k+1)..t, regain the candidate hosts (Sec. 4.2) and
  * report SSP(max(0, t-k+1), k) sorted by ip, one entry per ip with its largest

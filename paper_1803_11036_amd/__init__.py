@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "SSD_VERIFY_REHASH", "SSD_ADVANCE_ONLY", "SSDError", "Params", "make_params",
-    "query_sizes", "Detector", "init_detector", "scan_slice", "close_slice", "close_begin", "close_end",
+    "query_sizes", "Detector", "init_detector", "scan_slice", "scan_slice_noalloc", "close_slice", "close_begin", "close_end",
     "get_results", "merge_router_state", "read_canonical_state", "read_rk",
     "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
     "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
@@ -41,6 +41,7 @@ SSD_ABI_VERSION = 1
 SSD_VERIFY_REHASH = 0x1
 SSD_ADVANCE_ONLY = 0x1
 SSD_E_TRUNC = -6
+SSD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 RESULT_DTYPE = np.dtype([("ip", "<u4"), ("rk", "<u4"), ("est", "<f8")])
 
@@ -90,6 +91,7 @@ def _lib():
         L.ssd_init_detector.argtypes = [C.POINTER(Params), C.POINTER(C.c_uint32), vp, u64, vp, u64, vp,
                                         C.POINTER(vp)]
         L.ssd_scan_slice.argtypes = [vp, vp, u64, u64]
+        L.ssd_scan_slice_noalloc.argtypes = [vp, vp, u64, u64]
         L.ssd_close_slice.argtypes = [vp, u32, vp, u64, u64p]
         L.ssd_get_results.argtypes = [vp, vp, u64, u64p]
         L.ssd_close_begin.argtypes = [vp]
@@ -126,7 +128,7 @@ def _lib():
         L.ssd_strerror.restype = C.c_char_p
         L.ssd_last_error.argtypes = []
         L.ssd_last_error.restype = C.c_char_p
-        for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice",
+        for name in ("ssd_query_sizes", "ssd_init_detector", "ssd_scan_slice", "ssd_scan_slice_noalloc",
                      "ssd_close_slice",
                      "ssd_get_results", "ssd_merge_router_state", "ssd_read_canonical_state",
                      "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
@@ -217,6 +219,17 @@ def scan_slice(det: Detector, pairs: torch.Tensor, slice_id: int) -> None:
         raise ValueError("pairs must be a contiguous (n, 2) 32-bit tensor on the detector's device")
     n = pairs.shape[0] if pairs.dim() == 2 else 0
     _check(_lib().ssd_scan_slice(det.handle, pairs.data_ptr() if n else None, n, slice_id), "scan_slice")
+
+
+def scan_slice_noalloc(det: Detector, pairs: torch.Tensor, slice_id: int) -> None:
+    """As scan_slice, with the binned scan's staging in the library's static
+    device array instead of the detector's scratch (no allocation)."""
+    if pairs.numel() and (pairs.device != det.state.device or pairs.element_size() != 4
+                          or not pairs.is_contiguous() or pairs.dim() != 2 or pairs.shape[1] != 2):
+        raise ValueError("pairs must be a contiguous (n, 2) 32-bit tensor on the detector's device")
+    n = pairs.shape[0] if pairs.dim() == 2 else 0
+    _check(_lib().ssd_scan_slice_noalloc(det.handle, pairs.data_ptr() if n else None, n, slice_id),
+           "scan_slice_noalloc")
 
 
 def _results(det: Detector, fn, *args) -> np.ndarray:

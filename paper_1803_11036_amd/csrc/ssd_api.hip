@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,40 @@
 
 using namespace ssd;
 
+// Staging of ssd_scan_slice_noalloc: a static device array that every device
+// the library runs on holds until the process ends.  Host code never uses
+// its name as an address: the per-device address comes from
+// hipGetSymbolAddress, taken once per device at ssd_init_detector.
+static __device__ __align__(256) uint8_t scratch[SSD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+uint8_t* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Look up (once per device, with that device current) the address of this
+// device's copy of the static array.
+hipError_t noalloc_setup(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return err;
+    g_noalloc_ptr[device] = static_cast<uint8_t*>(ptr);
+    return hipSuccess;
+}
+
+uint8_t* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return g_noalloc_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -1242,6 +1277,14 @@ int ssd_init_detector(const ssd_params* p, const uint32_t* tables_host, void* st
         delete d;
         return rc;
     }
+    // the address of this device's static scratch (ssd_scan_slice_noalloc)
+    const hipError_t err = noalloc_setup(d->e.device);
+    if (err != hipSuccess) {
+        rc = dev_fail(&d->e, err, "hipGetSymbolAddress(scratch)");
+        engine_release(&d->e);
+        delete d;
+        return rc;
+    }
     d->e.use_graph = true;
     *out = d;
     return SSD_OK;
@@ -1320,6 +1363,39 @@ int ssd_scan_slice(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint6
         return enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes, d->apply_segments,
                                    engine_bins(e));
     return enqueue_pass_scan(d, reinterpret_cast<const uint2*>(pairs_dev), n);
+}
+
+int ssd_scan_slice_noalloc(ssd_detector* d, const uint32_t* pairs_dev, uint64_t n, uint64_t slice_id)
+{
+    if (!d) return fail(SSD_E_PARAM, "detector is NULL");
+    Engine* e = &d->e;
+    int rc = scan_checks(d, pairs_dev, n, slice_id);
+    if (rc || n == 0) return rc;
+    // no phase timing: its events would be created on first use
+    const bool timing = e->timing;
+    e->timing = false;
+    if (scans_binned(d)) {
+        // the binning's staging in this device's static array, looked up at
+        // ssd_init_detector; one step for the whole call
+        uint8_t* base = noalloc_scratch(e->device);
+        const BinnedCall c = binned_call(e, 0, n, d->bin_bytes);
+        const uint64_t blocks = (n + c.bp.pb - 1) / c.bp.pb;
+        const uint64_t items = align_up(blocks * c.seg * 4), table = (uint64_t)(c.bp.n_bins + 1) * blocks * 4;
+        if (!base) rc = fail(SSD_E_STATE, "no static scratch for device %d", e->device);
+        else if (items + table > SSD_NOALLOC_SCRATCH_BYTES)
+            rc = fail(SSD_E_NOMEM, "a binned scan of %llu pairs needs %llu bytes of staging, the static scratch holds "
+                      "%llu: split the slice over smaller calls", (unsigned long long)n,
+                      (unsigned long long)(items + table), (unsigned long long)SSD_NOALLOC_SCRATCH_BYTES);
+        else
+            rc = enqueue_binned_scan(e, 0, reinterpret_cast<const uint2*>(pairs_dev), n, d->bin_bytes,
+                                     d->apply_segments,
+                                     {reinterpret_cast<uint32_t*>(base), reinterpret_cast<uint32_t*>(base + items),
+                                      blocks * c.seg, (uint64_t)(c.bp.n_bins + 1) * blocks});
+    } else {
+        rc = enqueue_pass_scan(d, reinterpret_cast<const uint2*>(pairs_dev), n);     // no staging
+    }
+    e->timing = timing;
+    return rc;
 }
 
 int ssd_close_begin(ssd_detector* d)
