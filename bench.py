@@ -131,6 +131,18 @@ def roofline(cands: dict, workload: str) -> dict:
                        for k, v in cands.items() if k != dom}}
 
 
+def calibration_copy(dev, mib: int) -> None:
+    """One plain device copy of known size: the reference against which the
+    HBM counters of a profiled run are scaled."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 # ----------------------------------------------------------------------------
 # memory ceilings (probes in the library)
 
@@ -413,6 +425,8 @@ def run_batched(args) -> dict:
     b.destroy()
     del b
     torch.cuda.empty_cache()
+    if args.calibrate_copy_mib:
+        calibration_copy(dev, args.calibrate_copy_mib)
 
     total_pairs = sum(int(slices[i % n_var][1][-1]) for i in range(W, W + K))
     pps_b, pps_p = total_pairs / batch_s, total_pairs / plain_s
@@ -612,12 +626,7 @@ def run_core(args, secondary: bool = False) -> dict:
         del host, bufs
 
     if args.calibrate_copy_mib and not secondary:
-        a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calibration_copy(dev, args.calibrate_copy_mib)
 
     pps = n_timed / elapsed
     avg_pairs = n_timed / K
