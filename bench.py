@@ -385,6 +385,7 @@ def run_batched(args) -> dict:
     for (lists, status), ref in zip(batch_lists, plain_lists):
         same &= all(np.array_equal(x, y) for x, y in zip(lists, ref)) and not status.any()
     tuned = (ssd.batch_get_tuning(b, ssd.SSD_TUNE_SCAN_PASS_BYTES), ssd.batch_get_tuning(b, ssd.SSD_TUNE_SCAN_TILE_PAIRS))
+    link_info = [ssd.batch_get_info(b, l) for l in range(len(cfgs))]
 
     # end to end: every step's pairs copied from pinned host memory on a copy
     # stream, the next slice's copy overlapping this slice's scan and close
@@ -435,30 +436,36 @@ def run_batched(args) -> dict:
     # pair, the pair read and one recorder written per row; hot detection:
     # the whole state of every link it reads once per close)
     per_slice = np.diff(slices[0][1]).astype(np.int64)
-    big = [l for l, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > (256 << 20) and per_slice[l] >= (1 << 20)]
-    tile_links = [l for l in range(len(cfgs)) if l not in big]
+    binned = [l for l in range(len(cfgs)) if per_slice[l] >= (1 << 16)]      # the library's batch rule
+    tile_links = [l for l in range(len(cfgs)) if l not in binned]
     tile_alg = float(sum((8 + cfgs[l].r) * per_slice[l] for l in tile_links))
-    bin_alg = float(sum((8 + cfgs[l].r) * per_slice[l] for l in big))
+    bin_alg = float(sum((8 + cfgs[l].r) * per_slice[l] for l in binned))
+    counted_links = [l for l in range(len(cfgs)) if link_info[l]["counted"]]
     cands = {}
     if timing["scan_tiles"][1]:
         ms = timing["scan_tiles"][0]
         cands["k_scan_tiles"] = (ms / K, tile_alg, ms / timing["scan_tiles"][1], timing["scan_tiles"][1] // K, None)
     if timing["scan"][1]:
-        ms = timing["scan"][0]
-        n_l = timing["scan"][1]
-        counted = timing["count_detect"][1] > 0
-        impl = float(sum((5 + (1 if counted else 0)) * cfgs[l].r * per_slice[l] for l in big)) / max(1, len(big))
-        cands["k_apply_counted" if counted else "k_apply"] = (ms / K, bin_alg / max(1, len(big)), ms / n_l, n_l // K,
-                                                             impl)
+        # k_apply_counted_multi / k_apply_multi: the binned links' stores,
+        # one launch per group of links and kind
+        ms, n_l = timing["scan"]
+        per = max(1, n_l // K)
+        impl = float(sum((6 if l in counted_links else 5) * cfgs[l].r * per_slice[l] for l in binned))
+        cands["binned_stores"] = (ms / K, bin_alg / per, ms / n_l, per, impl / per)
     if timing["scan_bin"][1]:
-        ms = timing["scan_bin"][0]
-        n_l = timing["scan_bin"][1]
-        impl = float(sum((8 + 4 * cfgs[l].r) * per_slice[l] for l in big)) / max(1, len(big))
-        cands["k_bin"] = (ms / K, 8.0 * sum(per_slice[l] for l in big) / max(1, len(big)), ms / n_l, n_l // K, impl)
+        ms, n_l = timing["scan_bin"]
+        per = max(1, n_l // K)
+        impl = float(sum((8 + 4 * cfgs[l].r) * per_slice[l] for l in binned))
+        cands["k_bin_multi"] = (ms / K, 8.0 * sum(per_slice[l] for l in binned) / per, ms / n_l, per, impl / per)
     if timing["hot_detect"][1]:
         ms = timing["hot_detect"][0]
-        read = float(sum(c.r * (1 << c.q) * c.eta for l, c in enumerate(cfgs) if l not in big or not timing["count_detect"][1]))
+        read = float(sum(c.r * (1 << c.q) * c.eta for l, c in enumerate(cfgs) if l not in counted_links))
         cands["k_hot_detect"] = (ms / K, read, ms / timing["hot_detect"][1], timing["hot_detect"][1] // K, None)
+    if timing["count_detect"][1]:
+        ms, n_l = timing["count_detect"]
+        per = max(1, n_l // K)
+        cnt = float(sum((cfgs[l].r << cfgs[l].q) * (4 * cfgs[l].k + 8) for l in counted_links))
+        cands["k_count_multi"] = (ms / K, cnt / per, ms / n_l, per, cnt / per)
     if timing["close_graph"][1]:
         ms = timing["close_graph"][0]
         cands["close_graph"] = (ms / K, 0.0, ms / timing["close_graph"][1], timing["close_graph"][1] // K, None)
@@ -484,6 +491,7 @@ def run_batched(args) -> dict:
                                    "note": "sum of the 64 per-link close calls of a slice"},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1]} for k, v in timing.items() if v[1]},
         "autotuned": {"pass_bytes": tuned[0], "tile_pairs": tuned[1]},
+        "links_binned": len(binned), "links_counted": len(counted_links),
         "roofline": roof,
         "end_to_end": e2e,
         "ceilings": ceil,

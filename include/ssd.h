@@ -112,6 +112,10 @@ typedef struct {
     uint32_t hot_counts[16]; /* |HSE(i)| at the last close                     */
     uint64_t accepted;       /* accepted tuples at the last close              */
     uint64_t reported;       /* hosts in the last result list                  */
+    uint32_t counted;        /* R_k of the last close: 0 read from the state,
+                                1 from the per-slot counters, 2 from counters
+                                rebuilt from the state first                  */
+    uint32_t reserved;
 } ssd_info;
 
 /* Sizes the caller must allocate on the device for params p: the estimator
@@ -240,9 +244,10 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       (SSD_TUNE_SCAN_BIN_BYTES, a power of two, default 2 MiB), then each
  *       bin's stores are made by workgroups of one XCD, inside its L2;
  *       SSD_SCAN_AUTO (default) = binned for states above 256 MiB, else passes
- *       (batches: the links above 256 MiB with at least 2^20 pairs in the call
- *       are scanned binned, the others in the tile scan; batches take
- *       SSD_SCAN_PASSES or SSD_SCAN_AUTO). */
+ *       (batches: every link with at least 2^16 pairs in the call is scanned
+ *       binned, all such links together -- one binning launch per binning
+ *       variant and one store launch per kind, 2 MiB bins -- the others in
+ *       the tile scan; batches take SSD_SCAN_PASSES or SSD_SCAN_AUTO). */
 #define SSD_TUNE_SCAN_MODE 7u
 #define SSD_TUNE_SCAN_BIN_BYTES 8u
 #define SSD_TUNE_SCAN_APPLY_SEGMENTS 9u   /* binned: binning segments per store workgroup (default 2) */
@@ -265,11 +270,10 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       merge into the detector, an advance-only close, a pass scan or a
  *       group call leaves the counters stale: the close reads the state,
  *       or, when every binned call of the slice was large, rebuilds the
- *       counters from it.  Batches:
- *       the same for every link above 256 MiB that can count (reading 1 if
- *       any link counts); a link scanned by the tile scan in a slice (fewer
- *       than 2^20 pairs in the call, or SSD_SCAN_PASSES) leaves its counters
- *       stale likewise. */
+ *       counters from it.  Batches: the same for every link that can count
+ *       (reading 1 if any link counts); a link scanned by the tile scan in a
+ *       slice (fewer than 2^16 pairs in the call, or SSD_SCAN_PASSES) leaves
+ *       its counters stale likewise. */
 #define SSD_TUNE_COUNTED 10u
 #define SSD_TUNE_COUNTED_MIN_ITEMS 11u   /* counted scans: offsets per bin a call needs (default 2048) */
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
@@ -338,8 +342,10 @@ int ssd_batch_get_results(ssd_batch *b, ssd_super_point *out_host, uint64_t cap,
 int ssd_batch_set_tuning(ssd_batch *b, uint32_t knob, uint64_t value);
 int ssd_batch_get_tuning(ssd_batch *b, uint32_t knob, uint64_t *value);
 int ssd_batch_read_timing(ssd_batch *b, double *ms_out, uint64_t *launches_out, int reset);
-/* Inspection of link `link` at the last close, as ssd_read_rk and
- * ssd_read_hot for a single detector (R_k per estimator; hot lists). */
+/* Inspection of link `link` at the last close, as ssd_get_info, ssd_read_rk
+ * and ssd_read_hot for a single detector (facts, R_k per estimator, hot
+ * lists). */
+int ssd_batch_get_info(ssd_batch *b, uint32_t link, ssd_info *out);
 int ssd_batch_read_rk(ssd_batch *b, uint32_t link, uint32_t *out_host, uint64_t n);
 int ssd_batch_read_hot(ssd_batch *b, uint32_t link, uint32_t *counts_host, uint32_t *lists_host, uint64_t cap);
 void ssd_batch_destroy(ssd_batch *b);
@@ -376,6 +382,19 @@ int ssd_group_scan(ssd_group *g, ssd_detector *const *members, uint32_t n, const
  * (ssd_get_results). */
 int ssd_group_close(ssd_group *g, ssd_detector *const *members, uint32_t n, ssd_super_point *out_host,
                     uint64_t cap, uint64_t *counts_host, int *status_host);
+
+/* The same close in two halves (as ssd_close_begin / ssd_close_end), so that
+ * a serving loop keeps admitting and scanning while a close runs:
+ * ssd_group_close_begin enqueues the close of every member's open slice on
+ * the group's stream and opens each member's next slice at once, without
+ * waiting; ssd_group_close_end waits for that close only and returns the
+ * lists exactly as ssd_group_close would.  At most one close per group may
+ * be pending (SSD_E_ORDER).  While it is, its members may scan their next
+ * slice (group or own scans) but not close, merge or be inspected
+ * (SSD_E_ORDER), and must not be destroyed. */
+int ssd_group_close_begin(ssd_group *g, ssd_detector *const *members, uint32_t n);
+int ssd_group_close_end(ssd_group *g, ssd_super_point *out_host, uint64_t cap, uint64_t *counts_host,
+                        int *status_host);
 void ssd_group_destroy(ssd_group *g);
 
 #ifdef __cplusplus

@@ -29,8 +29,10 @@ __all__ = [
     "SSD_TUNE_SCAN_MODE", "SSD_TUNE_SCAN_BIN_BYTES", "SSD_TUNE_SCAN_APPLY_SEGMENTS", "SSD_SCAN_PASSES",
     "SSD_SCAN_BINNED", "SSD_SCAN_AUTO", "SSD_TUNE_COUNTED", "SSD_TUNE_COUNTED_MIN_ITEMS",
     "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
-    "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_read_rk", "batch_read_hot", "batch_destroy",
-    "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_destroy",
+    "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_get_info", "batch_read_rk",
+    "batch_read_hot", "batch_destroy",
+    "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_close_begin",
+    "group_close_end", "group_destroy",
     "library_path", "RESULT_DTYPE",
 ]
 
@@ -60,7 +62,8 @@ class _SuperPoint(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("open_slice", C.c_uint64), ("hot_threshold", C.c_uint32), ("r", C.c_uint32),
                 ("state_bytes", C.c_uint64), ("level_counts", C.c_uint64 * 16),
-                ("hot_counts", C.c_uint32 * 16), ("accepted", C.c_uint64), ("reported", C.c_uint64)]
+                ("hot_counts", C.c_uint32 * 16), ("accepted", C.c_uint64), ("reported", C.c_uint64),
+                ("counted", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 assert C.sizeof(_SuperPoint) == RESULT_DTYPE.itemsize == 16
@@ -112,6 +115,7 @@ def _lib():
         L.ssd_batch_set_tuning.argtypes = [vp, u32, u64]
         L.ssd_batch_get_tuning.argtypes = [vp, u32, u64p]
         L.ssd_batch_read_timing.argtypes = [vp, vp, vp, C.c_int]
+        L.ssd_batch_get_info.argtypes = [vp, u32, C.POINTER(_Info)]
         L.ssd_batch_read_rk.argtypes = [vp, u32, vp, u64]
         L.ssd_batch_read_hot.argtypes = [vp, u32, vp, vp, u64]
         L.ssd_batch_destroy.argtypes = [vp]
@@ -120,6 +124,8 @@ def _lib():
         L.ssd_group_init.argtypes = [u32, vp, u64, vp, C.POINTER(vp)]
         L.ssd_group_scan.argtypes = [vp, C.POINTER(vp), u32, vp, vp, vp]
         L.ssd_group_close.argtypes = [vp, C.POINTER(vp), u32, vp, u64, vp, vp]
+        L.ssd_group_close_begin.argtypes = [vp, C.POINTER(vp), u32]
+        L.ssd_group_close_end.argtypes = [vp, vp, u64, vp, vp]
         L.ssd_group_destroy.argtypes = [vp]
         L.ssd_group_destroy.restype = None
         L.ssd_destroy.argtypes = [vp]
@@ -134,9 +140,10 @@ def _lib():
                      "ssd_read_rk", "ssd_read_hot", "ssd_read_tuples", "ssd_get_info",
                      "ssd_set_tuning", "ssd_read_timing", "ssd_batch_query_sizes", "ssd_batch_init",
                      "ssd_batch_scan", "ssd_batch_close", "ssd_batch_get_results", "ssd_batch_set_tuning",
-                     "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_batch_read_rk", "ssd_batch_read_hot",
+                     "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_batch_get_info", "ssd_batch_read_rk", "ssd_batch_read_hot",
                      "ssd_group_query_sizes",
-                     "ssd_group_init", "ssd_group_scan", "ssd_group_close"):
+                     "ssd_group_init", "ssd_group_scan", "ssd_group_close", "ssd_group_close_begin",
+                     "ssd_group_close_end"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
     return _lib_handle
@@ -312,10 +319,15 @@ def read_tuples(det: Detector) -> np.ndarray:
 def get_info(det: Detector) -> Dict[str, object]:
     info = _Info()
     _check(_lib().ssd_get_info(det.handle, C.byref(info)), "get_info")
+    return _info_dict(info)
+
+
+def _info_dict(info) -> Dict[str, object]:
     r = info.r
     return {"open_slice": info.open_slice, "hot_threshold": info.hot_threshold,
             "state_bytes": info.state_bytes, "level_counts": list(info.level_counts)[:max(r - 2, 0)],
-            "hot_counts": list(info.hot_counts)[:r], "accepted": info.accepted, "reported": info.reported}
+            "hot_counts": list(info.hot_counts)[:r], "accepted": info.accepted, "reported": info.reported,
+            "counted": info.counted}
 
 
 SSD_TUNE_SCAN_PASS_BYTES = 1
@@ -467,6 +479,12 @@ def batch_read_timing(b: Batch, reset: bool = False) -> Dict[str, Tuple[float, i
     return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(PHASES)}
 
 
+def batch_get_info(b: Batch, link: int) -> Dict[str, object]:
+    info = _Info()
+    _check(_lib().ssd_batch_get_info(b.handle, link, C.byref(info)), "batch_get_info")
+    return _info_dict(info)
+
+
 def batch_read_rk(b: Batch, link: int) -> np.ndarray:
     p = b.params[link]
     out = np.zeros((p.r, 1 << p.q), dtype=np.uint32)
@@ -552,6 +570,33 @@ def group_scan(g: Group, dets: Sequence[Detector], pairs: torch.Tensor, offsets:
         raise ValueError("offsets run past the pairs tensor")
     ptr = pairs.data_ptr() if pairs.numel() else None
     _check(_lib().ssd_group_scan(g.handle, _members(dets), n, ptr, off.ctypes.data, ids.ctypes.data), "group_scan")
+
+
+def group_close_begin(g: Group, dets: Sequence[Detector]) -> None:
+    """Enqueue the close of every member's open slot and open the next ones
+    (no wait); collect the lists with group_close_end."""
+    g._pending = list(dets)
+    _check(_lib().ssd_group_close_begin(g.handle, _members(dets), len(dets)), "group_close_begin")
+
+
+def group_close_end(g: Group):
+    """Wait for the pending group close: (per-member result arrays, status codes)."""
+    dets = getattr(g, "_pending", None) or []
+    n = len(dets)
+    counts = np.zeros(max(n, 1), dtype=np.uint64)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    cap = 1 << 16
+    out = np.zeros(cap, dtype=RESULT_DTYPE)
+    st = _lib().ssd_group_close_end(g.handle, out.ctypes.data, cap, counts.ctypes.data, status.ctypes.data)
+    g._pending = None
+    if st == SSD_E_TRUNC:
+        return [get_results(d) for d in dets], status[:n]
+    _check(st, "group_close_end")
+    lists, o = [], 0
+    for c in counts[:n].tolist():
+        lists.append(out[o:o + c].copy())
+        o += c
+    return lists, status[:n]
 
 
 def group_close(g: Group, dets: Sequence[Detector]):

@@ -108,7 +108,7 @@ struct BinArgs {
     const uint2* pairs;
     uint64_t n;                   // pairs of this chunk
     const uint32_t* tables;
-    uint32_t* items;              // [blocks][pb * r] bin-local byte offsets
+    uint32_t* items;              // [blocks][pb * r] bin-local cell offsets
     uint32_t* table;              // [n_bins + 1][blocks] start of bin b in segment j; row n_bins = item count
     uint32_t q, r, delta, log2eta;
     uint32_t bin_shift, n_bins, pb, blocks;
@@ -129,6 +129,27 @@ struct ApplyArgs {
     uint32_t k, slot, log2eta;
     uint32_t cell16;              // 1: 16-bit cells (k_apply; bins and offsets count cells)
     uint64_t n_se;                // estimators of the link (the counters' slot stride)
+};
+
+// binned scans of several links in one launch: workgroup g works for the
+// link l with wg_prefix[l] <= g < wg_prefix[l + 1] (ranges are multiples of 8)
+struct MultiBinArgs {
+    const BinArgs* args;          // [n]
+    const uint32_t* wg_prefix;    // [n + 1]
+    uint32_t n;
+};
+struct MultiApplyArgs {
+    const ApplyArgs* args;        // [n]
+    const uint32_t* wg_prefix;    // [n + 1]
+    uint32_t n;
+};
+
+// counted hot detection of several links of an engine in one launch
+struct CountMultiArgs {
+    const LinkDesc* links;        // the engine's descriptors
+    const uint32_t* ids;          // [n] links counted by this launch
+    const uint32_t* wg_prefix;    // [n + 1] workgroups before each of them (256 estimators each)
+    uint32_t n;
 };
 
 // 8-byte words of one packed binning segment of n items (three 21-bit
@@ -190,8 +211,22 @@ constexpr uint32_t BIN_LDS_WORDS = 40960u - 32u;
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s);
+// Workgroups of one link in the multi-link launches (multiples of 8): its
+// binning, its uncounted stores and its counted stores.  The variant of the
+// binning kernel (0 general, else the register binning of that many rows).
+uint32_t bin_workgroups(const BinArgs& a);
+uint32_t apply_workgroups(const ApplyArgs& a);
+uint32_t apply_counted_workgroups(const ApplyArgs& a);
+uint32_t bin_variant(const BinArgs& a);
+// one launch over several links: bin (all of one variant), apply (uncounted,
+// packed offsets, 8-bit cells), counted apply (lds_bytes: the largest need)
+hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t variant, uint32_t total_wg, hipStream_t s);
+hipError_t launch_apply_multi(const MultiApplyArgs& m, uint32_t total_wg, hipStream_t s);
+hipError_t launch_apply_counted_multi(const MultiApplyArgs& m, uint32_t total_wg, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s);
 hipError_t launch_recount(const LinkDesc* link, uint64_t n_se, hipStream_t s);
+uint32_t count_workgroups(uint64_t n_se);
+hipError_t launch_count_multi(const CountMultiArgs& m, uint32_t total_wg, hipStream_t s);
 hipError_t launch_hot_detect(const DetectArgs& a, uint32_t max_chunks_per_lane, bool small, hipStream_t s);
 // hot detection (or, with expire_only, the rotating expiry) of one link of 16-bit cells
 hipError_t launch_hot_detect16(const DetectArgs& a, hipStream_t s);

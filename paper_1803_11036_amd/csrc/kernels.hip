@@ -349,9 +349,9 @@ __device__ __forceinline__ uint64_t cell_addr(uint2 pr, uint32_t i, uint32_t h0,
 // XCD g mod 8, which takes a contiguous eighth of the segments, so that the
 // bin table entries of neighbouring segments, which share sectors, are
 // written through one L2 and leave it merged.  At least the segment count.
-__device__ __forceinline__ uint32_t bin_segment(uint32_t blocks)
+__device__ __forceinline__ uint32_t bin_segment(uint32_t g, uint32_t blocks)
 {
-    return (blockIdx.x & 7u) * ((blocks + 7u) >> 3) + (blockIdx.x >> 3);
+    return (g & 7u) * ((blocks + 7u) >> 3) + (g >> 3);
 }
 
 // A workgroup's sorted offsets out to its segment, coalesced: 4 bytes each, or
@@ -388,11 +388,10 @@ __device__ __forceinline__ uint32_t read_item(const ApplyArgs& a, uint32_t j, ui
 // one bin in one segment is long (about 50 offsets at 2 MiB bins) and
 // k_apply's reads of the runs are dense.  Pass 1 counts the bins' offsets,
 // pass 2 hashes again and places each offset at its bin's next free slot.
-__global__ __launch_bounds__(1024) void k_bin(BinArgs a)
+// (workgroup g of this link's launch; lds: the dynamic LDS, wsum: 16 words)
+__device__ __forceinline__ void bin_generic(const BinArgs& a, uint32_t g, uint32_t* lds, uint32_t* wsum)
 {
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[16];
-    const uint32_t sg = bin_segment(a.blocks);
+    const uint32_t sg = bin_segment(g, a.blocks);
     if (sg >= a.blocks) return;
     uint32_t* tab = lds;
     uint32_t* hist = lds + 2048;
@@ -442,11 +441,9 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
 // between the two passes (R rows, up to PPT pairs per thread): the pairs are
 // hashed once, and each offset's rank in its bin comes from the count pass.
 template <int R, int PPT>
-__global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
+__device__ __forceinline__ void bin_reg(const BinArgs& a, uint32_t g, uint32_t* lds, uint32_t* wsum)
 {
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[16];
-    const uint32_t sg = bin_segment(a.blocks);
+    const uint32_t sg = bin_segment(g, a.blocks);
     if (sg >= a.blocks) return;
     uint32_t* tab = lds;
     uint32_t* hist = lds + 2048;
@@ -499,6 +496,32 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
     write_segment(a, sg, stage, np * R);
 }
 
+// R = 0: the general binning; else the register binning of R rows.
+template <int R, int PPT>
+__global__ __launch_bounds__(1024) void k_bin(BinArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wsum[16];
+    if constexpr (R == 0) bin_generic(a, blockIdx.x, lds, wsum);
+    else bin_reg<R, PPT>(a, blockIdx.x, lds, wsum);
+}
+
+// Several links in one launch: workgroup g belongs to the link whose range
+// of the workgroup prefix holds it.  Every link's range is a multiple of 8
+// workgroups, so that the dealing of its segments to XCDs is the one of a
+// launch of its own.
+template <int R, int PPT>
+__global__ __launch_bounds__(1024) void k_bin_multi(MultiBinArgs m)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wsum[16];
+    const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
+    const BinArgs a = m.args[l];
+    const uint32_t g = blockIdx.x - m.wg_prefix[l];
+    if constexpr (R == 0) bin_generic(a, g, lds, wsum);
+    else bin_reg<R, PPT>(a, g, lds, wsum);
+}
+
 // One wave per workgroup.  Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w /
 // parts)-th bin from the top with w = g / 8, segments [part * per_part, ...),
 // 64 segments per round: lane j holds segment j's run of the bin, and the
@@ -506,10 +529,10 @@ __global__ __launch_bounds__(1024) void k_bin_reg(BinArgs a)
 constexpr uint32_t APPLY_UNROLL = 2;      // items per lane in flight
 
 template <bool PACK, class T>
-__global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, uint32_t g)
 {
     const uint64_t seg_words = PACK ? packed_seg_words(a.seg) : a.seg;   // item words per segment
-    const uint32_t g = blockIdx.x, w = g >> 3;
+    const uint32_t w = g >> 3;
     const uint32_t walk = (g & 7u) + 8u * (w / a.parts);
     if (walk >= a.n_bins) return;
     const uint32_t bin = a.n_bins - 1u - walk;     // highest bins first: the lowest stay cached for hot detection
@@ -578,6 +601,21 @@ __global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
     }
 }
 
+template <bool PACK, class T>
+__global__ __launch_bounds__(64) void k_apply(ApplyArgs a)
+{
+    apply_body<PACK, T>(a, blockIdx.x);
+}
+
+// Several links in one launch (8-bit cells), as k_bin_multi.
+template <bool PACK>
+__global__ __launch_bounds__(64) void k_apply_multi(MultiApplyArgs m)
+{
+    const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
+    const ApplyArgs a = m.args[l];
+    apply_body<PACK, uint8_t>(a, blockIdx.x - m.wg_prefix[l]);
+}
+
 // Counted variant: one workgroup per bin.  The walk over the bin's items only
 // marks their cells in an LDS bitmap (a bit per cell); then every marked cell
 // is visited once, 16-byte chunk by chunk: a cell whose stamp is not the open
@@ -625,14 +663,16 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a)
+// (workgroup g of this link's launch; lds: the dynamic LDS; list / n_list:
+// the workgroup's list of marked words)
+__device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t g, uint32_t* lds, uint16_t* list,
+                                                   uint32_t& n_list, uint32_t* wsum)
 {
-    extern __shared__ uint32_t lds[];
     // workgroup g runs on XCD g mod 8, which takes a contiguous eighth of the
     // bins in order: neighbouring bins, whose runs share cache lines in every
     // segment, are read through the same L2 at about the same time
     const uint32_t per_xcd = (a.n_bins + 7u) >> 3;
-    const uint32_t bin = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    const uint32_t bin = (g & 7u) * per_xcd + (g >> 3);
     if (bin >= a.n_bins) return;
     const uint32_t bm_words = 1u << (a.bin_shift - 5u);
     const uint32_t n_est = 1u << (a.bin_shift - a.log2eta);
@@ -640,9 +680,6 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
     const uint32_t n_words = bm_words + n_est * k;
     uint32_t* bm = lds;
     int* cnt = reinterpret_cast<int*>(lds + bm_words);
-    // the words that received their first mark, in order of marking
-    __shared__ uint16_t list[CAPPLY_LIST];
-    __shared__ uint32_t n_list;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
     // this lane's run (segment j) of the wave's first group, loaded before the
@@ -769,6 +806,29 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a
     // is reused (which would wait for the store)
 #pragma unroll
     for (int u = 0; u < (int)(2 * CAPPLY_CHUNKS); u++) asm volatile("" : : "v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
+}
+
+__global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    // the marked words, in address order
+    __shared__ uint16_t list[CAPPLY_LIST];
+    __shared__ uint32_t n_list;
+    __shared__ uint32_t wsum[16];
+    apply_counted_body(a, blockIdx.x, lds, list, n_list, wsum);
+}
+
+// Several links in one launch, as k_bin_multi (the dynamic LDS is sized for
+// the largest of them).
+__global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted_multi(MultiApplyArgs m)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint16_t list[CAPPLY_LIST];
+    __shared__ uint32_t n_list;
+    __shared__ uint32_t wsum[16];
+    const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
+    const ApplyArgs a = m.args[l];
+    apply_counted_body(a, blockIdx.x - m.wg_prefix[l], lds, list, n_list, wsum);
 }
 
 // ---------------------------------------------------------------- hot detection
@@ -1008,15 +1068,14 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect16(DetectArgs a
 // waves in turn: hot ones (snapshot and bitmask bits) and those of this
 // slot's expiry phase (dead cells cleared).  The slot of the next slice is
 // zeroed for its scans.
-__global__ __launch_bounds__(256) void k_count(const LinkDesc* link, uint64_t n_se)
+// (workgroup blk of this link's launch; todo / todo_live / n_todo: the
+// workgroup's list of estimators to visit)
+__device__ __forceinline__ void count_body(const LinkDesc* D, uint64_t n_se, uint32_t blk, uint32_t* todo,
+                                           uint32_t* todo_live, uint32_t& n_todo)
 {
-    const LinkDesc* D = link;
-    __shared__ uint32_t todo[256];      // local estimator | 0x100 hot | 0x200 expiring
-    __shared__ uint32_t todo_live[256];
-    __shared__ uint32_t n_todo;
     if (threadIdx.x == 0) n_todo = 0u;
     __syncthreads();
-    const uint64_t s0 = (uint64_t)blockIdx.x * 256u;
+    const uint64_t s0 = (uint64_t)blk * 256u;
     const uint64_t s = s0 + threadIdx.x;
     const uint32_t k = D->k;
     const uint32_t next = (uint32_t)((D->clock->t + 1ull) % k);
@@ -1056,6 +1115,26 @@ __global__ __launch_bounds__(256) void k_count(const LinkDesc* link, uint64_t n_
         }
         if (hi) hot_finish<false>(D, si, todo_live[i], se, lane);
     }
+}
+
+__global__ __launch_bounds__(256) void k_count(const LinkDesc* link, uint64_t n_se)
+{
+    __shared__ uint32_t todo[256];      // local estimator | 0x100 hot | 0x200 expiring
+    __shared__ uint32_t todo_live[256];
+    __shared__ uint32_t n_todo;
+    count_body(link, n_se, blockIdx.x, todo, todo_live, n_todo);
+}
+
+// Several counted links of an engine in one launch: workgroup g works for
+// link ids[l] with wg_prefix[l] <= g < wg_prefix[l + 1].
+__global__ __launch_bounds__(256) void k_count_multi(CountMultiArgs m)
+{
+    __shared__ uint32_t todo[256];
+    __shared__ uint32_t todo_live[256];
+    __shared__ uint32_t n_todo;
+    const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
+    const LinkDesc* D = m.links + m.ids[l];
+    count_body(D, D->n_se, blockIdx.x - m.wg_prefix[l], todo, todo_live, n_todo);
 }
 
 // Bytes of a word equal to stamp s.
@@ -1769,31 +1848,74 @@ hipError_t launch_scan_tiles(const TileScanArgs& a, uint32_t blocks, hipStream_t
     return hipGetLastError();
 }
 
+// the dynamic LDS of the binning kernels, set once per kernel
+static hipError_t bin_lds_attr()
+{
+    static bool attr = false;
+    if (attr) return hipSuccess;
+    for (const void* f : {reinterpret_cast<const void*>(&k_bin<0, 0>), reinterpret_cast<const void*>(&k_bin<6, 6>),
+                          reinterpret_cast<const void*>(&k_bin<5, 7>), reinterpret_cast<const void*>(&k_bin_multi<0, 0>),
+                          reinterpret_cast<const void*>(&k_bin_multi<6, 6>),
+                          reinterpret_cast<const void*>(&k_bin_multi<5, 7>)}) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
+        if (e != hipSuccess) return e;
+    }
+    attr = true;
+    return hipSuccess;
+}
+
+uint32_t bin_variant(const BinArgs& a)
+{
+    if (a.r == 6 && a.pb <= 6u * 1024u) return 6;
+    if (a.r == 5 && a.pb <= 7u * 1024u) return 5;
+    return 0;
+}
+
+uint32_t bin_workgroups(const BinArgs& a) { return 8u * ((a.blocks + 7u) / 8u); }   // segments dealt to XCDs in eighths
+
 hipError_t launch_bin(const BinArgs& a, hipStream_t s)
 {
     const uint32_t words = bin_lds_words(a.n_bins, a.pb, a.r);
     if (a.blocks == 0 || words > BIN_LDS_WORDS) return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        for (const void* f : {reinterpret_cast<const void*>(&k_bin), reinterpret_cast<const void*>(&k_bin_reg<6, 6>),
-                              reinterpret_cast<const void*>(&k_bin_reg<5, 7>)}) {
-            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
-            if (e != hipSuccess) return e;
-        }
-        attr = true;
+    hipError_t e = bin_lds_attr();
+    if (e != hipSuccess) return e;
+    const uint32_t grid = bin_workgroups(a);
+    switch (bin_variant(a)) {
+    case 6: k_bin<6, 6><<<grid, 1024, words * 4u, s>>>(a); break;
+    case 5: k_bin<5, 7><<<grid, 1024, words * 4u, s>>>(a); break;
+    default: k_bin<0, 0><<<grid, 1024, words * 4u, s>>>(a); break;
     }
-    const uint32_t grid = 8u * ((a.blocks + 7u) / 8u);      // segments dealt to XCDs in contiguous eighths
-    if (a.r == 6 && a.pb <= 6u * 1024u) k_bin_reg<6, 6><<<grid, 1024, words * 4u, s>>>(a);
-    else if (a.r == 5 && a.pb <= 7u * 1024u) k_bin_reg<5, 7><<<grid, 1024, words * 4u, s>>>(a);
-    else k_bin<<<grid, 1024, words * 4u, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t variant, uint32_t total_wg, hipStream_t s)
+{
+    if (m.n == 0 || total_wg == 0) return hipErrorInvalidValue;
+    hipError_t e = bin_lds_attr();
+    if (e != hipSuccess) return e;
+    const uint32_t bytes = BIN_LDS_WORDS * 4u;         // every link's plan fits it
+    switch (variant) {
+    case 6: k_bin_multi<6, 6><<<total_wg, 1024, bytes, s>>>(m); break;
+    case 5: k_bin_multi<5, 7><<<total_wg, 1024, bytes, s>>>(m); break;
+    default: k_bin_multi<0, 0><<<total_wg, 1024, bytes, s>>>(m); break;
+    }
+    return hipGetLastError();
+}
+
+uint32_t apply_workgroups(const ApplyArgs& a) { return (uint32_t)(8ull * a.parts * ((a.n_bins + 7u) / 8u)); }
+uint32_t apply_counted_workgroups(const ApplyArgs& a) { return 8u * ((a.n_bins + 7u) / 8u); }
+
+hipError_t launch_apply_multi(const MultiApplyArgs& m, uint32_t total_wg, hipStream_t s)
+{
+    if (m.n == 0 || total_wg == 0) return hipErrorInvalidValue;
+    k_apply_multi<true><<<total_wg, 64, 0, s>>>(m);
     return hipGetLastError();
 }
 
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
 {
     if (a.parts == 0 || a.per_part == 0) return hipErrorInvalidValue;
-    const uint64_t groups = (a.n_bins + 7u) / 8u;
-    const uint32_t grid = (uint32_t)(8ull * a.parts * groups);
+    const uint32_t grid = apply_workgroups(a);
     if (a.cell16) {
         if (a.pack) k_apply<true, uint16_t><<<grid, 64, 0, s>>>(a);
         else k_apply<false, uint16_t><<<grid, 64, 0, s>>>(a);
@@ -1804,6 +1926,19 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+static hipError_t counted_lds_attr()
+{
+    static bool attr = false;
+    if (attr) return hipSuccess;
+    for (const void* f : {reinterpret_cast<const void*>(&k_apply_counted),
+                          reinterpret_cast<const void*>(&k_apply_counted_multi)}) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)COUNTED_LDS_BYTES);
+        if (e != hipSuccess) return e;
+    }
+    attr = true;
+    return hipSuccess;
+}
+
 hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s)
 {
     const uint64_t bytes = counted_lds_bytes(a.bin_shift, a.log2eta, a.k);
@@ -1812,15 +1947,18 @@ hipError_t launch_apply_counted(const ApplyArgs& a, hipStream_t s)
         return hipErrorInvalidValue;
     if (!a.pack || a.seg < 6u) return hipErrorInvalidValue;     // counted bins are at most 2 MiB: always packed
     if (a.cell16) return hipErrorInvalidValue;                   // counters are kept for 8-bit cells only
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_counted),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)COUNTED_LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const uint32_t grid = 8u * ((a.n_bins + 7u) / 8u);
-    k_apply_counted<<<grid, 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
+    hipError_t e = counted_lds_attr();
+    if (e != hipSuccess) return e;
+    k_apply_counted<<<apply_counted_workgroups(a), 64 * CAPPLY_WAVES, (uint32_t)bytes, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_counted_multi(const MultiApplyArgs& m, uint32_t total_wg, uint32_t lds_bytes, hipStream_t s)
+{
+    if (m.n == 0 || total_wg == 0 || lds_bytes > COUNTED_LDS_BYTES) return hipErrorInvalidValue;
+    hipError_t e = counted_lds_attr();
+    if (e != hipSuccess) return e;
+    k_apply_counted_multi<<<total_wg, 64 * CAPPLY_WAVES, lds_bytes, s>>>(m);
     return hipGetLastError();
 }
 
@@ -1828,6 +1966,15 @@ hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s)
 {
     if (n_se == 0) return hipErrorInvalidValue;
     k_count<<<(uint32_t)((n_se + 255u) / 256u), 256, 0, s>>>(link, n_se);
+    return hipGetLastError();
+}
+
+uint32_t count_workgroups(uint64_t n_se) { return (uint32_t)((n_se + 255u) / 256u); }
+
+hipError_t launch_count_multi(const CountMultiArgs& m, uint32_t total_wg, hipStream_t s)
+{
+    if (m.n == 0 || total_wg == 0) return hipErrorInvalidValue;
+    k_count_multi<<<total_wg, 256, 0, s>>>(m);
     return hipGetLastError();
 }
 

@@ -163,8 +163,16 @@ constexpr uint32_t DEFAULT_APPLY_SEGMENTS = 2;
 constexpr uint64_t AUTO_BINNED_ABOVE = 256ull << 20;
 constexpr uint32_t PHASE_SCAN_BIN = 8;
 constexpr uint32_t PHASE_SCAN_TILES = 10;
-// batch links scanned binned: a large state and at least this many pairs
-constexpr uint64_t BATCH_BINNED_MIN_PAIRS = 1ull << 20;
+// batch links scanned binned: at least this many pairs in the call (fewer
+// go to the persistent tile scan, since the binned stores cost workgroups
+// per bin whatever the call's size)
+constexpr uint64_t BATCH_BINNED_MIN_PAIRS = 1ull << 16;
+// group members scanned binned (each with its own launches): a large state
+// and at least this many pairs in the call
+constexpr uint64_t GROUP_BINNED_MIN_PAIRS = 1ull << 20;
+// staging of a batch's binned scan: the binning segments of up to this many
+// pairs (at 4 bytes per offset) for the links of one group of launches
+constexpr uint64_t BATCH_BIN_PAIRS = 64ull << 20;
 // Candidate expansion: depth first in one launch up to this many rows (its
 // per-row loop state is held in registers), level by level above.
 constexpr uint32_t DFS_MAX_ROWS = 8;
@@ -239,9 +247,21 @@ struct Layout {
     uint64_t links = 0, se_prefix = 0, row_table = 0, clock = 0, pack_offsets = 0, tiles = 0;
     uint64_t ctl = 0, hot_begin = 0, hot_end = 0, sort_tmp = 0, packed = 0, total = 0;
     uint64_t state_total = 0, pack_cap = 0, tile_cap = 0;
-    uint64_t bin_items = 0, bin_table = 0, bin_items_words = 0, bin_table_words = 0;   // single detectors
+    uint64_t bin_items = 0, bin_table = 0, bin_items_words = 0, bin_table_words = 0;   // binned scan staging
+    uint64_t multi_args = 0;      // batches: arguments of the multi-link binned launches
+    uint64_t count_list = 0;      // the links counted at a close and their workgroup prefix (2n + 1 words)
     std::vector<LinkLayout> link;
 };
+
+// Arguments of a batch's multi-link binned launches for n links: per link
+// one BinArgs and one ApplyArgs, and the workgroup prefixes of the launches
+// (at most five per group of links -- three binning variants, counted and
+// uncounted stores -- and at most n groups: 10 (n + 1) words).
+uint64_t multi_args_bytes(uint32_t n)
+{
+    return align_up((uint64_t)n * sizeof(BinArgs)) + align_up((uint64_t)n * sizeof(ApplyArgs)) +
+           align_up(10 * ((uint64_t)n + 1) * 4);
+}
 
 // Scratch layout of an engine: header (descriptors, prefix tables, clock,
 // scan tiles), tables, control blocks, the hot-bit pool (cleared by one fill
@@ -264,6 +284,7 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
     L.clock = o; o = align_up(o + n * sizeof(Clock));       // one clock per link
     L.pack_offsets = o; o = align_up(o + (n + 1) * 8);
     L.tiles = o; o = align_up(o + 8 + tile_cap * sizeof(ScanWindow));
+    L.count_list = o; o = align_up(o + (2ull * n + 1) * 4);
     for (uint32_t l = 0; l < n; l++) { L.link[l].tables = o; o += 2048 * 4; }
     o = align_up(o);
     L.ctl = o;
@@ -290,22 +311,40 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
         K.out = o; o = align_up(o + q.max_results * sizeof(SuperPointDev));
         // per-slot counters for the links whose scans are binned (single
         // detectors; batch links above the binned threshold) and can count
-        const bool binned = n == 1 || state_bytes_of(q) > AUTO_BINNED_ABOVE;
-        if (bins && binned && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
+        if (bins && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
     }
     uint64_t pw = 1;
     while (pw < maxres) pw <<= 1;
     L.sort_tmp = o; o = align_up(o + pw * 8);
     L.packed = o; o = align_up(o + pack_cap * sizeof(SuperPointDev));
-    if (bins) {
-        // shared by the links scanned binned, one after another: the largest
+    if (bins && n == 1) {
+        uint64_t iw = 0, tw = 0;
+        bin_capacity(p[0], &iw, &tw);
+        L.bin_items_words = iw;
+        L.bin_table_words = tw;
+    } else if (bins) {
+        // a batch: the links binned in one group of launches share these
+        // (a table word per bin and binning workgroup, whose segment holds
+        // at least 8 times as many offsets); at least one link's largest
+        // step, at most a quarter offset per cell of the batch's state
+        uint64_t cells = 0;
+        uint32_t rmax = 0;
         for (uint32_t l = 0; l < n; l++) {
-            if (n > 1 && state_bytes_of(p[l]) <= AUTO_BINNED_ABOVE) continue;
+            cells += state_cells(p[l]);
+            rmax = std::max(rmax, p[l].r);
             uint64_t iw = 0, tw = 0;
             bin_capacity(p[l], &iw, &tw);
             L.bin_items_words = std::max(L.bin_items_words, iw);
             L.bin_table_words = std::max(L.bin_table_words, tw);
         }
+        const uint64_t iw = std::min<uint64_t>(BATCH_BIN_PAIRS * rmax, cells / 4);
+        L.bin_items_words = std::max(L.bin_items_words, iw);
+        L.bin_table_words = std::max(L.bin_table_words, iw / 8 + MAX_BINS + 1);
+        // the per-link arguments and workgroup prefixes of the multi-link launches
+        L.multi_args = o;
+        o = align_up(o + multi_args_bytes(n));
+    }
+    if (bins) {
         L.bin_items = o; o = align_up(o + L.bin_items_words * 4);
         L.bin_table = o; o = align_up(o + L.bin_table_words * 4);
     }
@@ -346,6 +385,9 @@ struct Engine {
     uint64_t counted_bin_bytes = DEFAULT_COUNTED_BIN_BYTES;   // bin size request of counted scans
     uint64_t counted_min_items = DEFAULT_COUNTED_MIN_ITEMS;   // offsets per bin a call needs to count
     std::vector<uint8_t> count_small;      // a call of this slice stored uncounted for being small
+    std::vector<uint8_t> last_mode;        // hot detection of the last close: 0 state, 1 counters, 2 rebuilt
+    uint32_t* cl_pinned = nullptr;         // staging of the counted-link list (2n + 1 words)
+    hipEvent_t cl_done = nullptr;          // its last copy has run
     std::vector<LinkDesc> hl;          // host copies of the device descriptors
     std::vector<uint32_t> tables;      // n x 2048
     // pinned host mailbox: control blocks, staged result entries, pack offsets
@@ -485,6 +527,8 @@ void engine_release(Engine* e)
     if (e->graph) (void)hipGraphDestroy(e->graph);
     if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
     if (e->pinned) (void)hipHostFree(e->pinned);
+    if (e->cl_pinned) (void)hipHostFree(e->cl_pinned);
+    if (e->cl_done) (void)hipEventDestroy(e->cl_done);
     for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
 }
 
@@ -570,6 +614,7 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     e->count_valid.assign(n, 0);
     e->count_rebuild.assign(n, 0);
     e->count_small.assign(n, 0);
+    e->last_mode.assign(n, 0);
     for (uint32_t l = 0; l < n; l++)
         if (e->hl[l].counts) e->counting[l] = e->count_valid[l] = 1;
     e->detect_prefix = se_prefix;
@@ -649,29 +694,31 @@ BinBufs engine_bins(const Engine* e)
 // every binned link of a batch: the steps run one after another on the
 // engine's stream).  The stores keep the link's per-slot counters when they
 // are exact and the call is large enough; otherwise they leave them stale.
-int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs,
-                        const BinBufs& bb)
+// The counter bookkeeping of a binned call of link l: stores that do not
+// count leave the counters stale.
+void binned_count_state(Engine* e, uint32_t l, const BinnedCall& c)
 {
-    const LinkDesc& D = e->hl[l];
-    const BinnedCall c = binned_call(e, l, n, bin_bytes);
-    const bool counted = c.counted;
-    if (e->counting[l] && !counted) {
+    if (e->counting[l] && !c.counted) {
         e->count_valid[l] = 0;                 // these stores are not counted
         // the close rebuilds the counters from the state after large calls
         // only; with a small call in the slice it reads the state once
         if (!c.large) e->count_small[l] = 1;
         e->count_rebuild[l] = c.large && !e->count_small[l];
     }
+}
+
+// The arguments of both binned steps of link l for its plan c, staging at
+// items / table, segments per store workgroup segs; pairs and sizes are set
+// per step.
+void binned_args(const Engine* e, uint32_t l, const BinnedCall& c, uint32_t* items, uint32_t* table, uint32_t segs,
+                 BinArgs* ba_out, ApplyArgs* aa_out)
+{
+    const LinkDesc& D = e->hl[l];
     const BinPlan bp = c.bp;
-    if (counted && (!c.csh || bp.shift != c.csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
-    const uint64_t seg = c.seg;
-    const uint64_t max_blocks = std::min(bb.items_words / seg, bb.table_words / (bp.n_bins + 1));
-    const uint64_t chunk = max_blocks * bp.pb;
-    if (chunk == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
     BinArgs ba{};
     ba.tables = D.tables;
-    ba.items = bb.items;
-    ba.table = bb.table;
+    ba.items = items;
+    ba.table = table;
     ba.q = D.q; ba.r = D.r; ba.delta = D.delta; ba.log2eta = D.log2eta;
     ba.bin_shift = bp.shift; ba.n_bins = bp.n_bins; ba.pb = bp.pb;
     ba.pack = bp.shift <= 21 ? 1u : 0u;
@@ -681,18 +728,37 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
     aa.table = ba.table;
     aa.state = D.state;
     aa.n_bins = bp.n_bins;
-    aa.seg = (uint32_t)seg;
+    aa.seg = (uint32_t)c.seg;
     aa.bin_shift = bp.shift;
     aa.per_part = segs;
     aa.stamp = stamp_of(e->clock, D.cell16);
     aa.cell16 = D.cell16;
-    if (counted) {
+    if (c.counted) {
         aa.counts = D.counts;
         aa.k = D.k;
         aa.slot = (uint32_t)(e->clock % D.k);
         aa.log2eta = D.log2eta;
         aa.n_se = D.n_se;
     }
+    *ba_out = ba;
+    *aa_out = aa;
+}
+
+int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs,
+                        const BinBufs& bb)
+{
+    const BinnedCall c = binned_call(e, l, n, bin_bytes);
+    const bool counted = c.counted;
+    binned_count_state(e, l, c);
+    const BinPlan bp = c.bp;
+    if (counted && (!c.csh || bp.shift != c.csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
+    const uint64_t seg = c.seg;
+    const uint64_t max_blocks = std::min(bb.items_words / seg, bb.table_words / (bp.n_bins + 1));
+    const uint64_t chunk = max_blocks * bp.pb;
+    if (chunk == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
+    BinArgs ba{};
+    ApplyArgs aa{};
+    binned_args(e, l, c, bb.items, bb.table, segs, &ba, &aa);
     for (uint64_t done = 0; done < n; done += chunk) {
         const uint64_t m = std::min(chunk, n - done);
         ba.pairs = pairs + done;
@@ -746,14 +812,47 @@ int enqueue_close_head(Engine* e)
         HIPCHK(e, e->hl[0].cell16 ? launch_hot_detect16(da, s) : launch_hot_detect(da, e->max_chunks, e->detect_small, s));
         phase_end(e, pm, 1, 1);
     }
-    for (uint32_t l = 0; l < n; l++) {
-        if (mode[l]) {
-            // the next slot starts at zero
-            PhaseMark pm = phase_begin(e);
-            if (mode[l] == 2) HIPCHK(e, launch_recount(links + l, e->hl[l].n_se, s));
-            HIPCHK(e, launch_count(links + l, e->hl[l].n_se, s));
-            phase_end(e, pm, 9, mode[l]);
+    // counted links: counters rebuilt from the state where needed, then R_k
+    // from the counters (the next slot starts at zero) -- one launch for one
+    // link, one launch over all of them for several
+    std::vector<uint32_t> ids;
+    for (uint32_t l = 0; l < n; l++)
+        if (mode[l]) ids.push_back(l);
+    if (!ids.empty()) {
+        PhaseMark pm = phase_begin(e);
+        uint32_t launches = 1;
+        for (uint32_t l : ids)
+            if (mode[l] == 2) {
+                HIPCHK(e, launch_recount(links + l, e->hl[l].n_se, s));
+                launches++;
+            }
+        if (ids.size() == 1) {
+            HIPCHK(e, launch_count(links + ids[0], e->hl[ids[0]].n_se, s));
+        } else {
+            if (!e->cl_pinned) {
+                HIPCHK(e, hipHostMalloc(reinterpret_cast<void**>(&e->cl_pinned), (2ull * n + 1) * 4, hipHostMallocDefault));
+                HIPCHK(e, hipEventCreateWithFlags(&e->cl_done, hipEventDisableTiming));
+            } else {
+                HIPCHK(e, hipEventSynchronize(e->cl_done));     // the last copy out of the staging has run
+            }
+            const uint32_t m = (uint32_t)ids.size();
+            uint32_t total = 0;
+            for (uint32_t i = 0; i < m; i++) {
+                e->cl_pinned[i] = ids[i];
+                e->cl_pinned[m + i] = total;
+                total += count_workgroups(e->hl[ids[i]].n_se);
+            }
+            e->cl_pinned[2 * m] = total;
+            uint32_t* dev = e->at<uint32_t>(e->L.count_list);
+            HIPCHK(e, hipMemcpyAsync(dev, e->cl_pinned, (2ull * m + 1) * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(e, hipEventRecord(e->cl_done, s));
+            CountMultiArgs cm{links, dev, dev + m, m};
+            HIPCHK(e, launch_count_multi(cm, total, s));
         }
+        phase_end(e, pm, 9, launches);
+    }
+    for (uint32_t l = 0; l < n; l++) {
+        e->last_mode[l] = mode[l];
         e->count_valid[l] = mode[l] != 0;
         e->count_rebuild[l] = 0;
         e->count_small[l] = 0;
@@ -960,6 +1059,25 @@ int read_timing(Engine* e, double* ms_out, uint64_t* launches_out, int reset)
     return SSD_OK;
 }
 
+// Facts about link l of an engine.
+void engine_info(const Engine& e, uint32_t l, ssd_info* out)
+{
+    memset(out, 0, sizeof *out);
+    out->open_slice = e.clock;
+    out->hot_threshold = e.T[l];
+    out->r = e.p[l].r;
+    out->state_bytes = e.L.link.empty() ? state_bytes_of(e.p[l]) : e.L.link[l].state_bytes;
+    if (e.have_last) {
+        for (uint32_t i = 0; i < MAX_ROWS; i++) {
+            out->level_counts[i] = e.last[l].level_n[i];
+            out->hot_counts[i] = e.last[l].hot_n[i];
+        }
+        out->accepted = e.last[l].n_acc;
+        out->reported = e.results[l].size();
+        out->counted = e.last_mode[l];
+    }
+}
+
 // R_k of link l at the last close (host copy).
 int engine_read_rk(Engine* e, uint32_t l, uint32_t* out_host, uint64_t n)
 {
@@ -1011,6 +1129,7 @@ struct ssd_detector {
     uint64_t bin_bytes = DEFAULT_BIN_BYTES;
     uint32_t apply_segments = DEFAULT_APPLY_SEGMENTS;
     bool pending = false;               // a close begun and not yet ended
+    bool group_pending = false;         // a group close of this member begun and not yet ended
     uint64_t pending_prefix = 0;
     hipStream_t close_stream = nullptr; // runs the close after hot detection
     hipEvent_t detect_done = nullptr;   // hot detection of the last close done
@@ -1020,6 +1139,9 @@ struct ssd_detector {
 };
 
 namespace {
+
+// A close of the detector, its own or a group's, has begun and not ended.
+bool close_pending(const ssd_detector* d) { return d->pending || d->group_pending; }
 
 // The second stream of a single detector and its events (created on first use).
 int detector_streams(ssd_detector* d)
@@ -1102,6 +1224,11 @@ struct ssd_batch {
     bool tile_used[2] = {false, false};
     uint32_t tile_next = 0;
     uint32_t scan_blocks = 2048;
+    // pinned double-buffered arguments of the multi-link binned launches
+    void* mb_pinned[2] = {nullptr, nullptr};
+    hipEvent_t mb_done[2] = {nullptr, nullptr};
+    bool mb_used[2] = {false, false};
+    uint32_t mb_next = 0;
     // autotuner: candidate (pass window, tile pairs), each scan timed with events
     struct Cand { uint64_t pass, tile; double ns_per_pair; };
     std::vector<Cand> cands;
@@ -1141,6 +1268,147 @@ void autotune_collect(ssd_batch* b)
     }
 }
 
+// The binned scan of the batch's links `links` (each with enough pairs in
+// this call; offsets as in ssd_batch_scan).  The links are packed, in order,
+// into groups whose staging fits the batch's bin buffers; a group takes one
+// binning launch per binning variant and one store launch per kind (counted,
+// uncounted), every workgroup finding its link in the launch's workgroup
+// prefix.  A link whose staging alone exceeds the buffers (or whose offsets
+// are not packed) is scanned on its own, in steps.
+int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offsets, const std::vector<uint32_t>& links)
+{
+    Engine* e = &b->e;
+    const uint32_t n = e->n;
+    struct Plan {
+        uint32_t l;
+        BinnedCall c;
+        uint64_t blocks, items, table;
+    };
+    std::vector<Plan> plans;
+    std::vector<uint32_t> alone;
+    for (uint32_t l : links) {
+        const uint64_t np = offsets[l + 1] - offsets[l];
+        Plan p{l, binned_call(e, l, np, DEFAULT_BIN_BYTES), 0, 0, 0};
+        if (p.c.counted && (!p.c.csh || p.c.bp.shift != p.c.csh)) return fail(SSD_E_STATE, "counted bin plan mismatch");
+        p.blocks = (np + p.c.bp.pb - 1) / p.c.bp.pb;
+        p.items = p.blocks * p.c.seg;
+        p.table = (uint64_t)(p.c.bp.n_bins + 1) * p.blocks;
+        if (p.items > e->L.bin_items_words || p.table > e->L.bin_table_words || p.c.bp.shift > 21 || e->hl[l].cell16)
+            alone.push_back(l);
+        else
+            plans.push_back(p);
+    }
+    // the arguments of every launch of this call, staged in pinned memory
+    // and copied to the device once
+    const uint64_t bin_region = 0;
+    const uint64_t app_region = align_up((uint64_t)n * sizeof(BinArgs));
+    const uint64_t pre_region = app_region + align_up((uint64_t)n * sizeof(ApplyArgs));
+    const uint32_t buf = b->mb_next;
+    b->mb_next ^= 1u;
+    if (b->mb_used[buf]) HIPCHK(e, hipEventSynchronize(b->mb_done[buf]));      // its last copy has run
+    uint8_t* host = static_cast<uint8_t*>(b->mb_pinned[buf]);
+    uint8_t* dev = e->at<uint8_t>(e->L.multi_args);
+    BinArgs* hb = reinterpret_cast<BinArgs*>(host + bin_region);
+    ApplyArgs* ha = reinterpret_cast<ApplyArgs*>(host + app_region);
+    uint32_t* hp = reinterpret_cast<uint32_t*>(host + pre_region);
+    struct Launch {
+        uint32_t kind;        // 6, 5, 0: binning variant; 10 counted stores; 11 uncounted stores
+        uint32_t first, count, pre, total_wg, lds;
+    };
+    std::vector<Launch> launches;
+    uint32_t nb = 0, na = 0, np_words = 0;
+    uint32_t* items = e->at<uint32_t>(e->L.bin_items);
+    uint32_t* table = e->at<uint32_t>(e->L.bin_table);
+    for (size_t g0 = 0; g0 < plans.size();) {
+        // the group [g0, g1): staging fits the buffers
+        size_t g1 = g0;
+        uint64_t iw = 0, tw = 0;
+        while (g1 < plans.size() && iw + plans[g1].items <= e->L.bin_items_words &&
+               tw + plans[g1].table <= e->L.bin_table_words) {
+            iw += plans[g1].items;
+            tw += plans[g1].table;
+            g1++;
+        }
+        std::vector<BinArgs> ba(g1 - g0);
+        std::vector<ApplyArgs> aa(g1 - g0);
+        uint64_t io = 0, to = 0;
+        for (size_t i = g0; i < g1; i++) {
+            const Plan& p = plans[i];
+            binned_count_state(e, p.l, p.c);
+            BinArgs& x = ba[i - g0];
+            ApplyArgs& y = aa[i - g0];
+            binned_args(e, p.l, p.c, items + io, table + to, DEFAULT_APPLY_SEGMENTS, &x, &y);
+            x.pairs = pairs + offsets[p.l];
+            x.n = offsets[p.l + 1] - offsets[p.l];
+            x.blocks = (uint32_t)p.blocks;
+            y.blocks = x.blocks;
+            y.parts = (y.blocks + y.per_part - 1) / y.per_part;
+            io += p.items;
+            to += p.table;
+        }
+        // binning: one launch per variant
+        for (uint32_t v : {6u, 5u, 0u}) {
+            Launch L{v, nb, 0, np_words, 0, 0};
+            for (const BinArgs& x : ba) {
+                if (bin_variant(x) != v) continue;
+                hb[nb++] = x;
+                hp[np_words + L.count] = L.total_wg;
+                L.count++;
+                L.total_wg += bin_workgroups(x);
+            }
+            if (!L.count) continue;
+            hp[np_words + L.count] = L.total_wg;
+            np_words += L.count + 1;
+            launches.push_back(L);
+        }
+        // stores: counted, then uncounted
+        for (uint32_t kind : {10u, 11u}) {
+            Launch L{kind, na, 0, np_words, 0, 0};
+            for (const ApplyArgs& y : aa) {
+                if ((y.counts != nullptr) != (kind == 10u)) continue;
+                ha[na++] = y;
+                hp[np_words + L.count] = L.total_wg;
+                L.count++;
+                L.total_wg += kind == 10u ? apply_counted_workgroups(y) : apply_workgroups(y);
+                if (kind == 10u)
+                    L.lds = std::max<uint32_t>(L.lds, (uint32_t)counted_lds_bytes(y.bin_shift, y.log2eta, y.k));
+            }
+            if (!L.count) continue;
+            hp[np_words + L.count] = L.total_wg;
+            np_words += L.count + 1;
+            launches.push_back(L);
+        }
+        g0 = g1;
+    }
+    if (!launches.empty()) {
+        HIPCHK(e, hipMemcpyAsync(dev, host, multi_args_bytes(n), hipMemcpyHostToDevice, e->stream));
+        HIPCHK(e, hipEventRecord(b->mb_done[buf], e->stream));
+        b->mb_used[buf] = true;
+        const BinArgs* db = reinterpret_cast<const BinArgs*>(dev + bin_region);
+        const ApplyArgs* da = reinterpret_cast<const ApplyArgs*>(dev + app_region);
+        const uint32_t* dp = reinterpret_cast<const uint32_t*>(dev + pre_region);
+        for (const Launch& L : launches) {
+            PhaseMark pm = phase_begin(e);
+            if (L.kind >= 10u) {
+                MultiApplyArgs m{da + L.first, dp + L.pre, L.count};
+                HIPCHK(e, L.kind == 10u ? launch_apply_counted_multi(m, L.total_wg, L.lds, e->stream)
+                                        : launch_apply_multi(m, L.total_wg, e->stream));
+                phase_end(e, pm, 0, 1);
+            } else {
+                MultiBinArgs m{db + L.first, dp + L.pre, L.count};
+                HIPCHK(e, launch_bin_multi(m, L.kind, L.total_wg, e->stream));
+                phase_end(e, pm, PHASE_SCAN_BIN, 1);
+            }
+        }
+    }
+    for (uint32_t l : alone) {
+        int rc = enqueue_binned_scan(e, l, pairs + offsets[l], offsets[l + 1] - offsets[l], DEFAULT_BIN_BYTES,
+                                     DEFAULT_APPLY_SEGMENTS, engine_bins(e));
+        if (rc) return rc;
+    }
+    return SSD_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- group
@@ -1150,6 +1418,10 @@ struct ssd_group {
     uint32_t max_members = 0;
     uint32_t scan_blocks = 2048;       // tile-scan workgroups: 8 per compute unit
     std::vector<uint64_t> bound;       // ids of the members whose descriptors are on the device
+    // a close begun and not yet ended: its members and its completion
+    bool pending = false;
+    std::vector<ssd_detector*> pending_members;
+    hipEvent_t done = nullptr;
 };
 
 namespace {
@@ -1163,6 +1435,7 @@ Layout plan_group(uint32_t max_members)
     L.row_table = o; o = align_up(o + (uint64_t)max_members * MAX_ROWS * 4);
     L.pack_offsets = o; o = align_up(o + (max_members + 1) * 8);
     L.tiles = o; o = align_up(o + 8 + MAX_WINDOWS * sizeof(ScanWindow));
+    L.count_list = o; o = align_up(o + (2ull * max_members + 1) * 4);
     L.ctl = o; o = align_up(o + max_members * sizeof(Ctl));    // unused: members' own blocks are read
     L.packed = o; o = align_up(o + BATCH_STAGE * sizeof(SuperPointDev));
     L.total = o;
@@ -1216,6 +1489,7 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
     e->count_valid.assign(n, 0);
     e->count_rebuild.assign(n, 0);
     e->count_small.assign(n, 0);
+    e->last_mode.assign(n, 0);
     e->detect_prefix = se_prefix;
     HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
     HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice,
@@ -1331,7 +1605,7 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
     case SSD_TUNE_COUNTED:
         if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
         if (value && !d->e.hl[0].counts) return fail(SSD_E_PARAM, "this detector cannot count (eta < 32 k or too many bins)");
-        if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+        if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
         if (d->e.counting[0] != (value != 0)) {
             d->e.counting[0] = value != 0;
             d->e.count_valid[0] = 0;
@@ -1340,7 +1614,7 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
         return SSD_OK;
     case SSD_TUNE_SORT_BLOCK_LIMIT: {
         if (value > SORT_SMALL) return fail(SSD_E_PARAM, "sort block limit above %u", SORT_SMALL);
-        if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+        if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
         int rc = usable(&d->e);
         if (rc) return rc;
         d->e.hl[0].sort_limit = value;
@@ -1404,7 +1678,7 @@ int ssd_close_begin(ssd_detector* d)
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
-    if (d->pending) return fail(SSD_E_ORDER, "a close is already pending (ssd_close_end first)");
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is already pending (ssd_close_end first)");
     rc = detector_streams(d);
     if (rc) return rc;
     // the sort kernel writes the first host_cap entries of the list into the
@@ -1469,7 +1743,7 @@ int ssd_close_slice(ssd_detector* d, uint32_t flags, ssd_super_point* out_host, 
     if (rc) return rc;
     if (flags & ~SSD_ADVANCE_ONLY) return fail(SSD_E_PARAM, "unknown close flags 0x%x", flags);
     if (n_out) *n_out = 0;
-    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     if (flags & SSD_ADVANCE_ONLY) {
         rc = enqueue_advance_only(e);
         if (rc) return rc;
@@ -1514,7 +1788,7 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
     if (!g) return fail(SSD_E_PARAM, "detector is NULL");
     int rc = usable(&g->e);
     if (rc) return rc;
-    if (g->pending) return fail(SSD_E_ORDER, "the global detector has a close pending");
+    if (close_pending(g)) return fail(SSD_E_ORDER, "the global detector has a close pending");
     if (!routers || n < 1) return fail(SSD_E_PARAM, "need at least one router");
     const ssd_params& gp = g->p();
     for (uint32_t j = 0; j < n; j++) {
@@ -1522,7 +1796,7 @@ int ssd_merge_router_state(ssd_detector* g, ssd_detector* const* routers, uint32
         if (!r) return fail(SSD_E_PARAM, "router %u is NULL", j);
         if (r == g) return fail(SSD_E_PARAM, "router %u is the global detector", j);
         if (r->e.broken) return fail(SSD_E_STATE, "router %u is unusable", j);
-        if (r->pending) return fail(SSD_E_ORDER, "router %u has a close pending", j);
+        if (close_pending(r)) return fail(SSD_E_ORDER, "router %u has a close pending", j);
         const ssd_params& rp = r->p();
         if (rp.q != gp.q || rp.r != gp.r || rp.delta != gp.delta || rp.eta != gp.eta || rp.k != gp.k ||
             cell16(rp) != cell16(gp) ||
@@ -1572,14 +1846,14 @@ int ssd_read_canonical_state(ssd_detector* d, uint16_t* out_dev, uint64_t n_cell
 int ssd_read_rk(ssd_detector* d, uint32_t* out_host, uint64_t n)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     return engine_read_rk(&d->e, 0, out_host, n);
 }
 
 int ssd_read_hot(ssd_detector* d, uint32_t* counts_host, uint32_t* lists_host, uint64_t cap)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");
-    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     return engine_read_hot(&d->e, 0, counts_host, lists_host, cap);
 }
 
@@ -1589,7 +1863,7 @@ int ssd_read_tuples(ssd_detector* d, uint32_t* out_host, uint64_t cap, uint64_t*
     Engine* e = &d->e;
     int rc = usable(e);
     if (rc) return rc;
-    if (d->pending) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
     if (!e->have_last) return fail(SSD_E_STATE, "no reconstructing close yet");
     const ssd_params& p = d->p();
     const uint32_t lf = p.r - 3;
@@ -1624,34 +1898,15 @@ int ssd_read_timing(ssd_detector* d, double* ms_out, uint64_t* launches_out, int
 int ssd_get_info(ssd_detector* d, ssd_info* out)
 {
     if (!d || !out) return fail(SSD_E_PARAM, "NULL argument");
-    memset(out, 0, sizeof *out);
-    const Engine& e = d->e;
-    out->open_slice = e.clock;
-    out->hot_threshold = e.T[0];
-    out->r = d->p().r;
-    out->state_bytes = e.L.state_total;
-    if (e.have_last) {
-        for (uint32_t i = 0; i < MAX_ROWS; i++) {
-            out->level_counts[i] = e.last[0].level_n[i];
-            out->hot_counts[i] = e.last[0].hot_n[i];
-        }
-        out->accepted = e.last[0].n_acc;
-        out->reported = e.results[0].size();
-    }
+    engine_info(d->e, 0, out);
     return SSD_OK;
 }
 
 // ---- batch
 
-// a batch keeps bin buffers when some link's state is large enough for the
-// binned scan
-static bool batch_bins(const ssd_params* p, uint32_t n)
-{
-    if (!p) return false;
-    for (uint32_t l = 0; l < n && l < MAX_LINKS; l++)
-        if (((uint64_t)p[l].r << p[l].q) * p[l].eta > AUTO_BINNED_ABOVE) return true;
-    return false;
-}
+// a batch keeps the staging of the binned scan (any link with enough pairs
+// in a call is scanned binned)
+static bool batch_bins(const ssd_params* p, uint32_t n) { return p && n >= 1; }
 
 // batch links take 8-bit cells (the persistent tile scan and the batched hot
 // detection are written for them)
@@ -1686,6 +1941,8 @@ int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host,
         for (int i = 0; i < 2 && rc == SSD_OK; i++) {
             hipError_t err = hipHostMalloc(&b->tile_pinned[i], 8 + MAX_WINDOWS * sizeof(ScanWindow), hipHostMallocDefault);
             if (err == hipSuccess) err = hipEventCreateWithFlags(&b->tile_done[i], hipEventDisableTiming);
+            if (err == hipSuccess) err = hipHostMalloc(&b->mb_pinned[i], multi_args_bytes(n), hipHostMallocDefault);
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&b->mb_done[i], hipEventDisableTiming);
             if (err != hipSuccess) rc = dev_fail(&b->e, err, "batch staging");
         }
         hipDeviceProp_t prop;
@@ -1696,6 +1953,8 @@ int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host,
         for (int i = 0; i < 2; i++) {
             if (b->tile_pinned[i]) (void)hipHostFree(b->tile_pinned[i]);
             if (b->tile_done[i]) (void)hipEventDestroy(b->tile_done[i]);
+            if (b->mb_pinned[i]) (void)hipHostFree(b->mb_pinned[i]);
+            if (b->mb_done[i]) (void)hipEventDestroy(b->mb_done[i]);
         }
         engine_release(&b->e);
         delete b;
@@ -1716,6 +1975,8 @@ void ssd_batch_destroy(ssd_batch* b)
     for (int i = 0; i < 2; i++) {
         if (b->tile_pinned[i]) (void)hipHostFree(b->tile_pinned[i]);
         if (b->tile_done[i]) (void)hipEventDestroy(b->tile_done[i]);
+        if (b->mb_pinned[i]) (void)hipHostFree(b->mb_pinned[i]);
+        if (b->mb_done[i]) (void)hipEventDestroy(b->mb_done[i]);
     }
     delete b;
 }
@@ -1806,9 +2067,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
     std::vector<uint32_t> binned;
     if (b->scan_mode != SSD_SCAN_PASSES && e->L.bin_items_words) {
         for (uint32_t l = 0; l < e->n; l++)
-            if ((e->hl[l].n_se << e->hl[l].log2eta) > AUTO_BINNED_ABOVE &&
-                offsets_host[l + 1] - offsets_host[l] >= BATCH_BINNED_MIN_PAIRS)
-                binned.push_back(l);
+            if (offsets_host[l + 1] - offsets_host[l] >= BATCH_BINNED_MIN_PAIRS) binned.push_back(l);
     }
     auto is_binned = [&](uint32_t l) { return std::find(binned.begin(), binned.end(), l) != binned.end(); };
     // windows of every other link's state, ordered by address; tiles are implicit
@@ -1878,12 +2137,7 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
             b->tune_events.push_back({ta, tb});
         }
     }
-    for (uint32_t l : binned) {
-        rc = enqueue_binned_scan(e, l, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[l],
-                                 offsets_host[l + 1] - offsets_host[l], DEFAULT_BIN_BYTES, DEFAULT_APPLY_SEGMENTS,
-                                 engine_bins(e));
-        if (rc) return rc;
-    }
+    if (!binned.empty()) return enqueue_batch_binned(b, reinterpret_cast<const uint2*>(pairs_dev), offsets_host, binned);
     return SSD_OK;
 }
 
@@ -1931,6 +2185,14 @@ int ssd_batch_read_timing(ssd_batch* b, double* ms_out, uint64_t* launches_out, 
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
     return read_timing(&b->e, ms_out, launches_out, reset);
+}
+
+int ssd_batch_get_info(ssd_batch* b, uint32_t link, ssd_info* out)
+{
+    if (!b || !out) return fail(SSD_E_PARAM, "NULL argument");
+    if (link >= b->e.n) return fail(SSD_E_PARAM, "link %u of %u", link, b->e.n);
+    engine_info(b->e, link, out);
+    return SSD_OK;
 }
 
 int ssd_batch_read_rk(ssd_batch* b, uint32_t link, uint32_t* out_host, uint64_t n)
@@ -1994,7 +2256,10 @@ int ssd_group_init(uint32_t max_members, void* scratch_dev, uint64_t scratch_byt
 void ssd_group_destroy(ssd_group* g)
 {
     if (!g) return;
+    if (g->pending)     // members outlive a pending group close (see ssd_group_close_begin)
+        for (ssd_detector* m : g->pending_members) m->group_pending = false;
     engine_release(&g->e);
+    if (g->done) (void)hipEventDestroy(g->done);
     delete g;
 }
 
@@ -2025,7 +2290,7 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         if (m->e.stream != e->stream) return false;
         const uint64_t np = offsets_host[i + 1] - offsets_host[i];
         const uint64_t sb = e->hl[i].n_se << e->hl[i].log2eta;
-        return m->scan_mode != SSD_SCAN_PASSES && np >= BATCH_BINNED_MIN_PAIRS &&
+        return m->scan_mode != SSD_SCAN_PASSES && np >= GROUP_BINNED_MIN_PAIRS &&
                (m->scan_mode == SSD_SCAN_BINNED || sb > AUTO_BINNED_ABOVE);
     };
     // windows of every other member's state (its own pass window), in member order
@@ -2085,17 +2350,18 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     return SSD_OK;
 }
 
-int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_super_point* out_host,
-                    uint64_t cap, uint64_t* counts_host, int* status_host)
+int ssd_group_close_begin(ssd_group* g, ssd_detector* const* members, uint32_t n)
 {
     if (!g) return fail(SSD_E_PARAM, "group is NULL");
     Engine* e = &g->e;
     int rc = usable(e);
     if (rc) return rc;
+    if (g->pending) return fail(SSD_E_ORDER, "a group close is already pending (ssd_group_close_end first)");
     rc = group_bind(g, members, n);
     if (rc) return rc;
     for (uint32_t i = 0; i < n; i++)
-        if (members[i]->pending) return fail(SSD_E_ORDER, "member %u has a close pending", i);
+        if (close_pending(members[i])) return fail(SSD_E_ORDER, "member %u has a close pending", i);
+    if (!g->done) HIPCHK(e, hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
     // a group's close reads every member's state (served streams' calls are
     // mostly too small to count; counted group closes measured slower) and
     // zeroes no member's next slot
@@ -2105,17 +2371,48 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
     }
     rc = enqueue_close(e, true, 0);
     if (rc) return rc;
-    HIPCHK(e, hipStreamSynchronize(e->stream));
+    HIPCHK(e, hipEventRecord(g->done, e->stream));
+    // every member's next slice opens now: its scans may be enqueued before
+    // the lists are collected
+    g->pending = true;
+    g->pending_members.assign(members, members + n);
+    for (uint32_t i = 0; i < n; i++) {
+        members[i]->group_pending = true;
+        members[i]->e.clock++;
+    }
+    return SSD_OK;
+}
+
+int ssd_group_close_end(ssd_group* g, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host,
+                        int* status_host)
+{
+    if (!g) return fail(SSD_E_PARAM, "group is NULL");
+    Engine* e = &g->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (!g->pending) return fail(SSD_E_ORDER, "no group close is pending");
+    g->pending = false;
+    std::vector<ssd_detector*> members;
+    members.swap(g->pending_members);
+    const uint32_t n = (uint32_t)members.size();
+    for (ssd_detector* m : members) m->group_pending = false;
+    HIPCHK(e, hipEventSynchronize(g->done));
     phase_collect(e);
+    // the group may have been bound to other members since the close began
+    // (scans of the next slots): the close's lists are those of these members
+    for (uint32_t i = 0; i < n; i++)
+        if (members[i]->e.broken) return fail(SSD_E_STATE, "member %u is unusable", i);
+    rc = group_bind(g, members.data(), n);
+    if (rc) return rc;
     rc = collect_results(e, true, 0);
     if (rc) return rc;
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; i++) {
         Engine& me = members[i]->e;
-        me.clock++;
         me.results[0] = e->results[i];
         me.status[0] = e->status[i];
         me.last[0] = e->last[i];
+        me.last_mode[0] = e->last_mode[i];
         me.have_last = true;
         if (counts_host) counts_host[i] = e->results[i].size();
         if (status_host) status_host[i] = e->status[i];
@@ -2131,6 +2428,14 @@ int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_
         o += e->results[i].size();
     }
     return SSD_OK;
+}
+
+int ssd_group_close(ssd_group* g, ssd_detector* const* members, uint32_t n, ssd_super_point* out_host,
+                    uint64_t cap, uint64_t* counts_host, int* status_host)
+{
+    int rc = ssd_group_close_begin(g, members, n);
+    if (rc) return rc;
+    return ssd_group_close_end(g, out_host, cap, counts_host, status_host);
 }
 
 }  // extern "C"

@@ -6,11 +6,13 @@ HBM.  Each loop iteration
      (state + scratch of their detectors);
   2. scans every batch that has arrived for any admitted stream's open slot,
      all in one group scan launch (streams of different geometries together);
-  3. closes every stream whose open slot has ended, all in one group close;
-     the slice-close latency is measured from the slot's end to the list in
-     host memory;
-  4. frees the detectors of finished streams, so that waiting streams can be
-     admitted.
+  3. collects the lists of the group close begun in the previous iteration
+     (the slice-close latency is measured from the slot's end to the list in
+     host memory) and frees the detectors of finished streams, so that
+     waiting streams can be admitted;
+  4. begins one group close of every stream whose open slot has ended: the
+     close runs on the device while the next iteration admits streams and
+     enqueues their scans, and its streams' next slots are open at once.
 Requests arriving while others are on the GPU simply join the next iteration.
 All work runs in the library's kernels; this module only decides what runs
 together.  Stream time advances at `time_scale` times wall time.
@@ -25,7 +27,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 import torch
 
-from . import (Detector, Group, get_info, group_close, group_scan, init_detector, make_params, query_sizes)
+from . import (Detector, Group, get_info, group_close_begin, group_close_end, group_scan, init_detector,
+               make_params, query_sizes)
 
 
 @dataclasses.dataclass
@@ -86,6 +89,7 @@ class _Live:
         self.nbytes = nbytes
         self.slot = 0          # open slot
         self.next = 0          # next batch not yet scanned
+        self.closing = False   # a close of its previous slot is pending
 
 
 def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float = 1.0,
@@ -113,6 +117,26 @@ def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float =
 
     def now_tau() -> float:
         return (time.perf_counter() - t0) * time_scale
+
+    pending = None
+
+    def finish(closed, lists, status):
+        """Lists of closed (stream, slot)s are in host memory: latencies,
+        results, and the finished streams' detectors freed."""
+        nonlocal used, done
+        t_done = time.perf_counter()
+        for (L, slot), res, st in zip(closed, lists, status):
+            s = streams[L.idx]
+            slot_end_wall = t0 + (slot + 1) * s.slot / time_scale
+            lat.append((t_done - slot_end_wall) * 1e3)
+            if keep_results:
+                results[(L.idx, slot)] = res if st == 0 else None
+            L.closing = False
+            if L.slot >= s.n_slots:
+                L.det.destroy()
+                used -= L.nbytes
+                del live[L.idx]
+                done += 1
 
     while done < len(streams):
         iters += 1
@@ -166,40 +190,43 @@ def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float =
                     k += 1
                     scans += 1
                 pairs += cnt
-        # 3. one close over every stream whose open slot has ended
+        # 3. the lists of the close begun in the previous iteration: its
+        # kernels ran while this iteration's scans were enqueued behind them
+        if pending is not None:
+            closed, lists, status = pending[0], *group_close_end(group)
+            finish(closed, lists, status)
+            pending = None
+        # 4. one close over every stream whose open slot has ended
         closing = []
         for i, L in live.items():
             s = streams[i]
             end = (L.slot + 1) * s.slot
-            if end <= tau and (L.next >= s.arrivals.size or s.arrivals[L.next] >= end):
+            if L.slot < s.n_slots and end <= tau and (L.next >= s.arrivals.size or s.arrivals[L.next] >= end):
                 closing.append(L)
         if closing:
-            if batched:
-                lists, status = group_close(group, [L.det for L in closing])
-            else:
-                lists = [close_slice(L.det) for L in closing]
-                status = [0] * len(closing)
-            t_done = time.perf_counter()
             closes += 1
             max_close_m = max(max_close_m, len(closing))
-            for L, res, st in zip(closing, lists, status):
-                s = streams[L.idx]
-                slot_end_wall = t0 + (L.slot + 1) * s.slot / time_scale
-                lat.append((t_done - slot_end_wall) * 1e3)
-                if keep_results:
-                    results[(L.idx, L.slot)] = res if st == 0 else None
-                L.slot += 1
-                if L.slot >= s.n_slots:
-                    L.det.destroy()
-                    used -= L.nbytes
-                    del live[L.idx]
-                    done += 1
-        # 4. idle until the next arrival or slot end
-        if not members and not closing:
+            if batched:
+                group_close_begin(group, [L.det for L in closing])
+                pending = ([(L, L.slot) for L in closing],)
+                for L in closing:
+                    L.slot += 1          # the next slot is open: its batches may be scanned
+                    L.closing = True
+            else:
+                lists = [close_slice(L.det) for L in closing]
+                closed = [(L, L.slot) for L in closing]
+                for L in closing:
+                    L.slot += 1
+                    L.closing = True
+                finish(closed, lists, [0] * len(closing))
+        # 5. idle until the next arrival or slot end (not while a close is
+        # pending: its lists are collected next)
+        if not members and not closing and pending is None:
             nxt = []
             for i, L in live.items():
                 s = streams[i]
-                nxt.append((L.slot + 1) * s.slot)
+                if L.slot < s.n_slots:
+                    nxt.append((L.slot + 1) * s.slot)
                 if L.next < s.arrivals.size:
                     nxt.append(s.arrivals[L.next])
             if waiting:

@@ -161,3 +161,53 @@ def test_group_refuses_16bit_members():
     g.destroy()
     d8.destroy()
     d16.destroy()
+
+
+def test_group_close_begin_end():
+    """The group close in two halves: while it is pending the members' next
+    slot can be scanned (group scans), but a member cannot close, merge or be
+    inspected and the group cannot begin another close (SSD_E_ORDER); the
+    collected lists equal those of detectors of their own, slot after slot."""
+    cfgs = tg.batch_configs(n_links=4, pairs_scale=0.05)
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+
+    def params(c):
+        return ssd.make_params(q=c.q, r=c.r, delta=c.delta, eta=c.eta, k=c.k, theta=c.theta)
+
+    members = [ssd.init_detector(params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    alone = [ssd.init_detector(params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    g = ssd.group_init(len(cfgs), device="cuda:0")
+
+    def slot(t):
+        per = [tr.pairs(0, t % tr.cfg.n_slices) for tr in traces]
+        offs = np.zeros(len(per) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([p.shape[0] for p in per])
+        return per, offs, to_dev(np.concatenate(per))
+
+    per, offs, dev = slot(0)
+    ssd.group_scan(g, members, dev, offs, [0] * len(cfgs))
+    for t in range(1, 6):
+        ssd.group_close_begin(g, members)
+        for call in (lambda: ssd.group_close_begin(g, members), lambda: ssd.close_slice(members[0]),
+                     lambda: ssd.close_begin(members[1]), lambda: ssd.read_rk(members[2]),
+                     lambda: ssd.merge_router_state(members[3], [members[0]])):
+            with pytest.raises(ssd.SSDError) as e:
+                call()
+            assert e.value.status == -3
+        nper, noffs, ndev = slot(t)
+        ssd.group_scan(g, members, ndev, noffs, [t] * len(cfgs))     # slot t while the close of t-1 is pending
+        lists, status = ssd.group_close_end(g)
+        assert np.all(status == 0)
+        for i, d in enumerate(alone):
+            ssd.scan_slice(d, dev[int(offs[i]):int(offs[i + 1])], t - 1)
+            assert np.array_equal(lists[i], ssd.close_slice(d)), f"slot {t - 1} member {i}"
+            assert np.array_equal(ssd.get_results(members[i]), lists[i])
+        per, offs, dev = nper, noffs, ndev
+        log(f"group begin/end slot {t - 1}: {sum(len(x) for x in lists)} hosts")
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.group_close_end(g)
+    assert e.value.status == -3
+    g.destroy()
+    for d in members + alone:
+        d.destroy()
