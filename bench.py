@@ -346,6 +346,8 @@ def run_batched(args) -> dict:
     # batched: persistent scan + graph close; the autotuner times its
     # candidates on untimed scans first
     b = ssd.batch_init([params(c) for c in cfgs], tables, device=dev)
+    if args.counted_min_items is not None:
+        ssd.batch_set_tuning(b, ssd.SSD_TUNE_COUNTED_MIN_ITEMS, args.counted_min_items)
     t = 0
     if args.autotune:
         ssd.batch_set_tuning(b, ssd.SSD_TUNE_AUTOTUNE, 1)
@@ -857,6 +859,8 @@ def main() -> int:
     ap.add_argument("--apply-segments", type=int, default=None, help="binned scan: segments per store workgroup")
     ap.add_argument("--no-counted", action="store_true",
                     help="hot detection scans the whole state (no per-slot counters)")
+    ap.add_argument("--counted-min-items", type=int, default=None,
+                    help="batched workload: offsets per bin a link's call needs to keep counters (default: library)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (PMC calibration)")
     ap.add_argument("--links", type=int, default=64, help="batched workload: number of links")

@@ -262,11 +262,15 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       workgroup that marks the cells it has visited).  Its close then takes R_k from these
  *       counters and reads only the cells of hot estimators and of the
  *       estimators whose expiry phase it is, instead of the whole state.
- *       Possible when eta >= 32 k and the state fits 4096 bins; the
- *       counters take r * 2^q * k * 4 bytes of scratch (included in
- *       ssd_query_sizes).  A scan call with fewer cell offsets per bin on
- *       average than SSD_TUNE_COUNTED_MIN_ITEMS (default 2048) stores
- *       uncounted (the counted stores cost a workgroup per bin); it, a router
+ *       Possible when eta >= 8 k (the counters take at most half the
+ *       state), the cell bits and counters of one bin fit a workgroup's LDS
+ *       (1024 (k + 32) bytes at 256 KiB bins and eta = 1024: k <= 119) and
+ *       the state fits 4096 bins; the counters take r * 2^q * k * 4 bytes of
+ *       scratch (included in ssd_query_sizes).  A scan call with fewer cell
+ *       offsets per bin on average than SSD_TUNE_COUNTED_MIN_ITEMS (default
+ *       2048 for detectors, 256 for batches, which scan each link once per
+ *       slice) stores uncounted (the counted stores cost a workgroup per
+ *       bin); it, a router
  *       merge into the detector, an advance-only close, a pass scan or a
  *       group call leaves the counters stale: the close reads the state,
  *       or, when every binned call of the slice was large, rebuilds the
@@ -275,7 +279,7 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       slice (fewer than 2^16 pairs in the call, or SSD_SCAN_PASSES) leaves
  *       its counters stale likewise. */
 #define SSD_TUNE_COUNTED 10u
-#define SSD_TUNE_COUNTED_MIN_ITEMS 11u   /* counted scans: offsets per bin a call needs (default 2048) */
+#define SSD_TUNE_COUNTED_MIN_ITEMS 11u   /* counted scans: offsets per bin a call needs (default 2048, batches 256) */
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 
 /* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per

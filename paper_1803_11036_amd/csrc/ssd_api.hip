@@ -148,6 +148,11 @@ constexpr uint64_t DEFAULT_COUNTED_BIN_BYTES = 512ull << 10;
 // full-state hot detection instead (the served streams' 64K-4M-pair calls:
 // counting at 256 slowed their per-stream closes eightfold).
 constexpr uint64_t DEFAULT_COUNTED_MIN_ITEMS = 2048;
+// Batches scan every link once per slice, so that a link's counted stores
+// cost their workgroups per bin once, against a read of its whole state at
+// the close when uncounted: a lower bar (on the 64-link batch, 256 and 0 both
+// count every link, 2048 leaves 4 large states of slow links to be read)
+constexpr uint64_t BATCH_COUNTED_MIN_ITEMS = 256;
 // Pairs binned per step, at most.  The stores of a bin are spread over the
 // workgroups of one XCD, so the work in flight is about (bins in flight) x
 // (items per bin): larger steps put more items in every bin (8M and 16M
@@ -198,11 +203,12 @@ BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
 // 1 MiB, 512 KiB and 256 KiB, those whose cell bits and counters fit one
 // workgroup's LDS and that give at most MAX_BINS bins; the largest of them
 // not above the request, else the smallest.  0 when none does or when the
-// counters would exceed an eighth of the state (eta < 32 k): the link cannot
+// counters would exceed half the state (eta < 8 k: summing them at the close
+// would read more than half of what reading the cells does): the link cannot
 // count.
 uint32_t counted_shift(const ssd_params& p, uint64_t want = 1ull << 20)
 {
-    if (32ull * p.k > p.eta || cell16(p)) return 0;     // 16-bit cells keep no counters
+    if (8ull * p.k > p.eta || cell16(p)) return 0;      // 16-bit cells keep no counters
     const uint32_t le = log2u(p.eta);
     uint32_t best = 0, smallest = 0;
     for (uint32_t sh = 20; sh >= 18; sh--) {
@@ -1604,7 +1610,7 @@ int ssd_set_tuning(ssd_detector* d, uint32_t knob, uint64_t value)
         return SSD_OK;
     case SSD_TUNE_COUNTED:
         if (value > 1) return fail(SSD_E_PARAM, "counted detection is 0 or 1");
-        if (value && !d->e.hl[0].counts) return fail(SSD_E_PARAM, "this detector cannot count (eta < 32 k or too many bins)");
+        if (value && !d->e.hl[0].counts) return fail(SSD_E_PARAM, "this detector cannot count (eta < 8 k, counters beyond the LDS, or too many bins)");
         if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
         if (d->e.counting[0] != (value != 0)) {
             d->e.counting[0] = value != 0;
@@ -1938,6 +1944,7 @@ int ssd_batch_init(const ssd_params* p, uint32_t n, const uint32_t* tables_host,
                      BATCH_STAGE, MAX_WINDOWS, BATCH_STAGE, bins);
     if (rc == SSD_OK) {
         b->e.use_graph = true;
+        b->e.counted_min_items = BATCH_COUNTED_MIN_ITEMS;
         for (int i = 0; i < 2 && rc == SSD_OK; i++) {
             hipError_t err = hipHostMalloc(&b->tile_pinned[i], 8 + MAX_WINDOWS * sizeof(ScanWindow), hipHostMallocDefault);
             if (err == hipSuccess) err = hipEventCreateWithFlags(&b->tile_done[i], hipEventDisableTiming);

@@ -100,13 +100,15 @@ def test_ragged_batches_and_empty_slices(splits, mode):
 
 
 @pytest.mark.parametrize("k,mode", [(1, "passes"), (3, "passes"), (17, "passes"), (254, "passes"),
-                                    (1, "counted"), (3, "counted"), (17, "counted")])
+                                    (1, "counted"), (3, "counted"), (17, "counted"), (64, "counted"),
+                                    (100, "counted")])
 def test_stamp_wrap_and_expiry(k, mode):
     """300 slices: the 8-bit slot stamps wrap (255 slots) and the rotating
     expiry must keep every cell's distance exact, for the discrete window
     (k = 1, Sec. 3.1), short and maximal windows -- also for R_k taken from
     the per-slot counters, whose slot of an old stamp rests on that
-    distance."""
+    distance, up to windows whose counters take 40% of the state (k = 100
+    at eta = 1024, 100 KiB of counters per 256 KiB bin)."""
     q, r, delta, eta, theta, kb = 8, 4, 4, 1024, 150, 16
     n = 300
     # about 0.15 * 2^q * theta distinct background pairs per window
@@ -365,7 +367,7 @@ def test_counted_after_advance_and_merge():
     next binned scan rebuilds them from the state, a close with no scan of
     its own detects from the whole state.  Every product equals the
     oracle's, and counting cannot be switched on for a detector whose
-    counters would exceed an eighth of its state (eta < 32 k)."""
+    counters would exceed half its state (eta < 8 k)."""
     q, r, delta, eta, k, theta, kb = 8, 4, 4, 1024, 3, 200, 16
     tabs = tg.hash_tables(9)
     g, o = make_pair(q, r, delta, eta, k, theta, tabs, key_bits=kb)
