@@ -113,10 +113,12 @@ def load_traffic(kernel: str, workload: str):
 
 
 def roofline(cands: dict, workload: str) -> dict:
-    """The roofline of the kernel with the most device time per step.
+    """The roofline of the kernel with the most device time per step among
+    those that move algorithmic bytes (the close's chain of small launches,
+    which moves none, is listed with the others).
     cands: name -> (device ms per step, algorithmic bytes per launch, ms per
     launch, launches per step, implementation bytes per launch or None)."""
-    dom = max(cands, key=lambda k: cands[k][0])
+    dom = max((k for k in cands if cands[k][1] > 0), key=lambda k: cands[k][0])
     _, alg, ms, per_step, impl = cands[dom]
     achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     traffic = load_traffic(dom, workload)
@@ -453,7 +455,9 @@ def run_batched(args) -> dict:
         ms, n_l = timing["scan"]
         per = max(1, n_l // K)
         impl = float(sum((6 if l in counted_links else 5) * cfgs[l].r * per_slice[l] for l in binned))
-        cands["binned_stores"] = (ms / K, bin_alg / per, ms / n_l, per, impl / per)
+        n_cnt = sum(1 for l in binned if l in counted_links)
+        stores = "k_apply_counted_multi" if n_cnt == len(binned) else "k_apply_multi" if n_cnt == 0 else "binned_stores"
+        cands[stores] = (ms / K, bin_alg / per, ms / n_l, per, impl / per)
     if timing["scan_bin"][1]:
         ms, n_l = timing["scan_bin"]
         per = max(1, n_l // K)
@@ -783,6 +787,8 @@ def run_distributed(args) -> dict:
     glob = ssd.init_detector(params, tabs, device=dev)
     for d in routers + [glob]:
         ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
+    if args.calibrate_copy_mib:
+        calibration_copy(dev, args.calibrate_copy_mib)
     W, K = args.warmup, args.steps
     t = 0
     n_timed = 0
@@ -807,13 +813,23 @@ def run_distributed(args) -> dict:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tg_ = ssd.read_timing(glob, reset=True)
-    scan_ms = sum(ssd.read_timing(d, reset=True)["scan"][0] for d in routers)
+    rt = [ssd.read_timing(d, reset=True) for d in routers]
+    # the routers' binned scans: k_bin, then the stores (k_apply; the routers
+    # only advance, so their counters go stale after the first close and
+    # their stores do not count)
+    apply_ms, apply_n = sum(x["scan"][0] for x in rt), sum(x["scan"][1] for x in rt)
+    bin_ms, bin_n = sum(x["scan_bin"][0] for x in rt), sum(x["scan_bin"][1] for x in rt)
+    scan_ms = apply_ms + bin_ms
+    pairs_call = sum(int(p.shape[0]) for p in slices[0]) / cfg.n_streams
     state = glob.state.numel()
     merge_ms = tg_["merge"][0] / max(1, tg_["merge"][1])
     merge_bytes = (cfg.n_streams + 1) * state          # every router state read, the global written
-    cands = {"k_merge": (tg_["merge"][0] / K, float(merge_bytes), merge_ms, 1, None),
-             "router_scans": (scan_ms / K, float(sum((8 + cfg.r) * int(p.shape[0]) for p in slices[0])),
-                              scan_ms / K, cfg.n_streams, None)}
+    cands = {"k_merge": (tg_["merge"][0] / K, float(merge_bytes), merge_ms, 1, None)}
+    if apply_n:
+        cands["k_apply"] = (apply_ms / K, (8 + cfg.r) * pairs_call, apply_ms / apply_n, apply_n // K,
+                            5 * cfg.r * pairs_call)
+    if bin_n:
+        cands["k_bin"] = (bin_ms / K, 8.0 * pairs_call, bin_ms / bin_n, bin_n // K, (8 + 4 * cfg.r) * pairs_call)
     if tg_["hot_detect"][1]:
         cands["k_hot_detect"] = (tg_["hot_detect"][0] / K, float(state), tg_["hot_detect"][0] / tg_["hot_detect"][1],
                                  1, None)
