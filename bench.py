@@ -496,7 +496,9 @@ def run_batched(args) -> dict:
                                    "p99": round(float(np.percentile(plain_close, 99)), 4),
                                    "note": "sum of the 64 per-link close calls of a slice"},
         "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1]} for k, v in timing.items() if v[1]},
-        "autotuned": {"pass_bytes": tuned[0], "tile_pairs": tuned[1]},
+        "autotuned": {"pass_bytes": tuned[0], "tile_pairs": tuned[1],
+                      "counted_bin_kib_links": {str(v): sum(1 for x in link_info if x["counted_bin_kib"] == v)
+                                                for v in sorted({x["counted_bin_kib"] for x in link_info})}},
         "links_binned": len(binned), "links_counted": len(counted_links),
         "roofline": roof,
         "end_to_end": e2e,

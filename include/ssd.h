@@ -115,7 +115,8 @@ typedef struct {
     uint32_t counted;        /* R_k of the last close: 0 read from the state,
                                 1 from the per-slot counters, 2 from counters
                                 rebuilt from the state first                  */
-    uint32_t reserved;
+    uint32_t counted_bin_kib; /* bin size (KiB of cells) of the last scan call
+                                that kept the counters, 0 if none            */
 } ssd_info;
 
 /* Sizes the caller must allocate on the device for params p: the estimator
@@ -237,8 +238,15 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
 #define SSD_TUNE_TIMING 3u          /* 1: time every phase with HIP events */
 #define SSD_TUNE_SCAN_TILE_PAIRS 4u /* batches: pairs per scan work tile (default 4096) */
 #define SSD_TUNE_GRAPH 5u           /* 1 (default) = replay the close as a HIP graph (detectors, batches) */
-#define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = time the candidate (pass window, tile)
-                                       pairs on the next scans and keep the fastest */
+#define SSD_TUNE_AUTOTUNE 6u        /* batches: 1 = tune on the next scans (reads 1 until
+                                       done, 9 to 11 scans): the tile scan's (pass window,
+                                       tile) pair, each of 9 timed on one scan; and the bin
+                                       size of the counted stores by class of binned links
+                                       (same q and eta, pairs per call in the same factor-4
+                                       band), timed on the whole binned scan: 256 KiB,
+                                       512 KiB and 1 MiB for every class, the fastest kept,
+                                       then the two others for each of the 4 classes with
+                                       the most pairs, kept when 1% faster */
 /*   SSD_TUNE_SCAN_MODE: SSD_SCAN_PASSES = pass windows as above;
  *       SSD_SCAN_BINNED = each call's pairs are first sorted by state bin
  *       (SSD_TUNE_SCAN_BIN_BYTES, a power of two, default 2 MiB), then each

@@ -63,7 +63,7 @@ class _Info(C.Structure):
     _fields_ = [("open_slice", C.c_uint64), ("hot_threshold", C.c_uint32), ("r", C.c_uint32),
                 ("state_bytes", C.c_uint64), ("level_counts", C.c_uint64 * 16),
                 ("hot_counts", C.c_uint32 * 16), ("accepted", C.c_uint64), ("reported", C.c_uint64),
-                ("counted", C.c_uint32), ("reserved", C.c_uint32)]
+                ("counted", C.c_uint32), ("counted_bin_kib", C.c_uint32)]
 
 
 assert C.sizeof(_SuperPoint) == RESULT_DTYPE.itemsize == 16
@@ -327,7 +327,7 @@ def _info_dict(info) -> Dict[str, object]:
     return {"open_slice": info.open_slice, "hot_threshold": info.hot_threshold,
             "state_bytes": info.state_bytes, "level_counts": list(info.level_counts)[:max(r - 2, 0)],
             "hot_counts": list(info.hot_counts)[:r], "accepted": info.accepted, "reported": info.reported,
-            "counted": info.counted}
+            "counted": info.counted, "counted_bin_kib": info.counted_bin_kib}
 
 
 SSD_TUNE_SCAN_PASS_BYTES = 1

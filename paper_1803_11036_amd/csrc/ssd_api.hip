@@ -16,7 +16,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -392,6 +394,8 @@ struct Engine {
     uint64_t counted_min_items = DEFAULT_COUNTED_MIN_ITEMS;   // offsets per bin a call needs to count
     std::vector<uint8_t> count_small;      // a call of this slice stored uncounted for being small
     std::vector<uint8_t> last_mode;        // hot detection of the last close: 0 state, 1 counters, 2 rebuilt
+    std::vector<uint64_t> bin_req;         // per link: bin size request of its counted scans (0: counted_bin_bytes)
+    std::vector<uint8_t> last_csh;         // per link: bin shift of its last counted binned call (0: none)
     uint32_t* cl_pinned = nullptr;         // staging of the counted-link list (2n + 1 words)
     hipEvent_t cl_done = nullptr;          // its last copy has run
     std::vector<LinkDesc> hl;          // host copies of the device descriptors
@@ -621,6 +625,8 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     e->count_rebuild.assign(n, 0);
     e->count_small.assign(n, 0);
     e->last_mode.assign(n, 0);
+    e->bin_req.assign(n, 0);
+    e->last_csh.assign(n, 0);
     for (uint32_t l = 0; l < n; l++)
         if (e->hl[l].counts) e->counting[l] = e->count_valid[l] = 1;
     e->detect_prefix = se_prefix;
@@ -674,7 +680,7 @@ struct BinnedCall {
 BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_bytes)
 {
     BinnedCall c;
-    c.csh = e->counting[l] ? counted_shift(e->p[l], e->counted_bin_bytes) : 0;
+    c.csh = e->counting[l] ? counted_shift(e->p[l], e->bin_req[l] ? e->bin_req[l] : e->counted_bin_bytes) : 0;
     c.large = c.csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << c.csh).n_bins;
     c.counted = e->counting[l] && e->count_valid[l] && c.large;
     c.bp = bin_plan(e->p[l], c.counted ? 1ull << c.csh : bin_bytes);
@@ -704,6 +710,7 @@ BinBufs engine_bins(const Engine* e)
 // count leave the counters stale.
 void binned_count_state(Engine* e, uint32_t l, const BinnedCall& c)
 {
+    if (c.counted) e->last_csh[l] = (uint8_t)c.csh;
     if (e->counting[l] && !c.counted) {
         e->count_valid[l] = 0;                 // these stores are not counted
         // the close rebuilds the counters from the state after large calls
@@ -1082,6 +1089,7 @@ void engine_info(const Engine& e, uint32_t l, ssd_info* out)
         out->reported = e.results[l].size();
         out->counted = e.last_mode[l];
     }
+    if (l < e.last_csh.size() && e.last_csh[l]) out->counted_bin_kib = 1u << (e.last_csh[l] - 10);
 }
 
 // R_k of link l at the last close (host copy).
@@ -1241,7 +1249,37 @@ struct ssd_batch {
     int tune_idx = -1;                 // next candidate to time, -1 = not tuning
     std::vector<std::pair<int, uint64_t>> tune_pending;   // (candidate, pairs) per timed scan
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tune_events;
+    // autotuner, second dimension: the bin size request of the counted binned
+    // stores, by class of binned links (same q and eta, pairs per call within
+    // the same factor-4 band).  Every trial times the whole binned scan of a
+    // tuning scan (the classes share its launches, so a class is only as fast
+    // as the launches it shares): trials 0-2 give every class bin candidate
+    // 0-2; then, for the TUNE_CLASSES classes with the most pairs in turn,
+    // each other candidate, kept when it beats the best so far by 1%.
+    struct BinTrial { uint64_t cls; int cand; };       // cls = NO_CLASS: every class
+    std::vector<BinTrial> bt_trials;
+    int bt_next = -1;                                  // next trial, -1 = none
+    std::map<uint64_t, int> bt_choice;                 // classes whose candidate differs from bt_global
+    int bt_global = 1;
+    double bt_best = -1.0, bt_global_ns[3] = {-1.0, -1.0, -1.0};
+    std::map<uint64_t, uint64_t> bt_class_pairs;       // pairs per class over the tuning scans
+    struct BinTiming { int trial; uint64_t pairs; hipEvent_t a, b; };
+    std::vector<BinTiming> bt_pending;
+    std::vector<uint64_t> link_class;                  // per link: its class in its last tuning scan
 };
+
+// Bin size candidates of the counted stores (a link takes the largest of
+// its sizes that fit, not above the candidate, else its smallest).
+constexpr uint64_t TUNE_BIN_BYTES[3] = {256ull << 10, 512ull << 10, 1ull << 20};
+constexpr uint64_t NO_CLASS = ~0ull;
+constexpr uint32_t TUNE_CLASSES = 4;
+
+// Tuning class of a binned link with n pairs in the call.
+static uint64_t tune_class(const ssd_params& p, uint64_t n)
+{
+    const uint64_t band = n ? (uint64_t)log2u(n) / 2u : 0u;
+    return ((uint64_t)p.q << 16) | ((uint64_t)log2u(p.eta) << 8) | band;
+}
 
 namespace {
 
@@ -1262,6 +1300,46 @@ void autotune_collect(ssd_batch* b)
     }
     b->tune_pending.clear();
     b->tune_events.clear();
+    for (const auto& c : b->bt_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c.a, c.b) == hipSuccess && c.pairs) {
+            const double ns = ms * 1e6 / (double)c.pairs;
+            const ssd_batch::BinTrial& tr = b->bt_trials[c.trial];
+            if (tr.cls == NO_CLASS) {
+                b->bt_global_ns[tr.cand] = ns;
+            } else if (ns < 0.99 * b->bt_best) {
+                b->bt_choice[tr.cls] = tr.cand;
+                b->bt_best = ns;
+            }
+        }
+        (void)hipEventDestroy(c.a);
+        (void)hipEventDestroy(c.b);
+        if (c.trial == 2) {
+            // the global candidates timed: keep the fastest, then try the
+            // others on the classes with the most pairs
+            int g = 1;
+            for (int i = 0; i < 3; i++)
+                if (b->bt_global_ns[i] >= 0 && (b->bt_global_ns[g] < 0 || b->bt_global_ns[i] < b->bt_global_ns[g])) g = i;
+            b->bt_global = g;
+            b->bt_best = b->bt_global_ns[g];
+            std::vector<std::pair<uint64_t, uint64_t>> by(b->bt_class_pairs.begin(), b->bt_class_pairs.end());
+            std::sort(by.begin(), by.end(), [](const auto& x, const auto& y) { return x.second > y.second; });
+            if (b->bt_best >= 0)
+                for (size_t i = 0; i < by.size() && i < TUNE_CLASSES; i++)
+                    for (int c2 = 0; c2 < 3; c2++)
+                        if (c2 != g) b->bt_trials.push_back({by[i].first, c2});
+        }
+    }
+    b->bt_pending.clear();
+    if (b->bt_next >= (int)b->bt_trials.size()) {
+        // every trial done: each tuned link takes its class's candidate
+        for (uint32_t l = 0; l < b->e.n; l++) {
+            if (b->link_class[l] == NO_CLASS) continue;
+            const auto it = b->bt_choice.find(b->link_class[l]);
+            b->e.bin_req[l] = TUNE_BIN_BYTES[it == b->bt_choice.end() ? b->bt_global : it->second];
+        }
+        b->bt_next = -1;
+    }
     if (b->tune_idx >= (int)b->cands.size()) {
         int best = 0;
         for (int i = 1; i < (int)b->cands.size(); i++)
@@ -1496,6 +1574,8 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
     e->count_rebuild.assign(n, 0);
     e->count_small.assign(n, 0);
     e->last_mode.assign(n, 0);
+    e->bin_req.assign(n, 0);
+    e->last_csh.assign(n, 0);
     e->detect_prefix = se_prefix;
     HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
     HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice,
@@ -2020,10 +2100,17 @@ int ssd_batch_set_tuning(ssd_batch* b, uint32_t knob, uint64_t value)
         return SSD_OK;
     }
     case SSD_TUNE_AUTOTUNE:
-        if (!value) { b->tune_idx = -1; return SSD_OK; }
+        if (!value) { b->tune_idx = -1; b->bt_next = -1; return SSD_OK; }
         b->cands.clear();
         for (uint64_t pass : {64ull << 20, 128ull << 20, 256ull << 20})
             for (uint64_t tile : {1024ull, 4096ull, 16384ull}) b->cands.push_back({pass, tile, -1.0});
+        b->bt_trials = {{NO_CLASS, 0}, {NO_CLASS, 1}, {NO_CLASS, 2}};
+        b->bt_next = 0;
+        b->bt_choice.clear();
+        b->bt_class_pairs.clear();
+        b->bt_best = -1.0;
+        for (double& x : b->bt_global_ns) x = -1.0;
+        b->link_class.assign(b->e.n, NO_CLASS);
         b->tune_idx = 0;
         return SSD_OK;
     default: return fail(SSD_E_PARAM, "unknown tuning knob %u", knob);
@@ -2038,7 +2125,7 @@ int ssd_batch_get_tuning(ssd_batch* b, uint32_t knob, uint64_t* value)
     case SSD_TUNE_SCAN_TILE_PAIRS: *value = b->tile_pairs; return SSD_OK;
     case SSD_TUNE_TIMING: *value = b->e.timing; return SSD_OK;
     case SSD_TUNE_GRAPH: *value = b->e.use_graph; return SSD_OK;
-    case SSD_TUNE_AUTOTUNE: *value = b->tune_idx >= 0; return SSD_OK;
+    case SSD_TUNE_AUTOTUNE: *value = b->tune_idx >= 0 || b->bt_next >= 0; return SSD_OK;
     case SSD_TUNE_COUNTED:
         *value = 0;
         for (uint32_t l = 0; l < b->e.n; l++) *value |= b->e.counting[l];
@@ -2144,7 +2231,39 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
             b->tune_events.push_back({ta, tb});
         }
     }
-    if (!binned.empty()) return enqueue_batch_binned(b, reinterpret_cast<const uint2*>(pairs_dev), offsets_host, binned);
+    if (binned.empty()) return SSD_OK;
+    const uint2* pp = reinterpret_cast<const uint2*>(pairs_dev);
+    if (b->bt_next < 0 || b->bt_next >= (int)b->bt_trials.size())
+        return enqueue_batch_binned(b, pp, offsets_host, binned);
+    // a bin-size trial: its candidate for its class (every class for the
+    // global trials), the kept choices for the others; the whole binned scan
+    // timed
+    const int trial = b->bt_next++;
+    const ssd_batch::BinTrial tr = b->bt_trials[trial];
+    uint64_t pairs = 0;
+    for (uint32_t l : binned) {
+        const uint64_t n = offsets_host[l + 1] - offsets_host[l];
+        const uint64_t key = tune_class(e->p[l], n);
+        b->link_class[l] = key;
+        b->bt_class_pairs[key] += n;
+        pairs += n;
+        int c = b->bt_global;
+        const auto it = b->bt_choice.find(key);
+        if (it != b->bt_choice.end()) c = it->second;
+        if (tr.cls == NO_CLASS || tr.cls == key) c = tr.cand;
+        e->bin_req[l] = TUNE_BIN_BYTES[c];
+    }
+    ssd_batch::BinTiming bt{trial, pairs, nullptr, nullptr};
+    HIPCHK(e, hipEventCreate(&bt.a));
+    if (hipEventCreate(&bt.b) != hipSuccess) {
+        (void)hipEventDestroy(bt.a);
+        return dev_fail(e, hipErrorOutOfMemory, "hipEventCreate");
+    }
+    b->bt_pending.push_back(bt);
+    HIPCHK(e, hipEventRecord(bt.a, e->stream));
+    rc = enqueue_batch_binned(b, pp, offsets_host, binned);
+    if (rc) return rc;
+    HIPCHK(e, hipEventRecord(bt.b, e->stream));
     return SSD_OK;
 }
 

@@ -61,6 +61,12 @@ def test_batch_equals_separate_detectors(graph, autotune):
     assert total > 100
     if autotune:
         assert ssd.batch_get_tuning(b, ssd.SSD_TUNE_AUTOTUNE) == 0        # finished, a candidate kept
+        # the counted links' bin sizes: each class's fastest candidate, kept
+        # after tuning (the lists above equal the separate detectors' through
+        # the tuning scans' changes of bin size)
+        kib = [ssd.batch_get_info(b, i)["counted_bin_kib"] for i in range(len(cfgs))]
+        log(f"autotuned counted bin sizes (KiB): {kib}")
+        assert any(kib) and set(kib) <= {0, 256, 512, 1024}
     b.destroy()
     for d in plain:
         d.destroy()
