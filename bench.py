@@ -155,13 +155,20 @@ def _probe_lib():
     L.ssd_probe_stream_read.restype = C.c_int
     L.ssd_probe_scatter.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p]
     L.ssd_probe_scatter.restype = C.c_int
+    L.ssd_probe_rmw16.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint64, C.c_void_p]
+    L.ssd_probe_rmw16.restype = C.c_int
     return L
 
 
+RMW_BIN_BYTES, RMW_OPS_PER_BIN = 512 << 10, 2048
+
+
 def ceilings(dev, sizes_mib, stores: int = 1 << 28, reps: int = 3) -> dict:
-    """Stream read (GB/s) and random byte scatter (G stores/s, uniform and
-    XCD-local) at each working-set size, timed with events on the stream the
-    probes run on (torch's current stream)."""
+    """Stream read (GB/s), random byte scatter (G stores/s, uniform and
+    XCD-local) and random 16-byte read-modify-writes in 512 KiB bins (G
+    chunks/s, 2048 per bin: about the density of the counted stores' visit)
+    at each working-set size, timed with events on the stream the probes run
+    on (torch's current stream)."""
     import torch
     L = _probe_lib()
     s = torch.cuda.current_stream(dev)
@@ -176,7 +183,9 @@ def ceilings(dev, sizes_mib, stores: int = 1 << 28, reps: int = 3) -> dict:
                          ("scatter_uniform_gstores", lambda: L.ssd_probe_scatter(buf.data_ptr(), nbytes, stores, 7, 0,
                                                                                  s.cuda_stream)),
                          ("scatter_xcd_local_gstores", lambda: L.ssd_probe_scatter(buf.data_ptr(), nbytes, stores, 7,
-                                                                                   1, s.cuda_stream))):
+                                                                                   1, s.cuda_stream)),
+                         ("rmw16_bins_gchunks", lambda: L.ssd_probe_rmw16(buf.data_ptr(), nbytes, RMW_BIN_BYTES,
+                                                                         RMW_OPS_PER_BIN, 7, s.cuda_stream))):
             if name == "scatter_xcd_local_gstores" and (nbytes < (16 << 20) or nbytes % (2 << 20)):
                 continue
             if fn() != 0:
@@ -191,7 +200,8 @@ def ceilings(dev, sizes_mib, stores: int = 1 << 28, reps: int = 3) -> dict:
                 b.synchronize()
                 ms = a.elapsed_time(b)
                 best = ms if best is None else min(best, ms)
-            res[name] = round((nbytes / 1e9 if name == "stream_read_gbs" else stores / 1e9) / (best * 1e-3), 2)
+            work = {"stream_read_gbs": nbytes, "rmw16_bins_gchunks": nbytes // RMW_BIN_BYTES * RMW_OPS_PER_BIN}
+            res[name] = round(work.get(name, stores) / 1e9 / (best * 1e-3), 2)
         out[f"{mib}MiB"] = res
         del buf
     torch.cuda.empty_cache()
@@ -261,22 +271,78 @@ def cpu_baseline_batched(cfgs, traces, tables) -> dict:
             "host": host_info()}
 
 
-def cpu_baseline_link(cfg, trace, tables, n_slices: int) -> dict:
-    """The oracle as it stands, one thread, on the first n_slices slices of a
-    single-link workload (scan + full close each)."""
+def cpu_baseline_link(cfg, trace, tables, n_slices: int, fill_s: float = 30.0, timed_s: float = 10.0) -> dict:
+    """The oracle as it stands, one thread, on a single-link workload: the
+    window filled first, untimed (k - 1 slices, or as many as fill_s seconds
+    allow), then scan + full close of each following slice timed, until
+    timed_s seconds or n_slices slices (at least one)."""
     import oracle
     o = oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tables)
-    slices = [trace.pairs(0, t) for t in range(n_slices)]
-    t0 = time.perf_counter()
-    n = 0
-    for p in slices:
+    t = 0
+    f0 = time.perf_counter()
+    while t < cfg.k - 1 and time.perf_counter() - f0 < fill_s:
+        o.scan(trace.pairs(0, t % cfg.n_slices))
+        o.close()
+        t += 1
+    filled = t
+    n, dt, timed = 0, 0.0, 0
+    while timed < max(1, n_slices) and (timed == 0 or dt < timed_s):
+        p = trace.pairs(0, t % cfg.n_slices)
+        t0 = time.perf_counter()
         o.scan(p)
         o.close()
+        dt += time.perf_counter() - t0
         n += p.shape[0]
-    dt = time.perf_counter() - t0
+        timed += 1
+        t += 1
     del o
+    window = "full window" if filled >= cfg.k - 1 else f"window filled to {filled + 1} of {cfg.k} slices"
     return {"value": round(n / dt, 1), "unit": "packets/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_slices} slices of the workload ({n} pairs), scan + full close each, "
+            "sample": f"{filled} slices filled untimed, then {timed} slices timed ({n} pairs, {window}), "
+                      f"scan + full close each, {dt:.1f} s on one host thread", "host": host_info()}
+
+
+def cpu_baseline_distributed(cfg, trace, tables, n_slices: int, n_routers: int = 4, fill_s: float = 30.0,
+                             timed_s: float = 10.0) -> dict:
+    """The oracle as it stands, one thread, on the distributed workload cut to
+    its first n_routers routers (the merge's work per pair does not depend
+    on the router count): per slice every router scans its pairs, the routers
+    are merged into the global detector (Alg. 5), which closes, and the
+    routers advance.  The window is filled untimed first, as for one link."""
+    import oracle
+    mk = lambda: oracle.RSEA(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tables)
+    routers = [mk() for _ in range(n_routers)]
+    glob = mk()
+
+    def step(t):
+        per = trace.pairs_all(t % cfg.n_slices)[:n_routers]
+        t0 = time.perf_counter()
+        for o, p in zip(routers, per):
+            o.scan(p)
+        glob.merge_from(routers)
+        glob.close()
+        for o in routers:
+            o.close(advance_only=True)
+        return time.perf_counter() - t0, sum(int(p.shape[0]) for p in per)
+
+    t = 0
+    f0 = time.perf_counter()
+    while t < cfg.k - 1 and time.perf_counter() - f0 < fill_s:
+        step(t)
+        t += 1
+    filled = t
+    n, dt, timed = 0, 0.0, 0
+    while timed < max(1, n_slices) and (timed == 0 or dt < timed_s):
+        d, m = step(t)
+        dt += d
+        n += m
+        timed += 1
+        t += 1
+    del routers, glob
+    window = "full window" if filled >= cfg.k - 1 else f"window filled to {filled + 1} of {cfg.k} slices"
+    return {"value": round(n / dt, 1), "unit": "packets/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_routers} of the {cfg.n_streams} routers; {filled} slices filled untimed, then {timed} "
+                      f"slices timed ({n} pairs, {window}): router scans, merge, global close and router advances, "
                       f"{dt:.1f} s on one host thread", "host": host_info()}
 
 
@@ -854,6 +920,7 @@ def run_distributed(args) -> dict:
                     "merge": {"ms_per_launch": round(merge_ms, 5), "launches": tg_["merge"][1]},
                     "global_hot_detect": {"ms_per_launch": round(tg_["hot_detect"][0] / max(1, tg_["hot_detect"][1]), 5)}},
         "roofline": roof,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_distributed(cfg, tr, tabs, args.cpu_slices),
     }
 
 
@@ -866,7 +933,8 @@ def main() -> int:
                     help="batched (default) | core_link | tiny | paper | distributed | served | ceilings")
     ap.add_argument("--latency-steps", type=int, default=10)
     ap.add_argument("--e2e-steps", type=int, default=12, help="steps of the pinned-host end-to-end run (0 = off)")
-    ap.add_argument("--cpu-slices", type=int, default=4, help="single-link workloads: oracle slices timed")
+    ap.add_argument("--cpu-slices", type=int, default=8,
+                    help="single-link workloads: oracle slices timed after the window is filled (at most, until 10 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="batched: skip the core-link secondary run")
     ap.add_argument("--no-ceilings", action="store_true", help="batched: skip the memory-ceiling probes")
@@ -908,7 +976,9 @@ def main() -> int:
         torch.cuda.set_device(dev)
         out = {"workload": "ceilings", "ceilings": ceilings(dev, [int(x) for x in args.ceiling_mib.split(",")]),
                "note": "stream read GB/s; byte scatter G stores/s (uniform over the buffer, and XCD-local: "
-                       "workgroups of one XCD store into 2 MiB regions its L2 holds, every region in turn)"}
+                       "workgroups of one XCD store into 2 MiB regions its L2 holds, every region in turn); "
+                       "16-byte read-modify-writes G chunks/s (one workgroup per 512 KiB bin, 2048 hashed chunks "
+                       "per bin, bins dealt to the XCDs as the counted stores deal theirs)"}
     else:
         out = run_core(args)
     print(json.dumps(out), flush=True)

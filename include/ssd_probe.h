@@ -33,6 +33,16 @@ int ssd_probe_stream_read(const void *buf_dev, uint64_t bytes, void *sink_dev, v
 int ssd_probe_scatter(void *buf_dev, uint64_t bytes, uint64_t n_stores, uint64_t seed, uint32_t xcd_local,
                       void *stream);
 
+/* Random 16-byte read-modify-writes in bins: buf_dev (bytes, a multiple of
+ * bin_bytes, 16-byte aligned) is cut into bins of bin_bytes (a power of two,
+ * 4 KiB to 1 GiB); one workgroup per bin, the bins dealt to the XCDs in
+ * contiguous eighths, loads ops_per_bin (at most 2^20) chunks of its bin at
+ * positions hashed from (seed, bin, op), changes and stores them.  The
+ * memory side of the counted stores' visit (one read and one write of
+ * every touched 16-byte chunk), at the same density. */
+int ssd_probe_rmw16(void *buf_dev, uint64_t bytes, uint64_t bin_bytes, uint32_t ops_per_bin, uint64_t seed,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,7 +4,12 @@
 //   - random byte scatter: n one-byte stores at counter-hashed positions,
 //     either uniform over the whole buffer or XCD-local (workgroup g stores
 //     only into a 2 MiB region of its own XCD, g mod 8, as the binned scan's
-//     stores do).
+//     stores do);
+//   - random 16-byte read-modify-write in bins: one 1024-thread workgroup
+//     per bin, bins dealt to the XCDs as the counted stores deal theirs, each
+//     workgroup loading, changing and storing hashed 16-byte chunks of its
+//     bin, four per thread in flight (the memory side of the counted stores'
+//     visit, without their offsets).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,6 +59,35 @@ __global__ __launch_bounds__(256) void k_probe_scatter(uint8_t* buf, uint64_t by
     }
 }
 
+// Workgroup g takes bin (g mod 8) * per_xcd + g / 8 of n_bins bins of
+// 2^bin_shift bytes and makes ops read-modify-writes of hashed chunks in it.
+__global__ __launch_bounds__(1024) void k_probe_rmw16(uint4* buf, uint64_t n_bins, uint32_t bin_shift, uint32_t ops,
+                                                      uint64_t seed)
+{
+    const uint64_t per_xcd = (n_bins + 7u) >> 3;
+    const uint64_t bin = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    if (bin >= n_bins) return;
+    uint4* base = buf + (bin << (bin_shift - 4u));
+    const uint64_t mask = (1ull << (bin_shift - 4u)) - 1u;
+    const uint64_t key = seed + bin * ops;
+    for (uint32_t i0 = threadIdx.x; i0 < ops; i0 += 4u * 1024u) {
+        uint4 v[4];
+        uint64_t at[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint32_t i = i0 + (uint32_t)u * 1024u;
+            at[u] = mix64(key + i) & mask;
+            if (i < ops) v[u] = base[at[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (i0 + (uint32_t)u * 1024u >= ops) continue;
+            v[u].x ^= 1u;
+            base[at[u]] = v[u];
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -84,6 +118,23 @@ int ssd_probe_scatter(void* buf_dev, uint64_t bytes, uint64_t n_stores, uint64_t
     if (blocks > 0x7FFFFFFFull) return -1;
     k_probe_scatter<<<(uint32_t)blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
         static_cast<uint8_t*>(buf_dev), bytes, n_stores, seed, region_shift, per);
+    return hipGetLastError() == hipSuccess ? 0 : -7;
+}
+
+int ssd_probe_rmw16(void* buf_dev, uint64_t bytes, uint64_t bin_bytes, uint32_t ops_per_bin, uint64_t seed,
+                    void* stream)
+{
+    if (!buf_dev || ((uintptr_t)buf_dev & 15u) || bin_bytes < 4096 || bin_bytes > (1ull << 30) ||
+        (bin_bytes & (bin_bytes - 1u)) || bytes < bin_bytes || (bytes & (bin_bytes - 1u)) || ops_per_bin == 0 ||
+        ops_per_bin > (1u << 20))
+        return -1;
+    uint32_t shift = 0;
+    while ((1ull << shift) < bin_bytes) shift++;
+    const uint64_t n_bins = bytes >> shift;
+    const uint64_t blocks = (n_bins + 7u) / 8u * 8u;
+    if (blocks > 0x7FFFFFFFull) return -1;
+    k_probe_rmw16<<<(uint32_t)blocks, 1024, 0, static_cast<hipStream_t>(stream)>>>(
+        static_cast<uint4*>(buf_dev), n_bins, shift, ops_per_bin, seed);
     return hipGetLastError() == hipSuccess ? 0 : -7;
 }
 
