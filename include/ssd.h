@@ -271,9 +271,12 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       counters and reads only the cells of hot estimators and of the
  *       estimators whose expiry phase it is, instead of the whole state.
  *       Possible when eta >= 8 k (the counters take at most half the
- *       state), the cell bits and counters of one bin fit a workgroup's LDS
- *       (1024 (k + 32) bytes at 256 KiB bins and eta = 1024: k <= 119) and
- *       the state fits 4096 bins; the counters take r * 2^q * k * 4 bytes of
+ *       state), eta <= 2^14, the cell bits and 16-bit counters of one bin
+ *       fit a workgroup's LDS (a bit per cell and 2 bytes per estimator and
+ *       slice: at 256 KiB bins 32 KiB + 512 k bytes for eta = 1024; bins
+ *       are chosen so that two workgroups share a compute unit where one
+ *       size allows it) and the state fits 4096 bins; the counters take
+ *       r * 2^q * k * 4 bytes of
  *       scratch (included in ssd_query_sizes).  A scan call with fewer cell
  *       offsets per bin on average than SSD_TUNE_COUNTED_MIN_ITEMS (default
  *       2048 for detectors, 256 for batches, which scan each link once per

@@ -157,13 +157,19 @@ struct CountMultiArgs {
 // starts 16-byte aligned
 __host__ __device__ inline uint64_t packed_seg_words(uint64_t n_items) { return ((n_items + 2) / 3 + 1) & ~1ull; }
 
-// LDS of the counted apply: a bit per cell of the bin, then a signed counter
-// per estimator of the bin and slot
+// LDS of the counted apply: a bit per cell of the bin, then a 16-bit counter
+// per estimator of the bin and slot, two to a word (each biased by 0x8000:
+// a counter moves by at most eta <= 2^14 in one call, so a half never carries
+// into the other)
 inline uint64_t counted_lds_bytes(uint32_t bin_shift, uint32_t log2eta, uint32_t k)
 {
-    return (1ull << (bin_shift - 3)) + (1ull << (bin_shift - log2eta)) * k * 4ull;
+    return (1ull << (bin_shift - 3)) + ((1ull << (bin_shift - log2eta)) * k + 1u) / 2u * 4ull;
 }
 constexpr uint32_t COUNTED_LDS_BYTES = 151u * 1024u;   // 160 KiB less the kernel's static list of marked words
+// at most this much dynamic LDS lets two counted workgroups (the most their
+// 16 waves allow) share a compute unit
+constexpr uint32_t COUNTED_LDS_PAIR = 71u * 1024u;
+constexpr uint32_t COUNTED_MAX_LOG2ETA = 14;          // counters in 16-bit halves: eta <= 2^14
 
 struct DetectArgs {
     const LinkDesc* links;

@@ -630,12 +630,20 @@ constexpr uint32_t CAPPLY_WAVES = 16;
 constexpr uint32_t CAPPLY_CHUNKS = 4;     // bitmap words per thread in flight in the visit
 constexpr uint32_t CAPPLY_LIST = 4096;    // marked words listed for the visit (more: the whole bitmap is swept)
 
+// Add d to 16-bit counter i of the LDS counters (two biased halves per word;
+// the halves never carry into each other, so a 32-bit add does it).
+__device__ __forceinline__ void cnt_add(uint32_t* cw, uint32_t i, int d)
+{
+    atomicAdd(&cw[i >> 1], (uint32_t)d << ((i & 1u) * 16u));
+}
+
 // The marked cells of one 4-byte word (mask m, a bit per byte): the new
 // stamps, the count of cells restamped, and -1 on the slot of every old stamp
-// still in the window.  Byte masks are formed SWAR; only the restamped cells
-// with an old stamp are visited one by one.
+// still in the window (counters ce0 + slot of the LDS counters cw).  Byte
+// masks are formed SWAR; only the restamped cells with an old stamp are
+// visited one by one.
 __device__ __forceinline__ uint32_t stamp_word(uint32_t x, uint32_t m, uint32_t stamp, uint32_t k, uint32_t slot,
-                                               int* ce, uint32_t& changed)
+                                               uint32_t* cw, uint32_t ce0, uint32_t& changed)
 {
     const uint32_t lanes = ((m * 0x00204081u) & 0x01010101u) * 0xFFu;       // bit i of m -> byte i
     const uint32_t y = x ^ (stamp * 0x01010101u);
@@ -649,7 +657,7 @@ __device__ __forceinline__ uint32_t stamp_word(uint32_t x, uint32_t m, uint32_t 
         old &= old - 1u;
         const uint32_t b = (x >> (8u * i)) & 0xFFu;
         const uint32_t d = (stamp + 255u - b) % 255u;      // slices since the old stamp
-        if (d < k) atomicSub(&ce[slot >= d ? slot - d : slot + k - d], 1);
+        if (d < k) cnt_add(cw, ce0 + (slot >= d ? slot - d : slot + k - d), -1);
     }
     return (x & ~chg) | ((stamp * 0x01010101u) & chg);
 }
@@ -677,9 +685,9 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
     const uint32_t bm_words = 1u << (a.bin_shift - 5u);
     const uint32_t n_est = 1u << (a.bin_shift - a.log2eta);
     const uint32_t k = a.k, slot = a.slot;
-    const uint32_t n_words = bm_words + n_est * k;
+    const uint32_t n_words = bm_words + (n_est * k + 1u) / 2u;
     uint32_t* bm = lds;
-    int* cnt = reinterpret_cast<int*>(lds + bm_words);
+    uint32_t* cnt = lds + bm_words;                 // 16-bit counters [estimator][slot], biased by 0x8000
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
     // this lane's run (segment j) of the wave's first group, loaded before the
@@ -689,7 +697,7 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
         st = row[j];
         c = row[a.blocks + j] - st;
     }
-    for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) lds[i] = 0u;
+    for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) lds[i] = i < bm_words ? 0u : 0x80008000u;
     if (threadIdx.x == 0) n_list = 0u;
     __syncthreads();
     // walk: lane j reads run j itself, four aligned 16-byte loads (24 offsets)
@@ -769,7 +777,7 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
 #pragma unroll
         for (int u = 0; u < (int)CAPPLY_CHUNKS; u++) {
             if (!m[u]) continue;
-            int* ce = cnt + ((wd[u] << 5) >> a.log2eta) * k;
+            const uint32_t ce0 = ((wd[u] << 5) >> a.log2eta) * k;
             uint32_t changed = 0;
 #pragma unroll
             for (int h = 0; h < 2; h++) {
@@ -777,13 +785,13 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
                 if (!mh) continue;
                 uint4& x = v[2 * u + h];
                 const uint32_t before = changed;
-                x.x = stamp_word(x.x, mh & 0xFu, stamp, k, slot, ce, changed);
-                x.y = stamp_word(x.y, (mh >> 4) & 0xFu, stamp, k, slot, ce, changed);
-                x.z = stamp_word(x.z, (mh >> 8) & 0xFu, stamp, k, slot, ce, changed);
-                x.w = stamp_word(x.w, (mh >> 12) & 0xFu, stamp, k, slot, ce, changed);
+                x.x = stamp_word(x.x, mh & 0xFu, stamp, k, slot, cnt, ce0, changed);
+                x.y = stamp_word(x.y, (mh >> 4) & 0xFu, stamp, k, slot, cnt, ce0, changed);
+                x.z = stamp_word(x.z, (mh >> 8) & 0xFu, stamp, k, slot, cnt, ce0, changed);
+                x.w = stamp_word(x.w, (mh >> 12) & 0xFu, stamp, k, slot, cnt, ce0, changed);
                 if (changed != before) dirty |= 1u << (2 * u + h);
             }
-            if (changed) atomicAdd(&ce[slot], (int)changed);
+            if (changed) cnt_add(cnt, ce0 + slot, (int)changed);
         }
     }
     // every chunk load is waited for here, before any store or counter atomic
@@ -795,8 +803,8 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
     // (slot-major in memory: consecutive threads take consecutive estimators)
     uint32_t* dst = a.counts + ((uint64_t)bin << (a.bin_shift - a.log2eta));
     for (uint32_t i = threadIdx.x; i < n_est * k; i += blockDim.x) {
-        const uint32_t j = i / n_est, e = i - j * n_est;
-        const int c = cnt[e * k + j];
+        const uint32_t j = i / n_est, e = i - j * n_est, c16 = e * k + j;
+        const int c = (int)((cnt[c16 >> 1] >> ((c16 & 1u) * 16u)) & 0xFFFFu) - 0x8000;
         if (c) atomicAdd(&dst[(uint64_t)j * a.n_se + e], (uint32_t)c);
     }
 #pragma unroll

@@ -204,22 +204,28 @@ BinPlan bin_plan(const ssd_params& p, uint64_t bin_bytes)
 // Bin size of the counted scan (k_apply_counted) for a bin size request: of
 // 1 MiB, 512 KiB and 256 KiB, those whose cell bits and counters fit one
 // workgroup's LDS and that give at most MAX_BINS bins; the largest of them
-// not above the request, else the smallest.  0 when none does or when the
-// counters would exceed half the state (eta < 8 k: summing them at the close
-// would read more than half of what reading the cells does): the link cannot
-// count.
+// not above the request whose LDS lets two workgroups share a compute unit,
+// else the largest not above the request, else the smallest.  0 when none
+// fits, when eta > 2^14 (16-bit LDS counters) or when the counters would
+// exceed half the state (eta < 8 k: summing them at the close would read
+// more than half of what reading the cells does): the link cannot count.
 uint32_t counted_shift(const ssd_params& p, uint64_t want = 1ull << 20)
 {
     if (8ull * p.k > p.eta || cell16(p)) return 0;      // 16-bit cells keep no counters
     const uint32_t le = log2u(p.eta);
-    uint32_t best = 0, smallest = 0;
+    if (le > COUNTED_MAX_LOG2ETA) return 0;
+    uint32_t pair = 0, best = 0, smallest = 0;
     for (uint32_t sh = 20; sh >= 18; sh--) {
-        if (sh < le || counted_lds_bytes(sh, le, p.k) > COUNTED_LDS_BYTES) continue;
+        const uint64_t lds = counted_lds_bytes(sh, le, p.k);
+        if (sh < le || lds > COUNTED_LDS_BYTES) continue;
         if (bin_plan(p, 1ull << sh).shift != sh) break;   // more bins than MAX_BINS, and more below
         smallest = sh;
-        if (!best && (1ull << sh) <= want) best = sh;
+        if ((1ull << sh) <= want) {
+            if (!best) best = sh;
+            if (!pair && lds <= COUNTED_LDS_PAIR) pair = sh;
+        }
     }
-    return best ? best : smallest;
+    return pair ? pair : best ? best : smallest;
 }
 // Item and table words that every allowed bin size fits, for chunks of up to
 // BIN_CHUNK_PAIRS pairs (fewer for small states).
@@ -1396,7 +1402,8 @@ int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offse
     ApplyArgs* ha = reinterpret_cast<ApplyArgs*>(host + app_region);
     uint32_t* hp = reinterpret_cast<uint32_t*>(host + pre_region);
     struct Launch {
-        uint32_t kind;        // 6, 5, 0: binning variant; 10 counted stores; 11 uncounted stores
+        uint32_t kind;        // 6, 5, 0: binning variant; 10, 12 counted stores (LDS for two workgroups per
+                              // compute unit, more); 11 uncounted stores
         uint32_t first, count, pre, total_wg, lds;
     };
     std::vector<Launch> launches;
@@ -1445,16 +1452,22 @@ int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offse
             np_words += L.count + 1;
             launches.push_back(L);
         }
-        // stores: counted, then uncounted
-        for (uint32_t kind : {10u, 11u}) {
+        // stores: counted (the links whose LDS lets two workgroups share a
+        // compute unit, then the others: a launch's LDS is its largest
+        // link's), then uncounted
+        auto kind_of = [](const ApplyArgs& y) {
+            if (!y.counts) return 11u;
+            return counted_lds_bytes(y.bin_shift, y.log2eta, y.k) <= COUNTED_LDS_PAIR ? 10u : 12u;
+        };
+        for (uint32_t kind : {10u, 12u, 11u}) {
             Launch L{kind, na, 0, np_words, 0, 0};
             for (const ApplyArgs& y : aa) {
-                if ((y.counts != nullptr) != (kind == 10u)) continue;
+                if (kind_of(y) != kind) continue;
                 ha[na++] = y;
                 hp[np_words + L.count] = L.total_wg;
                 L.count++;
-                L.total_wg += kind == 10u ? apply_counted_workgroups(y) : apply_workgroups(y);
-                if (kind == 10u)
+                L.total_wg += kind == 11u ? apply_workgroups(y) : apply_counted_workgroups(y);
+                if (kind != 11u)
                     L.lds = std::max<uint32_t>(L.lds, (uint32_t)counted_lds_bytes(y.bin_shift, y.log2eta, y.k));
             }
             if (!L.count) continue;
@@ -1475,7 +1488,7 @@ int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offse
             PhaseMark pm = phase_begin(e);
             if (L.kind >= 10u) {
                 MultiApplyArgs m{da + L.first, dp + L.pre, L.count};
-                HIPCHK(e, L.kind == 10u ? launch_apply_counted_multi(m, L.total_wg, L.lds, e->stream)
+                HIPCHK(e, L.kind != 11u ? launch_apply_counted_multi(m, L.total_wg, L.lds, e->stream)
                                         : launch_apply_multi(m, L.total_wg, e->stream));
                 phase_end(e, pm, 0, 1);
             } else {
