@@ -536,7 +536,9 @@ def run_batched(args) -> dict:
     if timing["count_detect"][1]:
         ms, n_l = timing["count_detect"]
         per = max(1, n_l // K)
-        cnt = float(sum((cfgs[l].r << cfgs[l].q) * (4 * cfgs[l].k + 8) for l in counted_links))
+        # per estimator: the live-cell total and the next slice's slot read,
+        # both and R_k written (20 bytes)
+        cnt = float(sum((cfgs[l].r << cfgs[l].q) * 20 for l in counted_links))
         cands["k_count_multi"] = (ms / K, cnt / per, ms / n_l, per, cnt / per)
     if timing["close_graph"][1]:
         ms = timing["close_graph"][0]
@@ -741,7 +743,7 @@ def run_core(args, secondary: bool = False) -> dict:
         ms = timing["count_detect"][0]
         n_se = cfg.r << cfg.q
         n_hot = sum(info["hot_counts"][:cfg.r])
-        impl = n_se * (4 * cfg.k + 8) + n_hot * (cfg.eta + cfg.eta // 8) + n_se / (255 - cfg.k) * cfg.eta
+        impl = n_se * 20 + n_hot * (cfg.eta + cfg.eta // 8) + n_se / (255 - cfg.k) * cfg.eta
         # R_k of every estimator from its counters instead of the state: the
         # bytes it reads and writes (counters, hot and expiring estimators'
         # cells, snapshots) stand for its work

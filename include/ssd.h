@@ -253,8 +253,9 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       bin's stores are made by workgroups of one XCD, inside its L2;
  *       SSD_SCAN_AUTO (default) = binned for states above 256 MiB, else passes
  *       (batches: every link with at least 2^16 pairs in the call is scanned
- *       binned, all such links together -- one binning launch per binning
- *       variant and one store launch per kind, 2 MiB bins -- the others in
+ *       binned, all such links together -- per group of links whose staging
+ *       fits, one binning launch and one store launch per kind, 2 MiB bins
+ *       uncounted -- the others in
  *       the tile scan; batches take SSD_SCAN_PASSES or SSD_SCAN_AUTO). */
 #define SSD_TUNE_SCAN_MODE 7u
 #define SSD_TUNE_SCAN_BIN_BYTES 8u
@@ -275,8 +276,9 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       fit a workgroup's LDS (a bit per cell and 2 bytes per estimator and
  *       slice: at 256 KiB bins 32 KiB + 512 k bytes for eta = 1024; bins
  *       are chosen so that two workgroups share a compute unit where one
- *       size allows it) and the state fits 4096 bins; the counters take
- *       r * 2^q * k * 4 bytes of
+ *       size allows it) and the state fits 4096 bins; the counters (k
+ *       per-slice slots and a live-cell total) take r * 2^q * (k + 1) * 4
+ *       bytes of
  *       scratch (included in ssd_query_sizes).  A scan call with fewer cell
  *       offsets per bin on average than SSD_TUNE_COUNTED_MIN_ITEMS (default
  *       2048 for detectors, 256 for batches, which scan each link once per

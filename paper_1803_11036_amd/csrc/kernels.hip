@@ -522,6 +522,21 @@ __global__ __launch_bounds__(1024) void k_bin_multi(MultiBinArgs m)
     else bin_reg<R, PPT>(a, g, lds, wsum);
 }
 
+// Every binning variant in one launch: each workgroup takes its link's (the
+// register binning of five or six rows where the segment fits it, else the
+// general one); the launch keeps the larger register count of the two.
+__global__ __launch_bounds__(1024) void k_bin_multi_rows(MultiBinArgs m)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wsum[16];
+    const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
+    const BinArgs a = m.args[l];
+    const uint32_t g = blockIdx.x - m.wg_prefix[l];
+    if (a.r == 6 && a.pb <= 6u * 1024u) bin_reg<6, 6>(a, g, lds, wsum);
+    else if (a.r == 5 && a.pb <= 7u * 1024u) bin_reg<5, 7>(a, g, lds, wsum);
+    else bin_generic(a, g, lds, wsum);
+}
+
 // One wave per workgroup.  Workgroup g: XCD g mod 8, the (g mod 8) + 8 * (w /
 // parts)-th bin from the top with w = g / 8, segments [part * per_part, ...),
 // 64 segments per round: lane j holds segment j's run of the bin, and the
@@ -802,9 +817,20 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
     // counters added without waiting for them (atomics whose result is unused)
     // (slot-major in memory: consecutive threads take consecutive estimators)
     uint32_t* dst = a.counts + ((uint64_t)bin << (a.bin_shift - a.log2eta));
-    for (uint32_t i = threadIdx.x; i < n_est * k; i += blockDim.x) {
-        const uint32_t j = i / n_est, e = i - j * n_est, c16 = e * k + j;
-        const int c = (int)((cnt[c16 >> 1] >> ((c16 & 1u) * 16u)) & 0xFFFFu) - 0x8000;
+    for (uint32_t i = threadIdx.x; i < n_est * (k + 1u); i += blockDim.x) {
+        const uint32_t j = i / n_est, e = i - j * n_est;
+        int c = 0;
+        if (j < k) {
+            const uint32_t c16 = e * k + j;
+            c = (int)((cnt[c16 >> 1] >> ((c16 & 1u) * 16u)) & 0xFFFFu) - 0x8000;
+        } else {
+            // slot k: the estimator's live-cell total, moved by the sum of its
+            // slots' moves (+1 for every cell that was not live before)
+            for (uint32_t jj = 0; jj < k; jj++) {
+                const uint32_t c16 = e * k + jj;
+                c += (int)((cnt[c16 >> 1] >> ((c16 & 1u) * 16u)) & 0xFFFFu) - 0x8000;
+            }
+        }
         if (c) atomicAdd(&dst[(uint64_t)j * a.n_se + e], (uint32_t)c);
     }
 #pragma unroll
@@ -1069,13 +1095,14 @@ __global__ __launch_bounds__(64 * DETECT_WAVES) void k_hot_detect16(DetectArgs a
 }
 
 // ---------------------------------------------------------------- counted detection
-// R_k of every estimator from its per-slot counters (one thread per
-// estimator): the same live-cell count as a scan of the state, since every
-// live cell carries the stamp of exactly one slice of the window.  Only the
-// estimators that need their cells are then visited, by the workgroup's four
-// waves in turn: hot ones (snapshot and bitmask bits) and those of this
-// slot's expiry phase (dead cells cleared).  The slot of the next slice is
-// zeroed for its scans.
+// R_k of every estimator from its counters (one thread per estimator): slot
+// k holds the live-cell total, which every store moves by the sum of its
+// moves of the per-slice slots -- the same live-cell count as a scan of the
+// state, since every live cell carries the stamp of exactly one slice of the
+// window.  Only the estimators that need their cells are then visited, by
+// the workgroup's four waves in turn: hot ones (snapshot and bitmask bits)
+// and those of this slot's expiry phase (dead cells cleared).  The slot of
+// the next slice leaves the total and is zeroed for its scans.
 // (workgroup blk of this link's launch; todo / todo_live / n_todo: the
 // workgroup's list of estimators to visit)
 __device__ __forceinline__ void count_body(const LinkDesc* D, uint64_t n_se, uint32_t blk, uint32_t* todo,
@@ -1088,8 +1115,10 @@ __device__ __forceinline__ void count_body(const LinkDesc* D, uint64_t n_se, uin
     const uint32_t k = D->k;
     const uint32_t next = (uint32_t)((D->clock->t + 1ull) % k);
     if (s < n_se) {
-        uint32_t live = 0;
-        for (uint32_t j = 0; j < k; j++) live += D->counts[(uint64_t)j * n_se + s];
+        // the live-cell total (slot k) is R_k; the slot of the next slice,
+        // whose cells leave the window, leaves the total and is zeroed
+        const uint32_t live = D->counts[(uint64_t)k * n_se + s];
+        D->counts[(uint64_t)k * n_se + s] = live - D->counts[(uint64_t)next * n_se + s];
         D->counts[(uint64_t)next * n_se + s] = 0u;
         const bool hot = live >= D->T;
         const bool expire = (s % D->expire_period) == D->expire_phase;
@@ -1166,6 +1195,7 @@ __global__ __launch_bounds__(256) void k_recount(const LinkDesc* link, uint64_t 
     const uint32_t slot = (uint32_t)(t % k);
     const uint32_t chunks = 1u << (D->log2eta - 4);
     const uint4* se = reinterpret_cast<const uint4*>(D->state + (s << D->log2eta));
+    uint32_t total = 0;
     for (uint32_t j = 0; j < k; j++) {
         const uint32_t d = slot >= j ? slot - j : slot + k - j;   // slices back from t
         uint32_t n = 0;
@@ -1177,8 +1207,10 @@ __global__ __launch_bounds__(256) void k_recount(const LinkDesc* link, uint64_t 
             }
         }
         n = wave_sum(n);
+        total += n;
         if (lane == 0) D->counts[(uint64_t)j * n_se + s] = n;
     }
+    if (lane == 0) D->counts[(uint64_t)k * n_se + s] = total;      // the live-cell total
 }
 
 // ---------------------------------------------------------------- hot lists
@@ -1864,7 +1896,8 @@ static hipError_t bin_lds_attr()
     for (const void* f : {reinterpret_cast<const void*>(&k_bin<0, 0>), reinterpret_cast<const void*>(&k_bin<6, 6>),
                           reinterpret_cast<const void*>(&k_bin<5, 7>), reinterpret_cast<const void*>(&k_bin_multi<0, 0>),
                           reinterpret_cast<const void*>(&k_bin_multi<6, 6>),
-                          reinterpret_cast<const void*>(&k_bin_multi<5, 7>)}) {
+                          reinterpret_cast<const void*>(&k_bin_multi<5, 7>),
+                          reinterpret_cast<const void*>(&k_bin_multi_rows)}) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
         if (e != hipSuccess) return e;
     }
@@ -1905,6 +1938,7 @@ hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t variant, uint32_t to
     switch (variant) {
     case 6: k_bin_multi<6, 6><<<total_wg, 1024, bytes, s>>>(m); break;
     case 5: k_bin_multi<5, 7><<<total_wg, 1024, bytes, s>>>(m); break;
+    case 1: k_bin_multi_rows<<<total_wg, 1024, bytes, s>>>(m); break;
     default: k_bin_multi<0, 0><<<total_wg, 1024, bytes, s>>>(m); break;
     }
     return hipGetLastError();

@@ -325,7 +325,8 @@ Layout plan(const ssd_params* p, uint32_t n, uint64_t pack_cap, uint64_t tile_ca
         K.out = o; o = align_up(o + q.max_results * sizeof(SuperPointDev));
         // per-slot counters for the links whose scans are binned (single
         // detectors; batch links above the binned threshold) and can count
-        if (bins && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * q.k * 4); }
+        // (k per-slice slots and the live-cell total)
+        if (bins && counted_shift(q)) { K.counts = o; o = align_up(o + n_se * (q.k + 1ull) * 4); }
     }
     uint64_t pw = 1;
     while (pw < maxres) pw <<= 1;
@@ -1361,7 +1362,7 @@ void autotune_collect(ssd_batch* b)
 // The binned scan of the batch's links `links` (each with enough pairs in
 // this call; offsets as in ssd_batch_scan).  The links are packed, in order,
 // into groups whose staging fits the batch's bin buffers; a group takes one
-// binning launch per binning variant and one store launch per kind (counted,
+// binning launch and one store launch per kind (counted, in two LDS classes;
 // uncounted), every workgroup finding its link in the launch's workgroup
 // prefix.  A link whose staging alone exceeds the buffers (or whose offsets
 // are not packed) is scanned on its own, in steps.
@@ -1402,8 +1403,8 @@ int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offse
     ApplyArgs* ha = reinterpret_cast<ApplyArgs*>(host + app_region);
     uint32_t* hp = reinterpret_cast<uint32_t*>(host + pre_region);
     struct Launch {
-        uint32_t kind;        // 6, 5, 0: binning variant; 10, 12 counted stores (LDS for two workgroups per
-                              // compute unit, more); 11 uncounted stores
+        uint32_t kind;        // 1: binning (every variant); 10, 12 counted stores (LDS for two workgroups
+                              // per compute unit, more); 11 uncounted stores
         uint32_t first, count, pre, total_wg, lds;
     };
     std::vector<Launch> launches;
@@ -1437,17 +1438,15 @@ int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offse
             io += p.items;
             to += p.table;
         }
-        // binning: one launch per variant
-        for (uint32_t v : {6u, 5u, 0u}) {
-            Launch L{v, nb, 0, np_words, 0, 0};
+        // binning: one launch, each workgroup in its link's variant
+        {
+            Launch L{1u, nb, 0, np_words, 0, 0};
             for (const BinArgs& x : ba) {
-                if (bin_variant(x) != v) continue;
                 hb[nb++] = x;
                 hp[np_words + L.count] = L.total_wg;
                 L.count++;
                 L.total_wg += bin_workgroups(x);
             }
-            if (!L.count) continue;
             hp[np_words + L.count] = L.total_wg;
             np_words += L.count + 1;
             launches.push_back(L);

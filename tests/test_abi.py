@@ -140,7 +140,8 @@ def test_init_rejects_before_touching_the_device():
 
 
 def test_counter_scratch_only_for_detectors_that_can_count():
-    """The per-slot counters (u32 per estimator and window slice) are part of
+    """The per-slot counters (u32 per estimator and window slice, and a live-
+    cell total per estimator) are part of
     the scratch exactly when they take at most half the state (eta >= 8 k),
     eta <= 2^14 (16-bit counters in LDS) and the cell bits and counters of a
     256 KiB bin fit a workgroup's LDS (32 KiB + 512 bytes per window slice at
@@ -149,8 +150,8 @@ def test_counter_scratch_only_for_detectors_that_can_count():
     def scratch(k, eta=1024):
         return ssd.query_sizes(_p(k=k, eta=eta))[1]
     n_se = 6 << 12
-    assert scratch(4) - scratch(129) == n_se * 4 * 4           # k = 4: counted; k = 129 > 1024 / 8: not
-    assert scratch(128) - scratch(129) == n_se * 128 * 4       # the largest window that counts at eta 1024
+    assert scratch(4) - scratch(129) == n_se * 5 * 4           # k = 4: counted; k = 129 > 1024 / 8: not
+    assert scratch(128) - scratch(129) == n_se * 129 * 4       # the largest window that counts at eta 1024
     # eta = 4096: every 8-bit window counts (k = 254 at 256 KiB bins: 32 KiB + 254 * 128 bytes)
     assert scratch(254, 4096) - scratch(4, 4096) == n_se * 250 * 4
     # eta = 2^15: no counters, whatever the window

@@ -74,8 +74,8 @@ def test_batch_equals_separate_detectors(graph, autotune):
 
 def test_batch_binned_links_equal_separate_detectors():
     """Links with at least 2^16 pairs in the call take the binned scan inside
-    the batch -- all of them together, one binning launch per binning variant
-    and one store launch per kind -- keeping per-slot counters where they can
+    the batch -- all of them together, one binning launch and one store launch
+    per kind for each group of links -- keeping per-slot counters where they can
     (the rest the tile scan, with hot detection over their states).  Binned
     links that get fewer pairs in a slice are tile-scanned: their counters go
     stale, and the close after their next binned scan rebuilds them;
@@ -128,7 +128,7 @@ def test_batch_binned_links_equal_separate_detectors():
         if cut:
             assert tm["scan_bin"][1] == 0 and tm["scan_tiles"][1] == 1
         else:
-            assert 1 <= tm["scan_bin"][1] <= 3                 # one binning launch per variant
+            assert 1 <= tm["scan_bin"][1] <= 3                 # one binning launch per group of links
     b.destroy()
     for d in plain:
         d.destroy()
