@@ -528,7 +528,7 @@ def run_batched(args) -> dict:
         ms, n_l = timing["scan_bin"]
         per = max(1, n_l // K)
         impl = float(sum((8 + 4 * cfgs[l].r) * per_slice[l] for l in binned))
-        cands["k_bin_multi"] = (ms / K, 8.0 * sum(per_slice[l] for l in binned) / per, ms / n_l, per, impl / per)
+        cands["k_bin_multi_rows"] = (ms / K, 8.0 * sum(per_slice[l] for l in binned) / per, ms / n_l, per, impl / per)
     if timing["hot_detect"][1]:
         ms = timing["hot_detect"][0]
         read = float(sum(c.r * (1 << c.q) * c.eta for l, c in enumerate(cfgs) if l not in counted_links))
