@@ -203,6 +203,26 @@ int ssd_get_results(ssd_detector *d, ssd_super_point *out_host, uint64_t cap, ui
  * include global. */
 int ssd_merge_router_state(ssd_detector *global, ssd_detector *const *routers, uint32_t n);
 
+/* Checkpoint and resume.  The paper's distance recorders are set up once and
+ * then only stored to (Sec. 3.2), so a detector is its parameters, its hash
+ * tables, its open slice and its state.  The blob: an 80-byte header (format, the
+ * parameters' geometry, window, threshold, key width, flags and cell width,
+ * a hash of the tables, the open slice), then the state bytes as they lie in
+ * HBM (little-endian host).  The per-slot counters of a counting detector
+ * are not in it: the importing detector takes them as stale (rebuilt from
+ * the state after its next large binned call, else its next close reads the
+ * state), which changes no result.
+ * ssd_export_state: *n_out = the blob's size; the blob is written to
+ * out_host (host) when cap is at least that, else SSD_E_TRUNC.  No close may
+ * be pending (SSD_E_ORDER); waits for the detector's stream.
+ * ssd_import_state: the blob of ssd_export_state (n bytes, host) into a
+ * detector made with the same parameters and tables (SSD_E_INCOMPAT
+ * otherwise; SSD_E_PARAM for a blob of another format or size); no close
+ * pending.  The detector then continues from the blob's open slice exactly as
+ * the exporting detector would: same states, same lists.  Synchronous. */
+int ssd_export_state(ssd_detector *d, void *out_host, uint64_t cap, uint64_t *n_out);
+int ssd_import_state(ssd_detector *d, const void *blob_host, uint64_t n);
+
 /* Parity and inspection. */
 
 /* Canonical window state of the open slice t, after its scans and before its

@@ -22,7 +22,7 @@ import torch
 __all__ = [
     "SSD_VERIFY_REHASH", "SSD_ADVANCE_ONLY", "SSDError", "Params", "make_params",
     "query_sizes", "Detector", "init_detector", "scan_slice", "scan_slice_noalloc", "close_slice", "close_begin", "close_end",
-    "get_results", "merge_router_state", "read_canonical_state", "read_rk",
+    "get_results", "merge_router_state", "read_canonical_state", "read_rk", "export_state", "import_state",
     "read_hot", "read_tuples", "get_info", "set_tuning", "destroy",
     "SSD_TUNE_SCAN_PASS_BYTES", "SSD_TUNE_SORT_BLOCK_LIMIT", "SSD_TUNE_TIMING", "read_timing",
     "SSD_TUNE_SCAN_TILE_PAIRS", "SSD_TUNE_GRAPH", "SSD_TUNE_AUTOTUNE", "PHASES",
@@ -42,8 +42,10 @@ _LIB_PATH = os.path.join(_HERE, "libssd.so")
 SSD_ABI_VERSION = 1
 SSD_VERIFY_REHASH = 0x1
 SSD_ADVANCE_ONLY = 0x1
-SSD_E_TRUNC = -6
+SSD_E_PARAM, SSD_E_NOMEM, SSD_E_ORDER, SSD_E_OVERFLOW, SSD_E_INCOMPAT, SSD_E_TRUNC, SSD_E_DEVICE, SSD_E_STATE = \
+    -1, -2, -3, -4, -5, -6, -7, -8
 SSD_NOALLOC_SCRATCH_BYTES = 64 << 20
+STATE_HEADER_BYTES = 80            # the checkpoint blob's header (ssd_export_state)
 
 RESULT_DTYPE = np.dtype([("ip", "<u4"), ("rk", "<u4"), ("est", "<f8")])
 
@@ -101,6 +103,8 @@ def _lib():
         L.ssd_close_end.argtypes = [vp, vp, u64, u64p]
         L.ssd_merge_router_state.argtypes = [vp, C.POINTER(vp), u32]
         L.ssd_read_canonical_state.argtypes = [vp, vp, u64]
+        L.ssd_export_state.argtypes = [vp, vp, u64, u64p]
+        L.ssd_import_state.argtypes = [vp, vp, u64]
         L.ssd_read_rk.argtypes = [vp, vp, u64]
         L.ssd_read_hot.argtypes = [vp, vp, vp, u64]
         L.ssd_read_tuples.argtypes = [vp, vp, u64, u64p]
@@ -143,7 +147,7 @@ def _lib():
                      "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_batch_get_info", "ssd_batch_read_rk", "ssd_batch_read_hot",
                      "ssd_group_query_sizes",
                      "ssd_group_init", "ssd_group_scan", "ssd_group_close", "ssd_group_close_begin",
-                     "ssd_group_close_end"):
+                     "ssd_group_close_end", "ssd_export_state", "ssd_import_state"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
     return _lib_handle
@@ -277,6 +281,23 @@ def get_results(det: Detector) -> np.ndarray:
 def merge_router_state(global_det: Detector, routers: Sequence[Detector]) -> None:
     arr = (C.c_void_p * len(routers))(*[r.handle.value for r in routers])
     _check(_lib().ssd_merge_router_state(global_det.handle, arr, len(routers)), "merge_router_state")
+
+
+def export_state(det: Detector) -> np.ndarray:
+    """The detector's checkpoint blob (uint8 array in host memory)."""
+    n = C.c_uint64(0)
+    st = _lib().ssd_export_state(det.handle, None, 0, C.byref(n))
+    if st not in (0, SSD_E_TRUNC):
+        _check(st, "export_state")
+    out = np.empty(n.value, dtype=np.uint8)
+    _check(_lib().ssd_export_state(det.handle, out.ctypes.data, out.size, C.byref(n)), "export_state")
+    return out
+
+
+def import_state(det: Detector, blob: np.ndarray) -> None:
+    """Continue `det` from a blob of export_state (same parameters and tables)."""
+    b = np.ascontiguousarray(blob, dtype=np.uint8)
+    _check(_lib().ssd_import_state(det.handle, b.ctypes.data, b.size), "import_state")
 
 
 def read_canonical_state(det: Detector) -> torch.Tensor:

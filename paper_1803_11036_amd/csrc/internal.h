@@ -55,7 +55,8 @@ struct LinkDesc {
     uint64_t host_cap;            //   are written there by the close's last kernel
     uint32_t* hot_list;           // [r][2^q]
     uint16_t* live16;             // [r][2^q][eta / 16] live-cell bits of hot estimators (written at hot detection)
-    uint32_t* counts;             // [k][r][2^q] live cells per slot t mod k and estimator (counted detectors, else null)
+    uint32_t* counts;             // [k + 1][r][2^q] live cells per slot t mod k and estimator, then the
+                                  // live-cell total (counted detectors, else null)
     uint64_t* ctb_x[2];           // candidate buffers: regained bits
     uint32_t* ctb_h0[2];          //                    and he_0
     unsigned long long* acc;      // accepted keys

@@ -1941,6 +1941,100 @@ int ssd_read_canonical_state(ssd_detector* d, uint16_t* out_dev, uint64_t n_cell
     return SSD_OK;
 }
 
+// ---- checkpoint: header, then the state bytes
+namespace {
+struct StateHeader {
+    char magic[8];                 // "SSDSTATE"
+    uint32_t version, header_bytes;
+    uint32_t q, r, delta, eta, k, theta, key_bits, flags, cell_bits, pad;
+    uint64_t tables_hash;          // FNV-1a 64 of the 2048 table words
+    uint64_t clock;                // the open slice
+    uint64_t state_bytes;
+};
+constexpr uint32_t STATE_VERSION = 1;
+static_assert(sizeof(StateHeader) == 80, "the checkpoint header is 80 bytes");
+
+uint64_t tables_hash(const uint32_t* t)
+{
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (uint32_t i = 0; i < 2048; i++)
+        for (int b = 0; b < 4; b++) h = (h ^ ((t[i] >> (8 * b)) & 0xFFu)) * 0x100000001B3ull;
+    return h;
+}
+
+StateHeader state_header(const ssd_detector* d)
+{
+    StateHeader h{};
+    memcpy(h.magic, "SSDSTATE", 8);
+    h.version = STATE_VERSION;
+    h.header_bytes = sizeof(StateHeader);
+    const ssd_params& p = d->p();
+    h.q = p.q; h.r = p.r; h.delta = p.delta; h.eta = p.eta; h.k = p.k; h.theta = p.theta;
+    h.key_bits = p.key_bits; h.flags = p.flags; h.cell_bits = cell16(p) ? 16u : 8u;
+    h.tables_hash = tables_hash(d->e.tables.data());
+    h.clock = d->e.clock;
+    h.state_bytes = state_bytes_of(p);
+    return h;
+}
+}  // namespace
+
+int ssd_export_state(ssd_detector* d, void* out_host, uint64_t cap, uint64_t* n_out)
+{
+    if (!d || !n_out) return fail(SSD_E_PARAM, "NULL argument");
+    Engine* e = &d->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    const StateHeader h = state_header(d);
+    const uint64_t need = sizeof(StateHeader) + h.state_bytes;
+    *n_out = need;
+    if (!out_host || cap < need)
+        return fail(SSD_E_TRUNC, "the state blob holds %llu bytes, cap is %llu", (unsigned long long)need,
+                    (unsigned long long)cap);
+    memcpy(out_host, &h, sizeof h);
+    HIPCHK(e, hipMemcpyAsync(static_cast<uint8_t*>(out_host) + sizeof h, d->D().state, h.state_bytes,
+                             hipMemcpyDeviceToHost, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    return SSD_OK;
+}
+
+int ssd_import_state(ssd_detector* d, const void* blob_host, uint64_t n)
+{
+    if (!d || !blob_host) return fail(SSD_E_PARAM, "NULL argument");
+    Engine* e = &d->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (close_pending(d)) return fail(SSD_E_ORDER, "a close is pending (ssd_close_end first)");
+    StateHeader h;
+    if (n < sizeof h) return fail(SSD_E_PARAM, "a state blob holds at least a %zu-byte header", sizeof h);
+    memcpy(&h, blob_host, sizeof h);
+    if (memcmp(h.magic, "SSDSTATE", 8) != 0 || h.version != STATE_VERSION || h.header_bytes != sizeof h)
+        return fail(SSD_E_PARAM, "not a state blob of this library (format %u)", h.version);
+    const StateHeader mine = state_header(d);
+    if (h.q != mine.q || h.r != mine.r || h.delta != mine.delta || h.eta != mine.eta || h.k != mine.k ||
+        h.theta != mine.theta || h.key_bits != mine.key_bits || h.flags != mine.flags ||
+        h.cell_bits != mine.cell_bits)
+        return fail(SSD_E_INCOMPAT, "the blob's parameters differ from the detector's");
+    if (h.tables_hash != mine.tables_hash) return fail(SSD_E_INCOMPAT, "the blob's hash tables differ from the detector's");
+    if (h.state_bytes != mine.state_bytes || n != sizeof h + h.state_bytes)
+        return fail(SSD_E_PARAM, "the blob holds %llu bytes, its header says %llu", (unsigned long long)n,
+                    (unsigned long long)(sizeof h + h.state_bytes));
+    HIPCHK(e, hipMemcpyAsync(d->D().state, static_cast<const uint8_t*>(blob_host) + sizeof h, h.state_bytes,
+                             hipMemcpyHostToDevice, e->stream));
+    const Clock c{h.clock};
+    HIPCHK(e, hipMemcpyAsync(d->D().clock, &c, sizeof c, hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipStreamSynchronize(e->stream));
+    e->clock = h.clock;
+    // the counters are not in the blob: stale, rebuilt from the state after
+    // the next large binned call, else the next close reads the state
+    e->count_valid[0] = 0;
+    e->count_rebuild[0] = 0;
+    e->count_small[0] = 0;
+    e->have_last = false;
+    e->results[0].clear();
+    return SSD_OK;
+}
+
 int ssd_read_rk(ssd_detector* d, uint32_t* out_host, uint64_t n)
 {
     if (!d) return fail(SSD_E_PARAM, "detector is NULL");

@@ -14,6 +14,10 @@ HBM.  Each loop iteration
      close runs on the device while the next iteration admits streams and
      enqueues their scans, and its streams' next slots are open at once.
 Requests arriving while others are on the GPU simply join the next iteration.
+A stream can be dropped at a given stream time (its client gone): at the
+first iteration after that time with no close of it pending, its detector is
+freed mid-slot; its open slot is never closed and no other stream is
+touched.
 All work runs in the library's kernels; this module only decides what runs
 together.  Stream time advances at `time_scale` times wall time.
 """
@@ -93,11 +97,13 @@ class _Live:
 
 
 def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float = 1.0,
-          max_members: int = 64, device="cuda:0", keep_results: bool = True, batched: bool = True) -> ServeReport:
-    """Run every stream to its last slot; returns throughput, latencies and
-    (if keep_results) each stream's list per slot.  batched=False issues the
-    same work as plain per-stream launches (one scan per batch, one close per
-    stream), for comparison."""
+          max_members: int = 64, device="cuda:0", keep_results: bool = True, batched: bool = True,
+          drop: Optional[Dict[int, float]] = None) -> ServeReport:
+    """Run every stream to its last slot (or, for a stream in `drop`, to its
+    drop time in stream seconds); returns throughput, latencies and (if
+    keep_results) each stream's list per closed slot.  batched=False issues
+    the same work as plain per-stream launches (one scan per batch, one close
+    per stream), for comparison."""
     from . import close_slice, scan_slice
     dev = torch.device(device)
     group = Group(max_members, device=dev)
@@ -138,9 +144,20 @@ def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float =
                 del live[L.idx]
                 done += 1
 
+    drop = dict(drop or {})
     while done < len(streams):
         iters += 1
         tau = now_tau()
+        # 0. dropped streams: waiting ones leave the queue, admitted ones free
+        # their detector (not while a close of theirs is pending)
+        for i in [i for i in waiting if drop.get(i, float("inf")) <= tau]:
+            waiting.remove(i)
+            done += 1
+        for i in [i for i, L in live.items() if drop.get(i, float("inf")) <= tau and not L.closing]:
+            L = live.pop(i)
+            L.det.destroy()
+            used -= L.nbytes
+            done += 1
         # 1. admission in arrival order while the budget allows
         while waiting and len(live) < max_members:
             i = waiting[0]

@@ -70,6 +70,32 @@ def test_served_mix_equals_alone():
     assert checked >= 2
 
 
+def test_served_stream_dropped_mid_slot():
+    """A stream dropped halfway through its second slot, after some of that
+    slot's batches were scanned in shared group launches: its detector is
+    freed without a close, its first slot's list is the one it has alone,
+    and every other stream's lists are unchanged."""
+    inputs = _inputs(6, 4, 0x5EED3)
+    cand = [i for i, s in enumerate(inputs)
+            if np.any((s.arrivals >= s.slot) & (s.arrivals < 1.5 * s.slot))]
+    assert cand, "no stream has a batch in the first half of its second slot"
+    d = cand[0]
+    rep = serve.serve(inputs, budget_bytes=1 << 40, time_scale=1.0, drop={d: 1.5 * inputs[d].slot})
+    alone = serve.serve_alone(inputs[d])
+    got = sorted(o for (i, o) in rep.results if i == d)
+    log(f"dropped stream {d}: slots closed {got}")
+    assert set(got) <= {0}
+    for o in got:
+        assert np.array_equal(rep.results[(d, o)], alone[o])
+    others = [s for i, s in enumerate(inputs) if i != d]
+    sub = serve.ServeReport(wall_s=rep.wall_s, pairs=rep.pairs, latencies_ms=rep.latencies_ms,
+                            results={(j, o): rep.results[(i, o)] for j, i in enumerate(k for k in range(len(inputs)) if k != d)
+                                     for o in range(inputs[i].n_slots)},
+                            max_admitted=rep.max_admitted, admit_wait_s=rep.admit_wait_s,
+                            iterations=rep.iterations, scan_calls=rep.scan_calls, close_calls=rep.close_calls)
+    assert _check_equal(others, sub) > 0
+
+
 def test_served_admission_by_memory_budget():
     inputs = _inputs(6, 3, 0x5EED2)
     sizes = sorted(serve.stream_bytes(s.params) for s in inputs)
