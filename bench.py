@@ -426,18 +426,25 @@ def run_batched(args) -> dict:
             t += 1
         log(f"autotuned over {t} slices")
     ssd.batch_set_tuning(b, ssd.SSD_TUNE_TIMING, 1)
-    batch_lists = []
-    for i in range(W + K):
+    for i in range(W):
         pairs, offs = slices[i % n_var]
-        if i == W:
-            torch.cuda.synchronize()
-            ssd.batch_read_timing(b, reset=True)
-            t0 = time.perf_counter()
         ssd.batch_scan(b, pairs, offs, t)
-        lists, status = ssd.batch_close(b)
-        if i >= W:
-            batch_lists.append((lists, status))
+        ssd.batch_close(b)
         t += 1
+    torch.cuda.synchronize()
+    ssd.batch_read_timing(b, reset=True)
+    batch_lists = []
+    t0 = time.perf_counter()
+    # pipelined: slice t+1's scan is enqueued before slice t's lists are
+    # collected (ssd_batch_close_begin / _end), as for the single link
+    for i in range(K):
+        pairs, offs = slices[(W + i) % n_var]
+        ssd.batch_scan(b, pairs, offs, t)
+        if i > 0:
+            batch_lists.append(ssd.batch_close_end(b))
+        ssd.batch_close_begin(b)
+        t += 1
+    batch_lists.append(ssd.batch_close_end(b))
     torch.cuda.synchronize()
     batch_s = time.perf_counter() - t0
     timing = ssd.batch_read_timing(b, reset=True)

@@ -371,6 +371,18 @@ int ssd_batch_scan(ssd_batch *b, const uint32_t *pairs_dev, const uint64_t *offs
  * SSD_E_DEVICE. */
 int ssd_batch_close(ssd_batch *b, ssd_super_point *out_host, uint64_t cap, uint64_t *counts_host,
                     int *status_host);
+
+/* ssd_batch_close in two halves, so that the next slice's ssd_batch_scan can
+ * be enqueued while the close runs (the pipelined close of a detector, for
+ * a batch): _begin enqueues the close of every link and opens the next slice
+ * at once; _end waits for it and returns the lists as ssd_batch_close.  One
+ * close may be pending (SSD_E_ORDER otherwise); ssd_batch_get_results,
+ * ssd_batch_read_rk and ssd_batch_read_hot are refused while it is
+ * (SSD_E_ORDER).  Tuning samples of scans enqueued after the close are
+ * credited at a later _end. */
+int ssd_batch_close_begin(ssd_batch *b);
+int ssd_batch_close_end(ssd_batch *b, ssd_super_point *out_host, uint64_t cap, uint64_t *counts_host,
+                        int *status_host);
 int ssd_batch_get_results(ssd_batch *b, ssd_super_point *out_host, uint64_t cap, uint64_t *counts_host,
                           int *status_host);
 

@@ -28,7 +28,8 @@ __all__ = [
     "SSD_TUNE_SCAN_TILE_PAIRS", "SSD_TUNE_GRAPH", "SSD_TUNE_AUTOTUNE", "PHASES",
     "SSD_TUNE_SCAN_MODE", "SSD_TUNE_SCAN_BIN_BYTES", "SSD_TUNE_SCAN_APPLY_SEGMENTS", "SSD_SCAN_PASSES",
     "SSD_SCAN_BINNED", "SSD_SCAN_AUTO", "SSD_TUNE_COUNTED", "SSD_TUNE_COUNTED_MIN_ITEMS",
-    "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_get_results",
+    "Batch", "batch_query_sizes", "batch_init", "batch_scan", "batch_close", "batch_close_begin",
+    "batch_close_end", "batch_get_results",
     "batch_set_tuning", "batch_get_tuning", "batch_read_timing", "batch_get_info", "batch_read_rk",
     "batch_read_hot", "batch_destroy",
     "Group", "group_query_sizes", "group_init", "group_scan", "group_close", "group_close_begin",
@@ -115,6 +116,8 @@ def _lib():
         L.ssd_batch_init.argtypes = [vp, u32, vp, vp, u64, vp, u64, vp, C.POINTER(vp)]
         L.ssd_batch_scan.argtypes = [vp, vp, vp, u64]
         L.ssd_batch_close.argtypes = [vp, vp, u64, vp, vp]
+        L.ssd_batch_close_begin.argtypes = [vp]
+        L.ssd_batch_close_end.argtypes = [vp, vp, u64, vp, vp]
         L.ssd_batch_get_results.argtypes = [vp, vp, u64, vp, vp]
         L.ssd_batch_set_tuning.argtypes = [vp, u32, u64]
         L.ssd_batch_get_tuning.argtypes = [vp, u32, u64p]
@@ -147,7 +150,8 @@ def _lib():
                      "ssd_batch_get_tuning", "ssd_batch_read_timing", "ssd_batch_get_info", "ssd_batch_read_rk", "ssd_batch_read_hot",
                      "ssd_group_query_sizes",
                      "ssd_group_init", "ssd_group_scan", "ssd_group_close", "ssd_group_close_begin",
-                     "ssd_group_close_end", "ssd_export_state", "ssd_import_state"):
+                     "ssd_group_close_end", "ssd_export_state", "ssd_import_state", "ssd_batch_close_begin",
+                     "ssd_batch_close_end"):
             getattr(L, name).restype = C.c_int
         _lib_handle = L
     return _lib_handle
@@ -477,6 +481,16 @@ def batch_close(b: Batch):
     """Close the open slice of every link: (list of per-link result arrays,
     per-link status codes: 0 or -4 = capacity exceeded)."""
     return _batch_lists(b, _lib().ssd_batch_close)
+
+
+def batch_close_begin(b: Batch) -> None:
+    "Begin the close of every link; the next slice is open at once."
+    _check(_lib().ssd_batch_close_begin(b.handle), "batch_close_begin")
+
+
+def batch_close_end(b: Batch):
+    "Wait for the pending batch close: as batch_close."
+    return _batch_lists(b, _lib().ssd_batch_close_end)
 
 
 def batch_get_results(b: Batch):

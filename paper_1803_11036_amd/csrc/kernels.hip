@@ -845,7 +845,7 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
 __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted(ApplyArgs a)
 {
     extern __shared__ uint32_t lds[];
-    // the marked words, in address order
+    // the marked words, in the order they were first marked
     __shared__ uint16_t list[CAPPLY_LIST];
     __shared__ uint32_t n_list;
     __shared__ uint32_t wsum[16];

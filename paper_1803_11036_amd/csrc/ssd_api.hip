@@ -1272,6 +1272,9 @@ struct ssd_batch {
     std::map<uint64_t, uint64_t> bt_class_pairs;       // pairs per class over the tuning scans
     struct BinTiming { int trial; uint64_t pairs; hipEvent_t a, b; };
     std::vector<BinTiming> bt_pending;
+    // a close begun (ssd_batch_close_begin) and not yet ended
+    bool pending = false;
+    hipEvent_t done = nullptr;
     std::vector<uint64_t> link_class;                  // per link: its class in its last tuning scan
 };
 
@@ -1294,20 +1297,39 @@ namespace {
 // once every candidate has run, keep the fastest per pair.
 void autotune_collect(ssd_batch* b)
 {
+    // samples of scans enqueued after the waited-for close (the next slice's,
+    // with the close pipelined) stay for the next collection
+    auto ran = [](hipEvent_t ev) {
+        if (hipEventQuery(ev) == hipSuccess) return true;
+        (void)hipGetLastError();
+        return false;
+    };
+    std::vector<std::pair<int, uint64_t>> keep_p;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> keep_e;
     for (size_t i = 0; i < b->tune_pending.size(); i++) {
+        const auto ev = b->tune_events[i];
+        if (!ran(ev.second)) {
+            keep_p.push_back(b->tune_pending[i]);
+            keep_e.push_back(ev);
+            continue;
+        }
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, b->tune_events[i].first, b->tune_events[i].second) == hipSuccess &&
-            b->tune_pending[i].second) {
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess && b->tune_pending[i].second) {
             ssd_batch::Cand& c = b->cands[b->tune_pending[i].first];
             const double ns = ms * 1e6 / (double)b->tune_pending[i].second;
             if (c.ns_per_pair < 0 || ns < c.ns_per_pair) c.ns_per_pair = ns;
         }
-        (void)hipEventDestroy(b->tune_events[i].first);
-        (void)hipEventDestroy(b->tune_events[i].second);
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
     }
-    b->tune_pending.clear();
-    b->tune_events.clear();
+    b->tune_pending.swap(keep_p);
+    b->tune_events.swap(keep_e);
+    std::vector<ssd_batch::BinTiming> keep_b;
     for (const auto& c : b->bt_pending) {
+        if (!ran(c.b)) {
+            keep_b.push_back(c);
+            continue;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c.a, c.b) == hipSuccess && c.pairs) {
             const double ns = ms * 1e6 / (double)c.pairs;
@@ -1337,8 +1359,8 @@ void autotune_collect(ssd_batch* b)
                         if (c2 != g) b->bt_trials.push_back({by[i].first, c2});
         }
     }
-    b->bt_pending.clear();
-    if (b->bt_next >= (int)b->bt_trials.size()) {
+    b->bt_pending.swap(keep_b);
+    if (b->bt_next >= 0 && b->bt_next >= (int)b->bt_trials.size() && b->bt_pending.empty()) {
         // every trial done: each tuned link takes its class's candidate
         for (uint32_t l = 0; l < b->e.n; l++) {
             if (b->link_class[l] == NO_CLASS) continue;
@@ -1347,7 +1369,7 @@ void autotune_collect(ssd_batch* b)
         }
         b->bt_next = -1;
     }
-    if (b->tune_idx >= (int)b->cands.size()) {
+    if (b->tune_idx >= (int)b->cands.size() && b->tune_pending.empty()) {
         int best = 0;
         for (int i = 1; i < (int)b->cands.size(); i++)
             if (b->cands[i].ns_per_pair >= 0 &&
@@ -2161,9 +2183,14 @@ void ssd_batch_destroy(ssd_batch* b)
 {
     if (!b) return;
     engine_release(&b->e);
+    if (b->done) (void)hipEventDestroy(b->done);
     for (auto& ev : b->tune_events) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
+    }
+    for (auto& c : b->bt_pending) {
+        (void)hipEventDestroy(c.a);
+        (void)hipEventDestroy(c.b);
     }
     for (int i = 0; i < 2; i++) {
         if (b->tile_pinned[i]) (void)hipHostFree(b->tile_pinned[i]);
@@ -2373,27 +2400,51 @@ int ssd_batch_scan(ssd_batch* b, const uint32_t* pairs_dev, const uint64_t* offs
     return SSD_OK;
 }
 
-int ssd_batch_close(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host, int* status_host)
+int ssd_batch_close_begin(ssd_batch* b)
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
     Engine* e = &b->e;
     int rc = usable(e);
     if (rc) return rc;
+    if (b->pending) return fail(SSD_E_ORDER, "a batch close is already pending (ssd_batch_close_end first)");
+    if (!b->done) HIPCHK(e, hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
     rc = e->use_graph ? close_graph(e, true, 0) : enqueue_close(e, true, 0);
     if (rc) return rc;
-    HIPCHK(e, hipStreamSynchronize(e->stream));
+    HIPCHK(e, hipEventRecord(b->done, e->stream));
+    b->pending = true;
+    e->clock++;          // the next slice opens now: its scans may be enqueued before the lists are collected
+    return SSD_OK;
+}
+
+int ssd_batch_close_end(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host,
+                        int* status_host)
+{
+    if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    Engine* e = &b->e;
+    int rc = usable(e);
+    if (rc) return rc;
+    if (!b->pending) return fail(SSD_E_ORDER, "no batch close is pending");
+    b->pending = false;
+    HIPCHK(e, hipEventSynchronize(b->done));
     phase_collect(e);
     autotune_collect(b);
-    e->clock++;
     rc = collect_results(e, true, 0);
     if (rc) return rc;
     return ssd_batch_get_results(b, out_host, cap, counts_host, status_host);
+}
+
+int ssd_batch_close(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host, int* status_host)
+{
+    int rc = ssd_batch_close_begin(b);
+    if (rc) return rc;
+    return ssd_batch_close_end(b, out_host, cap, counts_host, status_host);
 }
 
 int ssd_batch_get_results(ssd_batch* b, ssd_super_point* out_host, uint64_t cap, uint64_t* counts_host,
                           int* status_host)
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    if (b->pending) return fail(SSD_E_ORDER, "a batch close is pending (ssd_batch_close_end first)");
     const Engine& e = b->e;
     uint64_t total = 0;
     for (uint32_t l = 0; l < e.n; l++) {
@@ -2430,6 +2481,7 @@ int ssd_batch_get_info(ssd_batch* b, uint32_t link, ssd_info* out)
 int ssd_batch_read_rk(ssd_batch* b, uint32_t link, uint32_t* out_host, uint64_t n)
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    if (b->pending) return fail(SSD_E_ORDER, "a batch close is pending (ssd_batch_close_end first)");
     if (link >= b->e.n) return fail(SSD_E_PARAM, "link %u of %u", link, b->e.n);
     return engine_read_rk(&b->e, link, out_host, n);
 }
@@ -2437,6 +2489,7 @@ int ssd_batch_read_rk(ssd_batch* b, uint32_t link, uint32_t* out_host, uint64_t 
 int ssd_batch_read_hot(ssd_batch* b, uint32_t link, uint32_t* counts_host, uint32_t* lists_host, uint64_t cap)
 {
     if (!b) return fail(SSD_E_PARAM, "batch is NULL");
+    if (b->pending) return fail(SSD_E_ORDER, "a batch close is pending (ssd_batch_close_end first)");
     if (link >= b->e.n) return fail(SSD_E_PARAM, "link %u of %u", link, b->e.n);
     return engine_read_hot(&b->e, link, counts_host, lists_host, cap);
 }

@@ -72,6 +72,56 @@ def test_batch_equals_separate_detectors(graph, autotune):
         d.destroy()
 
 
+def test_batch_close_begin_end_pipelined():
+    """The batch close in two halves with the next slice's scan enqueued
+    between them: every link's list equals its separate detector's and, for
+    small links, the oracle's, slice by slice; a second begin, an end with
+    nothing pending and reads while a close is pending are refused."""
+    cfgs = tg.batch_configs(n_links=64, pairs_scale=0.02)
+    traces = [tg.Trace(c) for c in cfgs]
+    tabs = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    b = ssd.batch_init([_params(c) for c in cfgs], tabs, device="cuda:0")
+    plain = [ssd.init_detector(_params(c), tabs[i], device="cuda:0") for i, c in enumerate(cfgs)]
+    small = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta <= 64 << 20][:3]
+    orcs = {i: oracle.RSEA(cfgs[i].q, cfgs[i].r, cfgs[i].delta, cfgs[i].eta, cfgs[i].k, cfgs[i].theta, tabs[i])
+            for i in small}
+    n_slices = 6
+    want = []
+    for t in range(n_slices):
+        per, offs, dev = _slice_pairs(traces, t)
+        ssd.batch_scan(b, dev, offs, t)                 # while slice t-1's close runs
+        if t > 0:
+            lists, status = ssd.batch_close_end(b)
+            assert np.all(status == 0)
+            for i, ref in enumerate(want):
+                assert np.array_equal(lists[i], ref), f"slice {t - 1} link {i}: pipelined batch differs"
+        want = []
+        for i in range(len(cfgs)):
+            ssd.scan_slice(plain[i], dev[int(offs[i]):int(offs[i + 1])], t)
+            want.append(ssd.close_slice(plain[i]))
+        for i, o in orcs.items():
+            o.scan(per[i])
+            ip, rk, est = o.close()
+            assert np.array_equal(want[i]["ip"], ip) and np.array_equal(want[i]["rk"], rk)
+        ssd.batch_close_begin(b)
+        if t == 2:
+            for call in (lambda: ssd.batch_close_begin(b), lambda: ssd.batch_get_results(b),
+                         lambda: ssd.batch_read_rk(b, 0)):
+                with pytest.raises(ssd.SSDError) as e:
+                    call()
+                assert e.value.status == ssd.SSD_E_ORDER
+        log(f"batch pipelined slice {t}: {sum(len(x) for x in want)} hosts")
+    lists, status = ssd.batch_close_end(b)
+    for i, ref in enumerate(want):
+        assert np.array_equal(lists[i], ref)
+    with pytest.raises(ssd.SSDError) as e:
+        ssd.batch_close_end(b)
+    assert e.value.status == ssd.SSD_E_ORDER
+    b.destroy()
+    for d in plain:
+        d.destroy()
+
+
 def test_batch_binned_links_equal_separate_detectors():
     """Links with at least 2^16 pairs in the call take the binned scan inside
     the batch -- all of them together, one binning launch and one store launch
