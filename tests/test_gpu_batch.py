@@ -122,6 +122,62 @@ def test_batch_close_begin_end_pipelined():
         d.destroy()
 
 
+def test_batch_counted_links_through_stamp_wrap():
+    """300 slices, so that every link's 8-bit stamps wrap (255 slots): six
+    links of 24 MiB states and 70K pairs per slice, windows k = 1, 3, 17, 64,
+    100 and 254, scanned by the batch's multi-link binned stores with per-slot
+    counters (k = 100 in the store launch whose LDS takes a whole compute
+    unit; k = 254 cannot count) and R_k from k_count_multi, against separate
+    detectors scanning pass windows and reading their whole states (pinned
+    to the oracle through the wrap): every link's list equal every slice."""
+    ks = [1, 3, 17, 64, 100, 254]
+    q, r, delta, eta, theta, kb = 12, 6, 5, 1024, 200, 24
+    params = [ssd.make_params(q=q, r=r, delta=delta, eta=eta, k=k, theta=theta, key_bits=kb) for k in ks]
+    tabs = [tg.hash_tables(40 + i) for i in range(len(ks))]
+    b = ssd.batch_init(params, tabs, device="cuda:0")
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_TIMING, 1)
+    plain = [ssd.init_detector(p, tabs[i], device="cuda:0") for i, p in enumerate(params)]
+    rng = np.random.default_rng(77)
+    hosts = [rng.choice(2 ** kb, 3000, replace=False).astype(np.uint32) for _ in ks]
+    heavy = [rng.choice(2 ** kb, 12, replace=False).astype(np.uint32) for _ in ks]
+    n_slices, total = 300, 0
+    for t in range(n_slices):
+        per = []
+        for i, k in enumerate(ks):
+            # about 2e5 distinct background pairs per window (3000 hosts, well
+            # below theta each), and four heavy hosts at a time, each active
+            # for 20-slice runs with about 2 theta distinct peers per window;
+            # the slice filled to 70K pairs with repeats of its distinct ones
+            nb = min(60_000, 200_000 // k)
+            bg = np.stack([rng.choice(hosts[i], nb), rng.integers(0, 2 ** 32, nb, dtype=np.uint64).astype(np.uint32)], 1)
+            act = heavy[i][(np.arange(12) + t // 20) % 3 == 0]
+            m = 2 * theta // k + 2
+            hv = np.stack([np.repeat(act, m), rng.integers(0, 2 ** 32, m * len(act), dtype=np.uint64).astype(np.uint32)], 1)
+            d = np.concatenate([bg, hv]).astype(np.uint32)
+            full = np.concatenate([d, d[rng.integers(0, d.shape[0], max(0, 70_000 - d.shape[0]))]])
+            per.append(full[rng.permutation(full.shape[0])])
+        offs = np.zeros(len(per) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([p.shape[0] for p in per])
+        dev = to_dev(np.concatenate(per))
+        ssd.batch_scan(b, dev, offs, t)
+        lists, status = ssd.batch_close(b)
+        assert np.all(status == 0)
+        for i in range(len(ks)):
+            ssd.scan_slice(plain[i], dev[int(offs[i]):int(offs[i + 1])], t)
+            want = ssd.close_slice(plain[i])
+            assert np.array_equal(lists[i], want), f"slice {t} link {i} (k = {ks[i]}): batch differs"
+            total += len(want)
+        if t % 50 == 0 or t == n_slices - 1:
+            modes = [ssd.batch_get_info(b, i)["counted"] for i in range(len(ks))]
+            log(f"batch wrap slice {t}: {sum(len(x) for x in lists)} hosts, detection modes {modes}")
+    modes = [ssd.batch_get_info(b, i)["counted"] for i in range(len(ks))]
+    assert modes[:5] == [1] * 5 and modes[5] == 0, modes
+    assert total > 1000
+    b.destroy()
+    for d in plain:
+        d.destroy()
+
+
 def test_batch_binned_links_equal_separate_detectors():
     """Links with at least 2^16 pairs in the call take the binned scan inside
     the batch -- all of them together, one binning launch and one store launch
