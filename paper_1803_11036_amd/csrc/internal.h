@@ -227,7 +227,7 @@ uint32_t apply_counted_workgroups(const ApplyArgs& a);
 uint32_t bin_variant(const BinArgs& a);
 // one launch over several links: bin (all of one variant), apply (uncounted,
 // packed offsets, 8-bit cells), counted apply (lds_bytes: the largest need)
-hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t variant, uint32_t total_wg, hipStream_t s);
+hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t total_wg, hipStream_t s);
 hipError_t launch_apply_multi(const MultiApplyArgs& m, uint32_t total_wg, hipStream_t s);
 hipError_t launch_apply_counted_multi(const MultiApplyArgs& m, uint32_t total_wg, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s);

@@ -509,20 +509,7 @@ __global__ __launch_bounds__(1024) void k_bin(BinArgs a)
 // Several links in one launch: workgroup g belongs to the link whose range
 // of the workgroup prefix holds it.  Every link's range is a multiple of 8
 // workgroups, so that the dealing of its segments to XCDs is the one of a
-// launch of its own.
-template <int R, int PPT>
-__global__ __launch_bounds__(1024) void k_bin_multi(MultiBinArgs m)
-{
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[16];
-    const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
-    const BinArgs a = m.args[l];
-    const uint32_t g = blockIdx.x - m.wg_prefix[l];
-    if constexpr (R == 0) bin_generic(a, g, lds, wsum);
-    else bin_reg<R, PPT>(a, g, lds, wsum);
-}
-
-// Every binning variant in one launch: each workgroup takes its link's (the
+// launch of its own.  Each workgroup takes its link's binning variant (the
 // register binning of five or six rows where the segment fits it, else the
 // general one); the launch keeps the larger register count of the two.
 __global__ __launch_bounds__(1024) void k_bin_multi_rows(MultiBinArgs m)
@@ -1894,9 +1881,7 @@ static hipError_t bin_lds_attr()
     static bool attr = false;
     if (attr) return hipSuccess;
     for (const void* f : {reinterpret_cast<const void*>(&k_bin<0, 0>), reinterpret_cast<const void*>(&k_bin<6, 6>),
-                          reinterpret_cast<const void*>(&k_bin<5, 7>), reinterpret_cast<const void*>(&k_bin_multi<0, 0>),
-                          reinterpret_cast<const void*>(&k_bin_multi<6, 6>),
-                          reinterpret_cast<const void*>(&k_bin_multi<5, 7>),
+                          reinterpret_cast<const void*>(&k_bin<5, 7>),
                           reinterpret_cast<const void*>(&k_bin_multi_rows)}) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BIN_LDS_WORDS * 4u));
         if (e != hipSuccess) return e;
@@ -1929,18 +1914,12 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t variant, uint32_t total_wg, hipStream_t s)
+hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t total_wg, hipStream_t s)
 {
     if (m.n == 0 || total_wg == 0) return hipErrorInvalidValue;
     hipError_t e = bin_lds_attr();
     if (e != hipSuccess) return e;
-    const uint32_t bytes = BIN_LDS_WORDS * 4u;         // every link's plan fits it
-    switch (variant) {
-    case 6: k_bin_multi<6, 6><<<total_wg, 1024, bytes, s>>>(m); break;
-    case 5: k_bin_multi<5, 7><<<total_wg, 1024, bytes, s>>>(m); break;
-    case 1: k_bin_multi_rows<<<total_wg, 1024, bytes, s>>>(m); break;
-    default: k_bin_multi<0, 0><<<total_wg, 1024, bytes, s>>>(m); break;
-    }
+    k_bin_multi_rows<<<total_wg, 1024, BIN_LDS_WORDS * 4u, s>>>(m);    // every link's plan fits the LDS
     return hipGetLastError();
 }
 

@@ -1517,7 +1517,7 @@ int enqueue_batch_binned(ssd_batch* b, const uint2* pairs, const uint64_t* offse
                 phase_end(e, pm, 0, 1);
             } else {
                 MultiBinArgs m{db + L.first, dp + L.pre, L.count};
-                HIPCHK(e, launch_bin_multi(m, L.kind, L.total_wg, e->stream));
+                HIPCHK(e, launch_bin_multi(m, L.total_wg, e->stream));
                 phase_end(e, pm, PHASE_SCAN_BIN, 1);
             }
         }
