@@ -8,6 +8,8 @@
   holds at any size: merging the routers' states gives the state, R_k and host
   list of one detector that scanned every router's pairs (Alg. 5, reading R3).
 - The same 16-router topology on a smaller array against the oracle's merge.
+- The 64-link batched workload at full size in the benchmark's launch
+  configuration, three sampled links against the oracle.
 """
 import numpy as np
 import pytest
@@ -168,3 +170,59 @@ def test_distributed_paper_geometry_against_oracle():
     assert all(ssd.read_timing(d)["scan_bin"][1] == cfg.k + 2 for d in routers)
     for d in routers + [glob]:
         d.destroy()
+
+
+def test_batched_workload_as_benchmarked_against_oracle():
+    """The 64-link batched workload at full size (152M pairs per slice, 19 GiB
+    of state) in the launch configuration bench.py times -- the autotuner
+    running on the first scans, one binning and one store launch for all 64
+    links, the close pipelined behind the next slice's scan -- with three
+    sampled links (windows up to 10 slices, states up to 1 GiB, binned and
+    counted) checked against the oracle fed the same device-generated pairs,
+    lists every slice, through the tuning scans and after them."""
+    import torch
+    cfgs = tg.batch_configs(n_links=64)
+    traces = [tg.Trace(c) for c in cfgs]
+    tables = [tg.hash_tables(c.hash_seed) for c in cfgs]
+    pick = [i for i, c in enumerate(cfgs)
+            if c.k <= 10 and c.r * (1 << c.q) * c.eta <= 1 << 30 and c.pairs_lo >= 1 << 16][:3]
+    assert len(pick) == 3, pick
+    params = [ssd.make_params(q=c.q, r=c.r, delta=c.delta, eta=c.eta, k=c.k, theta=c.theta,
+                              max_tuples=1 << 21, max_results=1 << 18) for c in cfgs]
+    b = ssd.batch_init(params, tables, device="cuda:0")
+    ssd.batch_set_tuning(b, ssd.SSD_TUNE_AUTOTUNE, 1)
+    orcs = {i: oracle.RSEA(cfgs[i].q, cfgs[i].r, cfgs[i].delta, cfgs[i].eta, cfgs[i].k, cfgs[i].theta, tables[i])
+            for i in pick}
+    # k + 2 slices of the longest sampled window, and enough for the
+    # autotuner to finish (up to 11 tuning scans, collected one close late)
+    # so that the tuned bin sizes are checked too
+    n_slices = max(max(cfgs[i].k for i in pick) + 2, 14)
+    want = None
+    for t in range(n_slices):
+        parts = [tr.pairs_device(0, t, "cuda:0") for tr in traces]
+        offs = np.zeros(len(parts) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([int(x.shape[0]) for x in parts])
+        pairs = torch.cat(parts).contiguous()
+        del parts
+        ssd.batch_scan(b, pairs, offs, t)                # while slice t-1's close runs
+        if want is not None:
+            lists, status = ssd.batch_close_end(b)
+            assert np.all(status == 0)
+            for i, (ip, rk, est) in want.items():
+                assert np.array_equal(lists[i]["ip"], ip) and np.array_equal(lists[i]["rk"], rk), \
+                    f"slice {t - 1} link {i}: lists differ from the oracle"
+                assert np.all(np.abs(lists[i]["est"] - est) <= 1e-6 * np.abs(est))
+            log(f"batched as benchmarked, slice {t - 1}: {sum(len(x) for x in lists)} hosts, sampled links "
+                f"{[len(want[i][0]) for i in pick]}")
+        ssd.batch_close_begin(b)
+        want = {}
+        for i in pick:
+            orcs[i].scan(pairs[int(offs[i]):int(offs[i + 1])].cpu().numpy().view(np.uint32))
+            want[i] = orcs[i].close()
+        del pairs
+    lists, status = ssd.batch_close_end(b)
+    for i, (ip, rk, est) in want.items():
+        assert np.array_equal(lists[i]["ip"], ip) and np.array_equal(lists[i]["rk"], rk)
+    assert all(ssd.batch_get_info(b, i)["counted"] == 1 for i in pick)
+    assert ssd.batch_get_tuning(b, ssd.SSD_TUNE_AUTOTUNE) == 0
+    b.destroy()
