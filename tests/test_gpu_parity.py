@@ -17,7 +17,7 @@ def _slices_small(seed, n_slices, key_bits, theta, q, sizes=None, heavy=20, heav
     """Random slices over a key_bits-wide host space: light background plus
     heavy hosts that enter and leave."""
     rng = np.random.default_rng(seed)
-    hosts = rng.choice(2 ** key_bits, 4000, replace=False).astype(np.uint32)
+    hosts = rng.choice(2 ** key_bits, min(4000, 2 ** key_bits // 2), replace=False).astype(np.uint32)
     hv = rng.choice(2 ** key_bits, heavy, replace=False).astype(np.uint32)
     start = rng.integers(0, max(1, n_slices - 2), heavy)
     span = rng.integers(1, 8, heavy)
@@ -322,6 +322,53 @@ def test_binned_scan_rows_match_oracle(q, r, delta, counted):
     tm = ssd.read_timing(g)
     assert tm["scan_bin"][1] >= len(sl)
     assert (tm["count_detect"][1] > 0) == bool(counted)
+
+
+# (q, r, delta, eta, k, theta, key_bits, cell_bits): the edges of the
+# parameter space the boundary accepts
+_EXTREMES = {
+    "r3_fewest_rows": (10, 3, 6, 1024, 2, 150, 16, 8),
+    "delta1": (12, 6, 1, 1024, 3, 200, 16, 8),
+    "delta12_cover38": (14, 4, 12, 1024, 3, 200, 32, 8),
+    "q4_fewest_columns": (4, 4, 3, 1024, 3, 150, 8, 8),
+    "eta16k_counted": (8, 4, 4, 16384, 3, 5000, 16, 8),
+    "eta32k": (7, 5, 4, 32768, 2, 10000, 16, 8),
+    "eta64k": (6, 4, 4, 65536, 3, 20000, 14, 8),
+    "eta64k_16bit": (6, 4, 4, 65536, 4, 20000, 14, 16),
+}
+
+
+@pytest.mark.parametrize("mode", ["auto", "binned"])
+@pytest.mark.parametrize("case", list(_EXTREMES))
+def test_parameter_extremes(case, mode):
+    """The edges of the accepted parameters against the oracle: the fewest
+    rows (r = 3: level 0 only), the narrowest and widest overlaps (delta = 1;
+    delta = 12 with (r-2)*delta + q = 38 > 32 bits), the fewest columns
+    (q = 4, 8-bit keys) and the largest estimators (eta = 2^14 with per-slot
+    counters, 2^15, and 2^16 with 8- and 16-bit cells), through the default
+    scan and through the binned scan; canonical state, R_k, hot lists, tuples
+    and lists every slice, one slice split over three calls."""
+    q, r, delta, eta, k, theta, kb, cb = _EXTREMES[case]
+    n_slices = k + 3
+    # about ten peers per background host and slice: only the heavy hosts go hot
+    bg = 10 * min(4000, 2 ** kb // 2)
+    sl = _slices_small(500 + q * 7 + r, n_slices, kb, theta, q, sizes=[bg] * n_slices, heavy=12)
+    g, o = make_pair(q, r, delta, eta, k, theta, tg.hash_tables(40 + q + r), key_bits=kb, cell_bits=cb)
+    if mode == "binned":
+        ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_BINNED)
+    ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
+    found = 0
+    for t, p in enumerate(sl):
+        log(f"extremes {case} {mode} slice {t} n={p.shape[0]}")
+        scan_both(g, o, p, t, splits=3 if t == 1 else 1)
+        compare_state(g, o)
+        found += len(close_both(g, o))
+    assert found > 0
+    tm = ssd.read_timing(g)
+    if mode == "binned":
+        assert tm["scan_bin"][1] >= n_slices
+    if case == "eta16k_counted" and mode == "binned":
+        assert tm["count_detect"][1] > 0
 
 
 def test_counted_detection_switches():
