@@ -1543,6 +1543,12 @@ struct ssd_group {
     bool pending = false;
     std::vector<ssd_detector*> pending_members;
     hipEvent_t done = nullptr;
+    // arguments of the binned members' multi-link launches, staged in pinned
+    // memory (two buffers, each reused once its last copy has run)
+    void* mb_pinned[2] = {nullptr, nullptr};
+    hipEvent_t mb_done[2] = {nullptr, nullptr};
+    bool mb_used[2] = {false, false};
+    uint32_t mb_next = 0;
 };
 
 namespace {
@@ -1559,6 +1565,7 @@ Layout plan_group(uint32_t max_members)
     L.count_list = o; o = align_up(o + (2ull * max_members + 1) * 4);
     L.ctl = o; o = align_up(o + max_members * sizeof(Ctl));    // unused: members' own blocks are read
     L.packed = o; o = align_up(o + BATCH_STAGE * sizeof(SuperPointDev));
+    L.multi_args = o; o = align_up(o + multi_args_bytes(max_members));
     L.total = o;
     L.pack_cap = BATCH_STAGE;
     L.tile_cap = MAX_WINDOWS;
@@ -2535,6 +2542,15 @@ int ssd_group_init(uint32_t max_members, void* scratch_dev, uint64_t scratch_byt
     e->mb_ctl = static_cast<Ctl*>(e->pinned);
     e->mb_stage = reinterpret_cast<SuperPointDev*>(e->mb_ctl + max_members);
     e->mb_offsets = reinterpret_cast<unsigned long long*>(e->mb_stage + BATCH_STAGE);
+    for (int i = 0; i < 2 && err == hipSuccess; i++) {
+        err = hipHostMalloc(&g->mb_pinned[i], multi_args_bytes(max_members), hipHostMallocDefault);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&g->mb_done[i], hipEventDisableTiming);
+    }
+    if (err != hipSuccess) {
+        int rc = dev_fail(e, err, "group staging");
+        ssd_group_destroy(g);
+        return rc;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, e->device) == hipSuccess) g->scan_blocks = (uint32_t)prop.multiProcessorCount * 8u;
     *out = g;
@@ -2548,6 +2564,10 @@ void ssd_group_destroy(ssd_group* g)
         for (ssd_detector* m : g->pending_members) m->group_pending = false;
     engine_release(&g->e);
     if (g->done) (void)hipEventDestroy(g->done);
+    for (int i = 0; i < 2; i++) {
+        if (g->mb_pinned[i]) (void)hipHostFree(g->mb_pinned[i]);
+        if (g->mb_done[i]) (void)hipEventDestroy(g->mb_done[i]);
+    }
     delete g;
 }
 
@@ -2627,13 +2647,87 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         phase_end(e, pm, PHASE_SCAN_TILES, 1);
     }
     for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;   // group scans store uncounted
+    // the binned members: rounds of one binning launch and one store launch
+    // over all of them, each member binning into its own staging (a member
+    // whose pairs exceed its staging takes part in several rounds); a member
+    // whose bins are too large for packed offsets is scanned alone
+    struct Binned {
+        ssd_detector* m;
+        BinnedCall c;
+        BinBufs bb;
+        uint64_t begin, n, chunk, done;
+    };
+    std::vector<Binned> bm;
     for (uint32_t i = 0; i < n; i++) {
         if (!binned(i)) continue;
         ssd_detector* m = members[i];
-        rc = enqueue_binned_scan(&m->e, 0, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[i],
-                                 offsets_host[i + 1] - offsets_host[i], m->bin_bytes, m->apply_segments,
-                                 engine_bins(&m->e));
-        if (rc) return rc;
+        const uint64_t np = offsets_host[i + 1] - offsets_host[i];
+        const BinnedCall c = binned_call(&m->e, 0, np, m->bin_bytes);
+        if (c.counted || c.bp.shift > 21) {
+            rc = enqueue_binned_scan(&m->e, 0, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[i], np,
+                                     m->bin_bytes, m->apply_segments, engine_bins(&m->e));
+            if (rc) return rc;
+            continue;
+        }
+        binned_count_state(&m->e, 0, c);
+        const BinBufs bb = engine_bins(&m->e);
+        const uint64_t max_blocks = std::min(bb.items_words / c.seg, bb.table_words / (c.bp.n_bins + 1));
+        if (max_blocks == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
+        bm.push_back({m, c, bb, offsets_host[i], np, max_blocks * c.bp.pb, 0});
+    }
+    const uint64_t app_region = align_up((uint64_t)g->max_members * sizeof(BinArgs));
+    const uint64_t pre_region = app_region + align_up((uint64_t)g->max_members * sizeof(ApplyArgs));
+    uint8_t* dev = e->at<uint8_t>(e->L.multi_args);
+    std::vector<uint32_t> round;
+    std::vector<PhaseMark> pm;
+    for (;;) {
+        round.clear();
+        for (uint32_t j = 0; j < (uint32_t)bm.size(); j++)
+            if (bm[j].done < bm[j].n) round.push_back(j);
+        if (round.empty()) break;
+        const uint32_t cnt = (uint32_t)round.size();
+        const uint32_t buf = g->mb_next;
+        g->mb_next ^= 1u;
+        if (g->mb_used[buf]) HIPCHK(e, hipEventSynchronize(g->mb_done[buf]));     // its last copy has run
+        uint8_t* host = static_cast<uint8_t*>(g->mb_pinned[buf]);
+        BinArgs* hb = reinterpret_cast<BinArgs*>(host);
+        ApplyArgs* ha = reinterpret_cast<ApplyArgs*>(host + app_region);
+        uint32_t* hp = reinterpret_cast<uint32_t*>(host + pre_region);    // [binning prefix][store prefix]
+        uint32_t bin_wg = 0, app_wg = 0;
+        for (uint32_t x = 0; x < cnt; x++) {
+            Binned& b = bm[round[x]];
+            const uint64_t np = std::min(b.chunk, b.n - b.done);
+            BinArgs ba{};
+            ApplyArgs aa{};
+            binned_args(&b.m->e, 0, b.c, b.bb.items, b.bb.table, b.m->apply_segments, &ba, &aa);
+            ba.pairs = reinterpret_cast<const uint2*>(pairs_dev) + b.begin + b.done;
+            ba.n = np;
+            ba.blocks = (uint32_t)((np + b.c.bp.pb - 1) / b.c.bp.pb);
+            aa.blocks = ba.blocks;
+            aa.parts = (aa.blocks + aa.per_part - 1) / aa.per_part;
+            b.done += np;
+            hb[x] = ba;
+            ha[x] = aa;
+            hp[x] = bin_wg;
+            hp[cnt + 1 + x] = app_wg;
+            bin_wg += bin_workgroups(ba);
+            app_wg += apply_workgroups(aa);
+        }
+        hp[cnt] = bin_wg;
+        hp[2 * cnt + 1] = app_wg;
+        HIPCHK(e, hipMemcpyAsync(dev, host, multi_args_bytes(g->max_members), hipMemcpyHostToDevice, e->stream));
+        HIPCHK(e, hipEventRecord(g->mb_done[buf], e->stream));
+        g->mb_used[buf] = true;
+        const uint32_t* dp = reinterpret_cast<const uint32_t*>(dev + pre_region);
+        // each member's own phase timing counts the launches that scanned it
+        pm.resize(cnt);
+        for (uint32_t x = 0; x < cnt; x++) pm[x] = phase_begin(&bm[round[x]].m->e);
+        HIPCHK(e, launch_bin_multi(MultiBinArgs{reinterpret_cast<const BinArgs*>(dev), dp, cnt}, bin_wg, e->stream));
+        for (uint32_t x = 0; x < cnt; x++) phase_end(&bm[round[x]].m->e, pm[x], PHASE_SCAN_BIN, 1);
+        for (uint32_t x = 0; x < cnt; x++) pm[x] = phase_begin(&bm[round[x]].m->e);
+        HIPCHK(e, launch_apply_multi(MultiApplyArgs{reinterpret_cast<const ApplyArgs*>(dev + app_region), dp + cnt + 1, cnt},
+                                     app_wg, e->stream));
+        for (uint32_t x = 0; x < cnt; x++) phase_end(&bm[round[x]].m->e, pm[x], 0, 1);
     }
     return SSD_OK;
 }

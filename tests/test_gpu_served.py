@@ -166,6 +166,93 @@ def test_group_binned_members_equal_separate_detectors():
         d.destroy()
 
 
+def _member_slices(seed, key_bits, n_slices, n_pairs, distinct, heavy=10, heavy_peers=600):
+    """Slices of n_pairs drawn with repeats from a pool of distinct pairs: a
+    light background over 20000 hosts plus heavy hosts present every slice."""
+    rng = np.random.default_rng(seed)
+    hosts = rng.integers(0, 2 ** key_bits, 20000, dtype=np.uint64)
+    hv = rng.integers(0, 2 ** key_bits, heavy, dtype=np.uint64)
+    out = []
+    for _ in range(n_slices):
+        bg = np.stack([rng.choice(hosts, distinct), rng.integers(0, 2 ** 32, distinct, dtype=np.uint64)], 1)
+        hp = np.stack([np.repeat(hv, heavy_peers), rng.integers(0, 2 ** 32, heavy * heavy_peers, dtype=np.uint64)], 1)
+        pool = np.concatenate([bg, hp]).astype(np.uint32)
+        out.append(pool[rng.integers(0, pool.shape[0], n_pairs)])
+    return out
+
+
+def test_group_binned_members_in_rounds():
+    """Group scans whose binned members' calls exceed their staging: every
+    round bins all of them in one launch and stores them in one launch.  Six
+    rows (3.5M pairs into a 24 MiB state: several rounds), five rows (6M
+    pairs into 80 MiB: two rounds), four rows (the general binning, 2.5M
+    pairs into 16 MiB: several rounds), a binned member with too few pairs and
+    a small member (both in the tile scan); each member's list, R_k, hot
+    lists and state against a detector of its own and the oracle, slice by
+    slice."""
+    # (q, r, delta, key_bits, scan mode, pairs per call, distinct pairs per slice)
+    spec = [(12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 3_500_000, 100_000),
+            (14, 5, 6, 32, ssd.SSD_SCAN_BINNED, 6_000_000, 100_000),
+            (12, 4, 10, 32, ssd.SSD_SCAN_BINNED, 2_500_000, 100_000),
+            (12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 500_000, 60_000),
+            (10, 6, 5, 30, ssd.SSD_SCAN_AUTO, 200_000, 30_000)]
+    eta, k, theta, n_slices = 1024, 3, 300, 4
+    slices = [_member_slices(900 + i, kb, n_slices, npairs, dist) for i, (_, _, _, kb, _, npairs, dist) in enumerate(spec)]
+    tabs = [tg.hash_tables(60 + i) for i in range(len(spec))]
+
+    def det(i):
+        q, r, delta, kb, mode, _, _ = spec[i]
+        d = ssd.init_detector(ssd.make_params(q=q, r=r, delta=delta, eta=eta, k=k, theta=theta, key_bits=kb),
+                              tabs[i], device="cuda:0")
+        ssd.set_tuning(d, ssd.SSD_TUNE_SCAN_MODE, mode)
+        return d
+
+    members = [det(i) for i in range(len(spec))]
+    alone = [det(i) for i in range(len(spec))]
+    for d in members:
+        ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
+    orcs = [oracle.RSEA(q, r, delta, eta, k, theta, tabs[i], key_bits=kb)
+            for i, (q, r, delta, kb, _, _, _) in enumerate(spec)]
+    g = ssd.group_init(len(spec), device="cuda:0")
+    for t in range(n_slices):
+        per = [sl[t] for sl in slices]
+        offs = np.zeros(len(per) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum([p.shape[0] for p in per])
+        dev = to_dev(np.concatenate(per))
+        log(f"group rounds slice {t}: {offs[-1]} pairs")
+        ssd.group_scan(g, members, dev, offs, [t] * len(spec))
+        for i in range(len(spec)):
+            orcs[i].scan(per[i])
+        for i in range(3):      # the binned members' window state, before the close
+            got = ssd.read_canonical_state(members[i]).cpu().numpy().view(np.uint16)
+            assert np.array_equal(got.reshape(orcs[i].r, -1, eta), orcs[i].canonical()), \
+                f"slice {t} member {i}: state differs"
+        lists, status = ssd.group_close(g, members)
+        assert np.all(status == 0)
+        for i in range(len(spec)):
+            ssd.scan_slice(alone[i], dev[int(offs[i]):int(offs[i + 1])], t)
+            res = ssd.close_slice(alone[i])
+            assert np.array_equal(lists[i], res), f"slice {t} member {i}: group and own detector differ"
+            o = orcs[i]
+            o.reconstruct()
+            ip, rk, est = o.results()
+            assert np.array_equal(lists[i]["ip"], ip) and np.array_equal(lists[i]["rk"], rk), \
+                f"slice {t} member {i}: group and oracle differ"
+            assert np.all(np.abs(lists[i]["est"] - est) <= 1e-6 * np.abs(est))
+            assert np.array_equal(ssd.read_rk(members[i]), o.rk()), f"slice {t} member {i}: R_k differs"
+            for row, (x, y) in enumerate(zip(ssd.read_hot(members[i]), o.hse())):
+                assert np.array_equal(x, y), f"slice {t} member {i}: HSE({row}) differs"
+            o.age()
+        assert sum(len(x) for x in lists) >= 10 * len(spec)
+    tm = [ssd.read_timing(d)["scan_bin"][1] for d in members]
+    log(f"binning launches per member: {tm}")
+    assert tm[0] >= 2 * n_slices and tm[2] >= 2 * n_slices, "the large calls took a single round"
+    assert tm[1] >= n_slices and tm[3] == 0 and tm[4] == 0
+    g.destroy()
+    for d in members + alone:
+        d.destroy()
+
+
 def test_group_refuses_16bit_members():
     """Groups take 8-bit members only: a detector with 16-bit cells (windows
     above 254 slots) in a group call is refused before any work."""
