@@ -420,7 +420,9 @@ int ssd_group_init(uint32_t max_members, void *scratch_dev, uint64_t scratch_byt
  * equal member i's open slice (SSD_E_ORDER).  Asynchronous.  The members
  * that get at least 2^20 pairs and whose own scan call would bin them (scan
  * mode SSD_SCAN_BINNED, or SSD_SCAN_AUTO with a state above 256 MiB) are
- * scanned binned with their own bin buffers; all others share one tile-scan
+ * scanned binned, each into its own bin buffers: per round one binning
+ * launch and one store launch over all of them (a member whose pairs exceed
+ * its buffers takes part in several rounds); all others share one tile-scan
  * launch. */
 int ssd_group_scan(ssd_group *g, ssd_detector *const *members, uint32_t n, const uint32_t *pairs_dev,
                    const uint64_t *offsets_host, const uint64_t *slice_ids_host);
