@@ -1549,9 +1549,26 @@ struct ssd_group {
     hipEvent_t mb_done[2] = {nullptr, nullptr};
     bool mb_used[2] = {false, false};
     uint32_t mb_next = 0;
+    // the tile scan's zeroed counter and windows, staged the same way
+    void* tile_pinned[2] = {nullptr, nullptr};
+    hipEvent_t tile_done[2] = {nullptr, nullptr};
+    bool tile_used[2] = {false, false};
+    uint32_t tile_next = 0;
+    // the bound members' descriptors, wave prefix and row table, staged the same way
+    void* bind_pinned[2] = {nullptr, nullptr};
+    hipEvent_t bind_done[2] = {nullptr, nullptr};
+    bool bind_used[2] = {false, false};
+    uint32_t bind_next = 0;
 };
 
 namespace {
+
+// Host staging of a group's bound members: descriptors, wave prefix, row table.
+uint64_t group_bind_bytes(uint32_t max_members)
+{
+    return align_up((uint64_t)max_members * sizeof(LinkDesc)) + align_up(((uint64_t)max_members + 1) * 8) +
+           (uint64_t)max_members * MAX_ROWS * 4;
+}
 
 Layout plan_group(uint32_t max_members)
 {
@@ -1621,11 +1638,23 @@ int group_bind(ssd_group* g, ssd_detector* const* m, uint32_t n)
     e->bin_req.assign(n, 0);
     e->last_csh.assign(n, 0);
     e->detect_prefix = se_prefix;
-    HIPCHK(e, hipMemcpyAsync(e->dev_links(), e->hl.data(), n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
-    HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), se_prefix.data(), (n + 1) * 8, hipMemcpyHostToDevice,
+    // uploaded from pinned staging (a buffer is reused once its last copies have run)
+    const uint32_t buf = g->bind_next;
+    g->bind_next ^= 1u;
+    if (g->bind_used[buf]) HIPCHK(e, hipEventSynchronize(g->bind_done[buf]));
+    uint8_t* host = static_cast<uint8_t*>(g->bind_pinned[buf]);
+    const uint64_t pre_at = align_up((uint64_t)g->max_members * sizeof(LinkDesc));
+    const uint64_t row_at = pre_at + align_up(((uint64_t)g->max_members + 1) * 8);
+    memcpy(host, e->hl.data(), n * sizeof(LinkDesc));
+    memcpy(host + pre_at, se_prefix.data(), (n + 1) * 8);
+    memcpy(host + row_at, row_table.data(), row_table.size() * 4);
+    HIPCHK(e, hipMemcpyAsync(e->dev_links(), host, n * sizeof(LinkDesc), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipMemcpyAsync(e->at<uint64_t>(e->L.se_prefix), host + pre_at, (n + 1) * 8, hipMemcpyHostToDevice,
                              e->stream));
-    HIPCHK(e, hipMemcpyAsync(e->at<uint32_t>(e->L.row_table), row_table.data(), row_table.size() * 4,
+    HIPCHK(e, hipMemcpyAsync(e->at<uint32_t>(e->L.row_table), host + row_at, row_table.size() * 4,
                              hipMemcpyHostToDevice, e->stream));
+    HIPCHK(e, hipEventRecord(g->bind_done[buf], e->stream));
+    g->bind_used[buf] = true;
     g->bound.resize(n);
     for (uint32_t i = 0; i < n; i++) g->bound[i] = m[i]->id;
     e->results.assign(n, {});
@@ -2545,6 +2574,10 @@ int ssd_group_init(uint32_t max_members, void* scratch_dev, uint64_t scratch_byt
     for (int i = 0; i < 2 && err == hipSuccess; i++) {
         err = hipHostMalloc(&g->mb_pinned[i], multi_args_bytes(max_members), hipHostMallocDefault);
         if (err == hipSuccess) err = hipEventCreateWithFlags(&g->mb_done[i], hipEventDisableTiming);
+        if (err == hipSuccess) err = hipHostMalloc(&g->tile_pinned[i], 8 + MAX_WINDOWS * sizeof(ScanWindow), hipHostMallocDefault);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&g->tile_done[i], hipEventDisableTiming);
+        if (err == hipSuccess) err = hipHostMalloc(&g->bind_pinned[i], group_bind_bytes(max_members), hipHostMallocDefault);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&g->bind_done[i], hipEventDisableTiming);
     }
     if (err != hipSuccess) {
         int rc = dev_fail(e, err, "group staging");
@@ -2567,6 +2600,10 @@ void ssd_group_destroy(ssd_group* g)
     for (int i = 0; i < 2; i++) {
         if (g->mb_pinned[i]) (void)hipHostFree(g->mb_pinned[i]);
         if (g->mb_done[i]) (void)hipEventDestroy(g->mb_done[i]);
+        if (g->tile_pinned[i]) (void)hipHostFree(g->tile_pinned[i]);
+        if (g->tile_done[i]) (void)hipEventDestroy(g->tile_done[i]);
+        if (g->bind_pinned[i]) (void)hipHostFree(g->bind_pinned[i]);
+        if (g->bind_done[i]) (void)hipEventDestroy(g->bind_done[i]);
     }
     delete g;
 }
@@ -2628,12 +2665,19 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     const uint64_t n_wins = ws.size() - 1;
     if (n_wins > MAX_WINDOWS) return fail(SSD_E_PARAM, "too many scan windows (%llu)", (unsigned long long)n_wins);
     if (n_wins) {
-        // the device block is [counter (8 bytes)][windows]; the first vector entry only supplies the zero counter
+        // the device block is [counter (8 bytes)][windows], copied from
+        // pinned staging (the first vector entry is only a placeholder)
+        const uint32_t buf = g->tile_next;
+        g->tile_next ^= 1u;
+        if (g->tile_used[buf]) HIPCHK(e, hipEventSynchronize(g->tile_done[buf]));   // its last copy has run
+        unsigned long long* counter = static_cast<unsigned long long*>(g->tile_pinned[buf]);
+        *counter = 0;
+        memcpy(counter + 1, ws.data() + 1, n_wins * sizeof(ScanWindow));
         unsigned long long* dcounter = e->at<unsigned long long>(e->L.tiles);
-        const unsigned long long zero = 0;
-        HIPCHK(e, hipMemcpyAsync(dcounter, &zero, 8, hipMemcpyHostToDevice, e->stream));
-        HIPCHK(e, hipMemcpyAsync(dcounter + 1, ws.data() + 1, n_wins * sizeof(ScanWindow), hipMemcpyHostToDevice,
+        HIPCHK(e, hipMemcpyAsync(dcounter, counter, 8 + n_wins * sizeof(ScanWindow), hipMemcpyHostToDevice,
                                  e->stream));
+        HIPCHK(e, hipEventRecord(g->tile_done[buf], e->stream));
+        g->tile_used[buf] = true;
         TileScanArgs a{};
         a.pairs = reinterpret_cast<const uint2*>(pairs_dev);
         a.links = e->dev_links();
