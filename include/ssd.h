@@ -418,9 +418,8 @@ int ssd_group_init(uint32_t max_members, void *scratch_dev, uint64_t scratch_byt
 /* Scan into the open slice of every member: member i's pairs are
  * pairs_dev[offsets_host[i] .. offsets_host[i+1]); slice_ids_host[i] must
  * equal member i's open slice (SSD_E_ORDER).  Asynchronous.  The members
- * that get at least 2^20 pairs and whose own scan call would bin them (scan
- * mode SSD_SCAN_BINNED, or SSD_SCAN_AUTO with a state above 256 MiB) are
- * scanned binned, each into its own bin buffers: per round one binning
+ * that get at least 2^18 pairs (and whose scan mode is not SSD_SCAN_PASSES)
+ * are scanned binned, each into its own bin buffers: per round one binning
  * launch and one store launch over all of them (a member whose pairs exceed
  * its buffers takes part in several rounds); all others share one tile-scan
  * launch. */

@@ -174,9 +174,10 @@ constexpr uint32_t PHASE_SCAN_TILES = 10;
 // go to the persistent tile scan, since the binned stores cost workgroups
 // per bin whatever the call's size)
 constexpr uint64_t BATCH_BINNED_MIN_PAIRS = 1ull << 16;
-// group members scanned binned (each with its own launches): a large state
-// and at least this many pairs in the call
-constexpr uint64_t GROUP_BINNED_MIN_PAIRS = 1ull << 20;
+// group members scanned binned (in the multi-member launches): at least this
+// many pairs in the call, whatever the state's size (a member whose scan mode
+// is SSD_SCAN_PASSES keeps the tile scan)
+constexpr uint64_t GROUP_BINNED_MIN_PAIRS = 1ull << 18;
 // staging of a batch's binned scan: the binning segments of up to this many
 // pairs (at 4 bytes per offset) for the links of one group of launches.  On
 // the 64-link workload (152M pairs per slice) one group, 4.6 GB of staging,
@@ -2626,17 +2627,16 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     }
     if (offsets_host[n] == offsets_host[0]) return SSD_OK;
     if (!pairs_dev || ((uintptr_t)pairs_dev & 7u)) return fail(SSD_E_PARAM, "pairs must be a non-NULL 8-byte aligned device pointer");
-    // members that a call of their own would scan binned (large state, enough
-    // pairs) are scanned binned here too, with their own bin buffers, after
-    // the tile scan of the others -- when they were set up on the group's
-    // stream, so that the group's close stays ordered after their scan
+    // members with at least GROUP_BINNED_MIN_PAIRS pairs in the call are
+    // scanned binned, each into its own bin buffers, after the tile scan of
+    // the others (as the links of a batch: XCD-local stores beat pass windows
+    // for such calls whatever the state's size) -- when they were set up on
+    // the group's stream, so that the group's close stays ordered after them
     auto binned = [&](uint32_t i) {
         const ssd_detector* m = members[i];
         if (m->e.stream != e->stream) return false;
         const uint64_t np = offsets_host[i + 1] - offsets_host[i];
-        const uint64_t sb = e->hl[i].n_se << e->hl[i].log2eta;
-        return m->scan_mode != SSD_SCAN_PASSES && np >= GROUP_BINNED_MIN_PAIRS &&
-               (m->scan_mode == SSD_SCAN_BINNED || sb > AUTO_BINNED_ABOVE);
+        return m->scan_mode != SSD_SCAN_PASSES && np >= GROUP_BINNED_MIN_PAIRS;
     };
     // windows of every other member's state (its own pass window), in member order
     std::vector<ScanWindow> ws;

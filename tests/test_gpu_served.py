@@ -107,8 +107,8 @@ def test_served_admission_by_memory_budget():
 
 
 def test_group_binned_members_equal_separate_detectors():
-    """Members with a state above 256 MiB and at least 2^20 pairs in the call
-    are scanned binned inside the group scan (the rest share the tile scan);
+    """Members with at least 2^18 pairs in the call are scanned binned inside
+    the group scan, whatever their state's size (the rest share the tile scan);
     each member's list equals that of a detector of its own fed the same
     pairs, and the oracle's (lists, R_k and hot lists), slice by slice, also
     when only a subset of the members scans and closes."""
@@ -125,7 +125,7 @@ def test_group_binned_members_equal_separate_detectors():
         ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
     orcs = [oracle.RSEA(c.q, c.r, c.delta, c.eta, c.k, c.theta, tabs[i]) for i, c in enumerate(cfgs)]
     g = ssd.group_init(len(cfgs), device="cuda:0")
-    big = [i for i, c in enumerate(cfgs) if c.r * (1 << c.q) * c.eta > 256 << 20 and c.pairs_lo >= 1 << 20]
+    big = [i for i, c in enumerate(cfgs) if c.pairs_lo >= 1 << 18]
     assert big, "no member takes the binned scan"
     clock = [0] * len(cfgs)           # open slice of member i and of its own detector
     for t in range(3):
@@ -186,15 +186,16 @@ def test_group_binned_members_in_rounds():
     round bins all of them in one launch and stores them in one launch.  Six
     rows (3.5M pairs into a 24 MiB state: several rounds), five rows (6M
     pairs into 80 MiB: two rounds), four rows (the general binning, 2.5M
-    pairs into 16 MiB: several rounds), a binned member with too few pairs and
-    a small member (both in the tile scan); each member's list, R_k, hot
+    pairs into 16 MiB: several rounds), and two members with calls below 2^18
+    pairs (in the tile scan, one of them set to bin its own calls); each
+    member's list, R_k, hot
     lists and state against a detector of its own and the oracle, slice by
     slice."""
     # (q, r, delta, key_bits, scan mode, pairs per call, distinct pairs per slice)
     spec = [(12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 3_500_000, 100_000),
             (14, 5, 6, 32, ssd.SSD_SCAN_BINNED, 6_000_000, 100_000),
             (12, 4, 10, 32, ssd.SSD_SCAN_BINNED, 2_500_000, 100_000),
-            (12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 500_000, 60_000),
+            (12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 200_000, 60_000),
             (10, 6, 5, 30, ssd.SSD_SCAN_AUTO, 200_000, 30_000)]
     eta, k, theta, n_slices = 1024, 3, 300, 4
     slices = [_member_slices(900 + i, kb, n_slices, npairs, dist) for i, (_, _, _, kb, _, npairs, dist) in enumerate(spec)]
