@@ -49,14 +49,25 @@ class StreamInput:
     starts: np.ndarray
     reservoir: torch.Tensor
 
-    def batch(self, j: int) -> torch.Tensor:
-        """Exactly sizes[j] rows, wrapping around the reservoir as often as needed."""
+    def pieces(self, j: int) -> List[torch.Tensor]:
+        """Batch j as views of the reservoir: exactly sizes[j] rows from
+        starts[j] on, wrapping around the reservoir as often as needed."""
         R = self.reservoir.shape[0]
         a, n = int(self.starts[j]) % R, int(self.sizes[j])
-        if a + n <= R:
-            return self.reservoir[a:a + n]
-        idx = (torch.arange(n, device=self.reservoir.device) + a) % R
-        return self.reservoir[idx]
+        out = []
+        while n > 0:
+            m = min(n, R - a)
+            out.append(self.reservoir[a:a + m])
+            n -= m
+            a = 0
+        return out
+
+    def batch(self, j: int) -> torch.Tensor:
+        """Batch j as one tensor (a view when it does not wrap, else a copy)."""
+        p = self.pieces(j)
+        if not p:
+            return self.reservoir[:0]
+        return p[0] if len(p) == 1 else torch.cat(p)
 
 
 @dataclasses.dataclass
@@ -184,7 +195,11 @@ def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float =
                 j += 1
             if j > L.next:
                 members.append(L)
-                parts.extend(s.batch(b) for b in range(L.next, j))
+                if batched:
+                    for b in range(L.next, j):
+                        parts.extend(s.pieces(b))
+                else:
+                    parts.extend(s.batch(b) for b in range(L.next, j))
                 counts.append(int(s.sizes[L.next:j].sum()))
                 ids.append(L.slot)
                 L.next = j
