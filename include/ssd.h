@@ -116,7 +116,7 @@ typedef struct {
                                 1 from the per-slot counters, 2 from counters
                                 rebuilt from the state first                  */
     uint32_t counted_bin_kib; /* bin size (KiB of cells) of the last scan call
-                                that kept the counters, 0 if none            */
+                                that took the counted stores, 0 if none      */
 } ssd_info;
 
 /* Sizes the caller must allocate on the device for params p: the estimator
@@ -420,9 +420,12 @@ int ssd_group_init(uint32_t max_members, void *scratch_dev, uint64_t scratch_byt
  * equal member i's open slice (SSD_E_ORDER).  Asynchronous.  The members
  * that get at least 2^18 pairs (and whose scan mode is not SSD_SCAN_PASSES)
  * are scanned binned, each into its own bin buffers: per round one binning
- * launch and one store launch over all of them (a member whose pairs exceed
- * its buffers takes part in several rounds); all others share one tile-scan
- * launch. */
+ * launch and one store launch per store kind over all of them (a member
+ * whose pairs exceed its buffers takes part in several rounds); all others
+ * share one tile-scan launch.  A member that keeps per-slot counters takes
+ * the counted stores for a large call (each touched chunk restamped once),
+ * its counters then untrusted until its own close rebuilds them: group
+ * closes read every member's state. */
 int ssd_group_scan(ssd_group *g, ssd_detector *const *members, uint32_t n, const uint32_t *pairs_dev,
                    const uint64_t *offsets_host, const uint64_t *slice_ids_host);
 

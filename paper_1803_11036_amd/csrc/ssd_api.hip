@@ -688,12 +688,15 @@ struct BinnedCall {
     BinPlan bp;
     uint64_t seg = 0;        // offsets per binning workgroup (pb * r)
 };
-BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_bytes)
+// (untrusted: the counted stores also for counters that are not exact --
+// they then restamp each touched chunk once, as a faster store, and leave the
+// counters to be rebuilt)
+BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_bytes, bool untrusted = false)
 {
     BinnedCall c;
     c.csh = e->counting[l] ? counted_shift(e->p[l], e->bin_req[l] ? e->bin_req[l] : e->counted_bin_bytes) : 0;
     c.large = c.csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << c.csh).n_bins;
-    c.counted = e->counting[l] && e->count_valid[l] && c.large;
+    c.counted = e->counting[l] && (e->count_valid[l] || untrusted) && c.large;
     c.bp = bin_plan(e->p[l], c.counted ? 1ull << c.csh : bin_bytes);
     c.seg = (uint64_t)c.bp.pb * e->p[l].r;
     return c;
@@ -2692,9 +2695,14 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     }
     for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;   // group scans store uncounted
     // the binned members: rounds of one binning launch and one store launch
-    // over all of them, each member binning into its own staging (a member
-    // whose pairs exceed its staging takes part in several rounds); a member
-    // whose bins are too large for packed offsets is scanned alone
+    // per kind over all of them, each member binning into its own staging (a
+    // member whose pairs exceed its staging takes part in several rounds); a
+    // member whose bins are too large for packed offsets is scanned alone.
+    // A member that keeps per-slot counters takes the counted stores for a
+    // large call: each touched 16-byte chunk is restamped once, which beats a
+    // byte store per offset when the pairs repeat.  Its counters stay
+    // untrusted (the group's close reads every member's state; the member's
+    // own close rebuilds them before it counts again).
     struct Binned {
         ssd_detector* m;
         BinnedCall c;
@@ -2706,14 +2714,14 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         if (!binned(i)) continue;
         ssd_detector* m = members[i];
         const uint64_t np = offsets_host[i + 1] - offsets_host[i];
-        const BinnedCall c = binned_call(&m->e, 0, np, m->bin_bytes);
-        if (c.counted || c.bp.shift > 21) {
+        const BinnedCall c = binned_call(&m->e, 0, np, m->bin_bytes, true);
+        if (c.bp.shift > 21) {
             rc = enqueue_binned_scan(&m->e, 0, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[i], np,
                                      m->bin_bytes, m->apply_segments, engine_bins(&m->e));
             if (rc) return rc;
             continue;
         }
-        binned_count_state(&m->e, 0, c);
+        if (c.counted) m->e.last_csh[0] = (uint8_t)c.csh;
         const BinBufs bb = engine_bins(&m->e);
         const uint64_t max_blocks = std::min(bb.items_words / c.seg, bb.table_words / (c.bp.n_bins + 1));
         if (max_blocks == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
@@ -2736,8 +2744,20 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         uint8_t* host = static_cast<uint8_t*>(g->mb_pinned[buf]);
         BinArgs* hb = reinterpret_cast<BinArgs*>(host);
         ApplyArgs* ha = reinterpret_cast<ApplyArgs*>(host + app_region);
-        uint32_t* hp = reinterpret_cast<uint32_t*>(host + pre_region);    // [binning prefix][store prefix]
-        uint32_t bin_wg = 0, app_wg = 0;
+        uint32_t* hp = reinterpret_cast<uint32_t*>(host + pre_region);    // [binning prefix][3 store prefixes]
+        // the round's members by store kind: counted whose LDS lets two
+        // workgroups share a compute unit (0), uncounted (1), counted needing
+        // more LDS (2); a launch per kind, with its own workgroup prefix
+        auto kind_of = [&](const Binned& b) -> uint32_t {
+            if (!b.c.counted) return 1u;
+            const LinkDesc& D = b.m->e.hl[0];
+            return counted_lds_bytes(b.c.bp.shift, D.log2eta, D.k) <= COUNTED_LDS_PAIR ? 0u : 2u;
+        };
+        std::stable_sort(round.begin(), round.end(),
+                         [&](uint32_t a, uint32_t c) { return kind_of(bm[a]) < kind_of(bm[c]); });
+        uint32_t bin_wg = 0, app_wg[3] = {0, 0, 0}, kcount[3] = {0, 0, 0}, lds[3] = {0, 0, 0};
+        for (uint32_t x = 0; x < cnt; x++) kcount[kind_of(bm[round[x]])]++;
+        const uint32_t kfirst[3] = {0, kcount[0], kcount[0] + kcount[1]};
         for (uint32_t x = 0; x < cnt; x++) {
             Binned& b = bm[round[x]];
             const uint64_t np = std::min(b.chunk, b.n - b.done);
@@ -2753,12 +2773,14 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
             hb[x] = ba;
             ha[x] = aa;
             hp[x] = bin_wg;
-            hp[cnt + 1 + x] = app_wg;
             bin_wg += bin_workgroups(ba);
-            app_wg += apply_workgroups(aa);
+            const uint32_t kd = kind_of(b);
+            hp[(kd + 1) * (cnt + 1) + (x - kfirst[kd])] = app_wg[kd];
+            app_wg[kd] += kd == 1u ? apply_workgroups(aa) : apply_counted_workgroups(aa);
+            if (kd != 1u) lds[kd] = std::max<uint32_t>(lds[kd], (uint32_t)counted_lds_bytes(aa.bin_shift, aa.log2eta, aa.k));
         }
         hp[cnt] = bin_wg;
-        hp[2 * cnt + 1] = app_wg;
+        for (uint32_t kd = 0; kd < 3; kd++) hp[(kd + 1) * (cnt + 1) + kcount[kd]] = app_wg[kd];
         HIPCHK(e, hipMemcpyAsync(dev, host, multi_args_bytes(g->max_members), hipMemcpyHostToDevice, e->stream));
         HIPCHK(e, hipEventRecord(g->mb_done[buf], e->stream));
         g->mb_used[buf] = true;
@@ -2769,8 +2791,13 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         HIPCHK(e, launch_bin_multi(MultiBinArgs{reinterpret_cast<const BinArgs*>(dev), dp, cnt}, bin_wg, e->stream));
         for (uint32_t x = 0; x < cnt; x++) phase_end(&bm[round[x]].m->e, pm[x], PHASE_SCAN_BIN, 1);
         for (uint32_t x = 0; x < cnt; x++) pm[x] = phase_begin(&bm[round[x]].m->e);
-        HIPCHK(e, launch_apply_multi(MultiApplyArgs{reinterpret_cast<const ApplyArgs*>(dev + app_region), dp + cnt + 1, cnt},
-                                     app_wg, e->stream));
+        for (uint32_t kd = 0; kd < 3; kd++) {
+            if (!kcount[kd]) continue;
+            const MultiApplyArgs ma{reinterpret_cast<const ApplyArgs*>(dev + app_region) + kfirst[kd],
+                                    dp + (kd + 1) * (cnt + 1), kcount[kd]};
+            if (kd == 1u) HIPCHK(e, launch_apply_multi(ma, app_wg[kd], e->stream));
+            else HIPCHK(e, launch_apply_counted_multi(ma, app_wg[kd], lds[kd], e->stream));
+        }
         for (uint32_t x = 0; x < cnt; x++) phase_end(&bm[round[x]].m->e, pm[x], 0, 1);
     }
     return SSD_OK;

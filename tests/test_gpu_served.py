@@ -183,26 +183,31 @@ def _member_slices(seed, key_bits, n_slices, n_pairs, distinct, heavy=10, heavy_
 
 def test_group_binned_members_in_rounds():
     """Group scans whose binned members' calls exceed their staging: every
-    round bins all of them in one launch and stores them in one launch.  Six
-    rows (3.5M pairs into a 24 MiB state: several rounds), five rows (6M
-    pairs into 80 MiB: two rounds), four rows (the general binning, 2.5M
-    pairs into 16 MiB: several rounds), and two members with calls below 2^18
-    pairs (in the tile scan, one of them set to bin its own calls); each
-    member's list, R_k, hot
-    lists and state against a detector of its own and the oracle, slice by
-    slice."""
-    # (q, r, delta, key_bits, scan mode, pairs per call, distinct pairs per slice)
-    spec = [(12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 3_500_000, 100_000),
-            (14, 5, 6, 32, ssd.SSD_SCAN_BINNED, 6_000_000, 100_000),
-            (12, 4, 10, 32, ssd.SSD_SCAN_BINNED, 2_500_000, 100_000),
-            (12, 6, 5, 32, ssd.SSD_SCAN_BINNED, 200_000, 60_000),
-            (10, 6, 5, 30, ssd.SSD_SCAN_AUTO, 200_000, 30_000)]
-    eta, k, theta, n_slices = 1024, 3, 300, 4
-    slices = [_member_slices(900 + i, kb, n_slices, npairs, dist) for i, (_, _, _, kb, _, npairs, dist) in enumerate(spec)]
+    round bins all of them in one launch and stores them in one launch per
+    store kind.  Six rows (3.5M pairs into a 24 MiB state: several rounds),
+    five rows (6M pairs into 80 MiB: two rounds), four rows (the general
+    binning, 2.5M pairs into 16 MiB: several rounds) -- all three with the
+    counted stores of two workgroups per compute unit --, a member whose
+    counters need more LDS (k = 100), one that cannot count (k = 150 > eta / 8:
+    uncounted stores), and two members with calls below 2^18 pairs (in the
+    tile scan, one of them set to bin its own calls); each member's list,
+    R_k, hot lists and state against a detector of its own and the oracle,
+    slice by slice."""
+    # (q, r, delta, key_bits, k, scan mode, pairs per call, distinct pairs per slice)
+    spec = [(12, 6, 5, 32, 3, ssd.SSD_SCAN_BINNED, 3_500_000, 100_000),
+            (14, 5, 6, 32, 3, ssd.SSD_SCAN_BINNED, 6_000_000, 100_000),
+            (12, 4, 10, 32, 3, ssd.SSD_SCAN_BINNED, 2_500_000, 100_000),
+            (12, 6, 5, 32, 100, ssd.SSD_SCAN_BINNED, 2_500_000, 100_000),
+            (12, 6, 5, 32, 150, ssd.SSD_SCAN_BINNED, 2_000_000, 100_000),
+            (12, 6, 5, 32, 3, ssd.SSD_SCAN_BINNED, 200_000, 60_000),
+            (10, 6, 5, 30, 3, ssd.SSD_SCAN_AUTO, 200_000, 30_000)]
+    n_binned = 5
+    eta, theta, n_slices = 1024, 300, 4
+    slices = [_member_slices(900 + i, x[3], n_slices, x[6], x[7]) for i, x in enumerate(spec)]
     tabs = [tg.hash_tables(60 + i) for i in range(len(spec))]
 
     def det(i):
-        q, r, delta, kb, mode, _, _ = spec[i]
+        q, r, delta, kb, k, mode, _, _ = spec[i]
         d = ssd.init_detector(ssd.make_params(q=q, r=r, delta=delta, eta=eta, k=k, theta=theta, key_bits=kb),
                               tabs[i], device="cuda:0")
         ssd.set_tuning(d, ssd.SSD_TUNE_SCAN_MODE, mode)
@@ -213,7 +218,7 @@ def test_group_binned_members_in_rounds():
     for d in members:
         ssd.set_tuning(d, ssd.SSD_TUNE_TIMING, 1)
     orcs = [oracle.RSEA(q, r, delta, eta, k, theta, tabs[i], key_bits=kb)
-            for i, (q, r, delta, kb, _, _, _) in enumerate(spec)]
+            for i, (q, r, delta, kb, k, _, _, _) in enumerate(spec)]
     g = ssd.group_init(len(spec), device="cuda:0")
     for t in range(n_slices):
         per = [sl[t] for sl in slices]
@@ -224,7 +229,7 @@ def test_group_binned_members_in_rounds():
         ssd.group_scan(g, members, dev, offs, [t] * len(spec))
         for i in range(len(spec)):
             orcs[i].scan(per[i])
-        for i in range(3):      # the binned members' window state, before the close
+        for i in range(n_binned):      # the binned members' window state, before the close
             got = ssd.read_canonical_state(members[i]).cpu().numpy().view(np.uint16)
             assert np.array_equal(got.reshape(orcs[i].r, -1, eta), orcs[i].canonical()), \
                 f"slice {t} member {i}: state differs"
@@ -246,9 +251,12 @@ def test_group_binned_members_in_rounds():
             o.age()
         assert sum(len(x) for x in lists) >= 10 * len(spec)
     tm = [ssd.read_timing(d)["scan_bin"][1] for d in members]
-    log(f"binning launches per member: {tm}")
+    kib = [ssd.get_info(d)["counted_bin_kib"] for d in members]
+    log(f"binning launches per member: {tm}; counted bins (KiB): {kib}")
     assert tm[0] >= 2 * n_slices and tm[2] >= 2 * n_slices, "the large calls took a single round"
-    assert tm[1] >= n_slices and tm[3] == 0 and tm[4] == 0
+    assert all(x >= n_slices for x in tm[:n_binned]) and tm[n_binned:] == [0, 0]
+    # counted stores for the members that keep counters, uncounted for the one that cannot
+    assert all(x > 0 for x in kib[:4]) and kib[4] == 0
     g.destroy()
     for d in members + alone:
         d.destroy()
