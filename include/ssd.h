@@ -307,7 +307,10 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       merge into the detector, an advance-only close, a pass scan or a
  *       group call leaves the counters stale: the close reads the state,
  *       or, when every binned call of the slice was large, rebuilds the
- *       counters from it.  Batches: the same for every link that can count
+ *       counters from it.  Large calls take the counted stores also while
+ *       the counters are stale (each touched 16-byte chunk is restamped
+ *       once, faster than a byte store per offset when pairs repeat); the
+ *       counters then stay stale until the rebuild.  Batches: the same for every link that can count
  *       (reading 1 if any link counts); a link scanned by the tile scan in a
  *       slice (fewer than 2^16 pairs in the call, or SSD_SCAN_PASSES) leaves
  *       its counters stale likewise. */

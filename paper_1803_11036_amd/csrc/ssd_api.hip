@@ -679,24 +679,26 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
     return SSD_OK;
 }
 
-// The binned scan of a call of n pairs of link l: whether its stores keep
-// the link's per-slot counters (they are exact and the call is large enough)
-// and its bin geometry.
+// The binned scan of a call of n pairs of link l: whether it takes the
+// counted stores (the link keeps per-slot counters and the call is large
+// enough), whether its counters stay exact through it (they were before),
+// and its bin geometry.  A link whose counters are stale still takes the
+// counted stores for a large call: each touched 16-byte chunk is restamped
+// once, which beats a byte store per offset when the pairs repeat, and the
+// counters are rebuilt at the close (or, in a group, left untrusted).
 struct BinnedCall {
-    bool large = false, counted = false;
+    bool large = false, counted = false, exact = false;
     uint32_t csh = 0;        // counted bin shift (0: the link cannot count)
     BinPlan bp;
     uint64_t seg = 0;        // offsets per binning workgroup (pb * r)
 };
-// (untrusted: the counted stores also for counters that are not exact --
-// they then restamp each touched chunk once, as a faster store, and leave the
-// counters to be rebuilt)
-BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_bytes, bool untrusted = false)
+BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_bytes)
 {
     BinnedCall c;
     c.csh = e->counting[l] ? counted_shift(e->p[l], e->bin_req[l] ? e->bin_req[l] : e->counted_bin_bytes) : 0;
     c.large = c.csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << c.csh).n_bins;
-    c.counted = e->counting[l] && (e->count_valid[l] || untrusted) && c.large;
+    c.counted = e->counting[l] && c.large;
+    c.exact = c.counted && e->count_valid[l];
     c.bp = bin_plan(e->p[l], c.counted ? 1ull << c.csh : bin_bytes);
     c.seg = (uint64_t)c.bp.pb * e->p[l].r;
     return c;
@@ -715,18 +717,14 @@ BinBufs engine_bins(const Engine* e)
             e->L.bin_table_words};
 }
 
-// Binned scan (k_bin, then k_apply_counted or k_apply) of n pairs of link l,
-// in steps that fit the staging buffers bb (the engine's own are shared by
-// every binned link of a batch: the steps run one after another on the
-// engine's stream).  The stores keep the link's per-slot counters when they
-// are exact and the call is large enough; otherwise they leave them stale.
-// The counter bookkeeping of a binned call of link l: stores that do not
-// count leave the counters stale.
+// The counter bookkeeping of a binned call of link l: after stores that do
+// not keep the counters exact, the counters are stale (rebuilt at the close
+// after a large call).
 void binned_count_state(Engine* e, uint32_t l, const BinnedCall& c)
 {
     if (c.counted) e->last_csh[l] = (uint8_t)c.csh;
-    if (e->counting[l] && !c.counted) {
-        e->count_valid[l] = 0;                 // these stores are not counted
+    if (e->counting[l] && !c.exact) {
+        e->count_valid[l] = 0;                 // the counters are not exact after these stores
         // the close rebuilds the counters from the state after large calls
         // only; with a small call in the slice it reads the state once
         if (!c.large) e->count_small[l] = 1;
@@ -771,6 +769,11 @@ void binned_args(const Engine* e, uint32_t l, const BinnedCall& c, uint32_t* ite
     *aa_out = aa;
 }
 
+// Binned scan (k_bin, then k_apply_counted or k_apply) of n pairs of link l,
+// in steps that fit the staging buffers bb (the engine's own are shared by
+// every binned link of a batch: the steps run one after another on the
+// engine's stream).  The counted stores keep the link's per-slot counters
+// exact when they were; otherwise the counters are left stale.
 int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, uint64_t bin_bytes, uint32_t segs,
                         const BinBufs& bb)
 {
@@ -2699,10 +2702,9 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
     // member whose pairs exceed its staging takes part in several rounds); a
     // member whose bins are too large for packed offsets is scanned alone.
     // A member that keeps per-slot counters takes the counted stores for a
-    // large call: each touched 16-byte chunk is restamped once, which beats a
-    // byte store per offset when the pairs repeat.  Its counters stay
-    // untrusted (the group's close reads every member's state; the member's
-    // own close rebuilds them before it counts again).
+    // large call (binned_call); its counters stay untrusted (the group's
+    // close reads every member's state; the member's own close rebuilds them
+    // before it counts again).
     struct Binned {
         ssd_detector* m;
         BinnedCall c;
@@ -2714,14 +2716,14 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         if (!binned(i)) continue;
         ssd_detector* m = members[i];
         const uint64_t np = offsets_host[i + 1] - offsets_host[i];
-        const BinnedCall c = binned_call(&m->e, 0, np, m->bin_bytes, true);
+        const BinnedCall c = binned_call(&m->e, 0, np, m->bin_bytes);
         if (c.bp.shift > 21) {
             rc = enqueue_binned_scan(&m->e, 0, reinterpret_cast<const uint2*>(pairs_dev) + offsets_host[i], np,
                                      m->bin_bytes, m->apply_segments, engine_bins(&m->e));
             if (rc) return rc;
             continue;
         }
-        if (c.counted) m->e.last_csh[0] = (uint8_t)c.csh;
+        binned_count_state(&m->e, 0, c);
         const BinBufs bb = engine_bins(&m->e);
         const uint64_t max_blocks = std::min(bb.items_words / c.seg, bb.table_words / (c.bp.n_bins + 1));
         if (max_blocks == 0) return fail(SSD_E_STATE, "binned scan buffers too small");
