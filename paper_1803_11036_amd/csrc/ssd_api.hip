@@ -2696,7 +2696,7 @@ int ssd_group_scan(ssd_group* g, ssd_detector* const* members, uint32_t n, const
         HIPCHK(e, launch_scan_tiles(a, (uint32_t)std::min<uint64_t>(g->scan_blocks, tiles), e->stream));
         phase_end(e, pm, PHASE_SCAN_TILES, 1);
     }
-    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;   // group scans store uncounted
+    for (uint32_t i = 0; i < n; i++) members[i]->e.count_valid[0] = 0;   // group scans leave the counters stale
     // the binned members: rounds of one binning launch and one store launch
     // per kind over all of them, each member binning into its own staging (a
     // member whose pairs exceed its staging takes part in several rounds); a
