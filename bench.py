@@ -733,8 +733,13 @@ def run_core(args, secondary: bool = False) -> dict:
     cell_b = 2 if cell_bits == 16 else 1
     alg_scan = avg_pairs * (8 + cfg.r * cell_b)
     cands = {}
-    stores = ("k_apply_counted" if counted else "k_apply") if binned else "k_scan"
-    impl_scan = avg_pairs * ((6 if counted else 5) * cfg.r) if binned else None
+    # the binned stores: counted, the bitmap stores of 16-bit cells (no
+    # counters; the last call's bin size is reported), or a byte store per offset
+    marked = binned and not counted and cell_bits == 16 and info["counted_bin_kib"] > 0
+    stores = ("k_apply_counted" if counted else "k_apply_marked16" if marked else "k_apply") if binned else "k_scan"
+    # implementation bytes: the 4-byte offsets plus the cells stored (read too
+    # by the stores that read-modify-write 16-byte chunks)
+    impl_scan = avg_pairs * cfg.r * (4 + cell_b * (2 if counted or marked else 1)) if binned else None
     n_scan = timing["scan"][1]
     if n_scan:
         cands[stores] = (timing["scan"][0] / K, alg_scan / max(1, n_scan // K), timing["scan"][0] / n_scan,
@@ -891,9 +896,12 @@ def run_distributed(args) -> dict:
     elapsed = time.perf_counter() - t0
     tg_ = ssd.read_timing(glob, reset=True)
     rt = [ssd.read_timing(d, reset=True) for d in routers]
-    # the routers' binned scans: k_bin, then the stores (k_apply; the routers
-    # only advance, so their counters go stale after the first close and
-    # their stores do not count)
+    # the routers' binned scans: k_bin, then the stores (the routers only
+    # advance, so their counters go stale after the first close; a large call
+    # still takes the counted stores, k_apply_counted, when the routers can
+    # count -- the bin size of their last such call is reported -- else
+    # k_apply)
+    counted_routers = all(ssd.get_info(d)["counted_bin_kib"] > 0 for d in routers)
     apply_ms, apply_n = sum(x["scan"][0] for x in rt), sum(x["scan"][1] for x in rt)
     bin_ms, bin_n = sum(x["scan_bin"][0] for x in rt), sum(x["scan_bin"][1] for x in rt)
     scan_ms = apply_ms + bin_ms
@@ -903,8 +911,9 @@ def run_distributed(args) -> dict:
     merge_bytes = (cfg.n_streams + 1) * state          # every router state read, the global written
     cands = {"k_merge": (tg_["merge"][0] / K, float(merge_bytes), merge_ms, 1, None)}
     if apply_n:
-        cands["k_apply"] = (apply_ms / K, (8 + cfg.r) * pairs_call, apply_ms / apply_n, apply_n // K,
-                            5 * cfg.r * pairs_call)
+        cands["k_apply_counted" if counted_routers else "k_apply"] = (
+            apply_ms / K, (8 + cfg.r) * pairs_call, apply_ms / apply_n, apply_n // K,
+            (6 if counted_routers else 5) * cfg.r * pairs_call)
     if bin_n:
         cands["k_bin"] = (bin_ms / K, 8.0 * pairs_call, bin_ms / bin_n, bin_n // K, (8 + 4 * cfg.r) * pairs_call)
     if tg_["hot_detect"][1]:

@@ -116,7 +116,8 @@ typedef struct {
                                 1 from the per-slot counters, 2 from counters
                                 rebuilt from the state first                  */
     uint32_t counted_bin_kib; /* bin size (KiB of cells) of the last scan call
-                                that took the counted stores, 0 if none      */
+                                that took the bitmap stores (the counted
+                                ones, or those of 16-bit cells), 0 if none   */
 } ssd_info;
 
 /* Sizes the caller must allocate on the device for params p: the estimator
@@ -315,7 +316,10 @@ int ssd_get_info(ssd_detector *d, ssd_info *out);
  *       slice (fewer than 2^16 pairs in the call, or SSD_SCAN_PASSES) leaves
  *       its counters stale likewise. */
 #define SSD_TUNE_COUNTED 10u
-#define SSD_TUNE_COUNTED_MIN_ITEMS 11u   /* counted scans: offsets per bin a call needs (default 2048, batches 256) */
+#define SSD_TUNE_COUNTED_MIN_ITEMS 11u   /* counted scans: offsets per bin a call needs (default 2048, batches 256);
+                                           the same bar, over bins of 2^18 cells, lets a binned call of a
+                                           detector of 16-bit cells (which keep no counters) take the bitmap
+                                           stores: each touched 16-byte chunk restamped once */
 int ssd_set_tuning(ssd_detector *d, uint32_t knob, uint64_t value);
 
 /* Phase timing (with SSD_TUNE_TIMING on): device time in ms accumulated per

@@ -230,6 +230,11 @@ uint32_t bin_variant(const BinArgs& a);
 hipError_t launch_bin_multi(const MultiBinArgs& m, uint32_t total_wg, hipStream_t s);
 hipError_t launch_apply_multi(const MultiApplyArgs& m, uint32_t total_wg, hipStream_t s);
 hipError_t launch_apply_counted_multi(const MultiApplyArgs& m, uint32_t total_wg, uint32_t lds_bytes, hipStream_t s);
+// bitmap stores of 16-bit cells (no counters): bins of 2^10 .. 2^MARKED16_MAX_SHIFT
+// cells, packed offsets; the bitmap (a bit per cell) is the workgroup's LDS
+constexpr uint32_t MARKED16_MAX_SHIFT = 20;
+constexpr uint32_t MARKED16_LDS_MAX = (1u << (MARKED16_MAX_SHIFT - 5)) * 4u;
+hipError_t launch_apply_marked16(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_count(const LinkDesc* link, uint64_t n_se, hipStream_t s);
 hipError_t launch_recount(const LinkDesc* link, uint64_t n_se, hipStream_t s);
 uint32_t count_workgroups(uint64_t n_se);

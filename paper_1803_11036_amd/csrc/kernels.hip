@@ -673,23 +673,15 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// (workgroup g of this link's launch; lds: the dynamic LDS; list / n_list:
-// the workgroup's list of marked words)
-__device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t g, uint32_t* lds, uint16_t* list,
-                                                   uint32_t& n_list, uint32_t* wsum)
+// The first half of the bitmap stores (bin `bin` of this launch): the LDS is
+// cleared -- its first bm_words words, the bitmap of the bin's cells, to 0,
+// the rest of its n_words to 0x80008000 (two biased 16-bit counters) -- and
+// every cell that an offset of the bin names is marked in the bitmap; a
+// word's first mark appends it to list (the marked words, in the order they
+// were first marked; n_list counts them all, also past CAPPLY_LIST).
+__device__ __forceinline__ void mark_runs(const ApplyArgs& a, uint32_t bin, uint32_t* lds, uint32_t bm_words,
+                                          uint32_t n_words, uint16_t* list, uint32_t& n_list)
 {
-    // workgroup g runs on XCD g mod 8, which takes a contiguous eighth of the
-    // bins in order: neighbouring bins, whose runs share cache lines in every
-    // segment, are read through the same L2 at about the same time
-    const uint32_t per_xcd = (a.n_bins + 7u) >> 3;
-    const uint32_t bin = (g & 7u) * per_xcd + (g >> 3);
-    if (bin >= a.n_bins) return;
-    const uint32_t bm_words = 1u << (a.bin_shift - 5u);
-    const uint32_t n_est = 1u << (a.bin_shift - a.log2eta);
-    const uint32_t k = a.k, slot = a.slot;
-    const uint32_t n_words = bm_words + (n_est * k + 1u) / 2u;
-    uint32_t* bm = lds;
-    uint32_t* cnt = lds + bm_words;                 // 16-bit counters [estimator][slot], biased by 0x8000
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t* row = a.table + (uint64_t)bin * a.blocks;
     // this lane's run (segment j) of the wave's first group, loaded before the
@@ -734,7 +726,7 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
                 for (uint32_t sft = 0; sft < 3; sft++) {
                     if (i0 + sft < st || i0 + sft >= end) continue;
                     const uint32_t off = (uint32_t)(wd >> (21u * sft)) & 0x1FFFFFu;
-                    if (atomicOr(&bm[off >> 5], 1u << (off & 31u)) == 0u) {
+                    if (atomicOr(&lds[off >> 5], 1u << (off & 31u)) == 0u) {
                         const uint32_t at = atomicAdd(&n_list, 1u);
                         if (at < CAPPLY_LIST) list[at] = (uint16_t)(off >> 5);
                     }
@@ -743,6 +735,26 @@ __device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t 
         }
     }
     __syncthreads();
+}
+
+// (workgroup g of this link's launch; lds: the dynamic LDS; list / n_list:
+// the workgroup's list of marked words)
+__device__ __forceinline__ void apply_counted_body(const ApplyArgs& a, uint32_t g, uint32_t* lds, uint16_t* list,
+                                                   uint32_t& n_list, uint32_t* wsum)
+{
+    // workgroup g runs on XCD g mod 8, which takes a contiguous eighth of the
+    // bins in order: neighbouring bins, whose runs share cache lines in every
+    // segment, are read through the same L2 at about the same time
+    const uint32_t per_xcd = (a.n_bins + 7u) >> 3;
+    const uint32_t bin = (g & 7u) * per_xcd + (g >> 3);
+    if (bin >= a.n_bins) return;
+    const uint32_t bm_words = 1u << (a.bin_shift - 5u);
+    const uint32_t n_est = 1u << (a.bin_shift - a.log2eta);
+    const uint32_t k = a.k, slot = a.slot;
+    const uint32_t n_words = bm_words + (n_est * k + 1u) / 2u;
+    uint32_t* bm = lds;
+    uint32_t* cnt = lds + bm_words;                 // 16-bit counters [estimator][slot], biased by 0x8000
+    mark_runs(a, bin, lds, bm_words, n_words, list, n_list);
     // visit: bitmap word w covers the 32 cells of 16-byte chunks 2w and 2w + 1;
     // unmarked halves load the bin's first chunk instead (one line, cached),
     // so that the loads issue back to back
@@ -850,6 +862,68 @@ __global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_counted_multi(Multi
     const uint32_t l = uniform(find_link(m.wg_prefix, m.n, blockIdx.x));
     const ApplyArgs a = m.args[l];
     apply_counted_body(a, blockIdx.x - m.wg_prefix[l], lds, list, n_list, wsum);
+}
+
+// 16-bit cells (windows above 254 slots), which keep no counters: the bitmap
+// stores without the counters, for calls whose offsets repeat cells.  After
+// the walk a bitmap word covers 32 cells, four 16-byte chunks of eight
+// cells; each chunk holding a marked cell is read once, its marked cells take
+// the stamp, and it is written back if that changed it.  Unmarked chunks of a
+// visited word load the bin's first chunk instead (one line, cached), so that
+// the loads issue back to back.
+constexpr uint32_t MARKED16_WORDS = 2;    // bitmap words per thread in flight in the visit
+
+// Cells (two to a 32-bit word) whose bits are set in m2 take the doubled stamp s2.
+__device__ __forceinline__ uint32_t restamp16(uint32_t x, uint32_t m2, uint32_t s2)
+{
+    const uint32_t lanes = ((m2 & 1u) ? 0x0000FFFFu : 0u) | ((m2 & 2u) ? 0xFFFF0000u : 0u);
+    return (x & ~lanes) | (s2 & lanes);
+}
+
+__global__ __launch_bounds__(64 * CAPPLY_WAVES) void k_apply_marked16(ApplyArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint16_t list[CAPPLY_LIST];
+    __shared__ uint32_t n_list;
+    const uint32_t g = blockIdx.x;
+    const uint32_t per_xcd = (a.n_bins + 7u) >> 3;
+    const uint32_t bin = (g & 7u) * per_xcd + (g >> 3);
+    if (bin >= a.n_bins) return;
+    const uint32_t bm_words = 1u << (a.bin_shift - 5u);
+    mark_runs(a, bin, lds, bm_words, bm_words, list, n_list);
+    uint4* chunk = reinterpret_cast<uint4*>(a.state + ((uint64_t)bin << (a.bin_shift + 1u)));    // 2 bytes a cell
+    const uint32_t s2 = (a.stamp & 0xFFFFu) * 0x00010001u;
+    const bool listed = n_list <= CAPPLY_LIST;
+    const uint32_t n_visit = listed ? n_list : bm_words;
+    for (uint32_t w0 = threadIdx.x; w0 < n_visit; w0 += blockDim.x * MARKED16_WORDS) {
+        uint32_t wd[MARKED16_WORDS], m[MARKED16_WORDS];
+#pragma unroll
+        for (int u = 0; u < (int)MARKED16_WORDS; u++) {
+            const uint32_t i = w0 + (uint32_t)u * blockDim.x;
+            wd[u] = i < n_visit ? (listed ? (uint32_t)list[i] : i) : 0u;
+            m[u] = i < n_visit ? lds[wd[u]] : 0u;
+        }
+        uint4 v[4 * MARKED16_WORDS];
+#pragma unroll
+        for (int u = 0; u < (int)MARKED16_WORDS; u++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) v[4 * u + c] = chunk[((m[u] >> (8 * c)) & 0xFFu) ? 4u * wd[u] + c : 0u];
+#pragma unroll
+        for (int u = 0; u < (int)MARKED16_WORDS; u++) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const uint32_t mc = (m[u] >> (8 * c)) & 0xFFu;     // cells 8c .. 8c + 7 of the word
+                if (!mc) continue;
+                const uint4 x = v[4 * u + c];
+                uint4 y;
+                y.x = restamp16(x.x, mc & 3u, s2);
+                y.y = restamp16(x.y, (mc >> 2) & 3u, s2);
+                y.z = restamp16(x.z, (mc >> 4) & 3u, s2);
+                y.w = restamp16(x.w, (mc >> 6) & 3u, s2);
+                if (y.x != x.x || y.y != x.y || y.z != x.z || y.w != x.w) chunk[4u * wd[u] + c] = y;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- hot detection
@@ -1944,6 +2018,21 @@ hipError_t launch_apply(const ApplyArgs& a, hipStream_t s)
         if (a.pack) k_apply<true, uint8_t><<<grid, 64, 0, s>>>(a);
         else k_apply<false, uint8_t><<<grid, 64, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_marked16(const ApplyArgs& a, hipStream_t s)
+{
+    if (!a.cell16 || !a.pack || a.bin_shift < 10 || a.bin_shift > MARKED16_MAX_SHIFT) return hipErrorInvalidValue;
+    const uint32_t lds = (1u << (a.bin_shift - 5u)) * 4u;      // the bitmap
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_marked16),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)MARKED16_LDS_MAX);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    k_apply_marked16<<<apply_counted_workgroups(a), 64 * CAPPLY_WAVES, lds, s>>>(a);
     return hipGetLastError();
 }
 

@@ -686,8 +686,11 @@ int engine_init(Engine* e, const ssd_params* p, uint32_t n, const uint32_t* tabl
 // counted stores for a large call: each touched 16-byte chunk is restamped
 // once, which beats a byte store per offset when the pairs repeat, and the
 // counters are rebuilt at the close (or, in a group, left untrusted).
+// (16-bit cells keep no counters: a large call of theirs takes the bitmap
+// stores without counters, `marked`, over bins of MARKED16_BIN_BYTES.)
+constexpr uint64_t MARKED16_BIN_BYTES = 512ull << 10;
 struct BinnedCall {
-    bool large = false, counted = false, exact = false;
+    bool large = false, counted = false, exact = false, marked = false;
     uint32_t csh = 0;        // counted bin shift (0: the link cannot count)
     BinPlan bp;
     uint64_t seg = 0;        // offsets per binning workgroup (pb * r)
@@ -699,7 +702,11 @@ BinnedCall binned_call(const Engine* e, uint32_t l, uint64_t n, uint64_t bin_byt
     c.large = c.csh && n * e->p[l].r >= e->counted_min_items * bin_plan(e->p[l], 1ull << c.csh).n_bins;
     c.counted = e->counting[l] && c.large;
     c.exact = c.counted && e->count_valid[l];
-    c.bp = bin_plan(e->p[l], c.counted ? 1ull << c.csh : bin_bytes);
+    if (cell16(e->p[l])) {
+        const BinPlan mp = bin_plan(e->p[l], MARKED16_BIN_BYTES);
+        c.marked = mp.shift <= MARKED16_MAX_SHIFT && n * e->p[l].r >= e->counted_min_items * mp.n_bins;
+    }
+    c.bp = bin_plan(e->p[l], c.counted ? 1ull << c.csh : c.marked ? MARKED16_BIN_BYTES : bin_bytes);
     c.seg = (uint64_t)c.bp.pb * e->p[l].r;
     return c;
 }
@@ -723,6 +730,7 @@ BinBufs engine_bins(const Engine* e)
 void binned_count_state(Engine* e, uint32_t l, const BinnedCall& c)
 {
     if (c.counted) e->last_csh[l] = (uint8_t)c.csh;
+    else if (c.marked) e->last_csh[l] = (uint8_t)c.bp.shift;
     if (e->counting[l] && !c.exact) {
         e->count_valid[l] = 0;                 // the counters are not exact after these stores
         // the close rebuilds the counters from the state after large calls
@@ -800,7 +808,9 @@ int enqueue_binned_scan(Engine* e, uint32_t l, const uint2* pairs, uint64_t n, u
         HIPCHK(e, launch_bin(ba, e->stream));
         phase_end(e, pm, PHASE_SCAN_BIN, 1);
         pm = phase_begin(e);
-        HIPCHK(e, counted ? launch_apply_counted(aa, e->stream) : launch_apply(aa, e->stream));
+        HIPCHK(e, counted    ? launch_apply_counted(aa, e->stream)
+                  : c.marked ? launch_apply_marked16(aa, e->stream)
+                             : launch_apply(aa, e->stream));
         phase_end(e, pm, 0, 1);
     }
     return SSD_OK;

@@ -129,7 +129,7 @@ def test_stamp_wrap_and_expiry(k, mode):
     log(f"wrap k={k} {mode} done")
 
 
-@pytest.mark.parametrize("mode,n_slices", [("binned", 302), ("passes", 24)])
+@pytest.mark.parametrize("mode,n_slices", [("binned", 302), ("marked", 302), ("passes", 24)])
 def test_paper_parameter_set_16bit_cells(mode, n_slices):
     """The paper's sliding-window parameter set (Sec. 5): windows of k = 300
     one-second slots, eta = 2^11, q = 14, r = 5, delta = 6, theta = 1024,
@@ -137,16 +137,20 @@ def test_paper_parameter_set_16bit_cells(mode, n_slices):
     background hosts, 60 planted, 30K pairs per slot; about 140 hot
     estimators per row in a full window, which keeps the oracle's literal
     enumeration within seconds per slot) runs k + 2 slots with the default
-    (binned) scan, so that the first slots leave the window, and 24 slots
-    with pass windows.  Lists at every slot; R_k, hot lists and tuples every
-    25 slots and at the last three; the whole canonical state every 60 slots
-    and at the end."""
+    (binned) scan, so that the first slots leave the window, the same with
+    every call taking the bitmap stores (each touched chunk restamped once;
+    by default only calls with 2048 offsets per bin of 2^18 cells), and 24
+    slots with pass windows.  Lists at every slot; R_k, hot lists and tuples
+    every 25 slots and at the last three; the whole canonical state every 60
+    slots and at the end."""
     cfg = tg.config("paper", pairs_lo=30_000, pairs_hi=30_000, n_hosts=300_000, n_planted=60)
     tr = tg.Trace(cfg)
     tabs = tg.hash_tables(cfg.hash_seed)
     g, o = make_pair(cfg.q, cfg.r, cfg.delta, cfg.eta, cfg.k, cfg.theta, tabs, cell_bits=16)
     if mode == "passes":
         ssd.set_tuning(g, ssd.SSD_TUNE_SCAN_MODE, ssd.SSD_SCAN_PASSES)
+    if mode == "marked":
+        ssd.set_tuning(g, ssd.SSD_TUNE_COUNTED_MIN_ITEMS, 0)
     ssd.set_tuning(g, ssd.SSD_TUNE_TIMING, 1)
     reported = 0
     for t in range(n_slices):
@@ -162,7 +166,8 @@ def test_paper_parameter_set_16bit_cells(mode, n_slices):
     assert reported > 0
     tm = ssd.read_timing(g)
     assert tm["hot_detect"][1] == n_slices and tm["count_detect"][1] == 0
-    assert (tm["scan_bin"][1] > 0) == (mode == "binned")
+    assert (tm["scan_bin"][1] > 0) == (mode != "passes")
+    assert ssd.get_info(g)["counted_bin_kib"] == (256 if mode == "marked" else 0)
     log(f"paper k=300 {mode}: {reported} hosts at slice {n_slices - 1}")
 
 
