@@ -49,18 +49,27 @@ class StreamInput:
     starts: np.ndarray
     reservoir: torch.Tensor
 
-    def pieces(self, j: int) -> List[torch.Tensor]:
-        """Batch j as views of the reservoir: exactly sizes[j] rows from
-        starts[j] on, wrapping around the reservoir as often as needed."""
+    def ranges(self, j: int) -> List[Tuple[int, int]]:
+        """Batch j as (first row, rows) ranges of the reservoir: exactly
+        sizes[j] rows from starts[j] on, wrapping around it as often as needed."""
         R = self.reservoir.shape[0]
         a, n = int(self.starts[j]) % R, int(self.sizes[j])
         out = []
         while n > 0:
             m = min(n, R - a)
-            out.append(self.reservoir[a:a + m])
+            out.append((a, m))
             n -= m
             a = 0
         return out
+
+    def pieces(self, j: int) -> List[torch.Tensor]:
+        """Batch j as views of the reservoir."""
+        return [self.reservoir[a:a + m] for a, m in self.ranges(j)]
+
+    def run_pieces(self, j0: int, j1: int) -> List[torch.Tensor]:
+        """Batches j0 .. j1 - 1 in order, as views of the reservoir, each
+        covering a run of rows that the batches take one after another."""
+        return [self.reservoir[a:a + m] for a, m in coalesce(r for j in range(j0, j1) for r in self.ranges(j))]
 
     def batch(self, j: int) -> torch.Tensor:
         """Batch j as one tensor (a view when it does not wrap, else a copy)."""
@@ -68,6 +77,20 @@ class StreamInput:
         if not p:
             return self.reservoir[:0]
         return p[0] if len(p) == 1 else torch.cat(p)
+
+
+def coalesce(ranges) -> List[Tuple[int, int]]:
+    """(first, count) ranges in order, each range that starts where the
+    previous one ends joined to it."""
+    out: List[Tuple[int, int]] = []
+    for a, m in ranges:
+        if m <= 0:
+            continue
+        if out and out[-1][0] + out[-1][1] == a:
+            out[-1] = (out[-1][0], out[-1][1] + m)
+        else:
+            out.append((a, m))
+    return out
 
 
 @dataclasses.dataclass
@@ -196,8 +219,7 @@ def serve(streams: Sequence[StreamInput], budget_bytes: int, time_scale: float =
             if j > L.next:
                 members.append(L)
                 if batched:
-                    for b in range(L.next, j):
-                        parts.extend(s.pieces(b))
+                    parts.extend(s.run_pieces(L.next, j))
                 else:
                     parts.extend(s.batch(b) for b in range(L.next, j))
                 counts.append(int(s.sizes[L.next:j].sum()))
